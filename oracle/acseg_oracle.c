@@ -1,0 +1,849 @@
+/*
+ * acseg_oracle.c -- plain FP64 CPU oracle for the vector-valued Allen-Cahn
+ * phase-field segmentation of Kay & Tomasi ("Colour Image Segmentation by the
+ * Vector-valued Allen-Cahn Phase-field Model: a Multigrid Solution").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant generator with the HIP implementation; it is slow
+ * on purpose and written so that each function can be checked against the
+ * paper by eye.
+ *
+ * What is computed, by section of the paper:
+ *   - the P1 finite-element space on the pixel lattice, its lumped mass
+ *     M_p = <eta_p, 1> and stiffness A_pq = <grad eta_p, grad eta_q>
+ *     (Section "Finite Element Notation"), assembled triangle by triangle;
+ *   - colour means c_ij = int u_i I_j / int u_i and fitting
+ *     F_i = sum_j (I_j - c_ij)^2 (eq. VV_fidelity and its multichannel form in
+ *     Section "Two Dimensional Examples"), with the lumped-mass quadrature
+ *     ("projection by node", Section "Data Projection");
+ *   - one backward-Euler time step of the discrete variational inequality
+ *     (eq. E_fe, eq. alpha): the diffusion and the simplex constraint are
+ *     implicit, the concave part -(2/eps) u and the fitting term are taken at
+ *     the old time level.  Readings: the stiffness enters with a positive sign
+ *     (it comes from eps |grad u|^2 / 2 in eq. E), and the time step multiplies
+ *     the whole bracket of eq. alpha;
+ *   - the Gibbs-simplex correction of Section "Gibbs Space Constraint
+ *     Pseudocode" (zero the negative components, spread the removed amount
+ *     equally over the others, repeat);
+ *   - a lexicographic projected block Gauss-Seidel sweep over the nodal
+ *     sub-problems (Section "Finite Element Notation") and a truncated
+ *     multigrid correction with an exact line search (Section "Multigrid
+ *     Solution"; truncation as motivated at the start of the Gibbs-constraint
+ *     section), iterated until the natural residual meets the tolerance;
+ *   - the discrete energy of eq. E and the composite / rounded composite of
+ *     Section "Post-processing".
+ *
+ * Data layout: node (x, y) of a W x H lattice has flat index p = y*W + x;
+ * phase fields are [N][H*W], images [C][H*W], all double.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAX_N 64
+
+typedef struct {
+    int32_t H, W, C, N;
+    double h, eps, lambda, tau;
+    int32_t levels;        /* lattice levels incl. the finest; 1 = Gauss-Seidel only, 0 = auto */
+    int32_t nu_pre, nu_post;
+    int32_t coarse_sweeps; /* Gauss-Seidel sweeps on the coarsest level */
+    int32_t max_cycles;
+    int32_t pad;
+    double tol;            /* on the natural residual (max norm) */
+} orc_params;
+
+typedef struct {
+    int32_t cycles;
+    int32_t converged;
+    int32_t empty_phase;
+    int32_t nonmonotone;   /* coarse corrections that raised the step objective */
+    double residual;
+    double objective;
+} orc_stats;
+
+/* ------------------------------------------------------------------------ */
+/* Finite-element space on the lattice                                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int W, H;
+    double h;
+    double *mass;   /* [H*W]   lumped mass <eta_p, 1> */
+    double *stiff;  /* [H*W*9] A_pq for q = p + (dx, dy), slot (dy+1)*3 + (dx+1) */
+} grid_t;
+
+static int slot(int dx, int dy) { return (dy + 1) * 3 + (dx + 1); }
+
+/* Add the contributions of one P1 triangle with lattice vertices v[3][2]. */
+static void add_triangle(grid_t *g, const int v[3][2])
+{
+    double X[3], Y[3];
+    for (int a = 0; a < 3; ++a) {
+        X[a] = v[a][0] * g->h;
+        Y[a] = v[a][1] * g->h;
+    }
+    /* twice the signed area */
+    double two_area = (X[1] - X[0]) * (Y[2] - Y[0]) - (X[2] - X[0]) * (Y[1] - Y[0]);
+    double area = fabs(two_area) / 2.0;
+    /* gradients of the three barycentric (hat) functions on this triangle */
+    double gx[3], gy[3];
+    for (int a = 0; a < 3; ++a) {
+        int b = (a + 1) % 3, c = (a + 2) % 3;
+        gx[a] = (Y[b] - Y[c]) / two_area;
+        gy[a] = (X[c] - X[b]) / two_area;
+    }
+    for (int a = 0; a < 3; ++a) {
+        int pa = v[a][1] * g->W + v[a][0];
+        g->mass[pa] += area / 3.0;  /* integral of a hat function over the triangle */
+        for (int b = 0; b < 3; ++b) {
+            int dx = v[b][0] - v[a][0], dy = v[b][1] - v[a][1];
+            g->stiff[(size_t)pa * 9 + slot(dx, dy)] += area * (gx[a] * gx[b] + gy[a] * gy[b]);
+        }
+    }
+}
+
+/* Every lattice cell is split along its diagonal (x,y)-(x+1,y+1). */
+static int grid_init(grid_t *g, int W, int H, double h)
+{
+    g->W = W;
+    g->H = H;
+    g->h = h;
+    g->mass = calloc((size_t)W * H, sizeof(double));
+    g->stiff = calloc((size_t)W * H * 9, sizeof(double));
+    if (!g->mass || !g->stiff) return -1;
+    for (int cy = 0; cy + 1 < H; ++cy)
+        for (int cx = 0; cx + 1 < W; ++cx) {
+            const int t1[3][2] = {{cx, cy}, {cx + 1, cy}, {cx + 1, cy + 1}};
+            const int t2[3][2] = {{cx, cy}, {cx + 1, cy + 1}, {cx, cy + 1}};
+            add_triangle(g, t1);
+            add_triangle(g, t2);
+        }
+    return 0;
+}
+
+static void grid_free(grid_t *g)
+{
+    free(g->mass);
+    free(g->stiff);
+    g->mass = g->stiff = NULL;
+}
+
+/* (A v)_p for one scalar field v on grid g */
+static double stiff_apply(const grid_t *g, const double *v, int x, int y)
+{
+    double s = 0.0;
+    int p = y * g->W + x;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            int qx = x + dx, qy = y + dy;
+            if (qx < 0 || qy < 0 || qx >= g->W || qy >= g->H) continue;
+            s += g->stiff[(size_t)p * 9 + slot(dx, dy)] * v[qy * g->W + qx];
+        }
+    return s;
+}
+
+/* sum over q != p of A_pq v_q */
+static double stiff_offdiag(const grid_t *g, const double *v, int x, int y)
+{
+    int p = y * g->W + x;
+    return stiff_apply(g, v, x, y) - g->stiff[(size_t)p * 9 + slot(0, 0)] * v[p];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gibbs-simplex projection                                                  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Euclidean projection of y onto {x : sum_i x_i = 1, x_i >= 0}, following the
+ * correction loop of Section "Gibbs Space Constraint Pseudocode":
+ *   1. move y onto the hyperplane sum = 1 along 1_N (the operator T of eq.
+ *      projection_operator_T applied to the update);
+ *   2. if no component is negative, stop;
+ *   3. set every negative component to zero and remove it from the free set;
+ *      the sum has then grown by the removed amount, which is taken off the
+ *      k remaining free components in equal parts;
+ *   4. repeat from 2 with the free set only.
+ * Each round removes at least one component, so there are at most N rounds.
+ * Returns the number of rounds (>= 1).
+ */
+int orc_project(int N, const double *y, double *x)
+{
+    unsigned char free_[ORC_MAX_N];
+    if (N < 1 || N > ORC_MAX_N) return -1;
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) s += y[i];
+    for (int i = 0; i < N; ++i) {
+        x[i] = y[i] + (1.0 - s) / N;
+        free_[i] = 1;
+    }
+    int rounds = 1;
+    for (;;) {
+        double removed = 0.0;
+        int nneg = 0, nfree = 0;
+        for (int i = 0; i < N; ++i)
+            if (free_[i] && x[i] < 0.0) {
+                removed += -x[i];
+                x[i] = 0.0;
+                free_[i] = 0;
+                ++nneg;
+            }
+        if (nneg == 0) break;
+        for (int i = 0; i < N; ++i) nfree += free_[i];
+        for (int i = 0; i < N; ++i)
+            if (free_[i]) x[i] -= removed / nfree;
+        ++rounds;
+    }
+    return rounds;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Colour means, fitting term, right-hand side                               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * c_ij = sum_p M_p u_pi I_pj / sum_p M_p u_pi.  A phase whose mass is below
+ * 1e-12 of the domain area has no mean; it keeps c_prev (or, without c_prev,
+ * the mean colour of the whole image).  Returns 1 if some phase was empty.
+ */
+static int colour_means(const grid_t *g, int N, int C, const double *I, const double *u,
+                        const double *c_prev, double *c)
+{
+    size_t n = (size_t)g->W * g->H;
+    double area = 0.0;
+    for (size_t p = 0; p < n; ++p) area += g->mass[p];
+    int empty = 0;
+    for (int i = 0; i < N; ++i) {
+        double S = 0.0;
+        for (size_t p = 0; p < n; ++p) S += g->mass[p] * u[i * n + p];
+        if (S > 1e-12 * area) {
+            for (int k = 0; k < C; ++k) {
+                double Sk = 0.0;
+                for (size_t p = 0; p < n; ++p) Sk += g->mass[p] * u[i * n + p] * I[k * n + p];
+                c[i * C + k] = Sk / S;
+            }
+        } else {
+            empty = 1;
+            for (int k = 0; k < C; ++k) {
+                if (c_prev) {
+                    c[i * C + k] = c_prev[i * C + k];
+                } else {
+                    double Sk = 0.0;
+                    for (size_t p = 0; p < n; ++p) Sk += g->mass[p] * I[k * n + p];
+                    c[i * C + k] = Sk / area;
+                }
+            }
+        }
+    }
+    return empty;
+}
+
+static double fitting(int C, const double *I, size_t n, size_t p, const double *ci)
+{
+    double F = 0.0;
+    for (int k = 0; k < C; ++k) {
+        double d = I[k * n + p] - ci[k];
+        F += d * d;
+    }
+    return F;
+}
+
+/* b_pi = M_p [ (1/tau + 2/eps) un_pi - lambda F_pi(c) ] */
+static void rhs(const grid_t *g, const orc_params *P, const double *I, const double *un,
+                const double *c, double *b)
+{
+    size_t n = (size_t)g->W * g->H;
+    for (int i = 0; i < P->N; ++i)
+        for (size_t p = 0; p < n; ++p)
+            b[i * n + p] = g->mass[p] * ((1.0 / P->tau + 2.0 / P->eps) * un[i * n + p]
+                                         - P->lambda * fitting(P->C, I, n, p, c + i * P->C));
+}
+
+/* ------------------------------------------------------------------------ */
+/* The step problem: minimise J(u) = sum_i [ u_i.H u_i / 2 - b_i.u_i ]       */
+/* over the product of simplices, H = M/tau + eps A.                          */
+/* ------------------------------------------------------------------------ */
+
+static double diag_H(const grid_t *g, const orc_params *P, size_t p)
+{
+    return g->mass[p] / P->tau + P->eps * g->stiff[p * 9 + slot(0, 0)];
+}
+
+/* Unconstrained nodal minimiser y_p of J in the block of node p (N values). */
+static void nodal_trial(const grid_t *g, const orc_params *P, const double *b, const double *u,
+                        int x, int y, double *yv)
+{
+    size_t n = (size_t)g->W * g->H, p = (size_t)y * g->W + x;
+    double d = diag_H(g, P, p);
+    for (int i = 0; i < P->N; ++i)
+        yv[i] = (b[i * n + p] - P->eps * stiff_offdiag(g, u + i * n, x, y)) / d;
+}
+
+/* One lexicographic (row-major) sweep of projected block Gauss-Seidel. */
+static void gs_sweep(const grid_t *g, const orc_params *P, const double *b, double *u)
+{
+    size_t n = (size_t)g->W * g->H;
+    double yv[ORC_MAX_N], xv[ORC_MAX_N];
+    for (int y = 0; y < g->H; ++y)
+        for (int x = 0; x < g->W; ++x) {
+            nodal_trial(g, P, b, u, x, y, yv);
+            orc_project(P->N, yv, xv);
+            for (int i = 0; i < P->N; ++i) u[i * n + (size_t)y * g->W + x] = xv[i];
+        }
+}
+
+/* Natural residual max_{p,i} |Pi(y_p(u)) - u_p|, every node evaluated at u. */
+static double natural_residual(const grid_t *g, const orc_params *P, const double *b,
+                               const double *u)
+{
+    size_t n = (size_t)g->W * g->H;
+    double yv[ORC_MAX_N], xv[ORC_MAX_N], r = 0.0;
+    for (int y = 0; y < g->H; ++y)
+        for (int x = 0; x < g->W; ++x) {
+            nodal_trial(g, P, b, u, x, y, yv);
+            orc_project(P->N, yv, xv);
+            for (int i = 0; i < P->N; ++i) {
+                double d = fabs(xv[i] - u[i * n + (size_t)y * g->W + x]);
+                if (d > r) r = d;
+            }
+        }
+    return r;
+}
+
+static double objective(const grid_t *g, const orc_params *P, const double *b, const double *u)
+{
+    size_t n = (size_t)g->W * g->H;
+    double J = 0.0;
+    for (int i = 0; i < P->N; ++i)
+        for (int y = 0; y < g->H; ++y)
+            for (int x = 0; x < g->W; ++x) {
+                size_t p = (size_t)y * g->W + x;
+                double Hu = g->mass[p] / P->tau * u[i * n + p] + P->eps * stiff_apply(g, u + i * n, x, y);
+                J += 0.5 * u[i * n + p] * Hu - b[i * n + p] * u[i * n + p];
+            }
+    return J;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lattice hierarchy and transfers                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Coarse node j sits on fine node 2j, so a side of n nodes coarsens to ceil(n/2). */
+static int coarse_side(int n) { return (n + 1) / 2; }
+
+int orc_auto_levels(int W, int H)
+{
+    int L = 1;
+    while ((W > H ? W : H) > 15 && (W < H ? W : H) >= 3) {
+        W = coarse_side(W);
+        H = coarse_side(H);
+        ++L;
+    }
+    return L;
+}
+
+/*
+ * Prolongation: the fine value at node (x, y) is the coarse P1 function
+ * evaluated at the fine node's position, (x/2, y/2) in coarse lattice units,
+ * clamped into the coarse lattice (a fine node past the last coarse row or
+ * column takes the value on that row or column).  The coarse cell is split
+ * along the same diagonal as the fine ones.  Emits up to 3 (coarse index,
+ * weight) pairs and returns their count.
+ */
+static int prolong_weights(int x, int y, int Wc, int Hc, int *q, double *wt)
+{
+    double X = 0.5 * x, Y = 0.5 * y;
+    if (X > Wc - 1) X = Wc - 1;
+    if (Y > Hc - 1) Y = Hc - 1;
+    int i0 = (int)floor(X), j0 = (int)floor(Y);
+    int i1 = i0 + 1 < Wc ? i0 + 1 : i0, j1 = j0 + 1 < Hc ? j0 + 1 : j0;
+    double s = X - i0, t = Y - j0;
+    int m = 0;
+    /* barycentric coordinates on the lower (s >= t) or upper (s < t) triangle */
+    if (s >= t) {
+        q[m] = j0 * Wc + i0; wt[m++] = 1.0 - s;
+        q[m] = j0 * Wc + i1; wt[m++] = s - t;
+        q[m] = j1 * Wc + i1; wt[m++] = t;
+    } else {
+        q[m] = j0 * Wc + i0; wt[m++] = 1.0 - t;
+        q[m] = j1 * Wc + i0; wt[m++] = t - s;
+        q[m] = j1 * Wc + i1; wt[m++] = s;
+    }
+    return m;
+}
+
+/* vf (fine, N planes) = P vc */
+static void prolong(const grid_t *f, const grid_t *cg, int N, const double *vc, double *vf)
+{
+    size_t nf = (size_t)f->W * f->H, nc = (size_t)cg->W * cg->H;
+    int q[3];
+    double wt[3];
+    for (int y = 0; y < f->H; ++y)
+        for (int x = 0; x < f->W; ++x) {
+            int m = prolong_weights(x, y, cg->W, cg->H, q, wt);
+            for (int i = 0; i < N; ++i) {
+                double s = 0.0;
+                for (int k = 0; k < m; ++k) s += wt[k] * vc[i * nc + q[k]];
+                vf[i * nf + (size_t)y * f->W + x] = s;
+            }
+        }
+}
+
+/* rc (coarse, N planes) = P^T rf */
+static void restrict_T(const grid_t *f, const grid_t *cg, int N, const double *rf, double *rc)
+{
+    size_t nf = (size_t)f->W * f->H, nc = (size_t)cg->W * cg->H;
+    int q[3];
+    double wt[3];
+    memset(rc, 0, sizeof(double) * N * nc);
+    for (int y = 0; y < f->H; ++y)
+        for (int x = 0; x < f->W; ++x) {
+            int m = prolong_weights(x, y, cg->W, cg->H, q, wt);
+            for (int i = 0; i < N; ++i)
+                for (int k = 0; k < m; ++k)
+                    rc[i * nc + q[k]] += wt[k] * rf[i * nf + (size_t)y * f->W + x];
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Linear coarse-level correction (componentwise, untruncated operator)       */
+/* ------------------------------------------------------------------------ */
+
+static void lin_gs_sweep(const grid_t *g, const orc_params *P, const double *r, double *v)
+{
+    size_t n = (size_t)g->W * g->H;
+    for (int y = 0; y < g->H; ++y)
+        for (int x = 0; x < g->W; ++x) {
+            size_t p = (size_t)y * g->W + x;
+            double d = diag_H(g, P, p);
+            for (int i = 0; i < P->N; ++i)
+                v[i * n + p] = (r[i * n + p] - P->eps * stiff_offdiag(g, v + i * n, x, y)) / d;
+        }
+}
+
+/* res = r - H v */
+static void lin_residual(const grid_t *g, const orc_params *P, const double *r, const double *v,
+                         double *res)
+{
+    size_t n = (size_t)g->W * g->H;
+    for (int i = 0; i < P->N; ++i)
+        for (int y = 0; y < g->H; ++y)
+            for (int x = 0; x < g->W; ++x) {
+                size_t p = (size_t)y * g->W + x;
+                res[i * n + p] = r[i * n + p] - (g->mass[p] / P->tau * v[i * n + p]
+                                                 + P->eps * stiff_apply(g, v + i * n, x, y));
+            }
+}
+
+/* Approximate solve of H_l v = r on level l (0 = finest) with a V-cycle, v from 0. */
+static void coarse_vcycle(const grid_t *G, int L, int l, const orc_params *P, const double *r,
+                          double *v)
+{
+    const grid_t *g = &G[l];
+    size_t n = (size_t)g->W * g->H;
+    memset(v, 0, sizeof(double) * P->N * n);
+    if (l == L - 1) {
+        for (int s = 0; s < P->coarse_sweeps; ++s) lin_gs_sweep(g, P, r, v);
+        return;
+    }
+    for (int s = 0; s < P->nu_pre; ++s) lin_gs_sweep(g, P, r, v);
+    const grid_t *c = &G[l + 1];
+    size_t nc = (size_t)c->W * c->H;
+    double *res = malloc(sizeof(double) * P->N * n);
+    double *rc = malloc(sizeof(double) * P->N * nc);
+    double *vc = malloc(sizeof(double) * P->N * nc);
+    double *e = malloc(sizeof(double) * P->N * n);
+    lin_residual(g, P, r, v, res);
+    restrict_T(g, c, P->N, res, rc);
+    coarse_vcycle(G, L, l + 1, P, rc, vc);
+    prolong(g, c, P->N, vc, e);
+    for (size_t k = 0; k < (size_t)P->N * n; ++k) v[k] += e[k];
+    for (int s = 0; s < P->nu_post; ++s) lin_gs_sweep(g, P, r, v);
+    free(res);
+    free(rc);
+    free(vc);
+    free(e);
+}
+
+/*
+ * T_I x: zero the components outside the free set I = {i : u_i > 0} and
+ * remove the mean over I from the others (the tangent projection restricted to
+ * the free components).  With one free component or fewer the result is 0.
+ */
+static void tangent_free(int N, const double *up, const double *xin, double *xout)
+{
+    int k = 0;
+    double s = 0.0;
+    for (int i = 0; i < N; ++i)
+        if (up[i] > 0.0) {
+            ++k;
+            s += xin[i];
+        }
+    for (int i = 0; i < N; ++i) xout[i] = (k >= 2 && up[i] > 0.0) ? xin[i] - s / k : 0.0;
+}
+
+/*
+ * One truncated multigrid cycle on the step problem:
+ *   pre-smooth; defect g = b - H u; truncate it node by node with T_I;
+ *   restrict; approximately solve the componentwise linear coarse problems;
+ *   prolong, truncate again, make it feasible (w = Pi(u + v) - u, a feasible
+ *   direction because the simplex is convex); exact line search on J along w
+ *   with the step clamped to [0, 1]; post-smooth.
+ * Returns 1 if the coarse correction raised J (never expected).
+ */
+static int mg_cycle(const grid_t *G, int L, const orc_params *P, const double *b, double *u)
+{
+    const grid_t *g = &G[0];
+    const grid_t *c = &G[1];
+    int N = P->N;
+    size_t n = (size_t)g->W * g->H, nc = (size_t)c->W * c->H;
+    for (int s = 0; s < P->nu_pre; ++s) gs_sweep(g, P, b, u);
+
+    double *gd = malloc(sizeof(double) * N * n);
+    double *gt = malloc(sizeof(double) * N * n);
+    double *rc = malloc(sizeof(double) * N * nc);
+    double *vc = malloc(sizeof(double) * N * nc);
+    double *v = malloc(sizeof(double) * N * n);
+    double *w = malloc(sizeof(double) * N * n);
+    double up[ORC_MAX_N], xi[ORC_MAX_N], xo[ORC_MAX_N];
+
+    /* defect g = b - H u (the negative gradient of J) */
+    for (int i = 0; i < N; ++i)
+        for (int y = 0; y < g->H; ++y)
+            for (int x = 0; x < g->W; ++x) {
+                size_t p = (size_t)y * g->W + x;
+                gd[i * n + p] = b[i * n + p] - (g->mass[p] / P->tau * u[i * n + p]
+                                                + P->eps * stiff_apply(g, u + i * n, x, y));
+            }
+    for (size_t p = 0; p < n; ++p) {
+        for (int i = 0; i < N; ++i) {
+            up[i] = u[i * n + p];
+            xi[i] = gd[i * n + p];
+        }
+        tangent_free(N, up, xi, xo);
+        for (int i = 0; i < N; ++i) gt[i * n + p] = xo[i];
+    }
+    restrict_T(g, c, N, gt, rc);
+    coarse_vcycle(G, L, 1, P, rc, vc);
+    prolong(g, c, N, vc, v);
+
+    /* feasible direction */
+    for (size_t p = 0; p < n; ++p) {
+        for (int i = 0; i < N; ++i) {
+            up[i] = u[i * n + p];
+            xi[i] = v[i * n + p];
+        }
+        tangent_free(N, up, xi, xo);
+        for (int i = 0; i < N; ++i) xi[i] = up[i] + xo[i];
+        orc_project(N, xi, xo);
+        for (int i = 0; i < N; ++i) w[i * n + p] = xo[i] - up[i];
+    }
+    /*
+     * Exact line search: J(u + a w) = J(u) - a <g,w> + a^2 <w,Hw> / 2.  The
+     * direction w is zero on the active components and sums to zero over the
+     * free ones at every node, so <g,w> = <T_I g, w>; the truncated defect is
+     * used because the full one carries the per-node multiplier of the sum
+     * constraint, whose round-off would swamp <g,w> near convergence.
+     */
+    double gw = 0.0, wHw = 0.0;
+    for (int i = 0; i < N; ++i)
+        for (int y = 0; y < g->H; ++y)
+            for (int x = 0; x < g->W; ++x) {
+                size_t p = (size_t)y * g->W + x;
+                gw += gt[i * n + p] * w[i * n + p];
+                wHw += w[i * n + p] * (g->mass[p] / P->tau * w[i * n + p]
+                                       + P->eps * stiff_apply(g, w + i * n, x, y));
+            }
+    int bad = 0;
+    if (wHw > 0.0 && gw > 0.0) {
+        double a = gw / wHw;
+        if (a > 1.0) a = 1.0;
+        double J0 = objective(g, P, b, u);
+        for (size_t k = 0; k < (size_t)N * n; ++k) u[k] += a * w[k];
+        double J1 = objective(g, P, b, u);
+        if (J1 > J0 + 1e-12 * fabs(J0)) bad = 1;
+    }
+    free(gd);
+    free(gt);
+    free(rc);
+    free(vc);
+    free(v);
+    free(w);
+    for (int s = 0; s < P->nu_post; ++s) gs_sweep(g, P, b, u);
+    return bad;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Public oracle entry points                                                */
+/* ------------------------------------------------------------------------ */
+
+static int hierarchy_init(const orc_params *P, grid_t *G, int *L_out)
+{
+    int L = P->levels > 0 ? P->levels : orc_auto_levels(P->W, P->H);
+    int W = P->W, H = P->H;
+    double h = P->h;
+    for (int l = 0; l < L; ++l) {
+        if (l > 0) {
+            W = coarse_side(W);
+            H = coarse_side(H);
+            h *= 2.0;
+        }
+        if (W < 2 || H < 2) return -1;
+        if (grid_init(&G[l], W, H, h)) return -1;
+    }
+    *L_out = L;
+    return 0;
+}
+
+static void hierarchy_free(grid_t *G, int L)
+{
+    for (int l = 0; l < L; ++l) grid_free(&G[l]);
+}
+
+/* Assembled lumped mass [H*W] and stiffness stencils [H*W*9] of a W x H lattice. */
+int orc_assemble(int W, int H, double h, double *mass, double *stiff)
+{
+    grid_t g;
+    if (grid_init(&g, W, H, h)) return -1;
+    memcpy(mass, g.mass, sizeof(double) * W * H);
+    memcpy(stiff, g.stiff, sizeof(double) * W * H * 9);
+    grid_free(&g);
+    return 0;
+}
+
+int orc_prolong(int Wf, int Hf, int N, const double *vc, double *vf)
+{
+    grid_t f = {Wf, Hf, 1.0, NULL, NULL}, c = {coarse_side(Wf), coarse_side(Hf), 2.0, NULL, NULL};
+    prolong(&f, &c, N, vc, vf);
+    return 0;
+}
+
+int orc_restrict(int Wf, int Hf, int N, const double *vf, double *vc)
+{
+    grid_t f = {Wf, Hf, 1.0, NULL, NULL}, c = {coarse_side(Wf), coarse_side(Hf), 2.0, NULL, NULL};
+    restrict_T(&f, &c, N, vf, vc);
+    return 0;
+}
+
+int orc_colour_means(const orc_params *P, const double *I, const double *u, const double *c_prev,
+                     double *c)
+{
+    grid_t g;
+    if (grid_init(&g, P->W, P->H, P->h)) return -1;
+    int e = colour_means(&g, P->N, P->C, I, u, c_prev, c);
+    grid_free(&g);
+    return e;
+}
+
+int orc_rhs(const orc_params *P, const double *I, const double *un, const double *c, double *b)
+{
+    grid_t g;
+    if (grid_init(&g, P->W, P->H, P->h)) return -1;
+    rhs(&g, P, I, un, c, b);
+    grid_free(&g);
+    return 0;
+}
+
+double orc_residual(const orc_params *P, const double *b, const double *u)
+{
+    grid_t g;
+    if (grid_init(&g, P->W, P->H, P->h)) return -1.0;
+    double r = natural_residual(&g, P, b, u);
+    grid_free(&g);
+    return r;
+}
+
+double orc_objective(const orc_params *P, const double *b, const double *u)
+{
+    grid_t g;
+    if (grid_init(&g, P->W, P->H, P->h)) return NAN;
+    double J = objective(&g, P, b, u);
+    grid_free(&g);
+    return J;
+}
+
+/* out = H v per component, H = M/tau + eps A on the W x H lattice of spacing h */
+int orc_apply_H(const orc_params *P, const double *v, double *out)
+{
+    grid_t g;
+    if (grid_init(&g, P->W, P->H, P->h)) return -1;
+    size_t n = (size_t)P->W * P->H;
+    for (int i = 0; i < P->N; ++i)
+        for (int y = 0; y < P->H; ++y)
+            for (int x = 0; x < P->W; ++x) {
+                size_t p = (size_t)y * P->W + x;
+                out[i * n + p] = g.mass[p] / P->tau * v[i * n + p] + P->eps * stiff_apply(&g, v + i * n, x, y);
+            }
+    grid_free(&g);
+    return 0;
+}
+
+/*
+ * Solve the step problem for a given right-hand side b, starting from u
+ * (overwritten with the result).  Cycles are multigrid cycles when the
+ * hierarchy has two or more levels, single Gauss-Seidel sweeps otherwise;
+ * they repeat until the natural residual is <= tol or max_cycles is reached.
+ */
+static int solve_rhs(const grid_t *G, int L, const orc_params *P, const double *b, double *u,
+                     orc_stats *st)
+{
+    int cycles = 0, bad = 0;
+    double r;
+    do {
+        if (L >= 2)
+            bad += mg_cycle(G, L, P, b, u);
+        else
+            gs_sweep(&G[0], P, b, u);
+        ++cycles;
+        r = natural_residual(&G[0], P, b, u);
+    } while (r > P->tol && cycles < P->max_cycles);
+    if (st) {
+        st->cycles = cycles;
+        st->converged = r <= P->tol;
+        st->nonmonotone = bad;
+        st->residual = r;
+        st->objective = objective(&G[0], P, b, u);
+    }
+    return 0;
+}
+
+/* Solve the step problem for a caller-supplied b (u: initial iterate in, result out). */
+int orc_solve_qp(const orc_params *P, const double *b, double *u, orc_stats *st)
+{
+    grid_t G[32];
+    int L;
+    if (hierarchy_init(P, G, &L)) return -1;
+    solve_rhs(G, L, P, b, u, st);
+    hierarchy_free(G, L);
+    return 0;
+}
+
+/*
+ * One time step: c = colour means of un (c_prev for empty phases), b from un
+ * and c, then u_out = argmin J over the simplices, starting from un.
+ * c_out receives the means used in this step.  Returns 0, or -1 on bad input.
+ */
+int orc_step(const orc_params *P, const double *I, const double *un, const double *c_prev,
+             double *u_out, double *c_out, orc_stats *st)
+{
+    grid_t G[32];
+    int L;
+    if (hierarchy_init(P, G, &L)) return -1;
+    size_t n = (size_t)P->W * P->H;
+    double *b = malloc(sizeof(double) * P->N * n);
+    int empty = colour_means(&G[0], P->N, P->C, I, un, c_prev, c_out);
+    rhs(&G[0], P, I, un, c_out, b);
+    memcpy(u_out, un, sizeof(double) * P->N * n);
+    solve_rhs(G, L, P, b, u_out, st);
+    if (st) st->empty_phase = empty;
+    free(b);
+    hierarchy_free(G, L);
+    return 0;
+}
+
+/*
+ * `steps` time steps from u0.  traj (optional) receives u^0..u^steps
+ * ([steps+1][N][H*W]), c_traj (optional) the means used in each step
+ * ([steps][N][C]), stats (optional) one record per step.  u_out gets u^steps.
+ */
+int orc_solve(const orc_params *P, int steps, const double *I, const double *u0, double *u_out,
+              double *traj, double *c_traj, orc_stats *stats)
+{
+    grid_t G[32];
+    int L;
+    if (hierarchy_init(P, G, &L)) return -1;
+    size_t n = (size_t)P->W * P->H, nu = (size_t)P->N * n;
+    double *b = malloc(sizeof(double) * nu);
+    double *cur = malloc(sizeof(double) * nu);
+    double *nxt = malloc(sizeof(double) * nu);
+    double *c = malloc(sizeof(double) * P->N * P->C);
+    double *cp = malloc(sizeof(double) * P->N * P->C);
+    memcpy(cur, u0, sizeof(double) * nu);
+    if (traj) memcpy(traj, u0, sizeof(double) * nu);
+    for (int s = 0; s < steps; ++s) {
+        int empty = colour_means(&G[0], P->N, P->C, I, cur, s > 0 ? cp : NULL, c);
+        rhs(&G[0], P, I, cur, c, b);
+        memcpy(nxt, cur, sizeof(double) * nu);
+        orc_stats st;
+        solve_rhs(G, L, P, b, nxt, &st);
+        st.empty_phase = empty;
+        if (stats) stats[s] = st;
+        if (c_traj) memcpy(c_traj + (size_t)s * P->N * P->C, c, sizeof(double) * P->N * P->C);
+        if (traj) memcpy(traj + (size_t)(s + 1) * nu, nxt, sizeof(double) * nu);
+        memcpy(cp, c, sizeof(double) * P->N * P->C);
+        double *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    memcpy(u_out, cur, sizeof(double) * nu);
+    free(b);
+    free(cur);
+    free(nxt);
+    free(c);
+    free(cp);
+    hierarchy_free(G, L);
+    return 0;
+}
+
+/*
+ * Discrete energy of eq. E on the P1 space with the lumped mass:
+ *   parts[0] = eps/2 sum_i u_i.A u_i                       (interface)
+ *   parts[1] = 1/eps sum_i sum_p M_p u_pi (1 - u_pi)         (concave potential)
+ *   parts[2] = lambda sum_i sum_p M_p u_pi F_pi(c(u))        (fitting)
+ * with c(u) the colour means of u itself (c_prev for an empty phase).
+ * Returns the total.
+ */
+double orc_energy(const orc_params *P, const double *I, const double *u, const double *c_prev,
+                  double *parts)
+{
+    grid_t g;
+    if (grid_init(&g, P->W, P->H, P->h)) return NAN;
+    size_t n = (size_t)P->W * P->H;
+    double *c = malloc(sizeof(double) * P->N * P->C);
+    colour_means(&g, P->N, P->C, I, u, c_prev, c);
+    double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+    for (int i = 0; i < P->N; ++i)
+        for (int y = 0; y < P->H; ++y)
+            for (int x = 0; x < P->W; ++x) {
+                size_t p = (size_t)y * P->W + x;
+                double v = u[i * n + p];
+                e0 += 0.5 * P->eps * v * stiff_apply(&g, u + i * n, x, y);
+                e1 += g.mass[p] * v * (1.0 - v) / P->eps;
+                e2 += P->lambda * g.mass[p] * v * fitting(P->C, I, n, p, c + i * P->C);
+            }
+    if (parts) {
+        parts[0] = e0;
+        parts[1] = e1;
+        parts[2] = e2;
+    }
+    free(c);
+    grid_free(&g);
+    return e0 + e1 + e2;
+}
+
+/*
+ * Post-processing: label_p = the phase with the largest u_pi (lowest index on
+ * ties); composite_kp = sum_i c_ik u_pi; rounded composite_kp = c_{label_p,k}.
+ * composite / rounded may be NULL.
+ */
+void orc_labels(int N, int C, int H, int W, const double *u, const double *c, uint8_t *labels,
+                double *composite, double *rounded)
+{
+    size_t n = (size_t)W * H;
+    for (size_t p = 0; p < n; ++p) {
+        int best = 0;
+        for (int i = 1; i < N; ++i)
+            if (u[i * n + p] > u[best * n + p]) best = i;
+        labels[p] = (uint8_t)best;
+        for (int k = 0; k < C; ++k) {
+            if (composite) {
+                double s = 0.0;
+                for (int i = 0; i < N; ++i) s += c[i * C + k] * u[i * n + p];
+                composite[k * n + p] = s;
+            }
+            if (rounded) rounded[k * n + p] = c[best * C + k];
+        }
+    }
+}
