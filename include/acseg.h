@@ -1,0 +1,200 @@
+/*
+ * acseg.h -- C ABI of the MI355X (gfx950) solver for the vector-valued
+ * Allen-Cahn phase-field colour segmentation of Kay & Tomasi
+ * ("Colour Image Segmentation by the Vector-valued Allen-Cahn Phase-field
+ * Model: a Multigrid Solution").
+ *
+ * The model (Section "A modified vector-valued Allen-Cahn equation"): an image
+ * I with C channels on a W x H pixel lattice is segmented by N phase fields
+ * u_1..u_N that stay on the Gibbs simplex (sum_i u_i = 1, u_i >= 0) at every
+ * node, evolving by the gradient flow of the energy of eq. E with the colour
+ * fitting term of eq. VV_fidelity.  Discretisation (Section "Discretisation
+ * and Numerical Solution"): P1 finite elements with one node per pixel, every
+ * lattice cell split along its (x,y)-(x+1,y+1) diagonal, lumped mass, natural
+ * boundary conditions; backward Euler with the diffusion and the simplex
+ * constraint implicit and the concave term -(2/eps) u and the fitting term
+ * at the old time level (eq. alpha, read with the stiffness entering with a
+ * positive sign and the time step multiplying the whole bracket).  Each time
+ * step is a strictly convex quadratic program over a product of simplices,
+ * solved by red-black projected block Gauss-Seidel (the per-node simplex
+ * correction of Section "Gibbs Space Constraint Pseudocode") with truncated
+ * multigrid corrections (Section "Multigrid Solution") until the natural
+ * residual max_{p,i} |Pi(y_p(u)) - u_p,i| is at most `tol`.
+ *
+ * Conventions for every entry point
+ *   - All array arguments are DEVICE pointers on the context's device,
+ *     contiguous, 4-byte aligned, owned by the caller; the library never
+ *     allocates, frees or retains them.  Results are undefined if input and
+ *     output arrays overlap unless stated otherwise.
+ *   - Layout is structure-of-arrays, row major: an image is float[C][H][W], a
+ *     phase field float[N][H][W]; node (x, y) has flat index y*W + x.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All work is
+ *     enqueued on it and the call returns without waiting, except where an
+ *     `acseg_stats*` output is non-NULL: then the call waits for the stream
+ *     and fills it.
+ *   - Return value: ACSEG_OK (0) or a negative error code.  Argument errors
+ *     are detected on the host before anything is enqueued and leave the
+ *     outputs untouched.  Conditions found on the device (not converged,
+ *     empty phase, non-finite image values) are reported through
+ *     acseg_stats.status, which may carry a positive warning code.
+ *   - The workspace `ws` is caller-allocated device memory of at least
+ *     acseg_workspace_size() bytes, 256-byte aligned; it must not be used by
+ *     two calls that can run concurrently.
+ */
+#ifndef ACSEG_H
+#define ACSEG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t acseg_status;
+
+#define ACSEG_OK 0
+#define ACSEG_ERR_INVALID_ARG (-1)  /* bad sizes or parameters, NULL where not allowed */
+#define ACSEG_ERR_NONFINITE (-2)    /* the image holds NaN or Inf (device-detected) */
+#define ACSEG_ERR_WORKSPACE (-3)    /* ws is NULL, misaligned or smaller than required */
+#define ACSEG_ERR_HIP (-4)          /* a HIP runtime call failed */
+#define ACSEG_ERR_UNSUPPORTED (-5)  /* N or C outside the compiled range */
+#define ACSEG_WARN_NOT_CONVERGED 1  /* some step hit max_cycles with residual > tol */
+#define ACSEG_WARN_EMPTY_PHASE 2    /* some phase had no mass; its colour mean was kept */
+
+/* Compiled ranges */
+#define ACSEG_MIN_N 2
+#define ACSEG_MAX_N 8
+#define ACSEG_MAX_C 4
+
+/* acseg_problem.flags */
+#define ACSEG_FLAG_STORE_CHECKPOINTS 1u  /* acseg_solve writes u^0..u^steps */
+
+/*
+ * One segmentation problem.  Parameters follow eq. E and eq. alpha:
+ *   h       lattice spacing (node (x,y) sits at (x h, y h)); > 0
+ *   eps     interface parameter epsilon; > 0
+ *   lambda  fitting weight; >= 0
+ *   tau     time step (delta t of eq. alpha); > 0
+ *   steps   number of time steps for acseg_solve; >= 0
+ *   levels  lattice levels of the multigrid hierarchy including the finest:
+ *           1 = Gauss-Seidel only; 0 = automatic (halve the sides, rounding
+ *           up, while the longer side exceeds 15 and the shorter is >= 3)
+ *   nu_pre, nu_post  smoothing sweeps before / after the coarse correction
+ *           (multigrid) -- with levels == 1, nu_pre + nu_post red-black
+ *           sweeps form one cycle; each >= 0, sum >= 1
+ *   max_cycles  cycle budget per time step; >= 1
+ *   tol     natural-residual tolerance (max norm, absolute); >= 0
+ */
+typedef struct acseg_problem {
+    int32_t H, W, C, N;
+    double h, eps, lambda, tau;
+    int32_t steps;
+    int32_t levels;
+    int32_t nu_pre, nu_post;
+    int32_t max_cycles;
+    uint32_t flags;
+    double tol;
+} acseg_problem;
+
+/* Filled (after waiting for the stream) when a non-NULL pointer is passed. */
+typedef struct acseg_stats {
+    int32_t status;              /* ACSEG_OK, a warning (>0) or ACSEG_ERR_NONFINITE */
+    int32_t steps_done;
+    int32_t cycles_total;        /* over all steps */
+    int32_t cycles_max;          /* largest count in one step */
+    int32_t steps_not_converged;
+    int32_t empty_phase_steps;
+    double final_residual;       /* natural residual after the last step */
+    double max_residual;         /* largest end-of-step residual */
+} acseg_stats;
+
+typedef struct acseg_ctx acseg_ctx;
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t acseg_version(void);
+
+/* Human-readable text for a status code (static storage). */
+const char *acseg_status_string(acseg_status s);
+
+/*
+ * Create a context bound to HIP device `device` (it becomes current for the
+ * calling thread).  The context holds device properties and small pinned
+ * host buffers for statistics; it holds no problem data.  One context per
+ * host thread.  *out is set to NULL on failure.
+ */
+acseg_status acseg_create(int device, acseg_ctx **out);
+
+/* Destroy a context created by acseg_create (NULL is allowed). */
+acseg_status acseg_destroy(acseg_ctx *ctx);
+
+/* Workspace bytes needed by acseg_step / acseg_solve / acseg_energy for p. */
+acseg_status acseg_workspace_size(const acseg_problem *p, size_t *bytes);
+
+/*
+ * Euclidean projection onto the Gibbs simplex of `count` vectors of length N
+ * (Section "Gibbs Space Constraint Pseudocode"): y and x are float[N][count]
+ * (component-major).  x may equal y.  2 <= N <= ACSEG_MAX_N.
+ */
+acseg_status acseg_project_simplex(acseg_ctx *ctx, int32_t N, int64_t count, const float *y,
+                                   float *x, void *stream);
+
+/*
+ * Colour means of eq. VV_fidelity with the lumped mass (one node per pixel):
+ *   c_ik = sum_p M_p u_pi I_pk / sum_p M_p u_pi,   c: float[N][C].
+ * A phase whose mass is below 1e-12 of the domain area keeps c_prev[i] (if
+ * c_prev is non-NULL) or gets the mean image colour; this is reported as
+ * ACSEG_WARN_EMPTY_PHASE.  Uses the workspace.
+ */
+acseg_status acseg_colour_means(acseg_ctx *ctx, const acseg_problem *p, const float *image,
+                                const float *u, const float *c_prev, float *c_out,
+                                acseg_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * One time step (eq. alpha): c = colour means of u_in (c_prev for empty
+ * phases, may be NULL), then u_out = the minimiser over the simplices of
+ *   sum_i [ u_i.(M/tau + eps A) u_i / 2 - b_i.u_i ],
+ *   b_pi = M_p [ (1/tau + 2/eps) u_in_pi - lambda F_pi(c) ],
+ * starting from u_in, to residual <= tol or max_cycles cycles.  c_out
+ * (float[N][C], may be NULL) receives the means used.  u_in and u_out must
+ * not overlap.
+ */
+acseg_status acseg_step(acseg_ctx *ctx, const acseg_problem *p, const float *image,
+                        const float *u_in, float *u_out, const float *c_prev, float *c_out,
+                        acseg_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * p->steps time steps.  u: float[N][H][W], holds u^0 on entry and u^steps on
+ * return.  c_out (float[N][C], may be NULL) receives the colour means of the
+ * returned u.  With ACSEG_FLAG_STORE_CHECKPOINTS, checkpoints (float[steps+1]
+ * [N][H][W]) receives u^0..u^steps; otherwise it may be NULL.
+ */
+acseg_status acseg_solve(acseg_ctx *ctx, const acseg_problem *p, const float *image, float *u,
+                         float *c_out, float *checkpoints, acseg_stats *stats, void *ws,
+                         size_t ws_bytes, void *stream);
+
+/*
+ * Post-processing of Section "Post-processing": labels[p] = argmax_i u_pi
+ * (lowest index on ties), composite_kp = sum_i c_ik u_pi, rounded composite
+ * rounded_kp = c_{labels[p],k}.  labels: uint8[H][W]; composite, rounded:
+ * float[C][H][W]; each output may be NULL.  c: float[N][C].
+ */
+acseg_status acseg_labels(acseg_ctx *ctx, const acseg_problem *p, const float *u, const float *c,
+                          uint8_t *labels, float *composite, float *rounded, void *stream);
+
+/*
+ * Discrete energy of eq. E on the P1 space with the lumped mass, with c the
+ * colour means of u itself: energy[0] = eps/2 sum_i u_i.A u_i (interface),
+ * energy[1] = 1/eps sum_{p,i} M_p u_pi (1 - u_pi) (concave potential),
+ * energy[2] = lambda sum_{p,i} M_p u_pi F_pi (fitting), energy[3] = total.
+ * energy: device double[4].  Uses the workspace.
+ */
+acseg_status acseg_energy(acseg_ctx *ctx, const acseg_problem *p, const float *image,
+                          const float *u, double *energy, void *ws, size_t ws_bytes,
+                          void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACSEG_H */

@@ -1,0 +1,278 @@
+"""Python binding of the gfx950 segmentation library (``include/acseg.h``).
+
+Argument marshalling only: every step of the solve runs in the HIP kernels of
+``libacseg.so``; torch provides device memory and the current stream.  There
+is no CPU fallback -- if the library is missing or no GPU is present the calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, asdict, replace
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libacseg.so")
+
+OK = 0
+ERR_INVALID_ARG = -1
+ERR_NONFINITE = -2
+ERR_WORKSPACE = -3
+ERR_HIP = -4
+ERR_UNSUPPORTED = -5
+WARN_NOT_CONVERGED = 1
+WARN_EMPTY_PHASE = 2
+FLAG_STORE_CHECKPOINTS = 1
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("C", ctypes.c_int32),
+                ("N", ctypes.c_int32), ("h", ctypes.c_double), ("eps", ctypes.c_double),
+                ("lam", ctypes.c_double), ("tau", ctypes.c_double), ("steps", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("nu_pre", ctypes.c_int32),
+                ("nu_post", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("tol", ctypes.c_double)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("steps_done", ctypes.c_int32),
+                ("cycles_total", ctypes.c_int32), ("cycles_max", ctypes.c_int32),
+                ("steps_not_converged", ctypes.c_int32), ("empty_phase_steps", ctypes.c_int32),
+                ("final_residual", ctypes.c_double), ("max_residual", ctypes.c_double)]
+
+
+@dataclass
+class Problem:
+    """Mirror of ``acseg_problem`` (see include/acseg.h for the meaning of each field)."""
+    H: int
+    W: int
+    C: int
+    N: int
+    h: float
+    eps: float
+    lam: float
+    tau: float
+    steps: int = 0
+    levels: int = 0
+    nu_pre: int = 1
+    nu_post: int = 1
+    max_cycles: int = 50
+    flags: int = 0
+    tol: float = 1e-6
+
+    def c(self) -> _Problem:
+        d = asdict(self)
+        return _Problem(*(d[k] for k, _ in _Problem._fields_))
+
+    @classmethod
+    def from_workload(cls, w, C: int = 3, **kw) -> "Problem":
+        p = cls(H=w.H, W=w.W, C=C, N=w.N, h=w.h, eps=w.eps, lam=w.lam, tau=w.tau, steps=w.steps,
+                levels=w.levels, tol=w.tol)
+        return replace(p, **kw)
+
+
+class AcsegError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {status_string(code)} ({code})")
+        self.code = code
+
+
+_lib = None
+_ctx = {}
+_ws_cache = {}
+
+
+def lib():
+    """Load libacseg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_0710_0736_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        pp, sp = ctypes.POINTER(_Problem), ctypes.POINTER(_Stats)
+        L.acseg_version.restype = ctypes.c_int32
+        L.acseg_status_string.argtypes = [ctypes.c_int32]
+        L.acseg_status_string.restype = ctypes.c_char_p
+        L.acseg_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+        L.acseg_destroy.argtypes = [vp]
+        L.acseg_workspace_size.argtypes = [pp, ctypes.POINTER(sz)]
+        L.acseg_project_simplex.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp]
+        L.acseg_colour_means.argtypes = [vp, pp, vp, vp, vp, vp, sp, vp, sz, vp]
+        L.acseg_step.argtypes = [vp, pp, vp, vp, vp, vp, vp, sp, vp, sz, vp]
+        L.acseg_solve.argtypes = [vp, pp, vp, vp, vp, vp, sp, vp, sz, vp]
+        L.acseg_labels.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp]
+        L.acseg_energy.argtypes = [vp, pp, vp, vp, vp, vp, sz, vp]
+        _lib = L
+    return _lib
+
+
+def status_string(code: int) -> str:
+    try:
+        return lib().acseg_status_string(code).decode()
+    except Exception:
+        return "status"
+
+
+def _check(code: int, what: str):
+    if code < 0:
+        raise AcsegError(code, what)
+    return code
+
+
+def ctx(device: Optional[int] = None):
+    if device is None:
+        device = torch.cuda.current_device()
+    if device not in _ctx:
+        h = ctypes.c_void_p()
+        _check(lib().acseg_create(device, ctypes.byref(h)), "acseg_create")
+        _ctx[device] = h
+    return _ctx[device]
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor, shape, dtype=torch.float32, name="tensor"):
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: need a contiguous {dtype} CUDA tensor of shape {tuple(shape)}, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+
+
+def workspace_size(p: Problem) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().acseg_workspace_size(ctypes.byref(p.c()), ctypes.byref(n)), "workspace_size")
+    return n.value
+
+
+def workspace(p: Problem, device=None) -> torch.Tensor:
+    """A cached device workspace large enough for ``p`` (torch is the allocator)."""
+    n = workspace_size(p)
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    ws = _ws_cache.get(dev)
+    if ws is None or ws.numel() < n:
+        ws = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
+        _ws_cache[dev] = ws
+    return ws
+
+
+def _stats_dict(s: _Stats) -> dict:
+    return {k: getattr(s, k) for k, _ in _Stats._fields_}
+
+
+# ---------------------------------------------------------------------------
+
+def project_simplex(y: torch.Tensor) -> torch.Tensor:
+    """Simplex projection of the columns of ``y`` ([N][count], float32, CUDA)."""
+    N, count = y.shape
+    _need(y, (N, count), name="y")
+    x = torch.empty_like(y)
+    _check(lib().acseg_project_simplex(ctx(y.device.index), N, count, _ptr(y), _ptr(x), _stream()),
+           "acseg_project_simplex")
+    return x
+
+
+def colour_means(p: Problem, image: torch.Tensor, u: torch.Tensor, c_prev=None):
+    _need(image, (p.C, p.H, p.W), name="image")
+    _need(u, (p.N, p.H, p.W), name="u")
+    c = torch.empty((p.N, p.C), dtype=torch.float32, device=u.device)
+    if c_prev is not None:
+        _need(c_prev, (p.N, p.C), name="c_prev")
+    ws = workspace(p, u.device.index)
+    st = _Stats()
+    _check(lib().acseg_colour_means(ctx(u.device.index), ctypes.byref(p.c()), _ptr(image), _ptr(u),
+                                    _ptr(c_prev), _ptr(c), ctypes.byref(st), _ptr(ws), ws.numel(),
+                                    _stream()), "acseg_colour_means")
+    return c, _stats_dict(st)
+
+
+def step(p: Problem, image: torch.Tensor, u_in: torch.Tensor, c_prev=None, want_stats=True):
+    """One time step from ``u_in``; returns (u_out, c_used, stats)."""
+    _need(image, (p.C, p.H, p.W), name="image")
+    _need(u_in, (p.N, p.H, p.W), name="u_in")
+    if c_prev is not None:
+        _need(c_prev, (p.N, p.C), name="c_prev")
+    u_out = torch.empty_like(u_in)
+    c = torch.empty((p.N, p.C), dtype=torch.float32, device=u_in.device)
+    ws = workspace(p, u_in.device.index)
+    st = _Stats()
+    _check(lib().acseg_step(ctx(u_in.device.index), ctypes.byref(p.c()), _ptr(image), _ptr(u_in),
+                            _ptr(u_out), _ptr(c_prev), _ptr(c),
+                            ctypes.byref(st) if want_stats else None, _ptr(ws), ws.numel(),
+                            _stream()), "acseg_step")
+    return u_out, c, (_stats_dict(st) if want_stats else None)
+
+
+def solve(p: Problem, image: torch.Tensor, u: torch.Tensor, checkpoints: bool = False,
+          want_stats: bool = True, c_out: bool = True):
+    """``p.steps`` time steps; ``u`` (u^0) is overwritten with u^steps.
+
+    Returns (u, c [N][C] of the result or None, stats or None, checkpoints or None).
+    """
+    _need(image, (p.C, p.H, p.W), name="image")
+    _need(u, (p.N, p.H, p.W), name="u")
+    ck = None
+    if checkpoints:
+        p = replace(p, flags=p.flags | FLAG_STORE_CHECKPOINTS)
+        ck = torch.empty((p.steps + 1, p.N, p.H, p.W), dtype=torch.float32, device=u.device)
+    c = torch.empty((p.N, p.C), dtype=torch.float32, device=u.device) if c_out else None
+    ws = workspace(p, u.device.index)
+    st = _Stats()
+    _check(lib().acseg_solve(ctx(u.device.index), ctypes.byref(p.c()), _ptr(image), _ptr(u),
+                             _ptr(c), _ptr(ck), ctypes.byref(st) if want_stats else None,
+                             _ptr(ws), ws.numel(), _stream()), "acseg_solve")
+    return u, c, (_stats_dict(st) if want_stats else None), ck
+
+
+def labels(p: Problem, u: torch.Tensor, c: torch.Tensor):
+    """Returns (labels uint8 [H][W], composite [C][H][W], rounded composite [C][H][W])."""
+    _need(u, (p.N, p.H, p.W), name="u")
+    _need(c, (p.N, p.C), name="c")
+    lab = torch.empty((p.H, p.W), dtype=torch.uint8, device=u.device)
+    comp = torch.empty((p.C, p.H, p.W), dtype=torch.float32, device=u.device)
+    rnd = torch.empty_like(comp)
+    _check(lib().acseg_labels(ctx(u.device.index), ctypes.byref(p.c()), _ptr(u), _ptr(c), _ptr(lab),
+                              _ptr(comp), _ptr(rnd), _stream()), "acseg_labels")
+    return lab, comp, rnd
+
+
+def energy(p: Problem, image: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
+    """float64[4]: interface, concave, fitting, total (eq. E)."""
+    _need(image, (p.C, p.H, p.W), name="image")
+    _need(u, (p.N, p.H, p.W), name="u")
+    e = torch.empty(4, dtype=torch.float64, device=u.device)
+    ws = workspace(p, u.device.index)
+    _check(lib().acseg_energy(ctx(u.device.index), ctypes.byref(p.c()), _ptr(image), _ptr(u),
+                              _ptr(e), _ptr(ws), ws.numel(), _stream()), "acseg_energy")
+    return e
+
+
+def segment(image: torch.Tensor, N: int, *, lam: float, steps: int, h: Optional[float] = None,
+            eps: Optional[float] = None, tau: Optional[float] = None, levels: int = 0,
+            tol: float = 1e-6, u0: Optional[torch.Tensor] = None, seed: int = 0, **kw):
+    """Segment a [C][H][W] float32 CUDA image into N phases.
+
+    Defaults follow the unit-square scale: h = 1/(max(W, H) - 1), eps = 2h,
+    tau = eps^2.  Returns (u, c, labels, stats).
+    """
+    C, H, W = image.shape
+    h = 1.0 / (max(W, H) - 1) if h is None else h
+    eps = 2.0 * h if eps is None else eps
+    tau = eps * eps if tau is None else tau
+    p = Problem(H=H, W=W, C=C, N=N, h=h, eps=eps, lam=lam, tau=tau, steps=steps, levels=levels,
+                tol=tol, **kw)
+    if u0 is None:
+        from .synth import random_simplex_field
+        u0 = torch.from_numpy(random_simplex_field(N, H, W, seed)).to(image.device)
+    u = u0.clone().contiguous()
+    u, c, st, _ = solve(p, image.contiguous(), u)
+    lab, _, _ = labels(p, u, c)
+    return u, c, lab, st

@@ -1,0 +1,340 @@
+// acseg_api.hip -- host runtime behind the C ABI declared in include/acseg.h.
+//
+// Validates problems, derives the float64 per-class constants of the nodal
+// system, carves the caller's workspace, and enqueues the kernels of the time
+// loop on the caller's stream.  Convergence is decided on the device: every
+// cycle kernel reads the control block's `done` flag and exits at once after
+// the step has converged, so the host never needs to read the residual.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "acseg.h"
+#include "acseg_internal.h"
+
+using namespace acseg;
+
+struct acseg_ctx {
+    int device = 0;
+    int cu_count = 0;
+    Ctl* host_ctl = nullptr;  // pinned, for statistics read-back
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxReduceBlocks = 1024;
+constexpr int kCmeansMaxM = ACSEG_MAX_N * ACSEG_MAX_C + ACSEG_MAX_N + ACSEG_MAX_C + 2;
+constexpr int kMaxLevels = 24;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int coarse_side(int n) { return (n + 1) / 2; }
+
+int auto_levels(int W, int H) {
+    int L = 1;
+    while (std::max(W, H) > 15 && std::min(W, H) >= 3) {
+        W = coarse_side(W);
+        H = coarse_side(H);
+        ++L;
+    }
+    return L;
+}
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+acseg_status validate(const acseg_problem* p, bool need_steps) {
+    if (!p) return ACSEG_ERR_INVALID_ARG;
+    if (p->W < 2 || p->H < 2 || p->C < 1 || p->N < 1) return ACSEG_ERR_INVALID_ARG;
+    if ((int64_t)p->W * p->H > ((int64_t)1 << 31)) return ACSEG_ERR_INVALID_ARG;
+    if (p->N < ACSEG_MIN_N || p->N > ACSEG_MAX_N || p->C > ACSEG_MAX_C) return ACSEG_ERR_UNSUPPORTED;
+    if (!finite_pos(p->h) || !finite_pos(p->eps) || !finite_pos(p->tau)) return ACSEG_ERR_INVALID_ARG;
+    if (!isfinite(p->lambda) || p->lambda < 0.0) return ACSEG_ERR_INVALID_ARG;
+    if (!isfinite(p->tol) || p->tol < 0.0) return ACSEG_ERR_INVALID_ARG;
+    if (need_steps && p->steps < 0) return ACSEG_ERR_INVALID_ARG;
+    if (p->nu_pre < 0 || p->nu_post < 0 || p->nu_pre + p->nu_post < 1) return ACSEG_ERR_INVALID_ARG;
+    if (p->max_cycles < 1 || p->levels < 0) return ACSEG_ERR_INVALID_ARG;
+    if (p->levels > auto_levels(p->W, p->H)) return ACSEG_ERR_INVALID_ARG;
+    if (p->levels != 0 && p->levels != 1) return ACSEG_ERR_UNSUPPORTED;
+    if ((p->flags & ~ACSEG_FLAG_STORE_CHECKPOINTS) != 0u) return ACSEG_ERR_INVALID_ARG;
+    return ACSEG_OK;
+}
+
+int levels_of(const acseg_problem* p) { return p->levels == 0 ? 1 : p->levels; }
+
+// Workspace carve-up (offsets in bytes from ws).
+struct Layout {
+    size_t ubuf = 0, rhs = 0, part_f = 0, part_d = 0, c64 = 0, ctl = 0, total = 0;
+};
+
+Layout layout_of(const acseg_problem* p) {
+    Layout L;
+    const size_t n = (size_t)p->W * p->H;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L.ubuf = take(sizeof(float) * p->N * n);
+    L.rhs = take(sizeof(float) * p->N * n);
+    L.part_f = take(sizeof(float) * (size_t)smooth_max_tiles(p->W, p->H));
+    L.part_d = take(sizeof(double) * (size_t)kMaxReduceBlocks * kCmeansMaxM);
+    L.c64 = take(sizeof(double) * 2 * ACSEG_MAX_N * ACSEG_MAX_C);
+    L.ctl = take(sizeof(Ctl));
+    L.total = off;
+    return L;
+}
+
+// Float64 constants of the fine-level nodal system, rounded once for the kernels.
+struct Coefs {
+    LevelCoef fine;
+    RhsCoef rhs;
+};
+
+Coefs coefs_of(const acseg_problem* p) {
+    static const double w[4] = {1.0, 0.5, 1.0 / 3.0, 1.0 / 6.0};  // lumped mass / h^2
+    static const double a[4] = {4.0, 2.0, 1.0, 1.0};              // stiffness diagonal
+    Coefs c;
+    memset(&c, 0, sizeof(c));
+    const double e2 = p->eps / (p->h * p->h);
+    for (int k = 0; k < 4; ++k) {
+        const double D = w[k] / p->tau + e2 * a[k];
+        c.fine.kappa[k] = (float)(e2 / D);
+        c.fine.inv_d[k] = (float)(1.0 / D);
+        c.fine.d[k] = (float)D;
+        c.rhs.wd[k] = w[k] / D;
+    }
+    c.fine.e2 = (float)e2;
+    c.rhs.a = 1.0 / p->tau + 2.0 / p->eps;
+    c.rhs.lambda = p->lambda;
+    return c;
+}
+
+acseg_status hip_status(hipError_t e) { return e == hipSuccess ? ACSEG_OK : ACSEG_ERR_HIP; }
+
+#define ACSEG_TRY(expr)                                   \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return ACSEG_ERR_HIP;       \
+    } while (0)
+
+acseg_status check_ws(const acseg_problem* p, void* ws, size_t ws_bytes, Layout* L) {
+    *L = layout_of(p);
+    if (!ws || ((uintptr_t)ws % kAlign) != 0 || ws_bytes < L->total) return ACSEG_ERR_WORKSPACE;
+    return ACSEG_OK;
+}
+
+template <class T>
+T* at(void* ws, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// Enqueue one time step on the current iterate bufs[ctl->cur]: colour means
+// (c64_cur from c64_prev), right-hand side, and max_cycles smoothing cycles
+// that exit at once after convergence, then the step statistics.
+acseg_status enqueue_step(const acseg_problem* p, const Coefs& cf, const float* image, Bufs bufs,
+                          const Layout& L, void* ws, const double* c64_prev, double* c64_cur,
+                          float* c_out, hipStream_t s) {
+    Ctl* ctl = at<Ctl>(ws, L.ctl);
+    float* rhs = at<float>(ws, L.rhs);
+    ACSEG_TRY(launch_cmeans(p->N, p->C, p->W, p->H, image, nullptr, bufs, ctl, c64_prev, c64_cur,
+                            c_out, at<double>(ws, L.part_d), kMaxReduceBlocks, s));
+    ACSEG_TRY(launch_rhs(p->N, p->C, p->W, p->H, image, bufs, ctl, c64_cur, cf.rhs, rhs, s));
+    const int sweeps = p->nu_pre + p->nu_post;
+    for (int c = 0; c < p->max_cycles; ++c)
+        ACSEG_TRY(launch_smooth(p->N, p->W, p->H, sweeps, true, bufs, ctl, rhs, cf.fine,
+                                (float)p->tol, p->max_cycles, at<float>(ws, L.part_f), s));
+    ACSEG_TRY(launch_step_end(ctl, (float)p->tol, s));
+    return ACSEG_OK;
+}
+
+acseg_status read_stats(acseg_ctx* ctx, const Layout& L, void* ws, hipStream_t s,
+                        acseg_stats* st) {
+    if (!st) return ACSEG_OK;
+    ACSEG_TRY(hipMemcpyAsync(ctx->host_ctl, at<Ctl>(ws, L.ctl), sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    ACSEG_TRY(hipStreamSynchronize(s));
+    const Ctl& c = *ctx->host_ctl;
+    memset(st, 0, sizeof(*st));
+    st->steps_done = c.steps_done;
+    st->cycles_total = c.cycles_total;
+    st->cycles_max = c.cycles_max;
+    st->steps_not_converged = c.steps_unconv;
+    st->empty_phase_steps = c.empty_steps;
+    st->final_residual = c.resid;
+    st->max_residual = c.max_resid;
+    if (c.nonfinite)
+        st->status = ACSEG_ERR_NONFINITE;
+    else if (c.steps_unconv)
+        st->status = ACSEG_WARN_NOT_CONVERGED;
+    else if (c.empty_steps || c.empty_now)
+        st->status = ACSEG_WARN_EMPTY_PHASE;
+    return ACSEG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t acseg_version(void) { return 100; }
+
+const char* acseg_status_string(acseg_status s) {
+    switch (s) {
+        case ACSEG_OK: return "ok";
+        case ACSEG_ERR_INVALID_ARG: return "invalid argument";
+        case ACSEG_ERR_NONFINITE: return "image holds non-finite values";
+        case ACSEG_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+        case ACSEG_ERR_HIP: return "HIP runtime error";
+        case ACSEG_ERR_UNSUPPORTED: return "unsupported size or option";
+        case ACSEG_WARN_NOT_CONVERGED: return "a step did not reach the tolerance";
+        case ACSEG_WARN_EMPTY_PHASE: return "a phase had no mass";
+        default: return "unknown status";
+    }
+}
+
+acseg_status acseg_create(int device, acseg_ctx** out) {
+    if (!out) return ACSEG_ERR_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return ACSEG_ERR_INVALID_ARG;
+    if (hipSetDevice(device) != hipSuccess) return ACSEG_ERR_HIP;
+    acseg_ctx* c = new acseg_ctx();
+    c->device = device;
+    if (hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        hipHostMalloc((void**)&c->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return ACSEG_ERR_HIP;
+    }
+    *out = c;
+    return ACSEG_OK;
+}
+
+acseg_status acseg_destroy(acseg_ctx* ctx) {
+    if (!ctx) return ACSEG_OK;
+    if (ctx->host_ctl) (void)hipHostFree(ctx->host_ctl);
+    delete ctx;
+    return ACSEG_OK;
+}
+
+acseg_status acseg_workspace_size(const acseg_problem* p, size_t* bytes) {
+    if (!bytes) return ACSEG_ERR_INVALID_ARG;
+    const acseg_status v = validate(p, false);
+    if (v != ACSEG_OK) return v;
+    *bytes = layout_of(p).total;
+    return ACSEG_OK;
+}
+
+acseg_status acseg_project_simplex(acseg_ctx* ctx, int32_t N, int64_t count, const float* y,
+                                   float* x, void* stream) {
+    if (!ctx || count < 0 || (count > 0 && (!y || !x))) return ACSEG_ERR_INVALID_ARG;
+    if (N < ACSEG_MIN_N || N > ACSEG_MAX_N) return ACSEG_ERR_UNSUPPORTED;
+    return hip_status(launch_project(N, count, y, x, (hipStream_t)stream));
+}
+
+acseg_status acseg_colour_means(acseg_ctx* ctx, const acseg_problem* p, const float* image,
+                                const float* u, const float* c_prev, float* c_out,
+                                acseg_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+    acseg_status v = validate(p, false);
+    if (v != ACSEG_OK) return v;
+    if (!ctx || !image || !u || !c_out) return ACSEG_ERR_INVALID_ARG;
+    Layout L;
+    if ((v = check_ws(p, ws, ws_bytes, &L)) != ACSEG_OK) return v;
+    hipStream_t s = (hipStream_t)stream;
+    Ctl* ctl = at<Ctl>(ws, L.ctl);
+    double* c64 = at<double>(ws, L.c64);
+    double* cprev = c64 + ACSEG_MAX_N * ACSEG_MAX_C;
+    ACSEG_TRY(launch_ctl_init(ctl, 0, s));
+    if (c_prev) ACSEG_TRY(launch_widen(c_prev, cprev, p->N * p->C, s));
+    const Bufs bufs{{u, u, u}};
+    ACSEG_TRY(launch_cmeans(p->N, p->C, p->W, p->H, image, u, bufs, ctl, c_prev ? cprev : nullptr,
+                            c64, c_out, at<double>(ws, L.part_d), kMaxReduceBlocks, s));
+    return read_stats(ctx, L, ws, s, stats);
+}
+
+acseg_status acseg_step(acseg_ctx* ctx, const acseg_problem* p, const float* image,
+                        const float* u_in, float* u_out, const float* c_prev, float* c_out,
+                        acseg_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+    acseg_status v = validate(p, false);
+    if (v != ACSEG_OK) return v;
+    if (!ctx || !image || !u_in || !u_out || u_in == u_out) return ACSEG_ERR_INVALID_ARG;
+    Layout L;
+    if ((v = check_ws(p, ws, ws_bytes, &L)) != ACSEG_OK) return v;
+    hipStream_t s = (hipStream_t)stream;
+    const Coefs cf = coefs_of(p);
+    const int64_t nu = (int64_t)p->N * p->W * p->H;
+    Ctl* ctl = at<Ctl>(ws, L.ctl);
+    double* c64 = at<double>(ws, L.c64);
+    double* cprev = c64 + ACSEG_MAX_N * ACSEG_MAX_C;
+    const Bufs bufs{{u_out, at<float>(ws, L.ubuf), u_in}};
+    ACSEG_TRY(launch_ctl_init(ctl, 2, s));
+    if (c_prev) ACSEG_TRY(launch_widen(c_prev, cprev, p->N * p->C, s));
+    v = enqueue_step(p, cf, image, bufs, L, ws, c_prev ? cprev : nullptr, c64, c_out, s);
+    if (v != ACSEG_OK) return v;
+    ACSEG_TRY(launch_copy_current(bufs, ctl, u_out, nu, s));
+    return read_stats(ctx, L, ws, s, stats);
+}
+
+acseg_status acseg_solve(acseg_ctx* ctx, const acseg_problem* p, const float* image, float* u,
+                         float* c_out, float* checkpoints, acseg_stats* stats, void* ws,
+                         size_t ws_bytes, void* stream) {
+    acseg_status v = validate(p, true);
+    if (v != ACSEG_OK) return v;
+    const bool ckpt = (p->flags & ACSEG_FLAG_STORE_CHECKPOINTS) != 0u;
+    if (!ctx || !image || !u || (ckpt && !checkpoints)) return ACSEG_ERR_INVALID_ARG;
+    Layout L;
+    if ((v = check_ws(p, ws, ws_bytes, &L)) != ACSEG_OK) return v;
+    hipStream_t s = (hipStream_t)stream;
+    const Coefs cf = coefs_of(p);
+    const int64_t nu = (int64_t)p->N * p->W * p->H;
+    Ctl* ctl = at<Ctl>(ws, L.ctl);
+    double* cA = at<double>(ws, L.c64);
+    double* cB = cA + ACSEG_MAX_N * ACSEG_MAX_C;
+    const Bufs bufs{{u, at<float>(ws, L.ubuf), u}};
+    ACSEG_TRY(launch_ctl_init(ctl, 0, s));
+    if (ckpt) ACSEG_TRY(hipMemcpyAsync(checkpoints, u, sizeof(float) * nu, hipMemcpyDeviceToDevice, s));
+    for (int n = 0; n < p->steps; ++n) {
+        v = enqueue_step(p, cf, image, bufs, L, ws, n > 0 ? cB : nullptr, cA, nullptr, s);
+        if (v != ACSEG_OK) return v;
+        std::swap(cA, cB);  // cB now holds this step's means
+        if (ckpt) ACSEG_TRY(launch_copy_current(bufs, ctl, checkpoints + (n + 1) * nu, nu, s));
+    }
+    ACSEG_TRY(launch_copy_current(bufs, ctl, u, nu, s));
+    if (c_out)
+        ACSEG_TRY(launch_cmeans(p->N, p->C, p->W, p->H, image, u, bufs, ctl,
+                                p->steps > 0 ? cB : nullptr, cA, c_out, at<double>(ws, L.part_d),
+                                kMaxReduceBlocks, s));
+    return read_stats(ctx, L, ws, s, stats);
+}
+
+acseg_status acseg_labels(acseg_ctx* ctx, const acseg_problem* p, const float* u, const float* c,
+                          uint8_t* labels, float* composite, float* rounded, void* stream) {
+    const acseg_status v = validate(p, false);
+    if (v != ACSEG_OK) return v;
+    if (!ctx || !u || !c) return ACSEG_ERR_INVALID_ARG;
+    return hip_status(launch_labels(p->N, p->C, p->W, p->H, u, c, labels, composite, rounded,
+                                    (hipStream_t)stream));
+}
+
+acseg_status acseg_energy(acseg_ctx* ctx, const acseg_problem* p, const float* image,
+                          const float* u, double* energy, void* ws, size_t ws_bytes,
+                          void* stream) {
+    acseg_status v = validate(p, false);
+    if (v != ACSEG_OK) return v;
+    if (!ctx || !image || !u || !energy) return ACSEG_ERR_INVALID_ARG;
+    Layout L;
+    if ((v = check_ws(p, ws, ws_bytes, &L)) != ACSEG_OK) return v;
+    hipStream_t s = (hipStream_t)stream;
+    Ctl* ctl = at<Ctl>(ws, L.ctl);
+    double* c64 = at<double>(ws, L.c64);
+    const Bufs bufs{{u, u, u}};
+    ACSEG_TRY(launch_ctl_init(ctl, 0, s));
+    ACSEG_TRY(launch_cmeans(p->N, p->C, p->W, p->H, image, u, bufs, ctl, nullptr, c64, nullptr,
+                            at<double>(ws, L.part_d), kMaxReduceBlocks, s));
+    ACSEG_TRY(launch_energy(p->N, p->C, p->W, p->H, image, u, c64, p->eps, p->lambda, p->h,
+                            at<double>(ws, L.part_d), kMaxReduceBlocks, ctl, energy, s));
+    return ACSEG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+* the built library loads and exports every function declared in include/acseg.h;
+* host-side validation maps bad problems to the documented status codes
+  (acseg_workspace_size validates without touching the device);
+* the seeded workload generators are deterministic.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_0710_0736_amd import acseg, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "acseg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(acseg_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = acseg.lib()
+    names = declared_functions()
+    assert "acseg_solve" in names and "acseg_step" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert L.acseg_version() >= 100
+
+
+def base_problem(**kw):
+    p = acseg.Problem(H=64, W=48, C=3, N=4, h=1 / 63, eps=2 / 63, lam=100.0, tau=(2 / 63) ** 2,
+                      steps=5, levels=1)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("N", 1, acseg.ERR_UNSUPPORTED), ("N", 9, acseg.ERR_UNSUPPORTED), ("C", 5, acseg.ERR_UNSUPPORTED),
+    ("C", 0, acseg.ERR_INVALID_ARG), ("W", 1, acseg.ERR_INVALID_ARG), ("H", 0, acseg.ERR_INVALID_ARG),
+    ("h", 0.0, acseg.ERR_INVALID_ARG), ("eps", -1.0, acseg.ERR_INVALID_ARG),
+    ("tau", float("nan"), acseg.ERR_INVALID_ARG), ("lam", -0.5, acseg.ERR_INVALID_ARG),
+    ("tol", -1e-6, acseg.ERR_INVALID_ARG), ("max_cycles", 0, acseg.ERR_INVALID_ARG),
+    ("nu_pre", -1, acseg.ERR_INVALID_ARG), ("levels", 40, acseg.ERR_INVALID_ARG),
+    ("flags", 1 << 20, acseg.ERR_INVALID_ARG),
+])
+def test_validation_codes(field, value, code):
+    p = base_problem(**{field: value})
+    n = ctypes.c_size_t()
+    assert acseg.lib().acseg_workspace_size(ctypes.byref(p.c()), ctypes.byref(n)) == code
+
+
+def test_workspace_size_grows_with_problem():
+    a = acseg.workspace_size(base_problem())
+    b = acseg.workspace_size(base_problem(W=96, H=128))
+    assert 0 < a < b
+    assert acseg.workspace_size(base_problem(nu_pre=0, nu_post=1)) == a
+
+
+def test_status_strings():
+    L = acseg.lib()
+    for code in (0, -1, -2, -3, -4, -5, 1, 2):
+        assert L.acseg_status_string(code).decode() not in ("", "unknown status")
+
+
+def test_generators_are_deterministic():
+    a = synth.VORONOI1024.scaled(96).make(3)
+    b = synth.VORONOI1024.scaled(96).make(3)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    img, u0, lab = a
+    assert img.dtype == np.float32 and u0.dtype == np.float32
+    assert np.abs(u0.sum(0) - 1).max() < 1e-6 and u0.min() > 0
+    assert set(np.unique(lab)) <= set(range(4))
