@@ -69,6 +69,13 @@ typedef int32_t acseg_status;
 
 /* acseg_problem.flags */
 #define ACSEG_FLAG_STORE_CHECKPOINTS 1u  /* acseg_solve writes u^0..u^steps */
+/*
+ * Every time step runs exactly max_cycles cycles instead of stopping at the
+ * first cycle whose residual is <= tol.  The residual after the last cycle
+ * still decides whether the step counts as converged (stats).  Without this
+ * flag, cycles after convergence are enqueued but exit at once on the device.
+ */
+#define ACSEG_FLAG_FIXED_CYCLES 2u
 
 /*
  * One segmentation problem.  Parameters follow eq. E and eq. alpha:
@@ -192,6 +199,24 @@ acseg_status acseg_labels(acseg_ctx *ctx, const acseg_problem *p, const float *u
 acseg_status acseg_energy(acseg_ctx *ctx, const acseg_problem *p, const float *image,
                           const float *u, double *energy, void *ws, size_t ws_bytes,
                           void *stream);
+
+/*
+ * Kernel timing (profiling aid).  While enabled on a context, the calls
+ * acseg_step and acseg_solve bracket each kernel family they enqueue with HIP
+ * events on the call's stream; acseg_timing_read waits for those events, adds
+ * up the elapsed times per family into out[0..*count-1] (at most max entries)
+ * and forgets them.  Families: "cmeans", "rhs", "smooth" (one smoothing
+ * cycle, or one launch of it when a cycle needs several), "mg", "other".
+ */
+typedef struct acseg_kernel_time {
+    char name[16];
+    int64_t launches;
+    double total_ms;
+} acseg_kernel_time;
+
+acseg_status acseg_timing_enable(acseg_ctx *ctx, int32_t enable);
+acseg_status acseg_timing_read(acseg_ctx *ctx, acseg_kernel_time *out, int32_t max,
+                               int32_t *count);
 
 #ifdef __cplusplus
 }

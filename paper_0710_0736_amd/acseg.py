@@ -26,6 +26,7 @@ ERR_UNSUPPORTED = -5
 WARN_NOT_CONVERGED = 1
 WARN_EMPTY_PHASE = 2
 FLAG_STORE_CHECKPOINTS = 1
+FLAG_FIXED_CYCLES = 2
 
 
 class _Problem(ctypes.Structure):
@@ -42,6 +43,11 @@ class _Stats(ctypes.Structure):
                 ("cycles_total", ctypes.c_int32), ("cycles_max", ctypes.c_int32),
                 ("steps_not_converged", ctypes.c_int32), ("empty_phase_steps", ctypes.c_int32),
                 ("final_residual", ctypes.c_double), ("max_residual", ctypes.c_double)]
+
+
+class _KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 16), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
 
 
 @dataclass
@@ -106,6 +112,9 @@ def lib():
         L.acseg_solve.argtypes = [vp, pp, vp, vp, vp, vp, sp, vp, sz, vp]
         L.acseg_labels.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp]
         L.acseg_energy.argtypes = [vp, pp, vp, vp, vp, vp, sz, vp]
+        L.acseg_timing_enable.argtypes = [vp, ctypes.c_int32]
+        L.acseg_timing_read.argtypes = [vp, ctypes.POINTER(_KernelTime), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32)]
         _lib = L
     return _lib
 
@@ -253,6 +262,19 @@ def energy(p: Problem, image: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
     _check(lib().acseg_energy(ctx(u.device.index), ctypes.byref(p.c()), _ptr(image), _ptr(u),
                               _ptr(e), _ptr(ws), ws.numel(), _stream()), "acseg_energy")
     return e
+
+
+def timing_enable(enable: bool = True, device=None):
+    """Bracket the library's kernel launches with HIP events (profiling aid)."""
+    _check(lib().acseg_timing_enable(ctx(device), 1 if enable else 0), "acseg_timing_enable")
+
+
+def timing_read(device=None) -> dict:
+    """{family: (launches, total_ms)} for the launches recorded since the last read."""
+    buf = (_KernelTime * 16)()
+    n = ctypes.c_int32()
+    _check(lib().acseg_timing_read(ctx(device), buf, 16, ctypes.byref(n)), "acseg_timing_read")
+    return {buf[k].name.decode(): (buf[k].launches, buf[k].total_ms) for k in range(n.value)}
 
 
 def segment(image: torch.Tensor, N: int, *, lam: float, steps: int, h: Optional[float] = None,

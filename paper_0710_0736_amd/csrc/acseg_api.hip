@@ -9,24 +9,35 @@
 #include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "acseg.h"
 #include "acseg_internal.h"
 
 using namespace acseg;
 
+namespace {
+enum Family { kFamCmeans = 0, kFamRhs, kFamSmooth, kFamMg, kFamOther, kFamCount };
+const char* const kFamName[kFamCount] = {"cmeans", "rhs", "smooth", "mg", "other"};
+struct TimedRec {
+    int fam;
+    hipEvent_t a, b;
+};
+}  // namespace
+
 struct acseg_ctx {
     int device = 0;
     int cu_count = 0;
     Ctl* host_ctl = nullptr;  // pinned, for statistics read-back
+    bool timing = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<TimedRec> recs;
 };
 
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kMaxReduceBlocks = 1024;
 constexpr int kCmeansMaxM = ACSEG_MAX_N * ACSEG_MAX_C + ACSEG_MAX_N + ACSEG_MAX_C + 2;
-constexpr int kMaxLevels = 24;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -57,16 +68,19 @@ acseg_status validate(const acseg_problem* p, bool need_steps) {
     if (p->max_cycles < 1 || p->levels < 0) return ACSEG_ERR_INVALID_ARG;
     if (p->levels > auto_levels(p->W, p->H)) return ACSEG_ERR_INVALID_ARG;
     if (p->levels != 0 && p->levels != 1) return ACSEG_ERR_UNSUPPORTED;
-    if ((p->flags & ~ACSEG_FLAG_STORE_CHECKPOINTS) != 0u) return ACSEG_ERR_INVALID_ARG;
+    if ((p->flags & ~(ACSEG_FLAG_STORE_CHECKPOINTS | ACSEG_FLAG_FIXED_CYCLES)) != 0u)
+        return ACSEG_ERR_INVALID_ARG;
     return ACSEG_OK;
 }
 
-int levels_of(const acseg_problem* p) { return p->levels == 0 ? 1 : p->levels; }
-
 // Workspace carve-up (offsets in bytes from ws).
 struct Layout {
-    size_t ubuf = 0, rhs = 0, part_f = 0, part_d = 0, c64 = 0, ctl = 0, total = 0;
+    size_t ubuf = 0, rhs = 0, part_f = 0, part_cm = 0, part_d = 0, c64 = 0, tot = 0, ctl = 0;
+    size_t total = 0;
+    int part_stride = 0;
 };
+
+constexpr int kNC = ACSEG_MAX_N * ACSEG_MAX_C;  // stride of one set of means in c64
 
 Layout layout_of(const acseg_problem* p) {
     Layout L;
@@ -79,9 +93,12 @@ Layout layout_of(const acseg_problem* p) {
     };
     L.ubuf = take(sizeof(float) * p->N * n);
     L.rhs = take(sizeof(float) * p->N * n);
-    L.part_f = take(sizeof(float) * (size_t)smooth_max_tiles(p->W, p->H));
-    L.part_d = take(sizeof(double) * (size_t)kMaxReduceBlocks * kCmeansMaxM);
-    L.c64 = take(sizeof(double) * 2 * ACSEG_MAX_N * ACSEG_MAX_C);
+    L.part_stride = cycle_tiles(p->N, p->W, p->H);
+    L.part_f = take(sizeof(float) * 2 * (size_t)L.part_stride);
+    L.part_cm = take(sizeof(double) * 2 * (size_t)L.part_stride * cmeans_width(p->N, p->C));
+    L.part_d = take(sizeof(double) * (size_t)kCmeansBlocks * kCmeansMaxM);
+    L.c64 = take(sizeof(double) * 3 * kNC);          // two alternating sets + a caller's c_prev
+    L.tot = take(sizeof(double) * 2 * kCmeansMaxM);  // reduced colour-mean sums, alternating
     L.ctl = take(sizeof(Ctl));
     L.total = off;
     return L;
@@ -131,22 +148,87 @@ T* at(void* ws, size_t off) {
     return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
-// Enqueue one time step on the current iterate bufs[ctl->cur]: colour means
-// (c64_cur from c64_prev), right-hand side, and max_cycles smoothing cycles
-// that exit at once after convergence, then the step statistics.
-acseg_status enqueue_step(const acseg_problem* p, const Coefs& cf, const float* image, Bufs bufs,
-                          const Layout& L, void* ws, const double* c64_prev, double* c64_cur,
-                          float* c_out, hipStream_t s) {
+hipEvent_t take_event(acseg_ctx* ctx) {
+    if (!ctx->pool.empty()) {
+        hipEvent_t e = ctx->pool.back();
+        ctx->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Run one launcher, bracketed by timing events when timing is enabled.
+template <class F>
+hipError_t timed(acseg_ctx* ctx, int fam, hipStream_t s, F&& launch) {
+    if (!ctx->timing) return launch();
+    hipEvent_t a = take_event(ctx), b = take_event(ctx);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, s);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    ctx->recs.push_back({fam, a, b});
+    return e;
+}
+
+// Enqueue time step n on the iterate bufs[ctl->cur] whose reduced colour-mean
+// sums are in `tot`: max_cycles smoothing cycles (after convergence they exit
+// at once unless the schedule is fixed), then the step's end, which leaves the
+// sums of the new iterate in tot_next.  The step's first launch writes the
+// means it uses to c64 (and c_out when non-NULL).
+acseg_status enqueue_step(acseg_ctx* ctx, const acseg_problem* p, const Coefs& cf,
+                          const float* image, Bufs bufs, const Layout& L, void* ws, int n,
+                          const double* tot, const double* c_prev64, double* c64, float* c_out,
+                          double* tot_next, hipStream_t s) {
     Ctl* ctl = at<Ctl>(ws, L.ctl);
-    float* rhs = at<float>(ws, L.rhs);
-    ACSEG_TRY(launch_cmeans(p->N, p->C, p->W, p->H, image, nullptr, bufs, ctl, c64_prev, c64_cur,
-                            c_out, at<double>(ws, L.part_d), kMaxReduceBlocks, s));
-    ACSEG_TRY(launch_rhs(p->N, p->C, p->W, p->H, image, bufs, ctl, c64_cur, cf.rhs, rhs, s));
+    const bool fixed = (p->flags & ACSEG_FLAG_FIXED_CYCLES) != 0u;
     const int sweeps = p->nu_pre + p->nu_post;
-    for (int c = 0; c < p->max_cycles; ++c)
-        ACSEG_TRY(launch_smooth(p->N, p->W, p->H, sweeps, true, bufs, ctl, rhs, cf.fine,
-                                (float)p->tol, p->max_cycles, at<float>(ws, L.part_f), s));
-    ACSEG_TRY(launch_step_end(ctl, (float)p->tol, s));
+    CycleLaunch c{};
+    c.N = p->N;
+    c.C = p->C;
+    c.W = p->W;
+    c.H = p->H;
+    c.sweeps = sweeps;
+    c.slot = n & 1;
+    c.fixed = fixed;
+    c.store_rhs = !(fixed && p->max_cycles == 1 && cycle_launches(sweeps) == 1);
+    c.bufs = bufs;
+    c.ctl = ctl;
+    c.image = image;
+    c.tot = tot;
+    c.c_prev64 = c_prev64;
+    c.c64 = c64;
+    c.c_out = c_out;
+    c.rhs = at<float>(ws, L.rhs);
+    c.res_part = at<float>(ws, L.part_f);
+    c.cm_part = at<double>(ws, L.part_cm);
+    c.part_stride = L.part_stride;
+    c.coef = cf.fine;
+    c.rc = cf.rhs;
+    c.tol = (float)p->tol;
+    for (int k = 0; k < p->max_cycles; ++k) {
+        c.cycle = k;
+        c.cm = !fixed || k == p->max_cycles - 1;
+        ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] { return launch_cycle(c, s); }));
+    }
+    ACSEG_TRY(timed(ctx, kFamOther, s, [&] {
+        return launch_step_end(p->N, p->C, p->W, p->H, ctl, c.res_part, c.cm_part, L.part_stride,
+                               p->max_cycles, sweeps, c.slot, (float)p->tol, tot_next, s);
+    }));
+    return ACSEG_OK;
+}
+
+// Colour means of an explicit field u: reduced sums into tot (may be NULL),
+// means into c64 / c_out.
+acseg_status enqueue_means(const acseg_problem* p, const float* image, const float* u,
+                           const Layout& L, void* ws, const double* c_prev64, double* c64,
+                           float* c_out, double* tot, hipStream_t s) {
+    const Bufs bufs{{u, u, u}};
+    Ctl* ctl = at<Ctl>(ws, L.ctl);
+    double* part_d = at<double>(ws, L.part_d);
+    ACSEG_TRY(launch_cmeans(p->N, p->C, p->W, p->H, image, u, bufs, ctl, part_d, s));
+    ACSEG_TRY(launch_cmeans_finish(p->N, p->C, p->W, p->H, part_d, ctl, c_prev64, c64, c_out, tot, s));
     return ACSEG_OK;
 }
 
@@ -213,6 +295,11 @@ acseg_status acseg_create(int device, acseg_ctx** out) {
 
 acseg_status acseg_destroy(acseg_ctx* ctx) {
     if (!ctx) return ACSEG_OK;
+    for (const TimedRec& r : ctx->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->host_ctl) (void)hipHostFree(ctx->host_ctl);
     delete ctx;
     return ACSEG_OK;
@@ -244,12 +331,11 @@ acseg_status acseg_colour_means(acseg_ctx* ctx, const acseg_problem* p, const fl
     hipStream_t s = (hipStream_t)stream;
     Ctl* ctl = at<Ctl>(ws, L.ctl);
     double* c64 = at<double>(ws, L.c64);
-    double* cprev = c64 + ACSEG_MAX_N * ACSEG_MAX_C;
+    double* cprev = c64 + 2 * kNC;
     ACSEG_TRY(launch_ctl_init(ctl, 0, s));
     if (c_prev) ACSEG_TRY(launch_widen(c_prev, cprev, p->N * p->C, s));
-    const Bufs bufs{{u, u, u}};
-    ACSEG_TRY(launch_cmeans(p->N, p->C, p->W, p->H, image, u, bufs, ctl, c_prev ? cprev : nullptr,
-                            c64, c_out, at<double>(ws, L.part_d), kMaxReduceBlocks, s));
+    v = enqueue_means(p, image, u, L, ws, c_prev ? cprev : nullptr, c64, c_out, nullptr, s);
+    if (v != ACSEG_OK) return v;
     return read_stats(ctx, L, ws, s, stats);
 }
 
@@ -266,11 +352,15 @@ acseg_status acseg_step(acseg_ctx* ctx, const acseg_problem* p, const float* ima
     const int64_t nu = (int64_t)p->N * p->W * p->H;
     Ctl* ctl = at<Ctl>(ws, L.ctl);
     double* c64 = at<double>(ws, L.c64);
-    double* cprev = c64 + ACSEG_MAX_N * ACSEG_MAX_C;
+    double* cprev = c64 + 2 * kNC;
     const Bufs bufs{{u_out, at<float>(ws, L.ubuf), u_in}};
+    double* tot = at<double>(ws, L.tot);
     ACSEG_TRY(launch_ctl_init(ctl, 2, s));
     if (c_prev) ACSEG_TRY(launch_widen(c_prev, cprev, p->N * p->C, s));
-    v = enqueue_step(p, cf, image, bufs, L, ws, c_prev ? cprev : nullptr, c64, c_out, s);
+    const double* cp = c_prev ? cprev : nullptr;
+    v = enqueue_means(p, image, u_in, L, ws, cp, c64, c_out, tot, s);
+    if (v != ACSEG_OK) return v;
+    v = enqueue_step(ctx, p, cf, image, bufs, L, ws, 0, tot, cp, c64, nullptr, tot + kCmeansMaxM, s);
     if (v != ACSEG_OK) return v;
     ACSEG_TRY(launch_copy_current(bufs, ctl, u_out, nu, s));
     return read_stats(ctx, L, ws, s, stats);
@@ -289,22 +379,27 @@ acseg_status acseg_solve(acseg_ctx* ctx, const acseg_problem* p, const float* im
     const Coefs cf = coefs_of(p);
     const int64_t nu = (int64_t)p->N * p->W * p->H;
     Ctl* ctl = at<Ctl>(ws, L.ctl);
-    double* cA = at<double>(ws, L.c64);
-    double* cB = cA + ACSEG_MAX_N * ACSEG_MAX_C;
+    double* c64 = at<double>(ws, L.c64);  // [2][kNC]: the means used by step n in set n & 1
+    double* tot = at<double>(ws, L.tot);  // [2][kCmeansMaxM]: sums of u^n in set n & 1
     const Bufs bufs{{u, at<float>(ws, L.ubuf), u}};
     ACSEG_TRY(launch_ctl_init(ctl, 0, s));
     if (ckpt) ACSEG_TRY(hipMemcpyAsync(checkpoints, u, sizeof(float) * nu, hipMemcpyDeviceToDevice, s));
+    v = enqueue_means(p, image, u, L, ws, nullptr, c64 + kNC, p->steps == 0 ? c_out : nullptr, tot, s);
+    if (v != ACSEG_OK) return v;
     for (int n = 0; n < p->steps; ++n) {
-        v = enqueue_step(p, cf, image, bufs, L, ws, n > 0 ? cB : nullptr, cA, nullptr, s);
+        const int a = n & 1, b = a ^ 1;
+        v = enqueue_step(ctx, p, cf, image, bufs, L, ws, n, tot + a * kCmeansMaxM,
+                         n > 0 ? c64 + b * kNC : nullptr, c64 + a * kNC, nullptr,
+                         tot + b * kCmeansMaxM, s);
         if (v != ACSEG_OK) return v;
-        std::swap(cA, cB);  // cB now holds this step's means
         if (ckpt) ACSEG_TRY(launch_copy_current(bufs, ctl, checkpoints + (n + 1) * nu, nu, s));
     }
     ACSEG_TRY(launch_copy_current(bufs, ctl, u, nu, s));
-    if (c_out)
-        ACSEG_TRY(launch_cmeans(p->N, p->C, p->W, p->H, image, u, bufs, ctl,
-                                p->steps > 0 ? cB : nullptr, cA, c_out, at<double>(ws, L.part_d),
-                                kMaxReduceBlocks, s));
+    if (c_out && p->steps > 0) {
+        const int a = p->steps & 1, b = a ^ 1;  // sums of u^steps; means used by the last step
+        ACSEG_TRY(launch_means_from_tot(p->N, p->C, tot + a * kCmeansMaxM, c64 + b * kNC, ctl,
+                                        nullptr, c_out, s));
+    }
     return read_stats(ctx, L, ws, s, stats);
 }
 
@@ -328,13 +423,49 @@ acseg_status acseg_energy(acseg_ctx* ctx, const acseg_problem* p, const float* i
     hipStream_t s = (hipStream_t)stream;
     Ctl* ctl = at<Ctl>(ws, L.ctl);
     double* c64 = at<double>(ws, L.c64);
-    const Bufs bufs{{u, u, u}};
     ACSEG_TRY(launch_ctl_init(ctl, 0, s));
-    ACSEG_TRY(launch_cmeans(p->N, p->C, p->W, p->H, image, u, bufs, ctl, nullptr, c64, nullptr,
-                            at<double>(ws, L.part_d), kMaxReduceBlocks, s));
+    v = enqueue_means(p, image, u, L, ws, nullptr, c64, nullptr, nullptr, s);
+    if (v != ACSEG_OK) return v;
     ACSEG_TRY(launch_energy(p->N, p->C, p->W, p->H, image, u, c64, p->eps, p->lambda, p->h,
-                            at<double>(ws, L.part_d), kMaxReduceBlocks, ctl, energy, s));
+                            at<double>(ws, L.part_d), energy, s));
     return ACSEG_OK;
+}
+
+acseg_status acseg_timing_enable(acseg_ctx* ctx, int32_t enable) {
+    if (!ctx) return ACSEG_ERR_INVALID_ARG;
+    ctx->timing = enable != 0;
+    return ACSEG_OK;
+}
+
+acseg_status acseg_timing_read(acseg_ctx* ctx, acseg_kernel_time* out, int32_t max,
+                               int32_t* count) {
+    if (!ctx || !count || max < 0 || (max > 0 && !out)) return ACSEG_ERR_INVALID_ARG;
+    int64_t launches[kFamCount] = {};
+    double total[kFamCount] = {};
+    acseg_status st = ACSEG_OK;
+    for (const TimedRec& r : ctx->recs) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+            st = ACSEG_ERR_HIP;
+        launches[r.fam] += 1;
+        total[r.fam] += ms;
+        ctx->pool.push_back(r.a);
+        ctx->pool.push_back(r.b);
+    }
+    ctx->recs.clear();
+    int n = 0;
+    for (int f = 0; f < kFamCount; ++f) {
+        if (launches[f] == 0) continue;
+        if (n < max) {
+            memset(&out[n], 0, sizeof(out[n]));
+            strncpy(out[n].name, kFamName[f], sizeof(out[n].name) - 1);
+            out[n].launches = launches[f];
+            out[n].total_ms = total[f];
+        }
+        ++n;
+    }
+    *count = n < max ? n : max;
+    return st;
 }
 
 }  // extern "C"

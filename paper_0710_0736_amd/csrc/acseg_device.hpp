@@ -65,39 +65,37 @@ __device__ __forceinline__ double mass_w(int cls) {
 // The correction loop of Section "Gibbs Space Constraint Pseudocode" in
 // threshold form: all free components are shifted by one common theta chosen
 // so that they sum to one; every free component that would go negative is
-// fixed at zero and leaves the free set; repeat.  At most N rounds.  Values
-// are taken relative to the largest component (which never leaves the free
-// set) so that the threshold arithmetic stays well conditioned in FP32.
+// fixed at zero and leaves the free set; repeat (at most N - 1 removals).
+// Values are first taken relative to the largest component, so every value
+// is <= 0 and the sum s of the free ones too; then theta = (s - 1)/k < 0, the
+// largest component (now exactly 0) is never removed, and the threshold
+// arithmetic stays well conditioned in FP32.
 template <int N>
 __device__ __forceinline__ void project_simplex(float (&v)[N]) {
     float vmax = v[0];
 #pragma unroll
     for (int i = 1; i < N; ++i) vmax = fmaxf(vmax, v[i]);
-    int imax = N - 1;
+    float s = 0.f;
 #pragma unroll
-    for (int i = N - 1; i >= 0; --i)
-        if (v[i] == vmax) imax = i;
-#pragma unroll
-    for (int i = 0; i < N; ++i) v[i] -= vmax;
+    for (int i = 0; i < N; ++i) {
+        v[i] -= vmax;
+        s += v[i];
+    }
+    float theta = (s - 1.0f) * (1.0f / (float)N);
     unsigned freem = (1u << N) - 1u;
-    float theta = 0.f;
 #pragma unroll
-    for (int r = 0; r < N; ++r) {
-        float s = 0.f;
-        int k = 0;
-#pragma unroll
-        for (int i = 0; i < N; ++i)
-            if ((freem >> i) & 1u) {
-                s += v[i];
-                ++k;
-            }
-        theta = (s - 1.0f) / (float)k;
+    for (int r = 0; r < N - 1; ++r) {
         unsigned out = 0u;
 #pragma unroll
         for (int i = 0; i < N; ++i)
-            if (((freem >> i) & 1u) && i != imax && v[i] < theta) out |= 1u << i;
+            if (((freem >> i) & 1u) && v[i] < theta) out |= 1u << i;
         if (out == 0u) break;
         freem &= ~out;
+        s = 0.f;
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if ((freem >> i) & 1u) s += v[i];
+        theta = (s - 1.0f) * __builtin_amdgcn_rcpf((float)__popc(freem));
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] = ((freem >> i) & 1u) ? fmaxf(v[i] - theta, 0.f) : 0.f;
@@ -134,25 +132,48 @@ __device__ __forceinline__ float block_max(float v, float* sh /* >= kBlock/kWave
     return r;
 }
 
-// Last-block detection: every block calls this once after writing its partial
-// results; it returns true in all threads of the block that arrives last, and
-// that block then sees every other block's partials.  Each thread publishes
-// its own writes with a device-scope fence before the barrier; the last block
-// fences again before reading.  The counter is reset by the last block.
-__device__ __forceinline__ bool arrive_last(unsigned* counter, int* sh_flag) {
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned prev = atomicAdd(counter, 1u);
-        *sh_flag = (prev == gridDim.x * gridDim.y * gridDim.z - 1u) ? 1 : 0;
+// Double wave sum over a block's kBlock threads is done per value; this
+// helper sums partial rows [nb][M] in a fixed order into tot[M] (LDS) so that
+// every caller obtains bit-identical results.  sh: LDS [kBlock/kWave][M].
+template <int M>
+__device__ void reduce_rows(const double* __restrict__ part, int nb, double* tot,
+                            double (*sh)[M]) {
+    double acc[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) acc[m] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock)
+#pragma unroll
+        for (int m = 0; m < M; ++m) acc[m] += part[(int64_t)b * M + m];
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const double v = wave_sum(acc[m]);
+        if (lane == 0) sh[wid][m] = v;
     }
     __syncthreads();
-    const bool last = *sh_flag != 0;
-    if (last) {
-        __threadfence();
-        if (threadIdx.x == 0) atomicExch(counter, 0u);
+    if (threadIdx.x < M) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / kWave; ++w) s += sh[w][threadIdx.x];
+        tot[threadIdx.x] = s;
     }
-    return last;
+    __syncthreads();
+}
+
+// c_ik = S_ik / S_i from the reduced sums; empty phases keep c_prev64 (or the
+// mean image colour).  Runs in every thread (cheap); returns the empty flag.
+template <int N, int C>
+__device__ int finish_means(const double* tot, const double* c_prev64, double* c) {
+    const double area = tot[N * C + N + C];
+    int empty = 0;
+    for (int i = 0; i < N; ++i) {
+        const double S = tot[N * C + i];
+        const bool has_mass = S > 1e-12 * area;
+        empty |= has_mass ? 0 : 1;
+        for (int k = 0; k < C; ++k)
+            c[i * C + k] = has_mass ? tot[i * C + k] / S
+                                    : (c_prev64 ? c_prev64[i * C + k] : tot[N * C + N + k] / area);
+    }
+    return empty;
 }
 
 }  // namespace acseg

@@ -9,39 +9,53 @@
 
 namespace acseg {
 
-// Per-step / per-solve control block in device memory.  Kernels read `cur`
-// (which of the three iterate buffers holds the current iterate) and `done`
-// (the current step has converged or spent its cycle budget); the last block
-// of each cycle kernel updates them.  Statistics accumulate over a solve.
+// Per-step convergence record; two alternate between consecutive steps so
+// that the end of one step can re-arm the slot of the step after next while
+// the kernels of the next step read theirs.
+struct StepSlot {
+    int done;    // a cycle kernel found the step converged before `cycles` cycles
+    int cycles;
+    float resid;
+    int pad;
+};
+
+// Control block in device memory, one per call.  Between time steps `cur`
+// names the iterate buffer holding the current field; within a step the
+// cycle kernels derive their input from it and their launch index, and never
+// write it.  k_step_end resolves the step, moves `cur` and folds the
+// statistics.  No kernel communicates across workgroups within a launch:
+// partial results are plain stores consumed by a later kernel.
 struct Ctl {
+    StepSlot step[2];
     int cur;
-    int done;
-    int cycles;          // cycles run in the current step
     int steps_done;
-    unsigned arrive;     // last-block counter (cycle kernels)
-    unsigned arrive2;    // last-block counter (reductions)
-    unsigned arrive3;    // last-block counter (line search)
     int empty_steps;
     int nonfinite;
     int steps_unconv;
     int cycles_total;
     int cycles_max;
-    float resid;         // natural residual after the last cycle
+    int empty_now;       // the last colour-means pass found an empty phase
+    float resid;         // natural residual at the end of the last step
     float max_resid;     // largest end-of-step residual
     double alpha;        // line-search step of the current coarse correction
-    int empty_now;       // the last colour-means pass found an empty phase
-    int pad[7];
+    int pad[12];
 };
 static_assert(sizeof(Ctl) <= 256, "control block must fit in 256 bytes");
 
-// Three iterate buffers: [0] and [1] alternate as cycle outputs, [2] may hold
-// a read-only initial iterate.  The output of a cycle reading buffer `cur` is
-// buffer (cur == 0 ? 1 : 0).
+// Three iterate buffers: [0] and [1] alternate as outputs, [2] may hold a
+// read-only initial iterate.  A launch reading buffer c writes out_of(c).
 struct Bufs {
     const float* b[3];
 };
 
-__device__ __forceinline__ int out_of(int cur) { return cur == 0 ? 1 : 0; }
+__host__ __device__ __forceinline__ int out_of(int cur) { return cur == 0 ? 1 : 0; }
+
+// Buffer holding the iterate after k buffer-flipping launches from `start`.
+__host__ __device__ __forceinline__ int iterate_buf(int start, int k) {
+    if (k <= 0) return start;
+    const int first = out_of(start);
+    return ((k - 1) & 1) ? out_of(first) : first;
+}
 
 // Fine-level constants for the right-hand side (float64).
 struct RhsCoef {
@@ -50,49 +64,86 @@ struct RhsCoef {
     double lambda;
 };
 
+constexpr int kCmeansBlocks = 128;  // workgroups of the colour-mean pass
+constexpr int kRhsBlocks = 512;     // workgroups of the right-hand-side pass
+
 // ---- launchers (kernels_fine.hip) ----------------------------------------
 
 hipError_t launch_project(int N, int64_t count, const float* y, float* x, hipStream_t s);
 
-// colour-mean partial sums of buffer bufs[ctl->cur] (or `u` when non-NULL);
-// the last block writes c64 (float64 [N][C]) using c_prev64 for empty phases
-// (c_prev64 may be NULL: mean image colour), and c_out (float, may be NULL).
+// Colour-mean partial sums of bufs[ctl->cur] (or `u` when non-NULL):
+// partials[cmeans_blocks][cmeans_width] float64.
+int cmeans_width(int N, int C);
+int cmeans_blocks(int W, int H);
 hipError_t launch_cmeans(int N, int C, int W, int H, const float* image, const float* u,
-                         Bufs bufs, Ctl* ctl, const double* c_prev64, double* c64,
-                         float* c_out, double* partials, int max_blocks, hipStream_t s);
+                         Bufs bufs, const Ctl* ctl, double* partials, hipStream_t s);
 
-// rhs' = w[(1/tau+2/eps) u - lambda F(c)] / D, shifted per node so that its
-// largest component is 0; resets the per-step control fields.
-hipError_t launch_rhs(int N, int C, int W, int H, const float* image, Bufs bufs, Ctl* ctl,
-                      const double* c64, RhsCoef rc, float* rhs, hipStream_t s);
+// One block: the reduced sums tot[cmeans_width] (may be NULL), c64 (float64
+// [N][C]) and c_out (float, may be NULL) from the partials; empty phases keep
+// c_prev64 (NULL: mean image colour).
+hipError_t launch_cmeans_finish(int N, int C, int W, int H, const double* partials, Ctl* ctl,
+                                const double* c_prev64, double* c64, float* c_out, double* tot,
+                                hipStream_t s);
 
-// One smoothing cycle: `sweeps` red-black projected block Gauss-Seidel sweeps
-// from bufs[cur] into bufs[out_of(cur)]; with `resid`, also the natural
-// residual of the result, the done flag and the statistics (last block).
-hipError_t launch_smooth(int N, int W, int H, int sweeps, bool resid, Bufs bufs, Ctl* ctl,
-                         const float* rhs, LevelCoef coef, float tol, int max_cycles,
-                         float* partials, hipStream_t s);
+// ---- launchers (kernels_cycle.hip) ---------------------------------------
 
-// Upper bound on the number of workgroups of one smoothing launch.
-int smooth_max_tiles(int W, int H);
+// One smoothing cycle of the current time step: `sweeps` red-black projected
+// block Gauss-Seidel sweeps (launches of at most two).  The step's first
+// launch builds the right-hand side from u^n (= bufs[ctl->cur]), the image
+// and c64 (stored to `rhs` when later launches need it); every closing launch
+// writes per-tile residual partials and, with `cm`, colour-mean partials of
+// its output.  Unless `fixed`, a cycle first checks the previous cycle's
+// residual and the rest of the step is skipped once it is <= tol.
+struct CycleLaunch {
+    int N, C, W, H;
+    int sweeps, cycle, slot;
+    bool fixed, store_rhs, cm;
+    Bufs bufs;
+    Ctl* ctl;
+    const float* image;
+    const double* tot;        // reduced colour-mean sums of u^n [cmeans_width]
+    const double* c_prev64;   // previous means for empty phases, or NULL
+    double* c64;              // out: the means of u^n
+    float* c_out;             // out (float), or NULL
+    float* rhs;
+    float* res_part;          // [2][part_stride]
+    double* cm_part;          // [2][cmeans_width][part_stride]
+    int part_stride;
+    LevelCoef coef;
+    RhsCoef rc;
+    float tol;
+};
+int cycle_launches(int sweeps);
+int cycle_tiles(int N, int W, int H);
+hipError_t launch_cycle(const CycleLaunch& c, hipStream_t s);
 
-// End of a step: fold the step's counters into the solve statistics.
-hipError_t launch_step_end(Ctl* ctl, float tol, hipStream_t s);
+// End of a time step: the reduced colour-mean sums of the new iterate into
+// tot_next, the step's residual and cycle count, the buffer holding the
+// iterate, statistics; re-arms control slot slot ^ 1.
+hipError_t launch_step_end(int N, int C, int W, int H, Ctl* ctl, const float* res_part,
+                           const double* cm_part, int part_stride, int max_cycles, int sweeps,
+                           int slot, float tol, double* tot_next, hipStream_t s);
+
+// One workgroup: colour means from reduced sums tot (empty phases keep
+// c_prev64) into c64 / c_out, flags in ctl.
+hipError_t launch_means_from_tot(int N, int C, const double* tot, const double* c_prev64,
+                                 Ctl* ctl, double* c64, float* c_out, hipStream_t s);
 
 // Initialise a control block (cur = initial buffer index).
 hipError_t launch_ctl_init(Ctl* ctl, int cur, hipStream_t s);
 
 // Copy bufs[ctl->cur] to dst unless it already is dst (count floats).
-hipError_t launch_copy_current(Bufs bufs, Ctl* ctl, float* dst, int64_t count, hipStream_t s);
+hipError_t launch_copy_current(Bufs bufs, const Ctl* ctl, float* dst, int64_t count,
+                               hipStream_t s);
 
 hipError_t launch_labels(int N, int C, int W, int H, const float* u, const float* c,
                          uint8_t* labels, float* composite, float* rounded, hipStream_t s);
 
 // Energy parts of eq. E with c64 the colour means of u; energy[0..3].
+// partials: at least kCmeansBlocks * 3 doubles.
 hipError_t launch_energy(int N, int C, int W, int H, const float* image, const float* u,
                          const double* c64, double eps, double lambda, double h,
-                         double* partials, int max_blocks, Ctl* ctl, double* energy,
-                         hipStream_t s);
+                         double* partials, double* energy, hipStream_t s);
 
 // dst[t] = (double)src[t] for t < count.
 hipError_t launch_widen(const float* src, double* dst, int count, hipStream_t s);

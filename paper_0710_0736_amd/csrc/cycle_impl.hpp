@@ -1,0 +1,499 @@
+// cycle_impl.hpp -- one smoothing cycle of a time step, on LDS tiles, and the
+// end-of-step reduction.  Instantiated per phase count in cycle_n*.hip.
+//
+// A cycle is `sweeps` red-black sweeps of projected block Gauss-Seidel over the
+// nodal sub-problems of the step (Section "Finite Element Notation": one
+// exact block minimisation per node, the nodes of one colour at a time), then
+// the natural residual of the result.  The first launch of a step also builds
+// the right-hand side of eq. alpha from u^n and the image while it stages the
+// tile, so a one-cycle step touches each node's data once:
+//     read u^n (N floats) and I (C floats), write u^{n+1} (N floats).
+// The closing launch of a cycle leaves, per tile, the largest residual and
+// the colour-mean partial sums of its output (the means of the next step).
+//
+// Tiles: a workgroup owns a TX x TY block of the lattice and stages it with a
+// halo of R = 2K (+1 for the residual) nodes in LDS, every row split into its
+// even-x and odd-x halves.  Half-sweep s updates one colour inside a region
+// that shrinks by one node per half-sweep, so the tile ends up exactly as K
+// global red-black sweeps leave it.
+//
+// Work split: each thread owns fixed horizontal node pairs of the staged
+// region, chosen so that the first node of every pair is red ((x+y) even) and
+// the second black: a half-sweep updates the same node of every pair, with
+// no per-lane colour selection.  Per pair the thread keeps in registers the
+// LDS slots of both nodes, their coupling weights kappa*c_pq, their distance
+// outside the tile interior, and the right-hand side of both nodes.  Tiles
+// are assigned so that the workgroups of one XCD (workgroup id mod 8) own a
+// contiguous band of tile rows and share halos in their L2.
+#pragma once
+
+#include "acseg_internal.h"
+
+namespace acseg {
+
+__host__ __device__ constexpr int cycle_ty(int N) { return N <= 3 ? 32 : 16; }
+constexpr int kTX = 64;
+constexpr int kXcd = 8;
+
+struct CycleArgs {
+    Bufs bufs;
+    Ctl* ctl;
+    const float* image;       // [C][H][W]
+    const double* tot;        // colour-mean sums of u^n [M] (step's first launch)
+    const double* c_prev64;   // previous step's means (empty phases), or NULL
+    double* c64;              // out, block 0 of the first launch: the means of u^n
+    float* c_out;             // out (float), or NULL
+    float* rhs;               // rhs' [N][H][W]: written by the first launch if store_rhs, else read
+    float* res_part;          // [2][part_stride]        row = cycle & 1
+    double* cm_part;          // [2][M][part_stride]     row = cycle & 1
+    int part_stride;
+    LevelCoef coef;
+    RhsCoef rc;
+    float tol;
+    int slot;                 // control slot of this step (step index & 1)
+    int cycle;                // cycle index within the step
+    int first;                // this launch opens the cycle
+    int launch;               // launch index within the step (buffer parity)
+    int fixed;                // no convergence checks
+    int store_rhs;
+    int cm;                   // closing launch accumulates colour-mean partials
+    int W, H;
+    int tiles_x, ntiles, tiles_per_xcd;
+};
+
+template <int N, int C, int K, bool FIRST, bool RESID>
+__global__ __launch_bounds__(kBlock) void k_cycle(CycleArgs a) {
+    constexpr int TX = kTX, TY = cycle_ty(N);
+    constexpr int R = 2 * K + (RESID ? 1 : 0);
+    constexpr int LX = TX + 2 * R, LY = TY + 2 * R;
+    constexpr int LXH = LX / 2;    // pairs per row
+    constexpr int HL = LXH + 1;    // half-row length in LDS (one spare slot)
+    constexpr int RW = 2 * HL;     // LDS row stride
+    constexpr int PL = LY * RW;    // LDS plane stride
+    constexpr int NP = LXH * LY;   // pairs in the staged region
+    constexpr int MP = (NP + kBlock - 1) / kBlock;
+    constexpr int M = N * C + N + C + 2;
+    constexpr int NHALF = 2 * K + (RESID ? 1 : 0);
+    constexpr int kOut = 255;      // "radius" of a node outside the image: never updated
+    extern __shared__ float lds[];
+    __shared__ float red[kBlock / kWave];
+    __shared__ double shd[kBlock / kWave][M];
+    __shared__ double cs[N * C];
+    __shared__ double cs2[N];
+    __shared__ int flag;
+
+    Ctl* ctl = a.ctl;
+    StepSlot* slot = &ctl->step[a.slot];
+    if (!a.fixed) {
+        if (slot->done) return;  // uniform: an earlier cycle of this step converged
+        if (a.first && a.cycle > 0) {
+            const float* prev = a.res_part + ((a.cycle - 1) & 1) * a.part_stride;
+            float r = 0.f;
+            for (int b = threadIdx.x; b < a.ntiles; b += kBlock) r = fmaxf(r, prev[b]);
+            r = block_max(r, red);
+            if (threadIdx.x == 0) flag = !(r > a.tol);
+            __syncthreads();
+            if (flag) {
+                if (blockIdx.x == 0 && threadIdx.x == 0) {
+                    slot->done = 1;
+                    slot->cycles = a.cycle;
+                    slot->resid = r;
+                }
+                return;
+            }
+        }
+    }
+    const int tile = (blockIdx.x % kXcd) * a.tiles_per_xcd + blockIdx.x / kXcd;
+    if (tile >= a.ntiles) return;
+    const int cur = iterate_buf(ctl->cur, a.launch);
+    const float* __restrict__ src = a.bufs.b[cur];
+    float* __restrict__ dst = const_cast<float*>(a.bufs.b[out_of(cur)]);
+    const float* __restrict__ image = a.image;
+    const int W = a.W, H = a.H;
+    const int64_t P = (int64_t)W * H;
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int x0 = tx * TX - R, y0 = ty * TY - R;  // LDS origin; x0 + y0 is even
+
+    if (FIRST && threadIdx.x == 0) {
+        // colour means of u^n from the reduced sums (identical in every block)
+        double c[N * C];
+        const int empty = finish_means<N, C>(a.tot, a.c_prev64, c);
+        for (int i = 0; i < N; ++i) {
+            double q = 0.0;
+            for (int k = 0; k < C; ++k) {
+                cs[i * C + k] = c[i * C + k];
+                q += c[i * C + k] * c[i * C + k];
+            }
+            cs2[i] = q;
+        }
+        if (blockIdx.x == 0) {
+            for (int q = 0; q < N * C; ++q) {
+                a.c64[q] = c[q];
+                if (a.c_out) a.c_out[q] = (float)c[q];
+            }
+            if (empty) ctl->empty_steps += 1;
+            if (a.tot[M - 1] > 0.0) ctl->nonfinite = 1;
+        }
+    }
+
+    // ---- stage u (all planes, halo included) in LDS: coalesced rows
+    for (int idx = threadIdx.x; idx < LX * LY; idx += kBlock) {
+        const int ly = idx / LX, lx = idx - ly * LX;
+        const int gx = x0 + lx, gy = y0 + ly;
+        const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
+        const int li = ly * RW + (lx & 1) * HL + (lx >> 1);
+        const int64_t g = (int64_t)gy * W + gx;
+#pragma unroll
+        for (int i = 0; i < N; ++i) lds[i * PL + li] = in ? src[i * P + g] : 0.f;
+    }
+
+    // ---- per-pair geometry and coefficients (registers)
+    int c0[MP], c1[MP];      // LDS slots of the red / black node
+    int rad0[MP], rad1[MP];  // distance outside the tile interior (kOut: off the image)
+    float kh0[MP], kv0[MP], kh1[MP], kv1[MP];
+#pragma unroll
+    for (int m = 0; m < MP; ++m) {
+        const int pi = threadIdx.x + m * kBlock;
+        const int ly = pi / LXH, j = pi - ly * LXH;
+        const int odd = ly & 1;
+        c0[m] = ly * RW + odd * HL + j;
+        c1[m] = ly * RW + (1 - odd) * HL + j + odd;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int lx = 2 * j + odd + e;
+            const int gx = x0 + lx, gy = y0 + ly;
+            const bool in = pi < NP && gx >= 0 && gx < W && gy >= 0 && gy < H && lx < LX;
+            const int dx = max(max(R - lx, lx - (R + TX - 1)), 0);
+            const int dy = max(max(R - ly, ly - (R + TY - 1)), 0);
+            const int rad = in ? max(dx, dy) : kOut;
+            float kh = 0.f, kv = 0.f;
+            if (in) {
+                const float kap = sel4(a.coef.kappa, node_class(gx, gy, W, H));
+                kh = kap * edge_w_h(gy, H);
+                kv = kap * edge_w_v(gx, W);
+            }
+            if (e == 0) {
+                rad0[m] = rad;
+                kh0[m] = kh;
+                kv0[m] = kv;
+            } else {
+                rad1[m] = rad;
+                kh1[m] = kh;
+                kv1[m] = kv;
+            }
+        }
+    }
+    __syncthreads();  // u staged, means known
+
+    // ---- right-hand side of the owned nodes (registers)
+    float rr0[MP][N], rr1[MP][N];
+#pragma unroll
+    for (int m = 0; m < MP; ++m) {
+        const int pi = threadIdx.x + m * kBlock;
+        const int ly = pi / LXH, j = pi - ly * LXH;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int lx = 2 * j + (ly & 1) + e;
+            const int gx = x0 + lx, gy = y0 + ly;
+            const bool in = (e == 0 ? rad0[m] : rad1[m]) != kOut;
+            const int64_t g = (int64_t)gy * W + gx;
+            float rv[N];
+            if (FIRST) {
+                // rhs'_i = w[(1/tau + 2/eps) u_i - lambda F_i(c)] / D in float64, with
+                // F_i = |I|^2 - 2 c_i.I + |c_i|^2 (the common |I|^2 dropped), shifted
+                // so that max_i rhs'_i = 0
+                if (in) {
+                    const int li = e == 0 ? c0[m] : c1[m];
+                    double I[C];
+#pragma unroll
+                    for (int k = 0; k < C; ++k) I[k] = (double)image[k * P + g];
+                    const double wd = sel4d(a.rc.wd, node_class(gx, gy, W, H));
+                    double r[N];
+                    double rmax = -1e300;
+#pragma unroll
+                    for (int i = 0; i < N; ++i) {
+                        double ci = 0.0;
+#pragma unroll
+                        for (int k = 0; k < C; ++k) ci += cs[i * C + k] * I[k];
+                        r[i] = wd * (a.rc.a * (double)lds[i * PL + li] +
+                                     a.rc.lambda * (2.0 * ci - cs2[i]));
+                        rmax = fmax(rmax, r[i]);
+                    }
+                    const bool interior = lx >= R && lx < R + TX && ly >= R && ly < R + TY;
+#pragma unroll
+                    for (int i = 0; i < N; ++i) {
+                        rv[i] = (float)(r[i] - rmax);
+                        if (a.store_rhs && interior) a.rhs[i * P + g] = rv[i];
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < N; ++i) rv[i] = 0.f;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < N; ++i) rv[i] = in ? a.rhs[i * P + g] : 0.f;
+            }
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                if (e == 0)
+                    rr0[m][i] = rv[i];
+                else
+                    rr1[m][i] = rv[i];
+            }
+        }
+    }
+
+    // ---- red-black half-sweeps on the shrinking region
+    float res = 0.f;
+    for (int s = 0; s < NHALF; ++s) {
+        const int r = R - 1 - s;
+        __syncthreads();
+        if ((s & 1) == 0) {  // red: the first node of every pair
+#pragma unroll
+            for (int m = 0; m < MP; ++m) {
+                if (rad0[m] > r) continue;
+                float v[N];
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    const float* L = lds + i * PL;
+                    v[i] = rr0[m][i] + kh0[m] * (L[c1[m] - 1] + L[c1[m]]) +
+                           kv0[m] * (L[c0[m] - RW] + L[c0[m] + RW]);
+                }
+                project_simplex<N>(v);
+                if (RESID && s == NHALF - 1) {
+#pragma unroll
+                    for (int i = 0; i < N; ++i) res = fmaxf(res, fabsf(v[i] - lds[i * PL + c0[m]]));
+                } else {
+#pragma unroll
+                    for (int i = 0; i < N; ++i) lds[i * PL + c0[m]] = v[i];
+                }
+            }
+        } else {  // black: the second node of every pair
+#pragma unroll
+            for (int m = 0; m < MP; ++m) {
+                if (rad1[m] > r) continue;
+                float v[N];
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    const float* L = lds + i * PL;
+                    v[i] = rr1[m][i] + kh1[m] * (L[c0[m]] + L[c0[m] + 1]) +
+                           kv1[m] * (L[c1[m] - RW] + L[c1[m] + RW]);
+                }
+                project_simplex<N>(v);
+#pragma unroll
+                for (int i = 0; i < N; ++i) lds[i * PL + c1[m]] = v[i];
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- write the tile's interior (coalesced rows)
+    for (int idx = threadIdx.x; idx < TX * TY; idx += kBlock) {
+        const int oy = idx / TX, ox = idx - oy * TX;
+        const int gx = x0 + R + ox, gy = y0 + R + oy;
+        if (gx >= W || gy >= H) continue;
+        const int lx = R + ox, ly = R + oy;
+        const int li = ly * RW + (lx & 1) * HL + (lx >> 1);
+        const int64_t g = (int64_t)gy * W + gx;
+#pragma unroll
+        for (int i = 0; i < N; ++i) dst[i * P + g] = lds[i * PL + li];
+    }
+    if (!RESID) return;
+
+    // ---- per-tile residual and colour-mean partials of the output
+    const int row = a.cycle & 1;
+    const float bm = block_max(res, red);
+    if (threadIdx.x == 0) a.res_part[row * a.part_stride + tile] = bm;
+    if (!a.cm) return;
+    float acc[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) acc[q] = 0.f;
+    for (int idx = threadIdx.x; idx < TX * TY; idx += kBlock) {
+        const int oy = idx / TX, ox = idx - oy * TX;
+        const int gx = x0 + R + ox, gy = y0 + R + oy;
+        if (gx >= W || gy >= H) continue;
+        const int lx = R + ox, ly = R + oy;
+        const int li = ly * RW + (lx & 1) * HL + (lx >> 1);
+        const int64_t g = (int64_t)gy * W + gx;
+        const float w = (float)mass_w(node_class(gx, gy, W, H));
+        float I[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) I[k] = image[k * P + g];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const float wu = w * lds[i * PL + li];
+            acc[N * C + i] += wu;
+#pragma unroll
+            for (int k = 0; k < C; ++k) acc[i * C + k] += wu * I[k];
+        }
+#pragma unroll
+        for (int k = 0; k < C; ++k) acc[N * C + N + k] += w * I[k];
+        acc[N * C + N + C] += w;
+    }
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        const double v = wave_sum((double)acc[q]);
+        if (lane == 0) shd[wid][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < M) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / kWave; ++w) t += shd[w][threadIdx.x];
+        a.cm_part[((int64_t)row * M + threadIdx.x) * a.part_stride + tile] = t;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// End of a time step, M + 1 workgroups.  Workgroup q < M sums row q of the
+// last cycle's colour-mean partials over the tiles (fixed order, so the
+// result is deterministic) into tot_next[q]: the sums of the new iterate.
+// Workgroup M takes the step's residual (the last cycle's, unless a cycle
+// kernel found convergence earlier), moves `cur` to the buffer holding the
+// iterate, folds the statistics and re-arms the other control slot for the
+// step after next.
+// ---------------------------------------------------------------------------
+
+struct StepEndArgs {
+    Ctl* ctl;
+    const float* res_part;
+    const double* cm_part;
+    double* tot_next;
+    int part_stride, ntiles;
+    int max_cycles, launches_per_cycle;
+    int slot;
+    float tol;
+};
+
+template <int N, int C>
+__global__ __launch_bounds__(kBlock) void k_step_end(StepEndArgs a) {
+    constexpr int M = N * C + N + C + 2;
+    __shared__ float red[kBlock / kWave];
+    __shared__ double shd[kBlock / kWave];
+    Ctl* ctl = a.ctl;
+    StepSlot* slot = &ctl->step[a.slot];
+    const int done = slot->done;
+    const int cycles = done ? slot->cycles : a.max_cycles;
+    if ((int)blockIdx.x < M) {
+        const int q = blockIdx.x;
+        const double* row = a.cm_part + ((int64_t)((cycles - 1) & 1) * M + q) * a.part_stride;
+        double t = 0.0;
+        for (int b = threadIdx.x; b < a.ntiles; b += kBlock) t += row[b];
+        t = wave_sum(t);
+        if (threadIdx.x % kWave == 0) shd[threadIdx.x / kWave] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int w = 0; w < kBlock / kWave; ++w) s += shd[w];
+            a.tot_next[q] = s;
+        }
+        return;
+    }
+    float resid;
+    if (done) {
+        resid = slot->resid;
+    } else {
+        const float* last = a.res_part + ((a.max_cycles - 1) & 1) * a.part_stride;
+        float r = 0.f;
+        for (int b = threadIdx.x; b < a.ntiles; b += kBlock) r = fmaxf(r, last[b]);
+        resid = block_max(r, red);
+    }
+    if (threadIdx.x != 0) return;
+    ctl->cur = iterate_buf(ctl->cur, cycles * a.launches_per_cycle);
+    ctl->resid = resid;
+    ctl->cycles_total += cycles;
+    ctl->cycles_max = cycles > ctl->cycles_max ? cycles : ctl->cycles_max;
+    if (resid > a.tol) ctl->steps_unconv += 1;
+    ctl->max_resid = fmaxf(ctl->max_resid, resid);
+    ctl->steps_done += 1;
+    StepSlot* next = &ctl->step[a.slot ^ 1];
+    next->done = 0;
+    next->cycles = 0;
+    next->resid = 0.f;
+}
+
+int cycle_launches(int sweeps);
+
+template <int N, int C, int K, bool FIRST, bool RESID>
+hipError_t run_cycle(CycleArgs a, hipStream_t s) {
+    constexpr int R = 2 * K + (RESID ? 1 : 0);
+    constexpr int HL = (kTX + 2 * R) / 2 + 1;
+    constexpr int lds = N * (cycle_ty(N) + 2 * R) * 2 * HL * 4;
+    static_assert(N * (cycle_ty(N) + 2 * (2 * K + 1)) * 2 * ((kTX + 2 * (2 * K + 1)) / 2 + 1) * 4 <= 65536,
+                  "tile does not fit in 64 KiB of LDS");
+    hipLaunchKernelGGL((k_cycle<N, C, K, FIRST, RESID>), dim3(a.tiles_per_xcd * kXcd), dim3(kBlock),
+                       lds, s, a);
+    return hipGetLastError();
+}
+
+// One cycle: launches of at most two sweeps; the step's first launch builds
+// the right-hand side, the cycle's last one closes the cycle.
+template <int N, int C>
+hipError_t run_cycle_nc(int sweeps, CycleArgs a, bool step_first, hipStream_t s) {
+    const int nl = cycle_launches(sweeps);
+    const int base = a.launch;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < nl && e == hipSuccess; ++k) {
+        const int kk = (k < nl - 1 || sweeps % 2 == 0) ? 2 : 1;
+        const bool last = k == nl - 1;
+        const bool first = step_first && k == 0;
+        a.first = k == 0;
+        a.launch = base + k;
+        if (kk == 2) {
+            if (first)
+                e = last ? run_cycle<N, C, 2, true, true>(a, s) : run_cycle<N, C, 2, true, false>(a, s);
+            else
+                e = last ? run_cycle<N, C, 2, false, true>(a, s) : run_cycle<N, C, 2, false, false>(a, s);
+        } else {
+            if (first)
+                e = last ? run_cycle<N, C, 1, true, true>(a, s) : run_cycle<N, C, 1, true, false>(a, s);
+            else
+                e = last ? run_cycle<N, C, 1, false, true>(a, s) : run_cycle<N, C, 1, false, false>(a, s);
+        }
+    }
+    return e;
+}
+
+template <int N, int C>
+hipError_t run_step_end_nc(const StepEndArgs& a, hipStream_t s) {
+    constexpr int M = N * C + N + C + 2;
+    hipLaunchKernelGGL((k_step_end<N, C>), dim3(M + 1), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+// Per-N entry points, each instantiated in its own translation unit.
+template <int N>
+hipError_t cycle_for_n(int C, int sweeps, const CycleArgs& a, bool step_first, hipStream_t s) {
+    switch (C) {
+        case 1: return run_cycle_nc<N, 1>(sweeps, a, step_first, s);
+        case 2: return run_cycle_nc<N, 2>(sweeps, a, step_first, s);
+        case 3: return run_cycle_nc<N, 3>(sweeps, a, step_first, s);
+        case 4: return run_cycle_nc<N, 4>(sweeps, a, step_first, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int N>
+hipError_t step_end_for_n(int C, const StepEndArgs& a, hipStream_t s) {
+    switch (C) {
+        case 1: return run_step_end_nc<N, 1>(a, s);
+        case 2: return run_step_end_nc<N, 2>(a, s);
+        case 3: return run_step_end_nc<N, 3>(a, s);
+        case 4: return run_step_end_nc<N, 4>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+#define ACSEG_CYCLE_EXTERN(n)                                                                   \
+    extern template hipError_t cycle_for_n<n>(int, int, const CycleArgs&, bool, hipStream_t); \
+    extern template hipError_t step_end_for_n<n>(int, const StepEndArgs&, hipStream_t);
+ACSEG_CYCLE_EXTERN(2)
+ACSEG_CYCLE_EXTERN(3)
+ACSEG_CYCLE_EXTERN(4)
+ACSEG_CYCLE_EXTERN(5)
+ACSEG_CYCLE_EXTERN(6)
+ACSEG_CYCLE_EXTERN(7)
+ACSEG_CYCLE_EXTERN(8)
+#undef ACSEG_CYCLE_EXTERN
+
+}  // namespace acseg

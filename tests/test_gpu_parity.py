@@ -207,3 +207,26 @@ def test_status_nonfinite_and_not_converged():
     _, _, st, _ = acseg.solve(p, cuda(img), cuda(u0))
     assert st["status"] == acseg.WARN_NOT_CONVERGED and st["steps_not_converged"] == 2
     assert st["cycles_total"] == 2
+
+
+@pytest.mark.parametrize("fixed", [False, True])
+def test_every_step_inside_a_pixel_unit_solve(fixed):
+    """Each step of one GPU solve (its colour means come from the in-solve
+    reduction) against the oracle's step from the GPU's own previous state."""
+    w = synth.pixel_twin(synth.VORONOI1024, 48)
+    img, u0, _ = w.make(6)
+    steps = 5
+    flags = acseg.FLAG_FIXED_CYCLES if fixed else 0
+    p = gpu_problem(w, steps=steps, flags=flags, max_cycles=120 if fixed else 400)
+    u, c, st, ck = acseg.solve(p, cuda(img), cuda(u0), checkpoints=True)
+    torch.cuda.synchronize()
+    assert st["status"] == acseg.OK, st
+    ck = host(ck)
+    P = orc_params(w, tol=1e-12, levels=0)
+    c_prev = None
+    for n in range(steps):
+        u_ref, c_used, _ = orc.step(P, img, ck[n], c_prev)
+        assert np.abs(ck[n + 1] - u_ref).max() <= GATE_U, n
+        c_prev = c_used
+    c_ref, _ = orc.colour_means(P, img, ck[-1], c_prev)
+    assert np.abs(host(c) - c_ref).max() < 1e-6
