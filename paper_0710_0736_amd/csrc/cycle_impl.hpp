@@ -61,8 +61,33 @@ struct CycleArgs {
     int tiles_x, ntiles, tiles_per_xcd;
 };
 
+constexpr int kCycT = 512;  // threads of a cycle workgroup (8 wave64)
+
+// Dynamic LDS of one cycle launch: the staged planes.
+template <int N, int K, bool RESID>
+__host__ __device__ constexpr int cycle_lds_bytes() {
+    constexpr int R = 2 * K + (RESID ? 1 : 0);
+    return N * (cycle_ty(N) + 2 * R) * ((kTX + 2 * R) / 2 + 1) * 2 * 4;
+}
+
+template <int T>
+__device__ __forceinline__ float block_max_t(float v, float* sh /* >= T/kWave */) {
+    v = wave_max(v);
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    float r = 0.f;
+    if (threadIdx.x == 0) {
+        r = sh[0];
+        for (int w = 1; w < T / kWave; ++w) r = fmaxf(r, sh[w]);
+    }
+    __syncthreads();
+    return r;
+}
+
 template <int N, int C, int K, bool FIRST, bool RESID>
-__global__ __launch_bounds__(kBlock) void k_cycle(CycleArgs a) {
+__global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
+    constexpr int T = kCycT;
     constexpr int TX = kTX, TY = cycle_ty(N);
     constexpr int R = 2 * K + (RESID ? 1 : 0);
     constexpr int LX = TX + 2 * R, LY = TY + 2 * R;
@@ -71,15 +96,24 @@ __global__ __launch_bounds__(kBlock) void k_cycle(CycleArgs a) {
     constexpr int RW = 2 * HL;     // LDS row stride
     constexpr int PL = LY * RW;    // LDS plane stride
     constexpr int NP = LXH * LY;   // pairs in the staged region
-    constexpr int MP = (NP + kBlock - 1) / kBlock;
+    constexpr int MP = (NP + T - 1) / T;
+    constexpr int NO = TX * TY / T;  // output nodes per thread
+    static_assert(TX * TY % T == 0, "output tile must split evenly");
+    static_assert(LY / 2 <= T, "straggler column must fit one pass");
     constexpr int M = N * C + N + C + 2;
     constexpr int NHALF = 2 * K + (RESID ? 1 : 0);
     constexpr int kOut = 255;      // "radius" of a node outside the image: never updated
+    // colour-mean rows reduced per LDS pass (each row: T + 1 floats)
+    constexpr int QCH = (cycle_lds_bytes<N, K, RESID>() / (4 * (T + 1))) < M
+                            ? (cycle_lds_bytes<N, K, RESID>() / (4 * (T + 1)))
+                            : M;
+    static_assert(!RESID || QCH >= 1, "staging area too small for one reduction row");
+    constexpr int PARTS = T / kWave;  // partial sums per row
     extern __shared__ float lds[];
-    __shared__ float red[kBlock / kWave];
-    __shared__ double shd[kBlock / kWave][M];
+    __shared__ float red[T / kWave];
     __shared__ double cs[N * C];
     __shared__ double cs2[N];
+    __shared__ double part[M][PARTS];
     __shared__ int flag;
 
     Ctl* ctl = a.ctl;
@@ -89,8 +123,8 @@ __global__ __launch_bounds__(kBlock) void k_cycle(CycleArgs a) {
         if (a.first && a.cycle > 0) {
             const float* prev = a.res_part + ((a.cycle - 1) & 1) * a.part_stride;
             float r = 0.f;
-            for (int b = threadIdx.x; b < a.ntiles; b += kBlock) r = fmaxf(r, prev[b]);
-            r = block_max(r, red);
+            for (int b = threadIdx.x; b < a.ntiles; b += T) r = fmaxf(r, prev[b]);
+            r = block_max_t<T>(r, red);
             if (threadIdx.x == 0) flag = !(r > a.tol);
             __syncthreads();
             if (flag) {
@@ -106,13 +140,101 @@ __global__ __launch_bounds__(kBlock) void k_cycle(CycleArgs a) {
     const int tile = (blockIdx.x % kXcd) * a.tiles_per_xcd + blockIdx.x / kXcd;
     if (tile >= a.ntiles) return;
     const int cur = iterate_buf(ctl->cur, a.launch);
-    const float* __restrict__ src = a.bufs.b[cur];
-    float* __restrict__ dst = const_cast<float*>(a.bufs.b[out_of(cur)]);
-    const float* __restrict__ image = a.image;
     const int W = a.W, H = a.H;
     const int64_t P = (int64_t)W * H;
+    // per-plane base pointers (uniform), 32-bit node indices
+    const float* __restrict__ srcp[N];
+    float* __restrict__ dstp[N];
+    const float* __restrict__ rhsp[N];
+    const float* __restrict__ imgp[C];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        srcp[i] = a.bufs.b[cur] + i * P;
+        dstp[i] = const_cast<float*>(a.bufs.b[out_of(cur)]) + i * P;
+        rhsp[i] = a.rhs + i * P;
+    }
+#pragma unroll
+    for (int k = 0; k < C; ++k) imgp[k] = a.image + k * P;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int x0 = tx * TX - R, y0 = ty * TY - R;  // LDS origin; x0 + y0 is even
+
+    // ---- one burst of global loads: u of the owned pairs (both nodes), their
+    //      image (first launch) or stored right-hand side, and the image of
+    //      the owned output nodes for the colour-mean partials
+    float u0v[MP][N], u1v[MP][N];
+    constexpr int NV = FIRST ? C : N;
+    float pv0[MP][NV], pv1[MP][NV];
+    int c0[MP];      // LDS slot of the red node; the black one follows from it
+    int pk[MP];      // rad0 | rad1 << 8 | odd row << 16
+    float kh0[MP], kv0[MP], kh1[MP], kv1[MP];
+#pragma unroll
+    for (int m = 0; m < MP; ++m) {
+        const int pi = threadIdx.x + m * T;
+        const int ly = pi / LXH, j = pi - ly * LXH;
+        const int odd = ly & 1;
+        c0[m] = ly * RW + odd * HL + j;
+        int packed = odd << 16;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int lx = 2 * j + odd + e;
+            const int gx = x0 + lx, gy = y0 + ly;
+            const bool in = pi < NP && gx >= 0 && gx < W && gy >= 0 && gy < H && lx < LX;
+            const int dx = max(max(R - lx, lx - (R + TX - 1)), 0);
+            const int dy = max(max(R - ly, ly - (R + TY - 1)), 0);
+            const int rad = in ? max(dx, dy) : kOut;
+            const bool need = rad <= R - 1;  // some half-sweep updates this node
+            const int g = in ? gy * W + gx : 0;
+            float uv[N], v[NV];
+#pragma unroll
+            for (int i = 0; i < N; ++i) uv[i] = in ? srcp[i][g] : 0.f;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) v[q] = need ? (FIRST ? imgp[q][g] : rhsp[q][g]) : 0.f;
+            float kh = 0.f, kv = 0.f;
+            if (in) {
+                const float kap = sel4(a.coef.kappa, node_class(gx, gy, W, H));
+                kh = kap * edge_w_h(gy, H);
+                kv = kap * edge_w_v(gx, W);
+            }
+            packed |= rad << (8 * e);
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                if (e == 0) u0v[m][i] = uv[i]; else u1v[m][i] = uv[i];
+            }
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                if (e == 0) pv0[m][q] = v[q]; else pv1[m][q] = v[q];
+            }
+            if (e == 0) {
+                kh0[m] = kh;
+                kv0[m] = kv;
+            } else {
+                kh1[m] = kh;
+                kv1[m] = kv;
+            }
+        }
+        pk[m] = packed;
+    }
+    // the x = 0 column of odd rows is not part of any pair
+    float us[N];
+    const int sly = 2 * threadIdx.x + 1;
+    const bool sin = threadIdx.x < LY / 2 && x0 >= 0 && x0 < W && y0 + sly >= 0 && y0 + sly < H;
+    const int sg = sin ? (y0 + sly) * W + x0 : 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) us[i] = sin ? srcp[i][sg] : 0.f;
+    float Io[NO][C];
+    bool on[NO];
+    if (RESID) {
+#pragma unroll
+        for (int q = 0; q < NO; ++q) {
+            const int idx = threadIdx.x + q * T;
+            const int oy = idx / TX, ox = idx - oy * TX;
+            const int gx = x0 + R + ox, gy = y0 + R + oy;
+            on[q] = a.cm && gx < W && gy < H;
+            const int g = on[q] ? gy * W + gx : 0;
+#pragma unroll
+            for (int k = 0; k < C; ++k) Io[q][k] = on[q] ? imgp[k][g] : 0.f;
+        }
+    }
 
     if (FIRST && threadIdx.x == 0) {
         // colour means of u^n from the reduced sums (identical in every block)
@@ -136,77 +258,39 @@ __global__ __launch_bounds__(kBlock) void k_cycle(CycleArgs a) {
         }
     }
 
-    // ---- stage u (all planes, halo included) in LDS: coalesced rows
-    for (int idx = threadIdx.x; idx < LX * LY; idx += kBlock) {
-        const int ly = idx / LX, lx = idx - ly * LX;
-        const int gx = x0 + lx, gy = y0 + ly;
-        const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
-        const int li = ly * RW + (lx & 1) * HL + (lx >> 1);
-        const int64_t g = (int64_t)gy * W + gx;
-#pragma unroll
-        for (int i = 0; i < N; ++i) lds[i * PL + li] = in ? src[i * P + g] : 0.f;
-    }
-
-    // ---- per-pair geometry and coefficients (registers)
-    int c0[MP], c1[MP];      // LDS slots of the red / black node
-    int rad0[MP], rad1[MP];  // distance outside the tile interior (kOut: off the image)
-    float kh0[MP], kv0[MP], kh1[MP], kv1[MP];
+    // ---- u into LDS
 #pragma unroll
     for (int m = 0; m < MP; ++m) {
-        const int pi = threadIdx.x + m * kBlock;
-        const int ly = pi / LXH, j = pi - ly * LXH;
-        const int odd = ly & 1;
-        c0[m] = ly * RW + odd * HL + j;
-        c1[m] = ly * RW + (1 - odd) * HL + j + odd;
+        if (threadIdx.x + m * T >= NP) continue;
+        const int cb = c0[m] + (((pk[m] >> 16) & 1) ? 1 - HL : HL);
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int lx = 2 * j + odd + e;
-            const int gx = x0 + lx, gy = y0 + ly;
-            const bool in = pi < NP && gx >= 0 && gx < W && gy >= 0 && gy < H && lx < LX;
-            const int dx = max(max(R - lx, lx - (R + TX - 1)), 0);
-            const int dy = max(max(R - ly, ly - (R + TY - 1)), 0);
-            const int rad = in ? max(dx, dy) : kOut;
-            float kh = 0.f, kv = 0.f;
-            if (in) {
-                const float kap = sel4(a.coef.kappa, node_class(gx, gy, W, H));
-                kh = kap * edge_w_h(gy, H);
-                kv = kap * edge_w_v(gx, W);
-            }
-            if (e == 0) {
-                rad0[m] = rad;
-                kh0[m] = kh;
-                kv0[m] = kv;
-            } else {
-                rad1[m] = rad;
-                kh1[m] = kh;
-                kv1[m] = kv;
-            }
+        for (int i = 0; i < N; ++i) {
+            lds[i * PL + c0[m]] = u0v[m][i];
+            lds[i * PL + cb] = u1v[m][i];
         }
     }
-    __syncthreads();  // u staged, means known
+    if (threadIdx.x < LY / 2) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) lds[i * PL + sly * RW] = us[i];  // x = 0: even half, slot 0
+    }
+    if (FIRST) __syncthreads();  // the means
 
     // ---- right-hand side of the owned nodes (registers)
     float rr0[MP][N], rr1[MP][N];
 #pragma unroll
     for (int m = 0; m < MP; ++m) {
-        const int pi = threadIdx.x + m * kBlock;
-        const int ly = pi / LXH, j = pi - ly * LXH;
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-            const int lx = 2 * j + (ly & 1) + e;
-            const int gx = x0 + lx, gy = y0 + ly;
-            const bool in = (e == 0 ? rad0[m] : rad1[m]) != kOut;
-            const int64_t g = (int64_t)gy * W + gx;
             float rv[N];
+            const int rad = (pk[m] >> (8 * e)) & 255;
             if (FIRST) {
                 // rhs'_i = w[(1/tau + 2/eps) u_i - lambda F_i(c)] / D in float64, with
                 // F_i = |I|^2 - 2 c_i.I + |c_i|^2 (the common |I|^2 dropped), shifted
                 // so that max_i rhs'_i = 0
-                if (in) {
-                    const int li = e == 0 ? c0[m] : c1[m];
-                    double I[C];
-#pragma unroll
-                    for (int k = 0; k < C; ++k) I[k] = (double)image[k * P + g];
+                if (rad <= R - 1) {
+                    const int pi = threadIdx.x + m * T;
+                    const int ly = pi / LXH, j = pi - ly * LXH;
+                    const int gx = x0 + 2 * j + (ly & 1) + e, gy = y0 + ly;
                     const double wd = sel4d(a.rc.wd, node_class(gx, gy, W, H));
                     double r[N];
                     double rmax = -1e300;
@@ -214,16 +298,16 @@ __global__ __launch_bounds__(kBlock) void k_cycle(CycleArgs a) {
                     for (int i = 0; i < N; ++i) {
                         double ci = 0.0;
 #pragma unroll
-                        for (int k = 0; k < C; ++k) ci += cs[i * C + k] * I[k];
-                        r[i] = wd * (a.rc.a * (double)lds[i * PL + li] +
-                                     a.rc.lambda * (2.0 * ci - cs2[i]));
+                        for (int k = 0; k < C; ++k)
+                            ci += cs[i * C + k] * (double)(e == 0 ? pv0[m][k] : pv1[m][k]);
+                        const double ui = (double)(e == 0 ? u0v[m][i] : u1v[m][i]);
+                        r[i] = wd * (a.rc.a * ui + a.rc.lambda * (2.0 * ci - cs2[i]));
                         rmax = fmax(rmax, r[i]);
                     }
-                    const bool interior = lx >= R && lx < R + TX && ly >= R && ly < R + TY;
 #pragma unroll
                     for (int i = 0; i < N; ++i) {
                         rv[i] = (float)(r[i] - rmax);
-                        if (a.store_rhs && interior) a.rhs[i * P + g] = rv[i];
+                        if (a.store_rhs && rad == 0) const_cast<float*>(rhsp[i])[gy * W + gx] = rv[i];
                     }
                 } else {
 #pragma unroll
@@ -231,7 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_cycle(CycleArgs a) {
                 }
             } else {
 #pragma unroll
-                for (int i = 0; i < N; ++i) rv[i] = in ? a.rhs[i * P + g] : 0.f;
+                for (int i = 0; i < N; ++i) rv[i] = e == 0 ? pv0[m][i] : pv1[m][i];
             }
 #pragma unroll
             for (int i = 0; i < N; ++i) {
@@ -251,12 +335,13 @@ __global__ __launch_bounds__(kBlock) void k_cycle(CycleArgs a) {
         if ((s & 1) == 0) {  // red: the first node of every pair
 #pragma unroll
             for (int m = 0; m < MP; ++m) {
-                if (rad0[m] > r) continue;
+                if ((pk[m] & 255) > r) continue;
+                const int cb = c0[m] + (((pk[m] >> 16) & 1) ? 1 - HL : HL);
                 float v[N];
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
                     const float* L = lds + i * PL;
-                    v[i] = rr0[m][i] + kh0[m] * (L[c1[m] - 1] + L[c1[m]]) +
+                    v[i] = rr0[m][i] + kh0[m] * (L[cb - 1] + L[cb]) +
                            kv0[m] * (L[c0[m] - RW] + L[c0[m] + RW]);
                 }
                 project_simplex<N>(v);
@@ -271,75 +356,88 @@ __global__ __launch_bounds__(kBlock) void k_cycle(CycleArgs a) {
         } else {  // black: the second node of every pair
 #pragma unroll
             for (int m = 0; m < MP; ++m) {
-                if (rad1[m] > r) continue;
+                if (((pk[m] >> 8) & 255) > r) continue;
+                const int cb = c0[m] + (((pk[m] >> 16) & 1) ? 1 - HL : HL);
                 float v[N];
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
                     const float* L = lds + i * PL;
                     v[i] = rr1[m][i] + kh1[m] * (L[c0[m]] + L[c0[m] + 1]) +
-                           kv1[m] * (L[c1[m] - RW] + L[c1[m] + RW]);
+                           kv1[m] * (L[cb - RW] + L[cb + RW]);
                 }
                 project_simplex<N>(v);
 #pragma unroll
-                for (int i = 0; i < N; ++i) lds[i * PL + c1[m]] = v[i];
+                for (int i = 0; i < N; ++i) lds[i * PL + cb] = v[i];
             }
         }
     }
     __syncthreads();
 
-    // ---- write the tile's interior (coalesced rows)
-    for (int idx = threadIdx.x; idx < TX * TY; idx += kBlock) {
+    // ---- the tile's interior: global stores (coalesced rows)
+    float uo[NO][N];
+#pragma unroll
+    for (int q = 0; q < NO; ++q) {
+        const int idx = threadIdx.x + q * T;
         const int oy = idx / TX, ox = idx - oy * TX;
         const int gx = x0 + R + ox, gy = y0 + R + oy;
-        if (gx >= W || gy >= H) continue;
         const int lx = R + ox, ly = R + oy;
         const int li = ly * RW + (lx & 1) * HL + (lx >> 1);
-        const int64_t g = (int64_t)gy * W + gx;
+        const bool o = gx < W && gy < H;
+        const int g = o ? gy * W + gx : 0;
 #pragma unroll
-        for (int i = 0; i < N; ++i) dst[i * P + g] = lds[i * PL + li];
+        for (int i = 0; i < N; ++i) {
+            uo[q][i] = lds[i * PL + li];
+            if (o) dstp[i][g] = uo[q][i];
+        }
     }
     if (!RESID) return;
 
     // ---- per-tile residual and colour-mean partials of the output
     const int row = a.cycle & 1;
-    const float bm = block_max(res, red);
+    const float bm = block_max_t<T>(res, red);
     if (threadIdx.x == 0) a.res_part[row * a.part_stride + tile] = bm;
     if (!a.cm) return;
     float acc[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) acc[q] = 0.f;
-    for (int idx = threadIdx.x; idx < TX * TY; idx += kBlock) {
-        const int oy = idx / TX, ox = idx - oy * TX;
-        const int gx = x0 + R + ox, gy = y0 + R + oy;
-        if (gx >= W || gy >= H) continue;
-        const int lx = R + ox, ly = R + oy;
-        const int li = ly * RW + (lx & 1) * HL + (lx >> 1);
-        const int64_t g = (int64_t)gy * W + gx;
-        const float w = (float)mass_w(node_class(gx, gy, W, H));
-        float I[C];
 #pragma unroll
-        for (int k = 0; k < C; ++k) I[k] = image[k * P + g];
+    for (int q = 0; q < NO; ++q) {
+        const int idx = threadIdx.x + q * T;
+        const int oy = idx / TX, ox = idx - oy * TX;
+        const float w = on[q] ? (float)mass_w(node_class(x0 + R + ox, y0 + R + oy, W, H)) : 0.f;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            const float wu = w * lds[i * PL + li];
+            const float wu = w * uo[q][i];
             acc[N * C + i] += wu;
 #pragma unroll
-            for (int k = 0; k < C; ++k) acc[i * C + k] += wu * I[k];
+            for (int k = 0; k < C; ++k) acc[i * C + k] += wu * Io[q][k];
         }
 #pragma unroll
-        for (int k = 0; k < C; ++k) acc[N * C + N + k] += w * I[k];
+        for (int k = 0; k < C; ++k) acc[N * C + N + k] += w * Io[q][k];
         acc[N * C + N + C] += w;
     }
-    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    // block sum in a fixed order: QCH rows at a time, every thread's partials
+    // into padded LDS rows (the staging area is free now); each wave adds 64
+    // entries of a row in float64, then M threads add the wave sums
 #pragma unroll
-    for (int q = 0; q < M; ++q) {
-        const double v = wave_sum((double)acc[q]);
-        if (lane == 0) shd[wid][q] = v;
+    for (int q0 = 0; q0 < M; q0 += QCH) {
+#pragma unroll
+        for (int q = 0; q < QCH; ++q)
+            if (q0 + q < M) lds[q * (T + 1) + threadIdx.x] = acc[q0 + q];
+        __syncthreads();
+        for (int t = threadIdx.x; t < QCH * PARTS; t += T) {
+            const int q = t / PARTS, h = t - q * PARTS;
+            if (q0 + q >= M) continue;
+            const float* rowp = lds + q * (T + 1) + h * kWave;
+            double v = 0.0;
+            for (int k = 0; k < kWave; ++k) v += (double)rowp[k];
+            part[q0 + q][h] = v;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     if (threadIdx.x < M) {
         double t = 0.0;
-        for (int w = 0; w < kBlock / kWave; ++w) t += shd[w][threadIdx.x];
+        for (int h = 0; h < PARTS; ++h) t += part[threadIdx.x][h];
         a.cm_part[((int64_t)row * M + threadIdx.x) * a.part_stride + tile] = t;
     }
 }
@@ -416,12 +514,9 @@ int cycle_launches(int sweeps);
 
 template <int N, int C, int K, bool FIRST, bool RESID>
 hipError_t run_cycle(CycleArgs a, hipStream_t s) {
-    constexpr int R = 2 * K + (RESID ? 1 : 0);
-    constexpr int HL = (kTX + 2 * R) / 2 + 1;
-    constexpr int lds = N * (cycle_ty(N) + 2 * R) * 2 * HL * 4;
-    static_assert(N * (cycle_ty(N) + 2 * (2 * K + 1)) * 2 * ((kTX + 2 * (2 * K + 1)) / 2 + 1) * 4 <= 65536,
-                  "tile does not fit in 64 KiB of LDS");
-    hipLaunchKernelGGL((k_cycle<N, C, K, FIRST, RESID>), dim3(a.tiles_per_xcd * kXcd), dim3(kBlock),
+    constexpr int lds = cycle_lds_bytes<N, K, RESID>();
+    static_assert(lds <= 65536, "tile does not fit in 64 KiB of LDS");
+    hipLaunchKernelGGL((k_cycle<N, C, K, FIRST, RESID>), dim3(a.tiles_per_xcd * kXcd), dim3(kCycT),
                        lds, s, a);
     return hipGetLastError();
 }

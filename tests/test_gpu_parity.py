@@ -230,3 +230,21 @@ def test_every_step_inside_a_pixel_unit_solve(fixed):
         c_prev = c_used
     c_ref, _ = orc.colour_means(P, img, ck[-1], c_prev)
     assert np.abs(host(c) - c_ref).max() < 1e-6
+
+
+@pytest.mark.parametrize("sweeps", [1, 2, 3])
+def test_reported_residual_is_the_natural_residual(sweeps):
+    """An unconverged fixed cycle: the residual the kernels report must be the
+    natural residual of the field they return (tiles away from the image
+    edge included)."""
+    w = synth.pixel_twin(synth.VORONOI1024, 150)
+    img, u0, _ = w.make(8)
+    p = gpu_problem(w, max_cycles=1, nu_pre=1, nu_post=sweeps - 1, flags=acseg.FLAG_FIXED_CYCLES)
+    u_g, c_g, st = acseg.step(p, cuda(img), cuda(u0))
+    ug = host(u_g)
+    P = orc_params(w)
+    c_ref, _ = orc.colour_means(P, img, u0)
+    b = orc.rhs(P, img, u0, c_ref)
+    rho = orc.residual(P, b, ug)
+    assert rho > 1e-3  # genuinely unconverged
+    assert abs(st["final_residual"] - rho) <= 1e-5 * max(1.0, rho) + 2e-6, (st["final_residual"], rho)
