@@ -158,10 +158,22 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int x0 = tx * TX - R, y0 = ty * TY - R;  // LDS origin; x0 + y0 is even
 
-    // ---- one burst of global loads: u of the owned pairs (both nodes), their
-    //      image (first launch) or stored right-hand side, and the image of
-    //      the owned output nodes for the colour-mean partials
-    float u0v[MP][N], u1v[MP][N];
+    // ---- one burst of global loads: u of the staged region in row order
+    //      (coalesced), the image (first launch) or stored right-hand side of
+    //      the owned pairs, and the image of the owned output nodes for the
+    //      colour-mean partials
+    constexpr int NS = (LX * LY + T - 1) / T;
+    float ust[NS][N];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const int idx = threadIdx.x + q * T;
+        const int ly = idx / LX, lx = idx - ly * LX;
+        const int gx = x0 + lx, gy = y0 + ly;
+        const bool in = idx < LX * LY && gx >= 0 && gx < W && gy >= 0 && gy < H;
+        const int g = in ? gy * W + gx : 0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) ust[q][i] = in ? srcp[i][g] : 0.f;
+    }
     constexpr int NV = FIRST ? C : N;
     float pv0[MP][NV], pv1[MP][NV];
     int c0[MP];      // LDS slot of the red node; the black one follows from it
@@ -183,10 +195,8 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
             const int dy = max(max(R - ly, ly - (R + TY - 1)), 0);
             const int rad = in ? max(dx, dy) : kOut;
             const bool need = rad <= R - 1;  // some half-sweep updates this node
-            const int g = in ? gy * W + gx : 0;
-            float uv[N], v[NV];
-#pragma unroll
-            for (int i = 0; i < N; ++i) uv[i] = in ? srcp[i][g] : 0.f;
+            const int g = need ? gy * W + gx : 0;
+            float v[NV];
 #pragma unroll
             for (int q = 0; q < NV; ++q) v[q] = need ? (FIRST ? imgp[q][g] : rhsp[q][g]) : 0.f;
             float kh = 0.f, kv = 0.f;
@@ -196,10 +206,6 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
                 kv = kap * edge_w_v(gx, W);
             }
             packed |= rad << (8 * e);
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                if (e == 0) u0v[m][i] = uv[i]; else u1v[m][i] = uv[i];
-            }
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
                 if (e == 0) pv0[m][q] = v[q]; else pv1[m][q] = v[q];
@@ -214,13 +220,6 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
         }
         pk[m] = packed;
     }
-    // the x = 0 column of odd rows is not part of any pair
-    float us[N];
-    const int sly = 2 * threadIdx.x + 1;
-    const bool sin = threadIdx.x < LY / 2 && x0 >= 0 && x0 < W && y0 + sly >= 0 && y0 + sly < H;
-    const int sg = sin ? (y0 + sly) * W + x0 : 0;
-#pragma unroll
-    for (int i = 0; i < N; ++i) us[i] = sin ? srcp[i][sg] : 0.f;
     float Io[NO][C];
     bool on[NO];
     if (RESID) {
@@ -260,20 +259,15 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
 
     // ---- u into LDS
 #pragma unroll
-    for (int m = 0; m < MP; ++m) {
-        if (threadIdx.x + m * T >= NP) continue;
-        const int cb = c0[m] + (((pk[m] >> 16) & 1) ? 1 - HL : HL);
+    for (int q = 0; q < NS; ++q) {
+        const int idx = threadIdx.x + q * T;
+        if (idx >= LX * LY) continue;
+        const int ly = idx / LX, lx = idx - ly * LX;
+        const int li = ly * RW + (lx & 1) * HL + (lx >> 1);
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            lds[i * PL + c0[m]] = u0v[m][i];
-            lds[i * PL + cb] = u1v[m][i];
-        }
+        for (int i = 0; i < N; ++i) lds[i * PL + li] = ust[q][i];
     }
-    if (threadIdx.x < LY / 2) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) lds[i * PL + sly * RW] = us[i];  // x = 0: even half, slot 0
-    }
-    if (FIRST) __syncthreads();  // the means
+    __syncthreads();  // u staged, means known
 
     // ---- right-hand side of the owned nodes (registers)
     float rr0[MP][N], rr1[MP][N];
@@ -300,7 +294,7 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
 #pragma unroll
                         for (int k = 0; k < C; ++k)
                             ci += cs[i * C + k] * (double)(e == 0 ? pv0[m][k] : pv1[m][k]);
-                        const double ui = (double)(e == 0 ? u0v[m][i] : u1v[m][i]);
+                        const double ui = (double)lds[i * PL + (e == 0 ? c0[m] : c0[m] + (((pk[m] >> 16) & 1) ? 1 - HL : HL))];
                         r[i] = wd * (a.rc.a * ui + a.rc.lambda * (2.0 * ci - cs2[i]));
                         rmax = fmax(rmax, r[i]);
                     }
