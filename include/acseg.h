@@ -86,10 +86,13 @@ typedef int32_t acseg_status;
  *   steps   number of time steps for acseg_solve; >= 0
  *   levels  lattice levels of the multigrid hierarchy including the finest:
  *           1 = Gauss-Seidel only; 0 = automatic (halve the sides, rounding
- *           up, while the longer side exceeds 15 and the shorter is >= 3)
+ *           up, while the longer side exceeds 15 and the shorter is >= 3);
+ *           at most the automatic count (ACSEG_ERR_INVALID_ARG otherwise)
  *   nu_pre, nu_post  smoothing sweeps before / after the coarse correction
  *           (multigrid) -- with levels == 1, nu_pre + nu_post red-black
- *           sweeps form one cycle; each >= 0, sum >= 1
+ *           sweeps form one cycle; each >= 0, sum >= 1.  With two or more
+ *           levels both must be >= 1 (ACSEG_ERR_UNSUPPORTED otherwise); the
+ *           coarse levels use the same counts and the coarsest level 8 sweeps
  *   max_cycles  cycle budget per time step; >= 1
  *   tol     natural-residual tolerance (max norm, absolute); >= 0
  */
@@ -145,6 +148,21 @@ acseg_status acseg_workspace_size(const acseg_problem *p, size_t *bytes);
  */
 acseg_status acseg_project_simplex(acseg_ctx *ctx, int32_t N, int64_t count, const float *y,
                                    float *x, void *stream);
+
+/*
+ * Transfer operators of the multigrid hierarchy (Section "Multigrid
+ * Solution"): the coarse lattice of a Wf x Hf lattice has ceil(Wf/2) x
+ * ceil(Hf/2) nodes, coarse node (X, Y) sitting on fine node (2X, 2Y).  The
+ * prolongation P interpolates the coarse P1 function at the fine nodes (every
+ * cell split along its (x,y)-(x+1,y+1) diagonal: a fine node halfway between
+ * two coarse nodes along a lattice line or that diagonal takes their mean); a
+ * fine node past the last coarse row or column (even side) takes the value of
+ * that row or column.  direction 0: dst[planes][Hf][Wf] = P src, with src
+ * [planes][Hc][Wc]; direction 1: dst[planes][Hc][Wc] = P^T src, with src
+ * [planes][Hf][Wf].  src and dst must not overlap.  Wf, Hf >= 2.
+ */
+acseg_status acseg_transfer(acseg_ctx *ctx, int32_t direction, int32_t planes, int32_t Wf,
+                            int32_t Hf, const float *src, float *dst, void *stream);
 
 /*
  * Colour means of eq. VV_fidelity with the lumped mass (one node per pixel):

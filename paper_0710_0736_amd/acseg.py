@@ -107,6 +107,8 @@ def lib():
         L.acseg_destroy.argtypes = [vp]
         L.acseg_workspace_size.argtypes = [pp, ctypes.POINTER(sz)]
         L.acseg_project_simplex.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp]
+        L.acseg_transfer.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, vp, vp, vp]
         L.acseg_colour_means.argtypes = [vp, pp, vp, vp, vp, vp, sp, vp, sz, vp]
         L.acseg_step.argtypes = [vp, pp, vp, vp, vp, vp, vp, sp, vp, sz, vp]
         L.acseg_solve.argtypes = [vp, pp, vp, vp, vp, vp, sp, vp, sz, vp]
@@ -187,6 +189,26 @@ def project_simplex(y: torch.Tensor) -> torch.Tensor:
     _check(lib().acseg_project_simplex(ctx(y.device.index), N, count, _ptr(y), _ptr(x), _stream()),
            "acseg_project_simplex")
     return x
+
+
+def prolong(vc: torch.Tensor, Wf: int, Hf: int) -> torch.Tensor:
+    """P1 prolongation of [planes][ceil(Hf/2)][ceil(Wf/2)] onto the Wf x Hf lattice."""
+    planes = vc.shape[0]
+    _need(vc, (planes, (Hf + 1) // 2, (Wf + 1) // 2), name="vc")
+    vf = torch.empty((planes, Hf, Wf), dtype=torch.float32, device=vc.device)
+    _check(lib().acseg_transfer(ctx(vc.device.index), 0, planes, Wf, Hf, _ptr(vc), _ptr(vf),
+                                _stream()), "acseg_transfer")
+    return vf
+
+
+def restrict(vf: torch.Tensor) -> torch.Tensor:
+    """Transpose of ``prolong``: [planes][Hf][Wf] -> [planes][ceil(Hf/2)][ceil(Wf/2)]."""
+    planes, Hf, Wf = vf.shape
+    _need(vf, (planes, Hf, Wf), name="vf")
+    vc = torch.empty((planes, (Hf + 1) // 2, (Wf + 1) // 2), dtype=torch.float32, device=vf.device)
+    _check(lib().acseg_transfer(ctx(vf.device.index), 1, planes, Wf, Hf, _ptr(vf), _ptr(vc),
+                                _stream()), "acseg_transfer")
+    return vc
 
 
 def colour_means(p: Problem, image: torch.Tensor, u: torch.Tensor, c_prev=None):

@@ -67,15 +67,78 @@ acseg_status validate(const acseg_problem* p, bool need_steps) {
     if (p->nu_pre < 0 || p->nu_post < 0 || p->nu_pre + p->nu_post < 1) return ACSEG_ERR_INVALID_ARG;
     if (p->max_cycles < 1 || p->levels < 0) return ACSEG_ERR_INVALID_ARG;
     if (p->levels > auto_levels(p->W, p->H)) return ACSEG_ERR_INVALID_ARG;
-    if (p->levels != 0 && p->levels != 1) return ACSEG_ERR_UNSUPPORTED;
+    // a multigrid cycle opens with pre-smoothing (right-hand side, convergence
+    // check) and closes with post-smoothing (residual)
+    const int L = p->levels == 0 ? auto_levels(p->W, p->H) : p->levels;
+    if (L >= 2 && (p->nu_pre < 1 || p->nu_post < 1)) return ACSEG_ERR_UNSUPPORTED;
     if ((p->flags & ~(ACSEG_FLAG_STORE_CHECKPOINTS | ACSEG_FLAG_FIXED_CYCLES)) != 0u)
         return ACSEG_ERR_INVALID_ARG;
     return ACSEG_OK;
 }
 
+// Multigrid hierarchy of a problem: level l has side ceil(side_{l-1} / 2) and
+// spacing 2^l h.  Levels tail..L-1 (both sides <= kTailSide) run in the LDS
+// tail kernel; tail == L when none does.
+struct MgPlan {
+    int L = 1, tail = 1;
+    int W[32], H[32];
+    LevelCoef coef[32];
+};
+
+LevelCoef level_coef(const acseg_problem* p, int l) {
+    static const double w[4] = {1.0, 0.5, 1.0 / 3.0, 1.0 / 6.0};  // lumped mass / (2^l h)^2
+    static const double a[4] = {4.0, 2.0, 1.0, 1.0};              // stiffness diagonal
+    LevelCoef c;
+    memset(&c, 0, sizeof(c));
+    const double e2 = p->eps / (p->h * p->h);
+    const double s = ldexp(1.0, 2 * l);  // (2^l)^2: mass in units of the finest h^2
+    for (int k = 0; k < 4; ++k) {
+        const double D = s * w[k] / p->tau + e2 * a[k];
+        c.kappa[k] = (float)(e2 / D);
+        c.inv_d[k] = (float)(1.0 / D);
+        c.d[k] = (float)D;
+    }
+    c.e2 = (float)e2;
+    return c;
+}
+
+size_t tail_lds_bytes(const MgPlan& m, int t0) {
+    size_t f = 0, big = 0;
+    for (int l = t0; l < m.L; ++l) {
+        const size_t n = (size_t)m.W[l] * m.H[l];
+        f += 2 * n;
+        big = std::max(big, n);
+    }
+    return (f + big) * sizeof(float);
+}
+
+MgPlan plan_of(const acseg_problem* p) {
+    MgPlan m;
+    m.L = p->levels == 0 ? auto_levels(p->W, p->H) : p->levels;
+    m.W[0] = p->W;
+    m.H[0] = p->H;
+    for (int l = 0; l < m.L; ++l) {
+        if (l > 0) {
+            m.W[l] = coarse_side(m.W[l - 1]);
+            m.H[l] = coarse_side(m.H[l - 1]);
+        }
+        m.coef[l] = level_coef(p, l);
+    }
+    m.tail = m.L;
+    for (int l = 1; l < m.L; ++l)
+        if (m.W[l] <= kTailSide && m.H[l] <= kTailSide && m.L - l <= kMaxTail &&
+            tail_lds_bytes(m, l) <= 65536) {
+            m.tail = l;
+            break;
+        }
+    return m;
+}
+
 // Workspace carve-up (offsets in bytes from ws).
 struct Layout {
     size_t ubuf = 0, rhs = 0, part_f = 0, part_cm = 0, part_d = 0, c64 = 0, tot = 0, ctl = 0;
+    size_t mg_gt = 0, mg_part = 0;
+    size_t mg_v[32] = {}, mg_r[32] = {}, mg_res[32] = {};  // coarse levels 1..L-1
     size_t total = 0;
     int part_stride = 0;
 };
@@ -100,6 +163,17 @@ Layout layout_of(const acseg_problem* p) {
     L.c64 = take(sizeof(double) * 3 * kNC);          // two alternating sets + a caller's c_prev
     L.tot = take(sizeof(double) * 2 * kCmeansMaxM);  // reduced colour-mean sums, alternating
     L.ctl = take(sizeof(Ctl));
+    const MgPlan m = plan_of(p);
+    if (m.L >= 2) {
+        L.mg_gt = take(sizeof(float) * p->N * n);
+        L.mg_part = take(sizeof(double) * 2 * kMgBlocks);
+        for (int l = 1; l < m.L; ++l) {
+            const size_t nl = (size_t)p->N * m.W[l] * m.H[l];
+            L.mg_v[l] = take(sizeof(float) * nl);
+            L.mg_r[l] = take(sizeof(float) * nl);
+            L.mg_res[l] = take(sizeof(float) * nl);
+        }
+    }
     L.total = off;
     return L;
 }
@@ -172,6 +246,117 @@ hipError_t timed(acseg_ctx* ctx, int fam, hipStream_t s, F&& launch) {
     return e;
 }
 
+// The truncated multigrid correction of the iterate left by `launch`
+// smoothing launches of the current step (in place).
+acseg_status enqueue_correction(acseg_ctx* ctx, const acseg_problem* p, const MgPlan& m,
+                                const Layout& L, void* ws, Bufs bufs, int slot, bool fixed,
+                                int launch, hipStream_t s) {
+    const int N = p->N;
+    Ctl* ctl = at<Ctl>(ws, L.ctl);
+    MgArgs f{};
+    f.bufs = bufs;
+    f.ctl = ctl;
+    f.rhs = at<float>(ws, L.rhs);
+    f.gt = at<float>(ws, L.mg_gt);
+    f.v1 = at<float>(ws, L.mg_v[1]);
+    f.part = at<double>(ws, L.mg_part);
+    f.coef = m.coef[0];
+    f.W = m.W[0];
+    f.H = m.H[0];
+    f.Wc = m.W[1];
+    f.Hc = m.H[1];
+    f.slot = slot;
+    f.fixed = fixed ? 1 : 0;
+    f.launch = launch;
+    f.nblocks = mg_blocks(f.W, f.H);
+    auto coarse = [&](int op, int l, const float* src, float* dst, const float* aux, float* res,
+                      int colour, int zero) {
+        CoarseArgs a{};
+        a.ctl = ctl;
+        a.src = src;
+        a.dst = dst;
+        a.aux = aux;
+        a.res = res;
+        a.coef = m.coef[l];
+        a.W = m.W[l];
+        a.H = m.H[l];
+        a.Wf = m.W[l - 1];
+        a.Hf = m.H[l - 1];
+        a.colour = colour;
+        a.zero = zero;
+        a.slot = slot;
+        a.fixed = f.fixed;
+        return timed(ctx, kFamMg, s, [&] { return launch_mg_coarse(N, op, a, s); });
+    };
+    auto sweeps = [&](int l, int count, bool zero) -> hipError_t {
+        float* v = at<float>(ws, L.mg_v[l]);
+        const float* r = at<float>(ws, L.mg_r[l]);
+        for (int k = 0; k < count; ++k) {
+            hipError_t e = coarse(kCoarseHalf, l, r, v, nullptr, nullptr, 0, zero && k == 0);
+            if (e == hipSuccess) e = coarse(kCoarseHalf, l, r, v, nullptr, nullptr, 1, 0);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    auto fine = [&](int op) { return timed(ctx, kFamMg, s, [&] { return launch_mg_fine(N, op, f, s); }); };
+
+    // truncated defect, restricted to level 1
+    ACSEG_TRY(fine(kMgDefect));
+    ACSEG_TRY(coarse(kCoarseRestrict, 1, f.gt, at<float>(ws, L.mg_r[1]), nullptr, nullptr, 0, 0));
+    // down: levels 1 .. tail-1 in global memory
+    const int last_global = std::min(m.tail, m.L) - 1;  // deepest level solved by global kernels
+    for (int l = 1; l <= last_global; ++l) {
+        const bool coarsest = l == m.L - 1;
+        ACSEG_TRY(sweeps(l, coarsest ? kCoarseSweeps : p->nu_pre, true));
+        if (coarsest) break;
+        ACSEG_TRY(coarse(kCoarseResid, l, at<float>(ws, L.mg_r[l]), nullptr, at<float>(ws, L.mg_v[l]),
+                         at<float>(ws, L.mg_res[l]), 0, 0));
+        ACSEG_TRY(coarse(kCoarseRestrict, l + 1, at<float>(ws, L.mg_res[l]),
+                         at<float>(ws, L.mg_r[l + 1]), nullptr, nullptr, 0, 0));
+    }
+    if (m.tail < m.L) {
+        TailArgs t{};
+        t.ctl = ctl;
+        t.r_in = at<float>(ws, L.mg_r[m.tail]);
+        t.v_out = at<float>(ws, L.mg_v[m.tail]);
+        t.nl = m.L - m.tail;
+        int off = 0;
+        int big = 0;
+        for (int l = 0; l < t.nl; ++l) {
+            const int g = m.tail + l;
+            t.lv[l].W = m.W[g];
+            t.lv[l].H = m.H[g];
+            t.lv[l].off_v = off;
+            off += m.W[g] * m.H[g];
+            t.lv[l].off_r = off;
+            off += m.W[g] * m.H[g];
+            big = std::max(big, m.W[g] * m.H[g]);
+            t.coef[l] = m.coef[g];
+        }
+        t.off_res = off;
+        t.nu_pre = p->nu_pre;
+        t.nu_post = p->nu_post;
+        t.coarse_sweeps = kCoarseSweeps;
+        t.slot = slot;
+        t.fixed = f.fixed;
+        const size_t bytes = (size_t)(off + big) * sizeof(float);
+        ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_coarse_tail(N, t, bytes, s); }));
+    }
+    // up: prolongate and post-smooth levels tail-1 .. 1
+    for (int l = std::min(m.tail, m.L - 1) - 1; l >= 1; --l) {
+        if (l == m.L - 1) continue;
+        ACSEG_TRY(coarse(kCoarseProlongAdd, l + 1, at<float>(ws, L.mg_v[l + 1]), at<float>(ws, L.mg_v[l]),
+                         nullptr, nullptr, 0, 0));
+        ACSEG_TRY(sweeps(l, p->nu_post, false));
+    }
+    // direction, line search, update
+    ACSEG_TRY(fine(kMgDir));
+    ACSEG_TRY(fine(kMgWhw));
+    ACSEG_TRY(fine(kMgAlpha));
+    ACSEG_TRY(fine(kMgUpdate));
+    return ACSEG_OK;
+}
+
 // Enqueue time step n on the iterate bufs[ctl->cur] whose reduced colour-mean
 // sums are in `tot`: max_cycles smoothing cycles (after convergence they exit
 // at once unless the schedule is fixed), then the step's end, which leaves the
@@ -207,14 +392,36 @@ acseg_status enqueue_step(acseg_ctx* ctx, const acseg_problem* p, const Coefs& c
     c.coef = cf.fine;
     c.rc = cf.rhs;
     c.tol = (float)p->tol;
+    const MgPlan m = plan_of(p);
+    const int lpre = cycle_launches(p->nu_pre), lpost = cycle_launches(p->nu_post);
+    const int lpc = m.L >= 2 ? lpre + lpost : cycle_launches(sweeps);
+    if (m.L >= 2) c.store_rhs = true;  // the defect reads it
     for (int k = 0; k < p->max_cycles; ++k) {
         c.cycle = k;
         c.cm = !fixed || k == p->max_cycles - 1;
+        c.launch0 = k * lpc;
+        c.step_first = k == 0;
+        c.opens = true;
+        if (m.L == 1) {
+            c.closes = true;
+            ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] { return launch_cycle(c, s); }));
+            continue;
+        }
+        c.sweeps = p->nu_pre;
+        c.closes = false;
+        ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] { return launch_cycle(c, s); }));
+        const acseg_status v = enqueue_correction(ctx, p, m, L, ws, bufs, c.slot, fixed, k * lpc + lpre, s);
+        if (v != ACSEG_OK) return v;
+        c.sweeps = p->nu_post;
+        c.launch0 = k * lpc + lpre;
+        c.step_first = false;
+        c.opens = false;
+        c.closes = true;
         ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] { return launch_cycle(c, s); }));
     }
     ACSEG_TRY(timed(ctx, kFamOther, s, [&] {
         return launch_step_end(p->N, p->C, p->W, p->H, ctl, c.res_part, c.cm_part, L.part_stride,
-                               p->max_cycles, sweeps, c.slot, (float)p->tol, tot_next, s);
+                               p->max_cycles, lpc, c.slot, (float)p->tol, tot_next, s);
     }));
     return ACSEG_OK;
 }
@@ -318,6 +525,14 @@ acseg_status acseg_project_simplex(acseg_ctx* ctx, int32_t N, int64_t count, con
     if (!ctx || count < 0 || (count > 0 && (!y || !x))) return ACSEG_ERR_INVALID_ARG;
     if (N < ACSEG_MIN_N || N > ACSEG_MAX_N) return ACSEG_ERR_UNSUPPORTED;
     return hip_status(launch_project(N, count, y, x, (hipStream_t)stream));
+}
+
+acseg_status acseg_transfer(acseg_ctx* ctx, int32_t direction, int32_t planes, int32_t Wf,
+                            int32_t Hf, const float* src, float* dst, void* stream) {
+    if (!ctx || (direction != 0 && direction != 1) || planes < 1 || Wf < 2 || Hf < 2 || !src ||
+        !dst || (int64_t)Wf * Hf > ((int64_t)1 << 31))
+        return ACSEG_ERR_INVALID_ARG;
+    return hip_status(launch_transfer(planes, direction, src, dst, Wf, Hf, (hipStream_t)stream));
 }
 
 acseg_status acseg_colour_means(acseg_ctx* ctx, const acseg_problem* p, const float* image,

@@ -42,13 +42,27 @@ struct LevelCoef {
     float pad[3];
 };
 
+// Uniform values forced into scalar registers: a per-lane select among them
+// is then a register select, not a select of kernel-argument addresses
+// followed by a dependent load.
+__device__ __forceinline__ float uniform_f(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ float sel4(const float (&a)[4], int k) {
-    // select without dynamic indexing of a kernel-argument array
-    return k == 0 ? a[0] : (k == 1 ? a[1] : (k == 2 ? a[2] : a[3]));
+    const float a0 = uniform_f(a[0]), a1 = uniform_f(a[1]), a2 = uniform_f(a[2]), a3 = uniform_f(a[3]);
+    return k == 0 ? a0 : (k == 1 ? a1 : (k == 2 ? a2 : a3));
 }
 
 __device__ __forceinline__ double sel4d(const double (&a)[4], int k) {
-    return k == 0 ? a[0] : (k == 1 ? a[1] : (k == 2 ? a[2] : a[3]));
+    const double a0 = uniform_d(a[0]), a1 = uniform_d(a[1]), a2 = uniform_d(a[2]), a3 = uniform_d(a[3]);
+    return k == 0 ? a0 : (k == 1 ? a1 : (k == 2 ? a2 : a3));
 }
 
 // Horizontal / vertical edge weights of node (x,y): 1/2 along the boundary line.

@@ -97,6 +97,10 @@ hipError_t launch_cmeans_finish(int N, int C, int W, int H, const double* partia
 struct CycleLaunch {
     int N, C, W, H;
     int sweeps, cycle, slot;
+    int launch0;              // launch index (within the step) of this call's first launch
+    bool opens;               // this call opens the cycle (convergence check)
+    bool closes;              // this call closes the cycle (residual, colour-mean partials)
+    bool step_first;          // this call's first launch opens the step (builds the rhs)
     bool fixed, store_rhs, cm;
     Bufs bufs;
     Ctl* ctl;
@@ -121,13 +125,84 @@ hipError_t launch_cycle(const CycleLaunch& c, hipStream_t s);
 // tot_next, the step's residual and cycle count, the buffer holding the
 // iterate, statistics; re-arms control slot slot ^ 1.
 hipError_t launch_step_end(int N, int C, int W, int H, Ctl* ctl, const float* res_part,
-                           const double* cm_part, int part_stride, int max_cycles, int sweeps,
-                           int slot, float tol, double* tot_next, hipStream_t s);
+                           const double* cm_part, int part_stride, int max_cycles,
+                           int launches_per_cycle, int slot, float tol, double* tot_next,
+                           hipStream_t s);
 
 // One workgroup: colour means from reduced sums tot (empty phases keep
 // c_prev64) into c64 / c_out, flags in ctl.
 hipError_t launch_means_from_tot(int N, int C, const double* tot, const double* c_prev64,
                                  Ctl* ctl, double* c64, float* c_out, hipStream_t s);
+
+// ---- launchers (kernels_mg.hip): the truncated multigrid correction -------
+
+constexpr int kMgBlocks = 1024;   // most workgroups of a fine-level pass (partials per dot)
+constexpr int kTailSide = 64;     // levels with both sides <= this run in the LDS tail
+constexpr int kMaxTail = 8;       // levels in the LDS tail
+constexpr int kCoarseSweeps = 8;  // red-black sweeps on the coarsest level
+
+enum MgOp { kMgDefect = 0, kMgDir, kMgWhw, kMgAlpha, kMgUpdate };
+
+// Fine-level passes.  The iterate is bufs[iterate_buf(ctl->cur, launch)] and
+// is updated in place; gt holds the truncated defect, then the direction.
+struct MgArgs {
+    Bufs bufs;
+    Ctl* ctl;
+    const float* rhs;   // stored right-hand side [N][H][W]
+    float* gt;          // [N][H][W]
+    const float* v1;    // correction on level 1 [N][Hc][Wc]
+    double* part;       // [2][kMgBlocks]: <g~,w> and <w,Hw> partials
+    LevelCoef coef;     // finest level
+    int W, H, Wc, Hc;
+    int slot, fixed, launch, nblocks;
+};
+
+enum CoarseOp { kCoarseRestrict = 0, kCoarseProlongAdd, kCoarseHalf, kCoarseResid };
+
+// One coarse-level pass on level (W, H); (Wf, Hf) is the next finer level.
+//   restrict:     dst[W x H] = P^T src[Wf x Hf]
+//   prolong_add:  dst[Wf x Hf] += P src[W x H]
+//   half:         red (colour 0) / black half-sweep of H v = src on dst = v
+//   resid:        res = src - H aux
+struct CoarseArgs {
+    const Ctl* ctl;
+    const float* src;
+    float* dst;
+    const float* aux;
+    float* res;
+    LevelCoef coef;
+    int W, H, Wf, Hf;
+    int colour, zero;
+    int slot, fixed;
+};
+
+struct TailLevel {
+    int W, H;
+    int off_v, off_r;  // float offsets in LDS
+};
+
+// V-cycle over the LDS-resident coarsest levels, one workgroup per component.
+struct TailArgs {
+    const Ctl* ctl;
+    const float* r_in;  // [N][lv[0].H][lv[0].W]
+    float* v_out;
+    TailLevel lv[kMaxTail];
+    LevelCoef coef[kMaxTail];
+    int nl, off_res;
+    int nu_pre, nu_post, coarse_sweeps;
+    int slot, fixed;
+};
+
+int mg_blocks(int W, int H);
+hipError_t launch_mg_fine(int N, int op, const MgArgs& a, hipStream_t s);
+hipError_t launch_mg_coarse(int N, int op, const CoarseArgs& a, hipStream_t s);
+hipError_t launch_coarse_tail(int N, const TailArgs& a, size_t lds_bytes, hipStream_t s);
+
+// Prolongation (dir 0: dst[planes][Hf][Wf] = P src) or restriction (dir 1:
+// dst[planes][Hc][Wc] = P^T src) between a Wf x Hf lattice and its coarse
+// lattice of ceil(Wf/2) x ceil(Hf/2) nodes.
+hipError_t launch_transfer(int planes, int dir, const float* src, float* dst, int Wf, int Hf,
+                           hipStream_t s);
 
 // Initialise a control block (cur = initial buffer index).
 hipError_t launch_ctl_init(Ctl* ctl, int cur, hipStream_t s);

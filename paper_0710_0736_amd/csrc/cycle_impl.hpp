@@ -114,6 +114,7 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
     __shared__ double cs[N * C];
     __shared__ double cs2[N];
     __shared__ double part[M][PARTS];
+    __shared__ double tsh[M + N * C];
     __shared__ int flag;
 
     Ctl* ctl = a.ctl;
@@ -172,7 +173,10 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
         const bool in = idx < LX * LY && gx >= 0 && gx < W && gy >= 0 && gy < H;
         const int g = in ? gy * W + gx : 0;
 #pragma unroll
-        for (int i = 0; i < N; ++i) ust[q][i] = in ? srcp[i][g] : 0.f;
+        for (int i = 0; i < N; ++i) {
+            const float t = srcp[i][g];
+            ust[q][i] = in ? t : 0.f;
+        }
     }
     constexpr int NV = FIRST ? C : N;
     float pv0[MP][NV], pv1[MP][NV];
@@ -196,9 +200,14 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
             const int rad = in ? max(dx, dy) : kOut;
             const bool need = rad <= R - 1;  // some half-sweep updates this node
             const int g = need ? gy * W + gx : 0;
+            // unconditional loads (index 0 is always valid): no branch between
+            // the loads of the burst
             float v[NV];
 #pragma unroll
-            for (int q = 0; q < NV; ++q) v[q] = need ? (FIRST ? imgp[q][g] : rhsp[q][g]) : 0.f;
+            for (int q = 0; q < NV; ++q) {
+                const float t = FIRST ? imgp[q][g] : rhsp[q][g];
+                v[q] = need ? t : 0.f;
+            }
             float kh = 0.f, kv = 0.f;
             if (in) {
                 const float kap = sel4(a.coef.kappa, node_class(gx, gy, W, H));
@@ -231,30 +240,21 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
             on[q] = a.cm && gx < W && gy < H;
             const int g = on[q] ? gy * W + gx : 0;
 #pragma unroll
-            for (int k = 0; k < C; ++k) Io[q][k] = on[q] ? imgp[k][g] : 0.f;
+            for (int k = 0; k < C; ++k) {
+                const float t = imgp[k][g];
+                Io[q][k] = on[q] ? t : 0.f;
+            }
         }
     }
 
-    if (FIRST && threadIdx.x == 0) {
-        // colour means of u^n from the reduced sums (identical in every block)
-        double c[N * C];
-        const int empty = finish_means<N, C>(a.tot, a.c_prev64, c);
-        for (int i = 0; i < N; ++i) {
-            double q = 0.0;
-            for (int k = 0; k < C; ++k) {
-                cs[i * C + k] = c[i * C + k];
-                q += c[i * C + k] * c[i * C + k];
-            }
-            cs2[i] = q;
-        }
-        if (blockIdx.x == 0) {
-            for (int q = 0; q < N * C; ++q) {
-                a.c64[q] = c[q];
-                if (a.c_out) a.c_out[q] = (float)c[q];
-            }
-            if (empty) ctl->empty_steps += 1;
-            if (a.tot[M - 1] > 0.0) ctl->nonfinite = 1;
-        }
+    // the colour-mean sums of u^n (and the previous means, for empty phases)
+    // join the burst: one value per thread of the first wave
+    constexpr int NT = M + N * C;
+    if (FIRST && threadIdx.x < NT) {
+        const int t = threadIdx.x;
+        const bool prev = t >= M;
+        const double* src = prev ? (a.c_prev64 ? a.c_prev64 : a.tot) : a.tot;
+        tsh[t] = src[prev ? t - M : t];
     }
 
     // ---- u into LDS
@@ -267,7 +267,41 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
 #pragma unroll
         for (int i = 0; i < N; ++i) lds[i * PL + li] = ust[q][i];
     }
-    __syncthreads();  // u staged, means known
+    __syncthreads();  // u and the sums staged
+    if (FIRST) {
+        // colour means of u^n (identical in every workgroup): lane i < N of
+        // the first wave finishes phase i
+        if (threadIdx.x < kWave) {
+            const int i = threadIdx.x;
+            bool empty = false;
+            if (i < N) {
+                const double area = tsh[N * C + N + C];
+                const double S = tsh[N * C + i];
+                const bool has_mass = S > 1e-12 * area;
+                empty = !has_mass;
+                double q2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < C; ++k) {
+                    const double c = has_mass ? tsh[i * C + k] / S
+                                              : (a.c_prev64 ? tsh[M + i * C + k]
+                                                            : tsh[N * C + N + k] / area);
+                    cs[i * C + k] = c;
+                    q2 += c * c;
+                    if (blockIdx.x == 0) {
+                        a.c64[i * C + k] = c;
+                        if (a.c_out) a.c_out[i * C + k] = (float)c;
+                    }
+                }
+                cs2[i] = q2;
+            }
+            const bool any_empty = __any(empty);
+            if (blockIdx.x == 0 && i == 0) {
+                if (any_empty) ctl->empty_steps += 1;
+                if (tsh[M - 1] > 0.0) ctl->nonfinite = 1;
+            }
+        }
+        __syncthreads();  // means known
+    }
 
     // ---- right-hand side of the owned nodes (registers)
     float rr0[MP][N], rr1[MP][N];
@@ -515,18 +549,24 @@ hipError_t run_cycle(CycleArgs a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// One cycle: launches of at most two sweeps; the step's first launch builds
-// the right-hand side, the cycle's last one closes the cycle.
+// What a run of smoothing launches is within its step and cycle.
+struct CycleRole {
+    bool step_first;  // the first launch opens the step: it builds the right-hand side
+    bool opens;       // the first launch opens the cycle: convergence check
+    bool closes;      // the last launch closes the cycle: residual and colour-mean partials
+};
+
+// `sweeps` sweeps in launches of at most two.
 template <int N, int C>
-hipError_t run_cycle_nc(int sweeps, CycleArgs a, bool step_first, hipStream_t s) {
+hipError_t run_cycle_nc(int sweeps, CycleArgs a, CycleRole role, hipStream_t s) {
     const int nl = cycle_launches(sweeps);
     const int base = a.launch;
     hipError_t e = hipSuccess;
     for (int k = 0; k < nl && e == hipSuccess; ++k) {
         const int kk = (k < nl - 1 || sweeps % 2 == 0) ? 2 : 1;
-        const bool last = k == nl - 1;
-        const bool first = step_first && k == 0;
-        a.first = k == 0;
+        const bool last = role.closes && k == nl - 1;
+        const bool first = role.step_first && k == 0;
+        a.first = role.opens && k == 0;
         a.launch = base + k;
         if (kk == 2) {
             if (first)
@@ -552,12 +592,12 @@ hipError_t run_step_end_nc(const StepEndArgs& a, hipStream_t s) {
 
 // Per-N entry points, each instantiated in its own translation unit.
 template <int N>
-hipError_t cycle_for_n(int C, int sweeps, const CycleArgs& a, bool step_first, hipStream_t s) {
+hipError_t cycle_for_n(int C, int sweeps, const CycleArgs& a, CycleRole role, hipStream_t s) {
     switch (C) {
-        case 1: return run_cycle_nc<N, 1>(sweeps, a, step_first, s);
-        case 2: return run_cycle_nc<N, 2>(sweeps, a, step_first, s);
-        case 3: return run_cycle_nc<N, 3>(sweeps, a, step_first, s);
-        case 4: return run_cycle_nc<N, 4>(sweeps, a, step_first, s);
+        case 1: return run_cycle_nc<N, 1>(sweeps, a, role, s);
+        case 2: return run_cycle_nc<N, 2>(sweeps, a, role, s);
+        case 3: return run_cycle_nc<N, 3>(sweeps, a, role, s);
+        case 4: return run_cycle_nc<N, 4>(sweeps, a, role, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -574,7 +614,7 @@ hipError_t step_end_for_n(int C, const StepEndArgs& a, hipStream_t s) {
 }
 
 #define ACSEG_CYCLE_EXTERN(n)                                                                   \
-    extern template hipError_t cycle_for_n<n>(int, int, const CycleArgs&, bool, hipStream_t); \
+    extern template hipError_t cycle_for_n<n>(int, int, const CycleArgs&, CycleRole, hipStream_t); \
     extern template hipError_t step_end_for_n<n>(int, const StepEndArgs&, hipStream_t);
 ACSEG_CYCLE_EXTERN(2)
 ACSEG_CYCLE_EXTERN(3)

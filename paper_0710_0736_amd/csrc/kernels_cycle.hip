@@ -29,7 +29,7 @@ hipError_t launch_cycle(const CycleLaunch& c, hipStream_t s) {
     a.tol = c.tol;
     a.slot = c.slot;
     a.cycle = c.cycle;
-    a.launch = c.cycle * cycle_launches(c.sweeps);
+    a.launch = c.launch0;
     a.fixed = c.fixed ? 1 : 0;
     a.store_rhs = c.store_rhs ? 1 : 0;
     a.cm = c.cm ? 1 : 0;
@@ -38,22 +38,23 @@ hipError_t launch_cycle(const CycleLaunch& c, hipStream_t s) {
     a.tiles_x = (c.W + kTX - 1) / kTX;
     a.ntiles = cycle_tiles(c.N, c.W, c.H);
     a.tiles_per_xcd = (a.ntiles + kXcd - 1) / kXcd;
-    const bool first = c.cycle == 0;
+    const CycleRole role{c.step_first, c.opens, c.closes};
     switch (c.N) {
-        case 2: return cycle_for_n<2>(c.C, c.sweeps, a, first, s);
-        case 3: return cycle_for_n<3>(c.C, c.sweeps, a, first, s);
-        case 4: return cycle_for_n<4>(c.C, c.sweeps, a, first, s);
-        case 5: return cycle_for_n<5>(c.C, c.sweeps, a, first, s);
-        case 6: return cycle_for_n<6>(c.C, c.sweeps, a, first, s);
-        case 7: return cycle_for_n<7>(c.C, c.sweeps, a, first, s);
-        case 8: return cycle_for_n<8>(c.C, c.sweeps, a, first, s);
+        case 2: return cycle_for_n<2>(c.C, c.sweeps, a, role, s);
+        case 3: return cycle_for_n<3>(c.C, c.sweeps, a, role, s);
+        case 4: return cycle_for_n<4>(c.C, c.sweeps, a, role, s);
+        case 5: return cycle_for_n<5>(c.C, c.sweeps, a, role, s);
+        case 6: return cycle_for_n<6>(c.C, c.sweeps, a, role, s);
+        case 7: return cycle_for_n<7>(c.C, c.sweeps, a, role, s);
+        case 8: return cycle_for_n<8>(c.C, c.sweeps, a, role, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_step_end(int N, int C, int W, int H, Ctl* ctl, const float* res_part,
-                           const double* cm_part, int part_stride, int max_cycles, int sweeps,
-                           int slot, float tol, double* tot_next, hipStream_t s) {
+                           const double* cm_part, int part_stride, int max_cycles,
+                           int launches_per_cycle, int slot, float tol, double* tot_next,
+                           hipStream_t s) {
     StepEndArgs a{};
     a.ctl = ctl;
     a.res_part = res_part;
@@ -62,7 +63,7 @@ hipError_t launch_step_end(int N, int C, int W, int H, Ctl* ctl, const float* re
     a.part_stride = part_stride;
     a.ntiles = cycle_tiles(N, W, H);
     a.max_cycles = max_cycles;
-    a.launches_per_cycle = cycle_launches(sweeps);
+    a.launches_per_cycle = launches_per_cycle;
     a.slot = slot;
     a.tol = tol;
     switch (N) {
