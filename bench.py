@@ -12,11 +12,18 @@ Default workload: 1024 x 1024 RGB, 4 Voronoi regions, noise sigma 0.1, N = 4
 phases, eps = 2h, tau = eps^2, lambda = 100, 50 time steps, residual 1e-6.
 
 The JSON line also carries
-  roofline      the smoothing kernel's algorithmic bytes per launch (read u and
-                rhs', write u: 12 N bytes per node) over its average launch
-                time, measured with HIP events on the solve's stream;
+  roofline      the smoothing kernel's (k_cycle) algorithmic bytes per launch
+                over its average launch time, measured with HIP events on the
+                solve's stream.  A time step whose single launch builds the
+                right-hand side, sweeps and closes the cycle reads u^n (4N B)
+                and the image (4C B) and writes u^{n+1} (4N B) per node; a
+                later launch reads u and the stored right-hand side and writes
+                u (12N B per node);
   cpu_baseline  the FP64 oracle on one host core, timed on the first few time
                 steps of the same workload and scaled to segmentations/s.
+
+--copy-calibration runs only a plain device copy of a known size (for scaling
+the DRAM byte counters of a profiler) and prints its size.
 """
 import argparse
 import json
@@ -31,10 +38,39 @@ sys.path.insert(0, ROOT)
 
 METRIC = "segmentations/s at 1024² N=4 (batched vs plain); smoother GB/s vs HBM peak"
 HBM_PEAK_GBS = 8000.0
+# DRAM bytes per k_cycle launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled
+# by the copy-kernel factor (profiles/k_cycle_voronoi1024_n4_pmc.md); None
+# until measured on the current kernel.
+TRAFFIC = {}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def smoother_bytes_per_launch(N: int, C: int, n: int, sweeps: int, cycles: int, fixed: bool) -> float:
+    """Algorithmic bytes of one k_cycle launch, averaged over a time step."""
+    lpc = (sweeps + 1) // 2
+    launches = cycles * lpc
+    store_rhs = not (fixed and cycles == 1 and lpc == 1)
+    first = 4 * (2 * N + C) + (4 * N if store_rhs else 0)
+    later = 12 * N
+    closing_means = 4 * C  # the image, for the colour-mean partials of a closing launch
+    total = first + (launches - 1) * later + (cycles - 1 if not fixed else 0) * closing_means
+    if launches > 1:
+        total += closing_means
+    return total * n / launches
+
+
+def copy_calibration(mib: int, reps: int):
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "reps": reps}), flush=True)
 
 
 def main():
@@ -50,7 +86,12 @@ def main():
                     help="time steps of the oracle run for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB on the device (profiler counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration, max(1, args.steps))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -119,11 +160,15 @@ def main():
         acseg.timing_enable(False)
         launches, total_ms = t["smooth"]
         avg_s = total_ms / launches / 1e3
-        bytes_per_launch = 12.0 * w.N * n
+        fixed = args.schedule == "fixed"
+        bytes_per_launch = smoother_bytes_per_launch(w.N, C, n, prob.nu_pre + prob.nu_post,
+                                                     cycles if fixed else st_run["cycles_total"] / w.steps,
+                                                     fixed)
         achieved = bytes_per_launch / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_smooth (one cycle: 2 red-black sweeps in LDS + residual)",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get(w.name),
+                "kernel": "k_cycle (time step: rhs + 2 red-black sweeps in LDS + residual + "
+                          "colour-mean partials)",
                 "bytes_per_launch": int(bytes_per_launch), "avg_launch_us": round(avg_s * 1e6, 2),
                 "launches": launches,
                 "per_family_ms": {k: round(v[1] / reps, 4) for k, v in t.items()}}
