@@ -1,12 +1,14 @@
 #!/usr/bin/env python3
 """Segmentation throughput on one MI355X.
 
-One benchmark step = one complete segmentation of a synthetic image: all time
-steps of the vector-valued Allen-Cahn model (colour means, right-hand side,
-smoothing cycles to the residual tolerance) plus the post-processing (colour
-means of the result, labels, composite, rounded composite).  Inputs are
-resident in device memory before the timed region; only the initial phase
-field is restored (a device copy) before every segmentation.
+One segmentation = all time steps of the vector-valued Allen-Cahn model on a
+synthetic image (colour means, right-hand side, smoothing cycles to the
+residual tolerance) plus the post-processing (colour means of the result,
+labels, composite, rounded composite).  One benchmark step = one batched solve
+of B such images (seeds 0..B-1, same shape; --batch, default 8); `value` is
+segmentations per second, and `plain` gives the same images solved one per
+call.  Inputs are resident in device memory before the timed region; only the
+initial phase fields are restored (device copies) before every solve.
 
 Default workload: 1024 x 1024 RGB, 4 Voronoi regions, noise sigma 0.1, N = 4
 phases, eps = 2h, tau = eps^2, lambda = 100, 50 time steps, residual 1e-6.
@@ -79,6 +81,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20, help="segmentations timed")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="voronoi1024_n4")
+    ap.add_argument("--batch", type=int, default=8,
+                    help="images per batched solve (seeds 0..B-1, same shape); 1 = plain only")
     ap.add_argument("--schedule", choices=["fixed", "adaptive"], default="fixed",
                     help="fixed: every time step runs the cycle count found sufficient in a "
                          "calibration solve; adaptive: stop at the residual on the device")
@@ -104,49 +108,77 @@ def main():
     w = synth.WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    img_np, u0_np, _ = w.make(0)
+    B = max(1, args.batch)
+    made = [w.make(seed) for seed in range(B)]
+    img_np, u0_np, _ = made[0]
     C = img_np.shape[0]
     n = w.W * w.H
-    img = torch.from_numpy(img_np).to(dev)
-    u0 = torch.from_numpy(u0_np).to(dev)
-    u = torch.empty_like(u0)
+    imgs = [torch.from_numpy(m[0]).to(dev) for m in made]
+    u0s = [torch.from_numpy(m[1]).to(dev) for m in made]
+    us = [torch.empty_like(u0) for u0 in u0s]
+    img, u0, u = imgs[0], u0s[0], us[0]
 
     base = acseg.Problem.from_workload(w, C=C, levels=1, nu_pre=1, nu_post=1, max_cycles=20)
 
-    # calibration: how many cycles does the slowest time step need?
-    u.copy_(u0)
-    _, _, st, _ = acseg.solve(base, img, u)
-    if st["status"] != acseg.OK:
-        raise RuntimeError(f"calibration solve did not converge: {st}")
-    cycles = st["cycles_max"]
+    # calibration: how many cycles does the slowest time step of any image need?
+    cycles = 1
+    for b in range(B):
+        us[b].copy_(u0s[b])
+        _, _, st, _ = acseg.solve(base, imgs[b], us[b])
+        if st["status"] != acseg.OK:
+            raise RuntimeError(f"calibration solve did not converge: {st}")
+        cycles = max(cycles, st["cycles_max"])
     if args.schedule == "fixed":
         prob = acseg.Problem(**{**base.__dict__, "max_cycles": cycles,
                                 "flags": acseg.FLAG_FIXED_CYCLES})
     else:
         prob = base
     log(f"[bench] {w.name}: {w.W}x{w.H} N={w.N} C={C} steps={w.steps} tol={w.tol} "
-        f"schedule={args.schedule} cycles/step<={cycles}")
+        f"schedule={args.schedule} cycles/step<={cycles} batch={B}")
 
     def segment():
         u.copy_(u0)
         _, c, _, _ = acseg.solve(prob, img, u, want_stats=False)
         return acseg.labels(prob, u, c)
 
-    for _ in range(args.warmup):
-        segment()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        segment()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    log(f"[bench] timed {args.steps} segmentations in {elapsed:.4f} s")
+    probs = [prob] * B
+
+    def segment_batch():
+        for b in range(B):
+            us[b].copy_(u0s[b])
+        _, cs, _ = acseg.solve_batched(probs, imgs, us, want_stats=False)
+        return [acseg.labels(prob, us[b], cs[b]) for b in range(B)]
+
+    def timed(fn, k):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    elapsed_plain = timed(segment, args.steps)
+    log(f"[bench] plain: {args.steps} segmentations in {elapsed_plain:.4f} s")
+    if B > 1:
+        elapsed = timed(segment_batch, args.steps)
+        log(f"[bench] batched: {args.steps} x {B} segmentations in {elapsed:.4f} s")
+    else:
+        elapsed = elapsed_plain
 
     # the timed schedule converges: check it once with statistics
     u.copy_(u0)
     _, _, st_run, _ = acseg.solve(prob, img, u)
     if st_run["status"] != acseg.OK:
         raise RuntimeError(f"benchmark schedule did not converge: {st_run}")
+    if B > 1:
+        for b in range(B):
+            us[b].copy_(u0s[b])
+        _, _, sts = acseg.solve_batched(probs, imgs, us)
+        bad = [x for x in sts if x["status"] != acseg.OK]
+        if bad:
+            raise RuntimeError(f"batched schedule did not converge: {bad[0]}")
 
     roof = None
     if not args.no_roofline:
@@ -154,21 +186,22 @@ def main():
         acseg.timing_read()
         reps = max(2, min(args.steps, 10))
         for _ in range(reps):
-            segment()
+            segment_batch() if B > 1 else segment()
         torch.cuda.synchronize()
         t = acseg.timing_read()
         acseg.timing_enable(False)
         launches, total_ms = t["smooth"]
         avg_s = total_ms / launches / 1e3
         fixed = args.schedule == "fixed"
-        bytes_per_launch = smoother_bytes_per_launch(w.N, C, n, prob.nu_pre + prob.nu_post,
-                                                     cycles if fixed else st_run["cycles_total"] / w.steps,
-                                                     fixed)
+        bytes_per_launch = B * smoother_bytes_per_launch(
+            w.N, C, n, prob.nu_pre + prob.nu_post,
+            cycles if fixed else st_run["cycles_total"] / w.steps, fixed)
         achieved = bytes_per_launch / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get(w.name),
-                "kernel": "k_cycle (time step: rhs + 2 red-black sweeps in LDS + residual + "
-                          "colour-mean partials)",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get((w.name, B)),
+                "kernel": ("k_cycle_batch" if B > 1 else "k_cycle") +
+                          " (time step: rhs + 2 red-black sweeps in LDS + residual + colour-mean partials)",
+                "images_per_launch": B,
                 "bytes_per_launch": int(bytes_per_launch), "avg_launch_us": round(avg_s * 1e6, 2),
                 "launches": launches,
                 "per_family_ms": {k: round(v[1] / reps, 4) for k, v in t.items()}}
@@ -191,18 +224,20 @@ def main():
 
     out = {
         "metric": METRIC,
-        "value": round(args.steps / elapsed, 3),
+        "value": round(B * args.steps / elapsed, 3),
         "unit": "segmentations/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "plain": {"value": round(args.steps / elapsed_plain, 3), "unit": "segmentations/s",
+                  "ms_per_segmentation": round(elapsed_plain / args.steps * 1e3, 4)},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "W": w.W, "H": w.H, "N": w.N, "C": C,
+        "config": {"workload": w.name, "batch": B, "W": w.W, "H": w.H, "N": w.N, "C": C,
                    "time_steps": w.steps, "lambda": w.lam, "h": w.h, "eps": w.eps, "tau": w.tau,
                    "tol": w.tol, "levels": prob.levels, "sweeps_per_cycle": prob.nu_pre + prob.nu_post,
                    "schedule": args.schedule, "cycles_per_step_max": cycles,

@@ -199,6 +199,27 @@ acseg_status acseg_solve(acseg_ctx *ctx, const acseg_problem *p, const float *im
                          size_t ws_bytes, void *stream);
 
 /*
+ * B independent segmentations in one time loop: the solve of acseg_solve
+ * (eq. alpha, time steps of Section "Multigrid Solution") for images[b] with
+ * ps[b], u^0 in us[b] (overwritten with u^steps) and, when c_outs and
+ * c_outs[b] are non-NULL, the colour means of the result in c_outs[b].  The
+ * images may differ in size, N, C and every model parameter; they must agree
+ * on steps, nu_pre, nu_post, max_cycles and flags (ACSEG_ERR_INVALID_ARG
+ * otherwise), use Gauss-Seidel cycles only (levels == 1, or 0 resolving to 1;
+ * ACSEG_ERR_UNSUPPORTED otherwise) and not ask for checkpoints.  Each cycle
+ * is one launch over the tiles of all images with the same N and C, and each
+ * image keeps its own convergence control, so the result for every image is
+ * identical to acseg_solve's.  images, us, c_outs and stats are HOST arrays
+ * of B entries (device pointers / statistics); stats may be NULL.
+ * 1 <= B <= 4096.  The workspace size comes from acseg_batch_workspace_size.
+ */
+acseg_status acseg_batch_workspace_size(int32_t B, const acseg_problem *ps, size_t *bytes);
+acseg_status acseg_solve_batched(acseg_ctx *ctx, int32_t B, const acseg_problem *ps,
+                                 const float *const *images, float *const *us,
+                                 float *const *c_outs, acseg_stats *stats, void *ws,
+                                 size_t ws_bytes, void *stream);
+
+/*
  * Post-processing of Section "Post-processing": labels[p] = argmax_i u_pi
  * (lowest index on ties), composite_kp = sum_i c_ik u_pi, rounded composite
  * rounded_kp = c_{labels[p],k}.  labels: uint8[H][W]; composite, rounded:

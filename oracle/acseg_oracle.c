@@ -847,3 +847,225 @@ void orc_labels(int N, int C, int H, int W, const double *u, const double *c, ui
         }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint of the time step (derived; the paper does not differentiate)      */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Derivative of the step map.  With the free sets I_p = {i : u^{n+1}_pi > 0}
+ * held fixed, u^{n+1} minimises J(u) = sum_i [u_i.H u_i / 2 - b_i.u_i] over
+ * the affine set {u_pi = 0 for i outside I_p, sum_{i in I_p} u_pi = 1}, so a
+ * change db moves it by du = T (T H T)^+ T db, where T applies tangent_free
+ * node by node (H is symmetric).  For a loss with gradient ubar at u^{n+1},
+ * the gradient at b is therefore z = (T H T)^+ T ubar (z = T z): solved here
+ * by conjugate gradients on the range of T.  Components with u = 0 count as
+ * active whatever their multiplier.
+ *
+ * The rest is the chain rule through eq. alpha and eq. VV_fidelity:
+ *   b_pi = M_p [(1/tau + 2/eps) un_pi - lambda F_pi],
+ *   F_pi = sum_k (I_pk - c_ik)^2,  c_ik = S_ik / S_i,
+ *   S_ik = sum_p M_p un_pi I_pk,   S_i = sum_p M_p un_pi,
+ *   H = M/tau + eps A.
+ * An empty phase's mean is the kept previous mean: treated as a constant.
+ */
+
+/* out = T(v) node by node, the free sets taken from u */
+static void tangent_field(size_t n, int N, const double *u, const double *v, double *out)
+{
+    double up[ORC_MAX_N], xi[ORC_MAX_N], xo[ORC_MAX_N];
+    for (size_t p = 0; p < n; ++p) {
+        for (int i = 0; i < N; ++i) {
+            up[i] = u[i * n + p];
+            xi[i] = v[i * n + p];
+        }
+        tangent_free(N, up, xi, xo);
+        for (int i = 0; i < N; ++i) out[i * n + p] = xo[i];
+    }
+}
+
+/* out = H v, componentwise */
+static void apply_H_field(const grid_t *g, const orc_params *P, const double *v, double *out)
+{
+    size_t n = (size_t)g->W * g->H;
+    for (int i = 0; i < P->N; ++i)
+        for (int y = 0; y < g->H; ++y)
+            for (int x = 0; x < g->W; ++x) {
+                size_t p = (size_t)y * g->W + x;
+                out[i * n + p] = g->mass[p] / P->tau * v[i * n + p] + P->eps * stiff_apply(g, v + i * n, x, y);
+            }
+}
+
+static double dotn(size_t m, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (size_t k = 0; k < m; ++k) s += a[k] * b[k];
+    return s;
+}
+
+/* z = (T H T)^+ T rhs by conjugate gradients; returns the iteration count */
+static int adjoint_solve(const grid_t *g, const orc_params *P, const double *unext, const double *rv,
+                         double *z, double rtol)
+{
+    size_t n = (size_t)g->W * g->H, m = (size_t)P->N * n;
+    double *r = malloc(sizeof(double) * m), *d = malloc(sizeof(double) * m);
+    double *q = malloc(sizeof(double) * m), *t = malloc(sizeof(double) * m);
+    memset(z, 0, sizeof(double) * m);
+    tangent_field(n, P->N, unext, rv, r);
+    memcpy(d, r, sizeof(double) * m);
+    double rr = dotn(m, r, r), r0 = sqrt(rr);
+    int it = 0;
+    while (sqrt(rr) > rtol * r0 && rr > 0.0 && it < 100000) {
+        apply_H_field(g, P, d, t);
+        tangent_field(n, P->N, unext, t, q);
+        double a = rr / dotn(m, d, q);
+        for (size_t k = 0; k < m; ++k) {
+            z[k] += a * d[k];
+            r[k] -= a * q[k];
+        }
+        double rr1 = dotn(m, r, r);
+        double beta = rr1 / rr;
+        rr = rr1;
+        for (size_t k = 0; k < m; ++k) d[k] = r[k] + beta * d[k];
+        ++it;
+    }
+    free(r);
+    free(d);
+    free(q);
+    free(t);
+    return it;
+}
+
+/*
+ * One step backwards.  Inputs: un = u^n, unext = u^{n+1} (the converged
+ * step), c_prev (the previous step's means, for empty phases; may be NULL),
+ * ubar_next = dL/du^{n+1}.  Outputs: ubar_n = dL/du^n through this step,
+ * z (optional, the gradient at b), cbar = dL/dc^n [N][C]; accumulated:
+ * Ibar += dL/dI, grads[0..2] += dL/dlambda, dL/deps (tau fixed), dL/dtau.
+ */
+static int adjoint_step(const grid_t *g, const orc_params *P, const double *I, const double *un,
+                        const double *c_prev, const double *unext, const double *ubar_next,
+                        double *ubar_n, double *Ibar, double *grads, double *cbar, double *z_out)
+{
+    const int N = P->N, C = P->C;
+    size_t n = (size_t)g->W * g->H, m = (size_t)N * n;
+    double c[ORC_MAX_N * 4];
+    double S[ORC_MAX_N];
+    unsigned char nonempty[ORC_MAX_N];
+    if (C > 4) return -1;
+    colour_means(g, N, C, I, un, c_prev, c);
+    double area = 0.0;
+    for (size_t p = 0; p < n; ++p) area += g->mass[p];
+    for (int i = 0; i < N; ++i) {
+        S[i] = 0.0;
+        for (size_t p = 0; p < n; ++p) S[i] += g->mass[p] * un[i * n + p];
+        nonempty[i] = S[i] > 1e-12 * area;
+    }
+    double *z = malloc(sizeof(double) * m);
+    adjoint_solve(g, P, unext, ubar_next, z, 1e-14);
+    if (z_out) memcpy(z_out, z, sizeof(double) * m);
+
+    const double a = 1.0 / P->tau + 2.0 / P->eps;
+    for (int i = 0; i < N; ++i)
+        for (int k = 0; k < C; ++k) cbar[i * C + k] = 0.0;
+    double gl = 0.0, ge = 0.0, gt = 0.0;
+    for (int i = 0; i < N; ++i)
+        for (int y = 0; y < g->H; ++y)
+            for (int x = 0; x < g->W; ++x) {
+                size_t p = (size_t)y * g->W + x;
+                double zp = z[i * n + p], Mp = g->mass[p];
+                double F = fitting(C, I, n, p, c + i * C);
+                /* db/du^n */
+                ubar_n[i * n + p] = a * Mp * zp;
+                /* b depends on lambda, eps, tau; H on eps, tau */
+                gl += zp * (-Mp * F);
+                ge += zp * (-2.0 / (P->eps * P->eps)) * Mp * un[i * n + p]
+                      - zp * stiff_apply(g, unext + i * n, x, y);
+                gt += -zp * Mp * un[i * n + p] / (P->tau * P->tau)
+                      + zp * Mp * unext[i * n + p] / (P->tau * P->tau);
+                /* F: direct image term and the means */
+                double Fbar = -P->lambda * Mp * zp;
+                for (int k = 0; k < C; ++k) {
+                    double d = I[k * n + p] - c[i * C + k];
+                    Ibar[k * n + p] += 2.0 * Fbar * d;
+                    cbar[i * C + k] += -2.0 * Fbar * d;
+                }
+            }
+    /* c_ik = S_ik / S_i */
+    for (int i = 0; i < N; ++i) {
+        if (!nonempty[i]) continue;
+        for (size_t p = 0; p < n; ++p) {
+            double Mp = g->mass[p];
+            for (int k = 0; k < C; ++k) {
+                Ibar[k * n + p] += cbar[i * C + k] * Mp * un[i * n + p] / S[i];
+                ubar_n[i * n + p] += cbar[i * C + k] * Mp * (I[k * n + p] - c[i * C + k]) / S[i];
+            }
+        }
+    }
+    grads[0] += gl;
+    grads[1] += ge;
+    grads[2] += gt;
+    free(z);
+    return 0;
+}
+
+/* The gradient at b of one step: z = (T H T)^+ T ubar, free sets from unext. */
+int orc_adjoint_solve(const orc_params *P, const double *unext, const double *ubar, double *z)
+{
+    grid_t g;
+    if (grid_init(&g, P->W, P->H, P->h)) return -1;
+    int it = adjoint_solve(&g, P, unext, ubar, z, 1e-14);
+    grid_free(&g);
+    return it;
+}
+
+int orc_adjoint_step(const orc_params *P, const double *I, const double *un, const double *c_prev,
+                     const double *unext, const double *ubar_next, double *ubar_n, double *Ibar,
+                     double *grads, double *cbar)
+{
+    grid_t g;
+    if (grid_init(&g, P->W, P->H, P->h)) return -1;
+    int r = adjoint_step(&g, P, I, un, c_prev, unext, ubar_next, ubar_n, Ibar, grads, cbar, NULL);
+    grid_free(&g);
+    return r;
+}
+
+/*
+ * Backwards through `steps` steps of a trajectory traj = u^0..u^steps
+ * ([steps+1][N][H*W]) for dL/du^steps = ubar_T.  Ibar [C][H*W] and
+ * grads[3] (lambda, eps at fixed tau, tau) are overwritten; cbar
+ * ([steps][N][C], optional) receives dL/dc^n of every step; ubar0
+ * (optional) dL/du^0.  The means are recomputed from the trajectory.
+ */
+int orc_backward(const orc_params *P, int steps, const double *I, const double *traj,
+                 const double *ubar_T, double *Ibar, double *grads, double *cbar, double *ubar0)
+{
+    grid_t g;
+    if (grid_init(&g, P->W, P->H, P->h)) return -1;
+    const int N = P->N, C = P->C;
+    size_t n = (size_t)P->W * P->H, m = (size_t)N * n;
+    double *cs = malloc(sizeof(double) * (size_t)(steps > 0 ? steps : 1) * N * C);
+    for (int s = 0; s < steps; ++s)
+        colour_means(&g, N, C, I, traj + (size_t)s * m, s > 0 ? cs + (size_t)(s - 1) * N * C : NULL,
+                     cs + (size_t)s * N * C);
+    double *ub = malloc(sizeof(double) * m), *ub2 = malloc(sizeof(double) * m);
+    double cb[ORC_MAX_N * 4];
+    memcpy(ub, ubar_T, sizeof(double) * m);
+    memset(Ibar, 0, sizeof(double) * C * n);
+    grads[0] = grads[1] = grads[2] = 0.0;
+    int r = 0;
+    for (int s = steps - 1; s >= 0 && r == 0; --s) {
+        r = adjoint_step(&g, P, I, traj + (size_t)s * m, s > 0 ? cs + (size_t)(s - 1) * N * C : NULL,
+                         traj + (size_t)(s + 1) * m, ub, ub2, Ibar, grads, cb, NULL);
+        if (cbar) memcpy(cbar + (size_t)s * N * C, cb, sizeof(double) * N * C);
+        double *t = ub;
+        ub = ub2;
+        ub2 = t;
+    }
+    if (ubar0) memcpy(ubar0, ub, sizeof(double) * m);
+    free(cs);
+    free(ub);
+    free(ub2);
+    grid_free(&g);
+    return r;
+}

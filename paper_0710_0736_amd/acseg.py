@@ -113,6 +113,9 @@ def lib():
         L.acseg_step.argtypes = [vp, pp, vp, vp, vp, vp, vp, sp, vp, sz, vp]
         L.acseg_solve.argtypes = [vp, pp, vp, vp, vp, vp, sp, vp, sz, vp]
         L.acseg_labels.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp]
+        L.acseg_batch_workspace_size.argtypes = [ctypes.c_int32, pp, ctypes.POINTER(sz)]
+        L.acseg_solve_batched.argtypes = [vp, ctypes.c_int32, pp, ctypes.POINTER(vp),
+                                          ctypes.POINTER(vp), ctypes.POINTER(vp), sp, vp, sz, vp]
         L.acseg_energy.argtypes = [vp, pp, vp, vp, vp, vp, sz, vp]
         L.acseg_timing_enable.argtypes = [vp, ctypes.c_int32]
         L.acseg_timing_read.argtypes = [vp, ctypes.POINTER(_KernelTime), ctypes.c_int32,
@@ -261,6 +264,47 @@ def solve(p: Problem, image: torch.Tensor, u: torch.Tensor, checkpoints: bool = 
                              _ptr(c), _ptr(ck), ctypes.byref(st) if want_stats else None,
                              _ptr(ws), ws.numel(), _stream()), "acseg_solve")
     return u, c, (_stats_dict(st) if want_stats else None), ck
+
+
+def _batch_arrays(problems):
+    arr = (_Problem * len(problems))(*[p.c() for p in problems])
+    return arr
+
+
+def batch_workspace_size(problems) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().acseg_batch_workspace_size(len(problems), _batch_arrays(problems), ctypes.byref(n)),
+           "batch_workspace_size")
+    return n.value
+
+
+def solve_batched(problems, images, us, want_stats: bool = True, c_out: bool = True):
+    """One time loop over independent images; every ``us[b]`` is overwritten.
+
+    Returns (us, cs (list of [N][C] or None), stats (list) or None).
+    """
+    B = len(problems)
+    if not (len(images) == len(us) == B) or B == 0:
+        raise ValueError("need one image and one field per problem")
+    for p, im, u in zip(problems, images, us):
+        _need(im, (p.C, p.H, p.W), name="image")
+        _need(u, (p.N, p.H, p.W), name="u")
+    dev = us[0].device
+    cs = [torch.empty((p.N, p.C), dtype=torch.float32, device=dev) for p in problems] if c_out else None
+    VP = ctypes.c_void_p * B
+    ims = VP(*[im.data_ptr() for im in images])
+    uus = VP(*[u.data_ptr() for u in us])
+    ccs = VP(*[c.data_ptr() for c in cs]) if c_out else None
+    n = batch_workspace_size(problems)
+    ws = _ws_cache.get(("batch", dev))
+    if ws is None or ws.numel() < n:
+        ws = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
+        _ws_cache[("batch", dev)] = ws
+    st = (_Stats * B)()
+    _check(lib().acseg_solve_batched(ctx(dev.index), B, _batch_arrays(problems), ims, uus, ccs,
+                                     st if want_stats else None, _ptr(ws), ws.numel(), _stream()),
+           "acseg_solve_batched")
+    return us, cs, ([_stats_dict(x) for x in st] if want_stats else None)
 
 
 def labels(p: Problem, u: torch.Tensor, c: torch.Tensor):

@@ -32,12 +32,19 @@ struct acseg_ctx {
     bool timing = false;
     std::vector<hipEvent_t> pool;
     std::vector<TimedRec> recs;
+    // pinned staging of a batch's descriptor tables; stage_ev marks the end of
+    // the last upload from it
+    void* stage = nullptr;
+    size_t stage_bytes = 0;
+    hipEvent_t stage_ev = nullptr;
 };
 
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kCmeansMaxM = ACSEG_MAX_N * ACSEG_MAX_C + ACSEG_MAX_N + ACSEG_MAX_C + 2;
+constexpr int kMaxBatch = 4096;
+static_assert(kCmeansMaxM == ACSEG_MAX_N * ACSEG_MAX_C + ACSEG_MAX_N + ACSEG_MAX_C + 2, "sums per set");
+static_assert(kNC == ACSEG_MAX_N * ACSEG_MAX_C, "means per set");
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -142,8 +149,6 @@ struct Layout {
     size_t total = 0;
     int part_stride = 0;
 };
-
-constexpr int kNC = ACSEG_MAX_N * ACSEG_MAX_C;  // stride of one set of means in c64
 
 Layout layout_of(const acseg_problem* p) {
     Layout L;
@@ -362,66 +367,88 @@ acseg_status enqueue_correction(acseg_ctx* ctx, const acseg_problem* p, const Mg
 // at once unless the schedule is fixed), then the step's end, which leaves the
 // sums of the new iterate in tot_next.  The step's first launch writes the
 // means it uses to c64 (and c_out when non-NULL).
+// Per-image constants of the cycle kernels.
+CycleArgs cycle_args_of(const acseg_problem* p, const Coefs& cf, const float* image, Bufs bufs,
+                        const Layout& L, void* ws) {
+    CycleArgs a{};
+    a.bufs = bufs;
+    a.ctl = at<Ctl>(ws, L.ctl);
+    a.image = image;
+    a.tot = at<double>(ws, L.tot);
+    a.c64 = at<double>(ws, L.c64);
+    a.c_out = nullptr;
+    a.rhs = at<float>(ws, L.rhs);
+    a.res_part = at<float>(ws, L.part_f);
+    a.cm_part = at<double>(ws, L.part_cm);
+    a.part_stride = L.part_stride;
+    a.coef = cf.fine;
+    a.rc = cf.rhs;
+    a.tol = (float)p->tol;
+    cycle_tiling(p->N, p->W, p->H, &a);
+    return a;
+}
+
+// Launches per cycle and whether the first launch must store the rhs.
+struct Schedule {
+    int lpc, lpre;
+    bool fixed, store_rhs, mg;
+};
+
+Schedule schedule_of(const acseg_problem* p) {
+    Schedule sc;
+    const MgPlan m = plan_of(p);
+    const int sweeps = p->nu_pre + p->nu_post;
+    sc.fixed = (p->flags & ACSEG_FLAG_FIXED_CYCLES) != 0u;
+    sc.mg = m.L >= 2;
+    sc.lpre = cycle_launches(p->nu_pre);
+    sc.lpc = sc.mg ? sc.lpre + cycle_launches(p->nu_post) : cycle_launches(sweeps);
+    // a one-launch step keeps the rhs in registers; the defect reads it
+    sc.store_rhs = sc.mg || !(sc.fixed && p->max_cycles == 1 && sc.lpc == 1);
+    return sc;
+}
+
+// Enqueue time step n on the iterate bufs[ctl->cur] whose reduced colour-mean
+// sums are in tot set tot_sel: max_cycles cycles (after convergence they exit
+// at once unless the schedule is fixed), then the step's end, which leaves the
+// sums of the new iterate in tot set tot_sel ^ 1.  The step's first launch
+// writes the means it uses to c64 set c64_sel (empty phases keep set
+// prev_sel, -1 for none).
 acseg_status enqueue_step(acseg_ctx* ctx, const acseg_problem* p, const Coefs& cf,
                           const float* image, Bufs bufs, const Layout& L, void* ws, int n,
-                          const double* tot, const double* c_prev64, double* c64, float* c_out,
-                          double* tot_next, hipStream_t s) {
-    Ctl* ctl = at<Ctl>(ws, L.ctl);
-    const bool fixed = (p->flags & ACSEG_FLAG_FIXED_CYCLES) != 0u;
-    const int sweeps = p->nu_pre + p->nu_post;
-    CycleLaunch c{};
-    c.N = p->N;
-    c.C = p->C;
-    c.W = p->W;
-    c.H = p->H;
-    c.sweeps = sweeps;
-    c.slot = n & 1;
-    c.fixed = fixed;
-    c.store_rhs = !(fixed && p->max_cycles == 1 && cycle_launches(sweeps) == 1);
-    c.bufs = bufs;
-    c.ctl = ctl;
-    c.image = image;
-    c.tot = tot;
-    c.c_prev64 = c_prev64;
-    c.c64 = c64;
-    c.c_out = c_out;
-    c.rhs = at<float>(ws, L.rhs);
-    c.res_part = at<float>(ws, L.part_f);
-    c.cm_part = at<double>(ws, L.part_cm);
-    c.part_stride = L.part_stride;
-    c.coef = cf.fine;
-    c.rc = cf.rhs;
-    c.tol = (float)p->tol;
+                          int tot_sel, int c64_sel, int prev_sel, hipStream_t s) {
+    const CycleArgs a = cycle_args_of(p, cf, image, bufs, L, ws);
+    const Schedule sc = schedule_of(p);
+    const CycleGrid single{nullptr, nullptr, 0};
+    CycleStep st{};
+    st.slot = n & 1;
+    st.fixed = sc.fixed ? 1 : 0;
+    st.store_rhs = sc.store_rhs ? 1 : 0;
+    st.tot_sel = tot_sel;
+    st.c64_sel = c64_sel;
+    st.prev_sel = prev_sel;
     const MgPlan m = plan_of(p);
-    const int lpre = cycle_launches(p->nu_pre), lpost = cycle_launches(p->nu_post);
-    const int lpc = m.L >= 2 ? lpre + lpost : cycle_launches(sweeps);
-    if (m.L >= 2) c.store_rhs = true;  // the defect reads it
     for (int k = 0; k < p->max_cycles; ++k) {
-        c.cycle = k;
-        c.cm = !fixed || k == p->max_cycles - 1;
-        c.launch0 = k * lpc;
-        c.step_first = k == 0;
-        c.opens = true;
-        if (m.L == 1) {
-            c.closes = true;
-            ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] { return launch_cycle(c, s); }));
+        st.cycle = k;
+        st.cm = (!sc.fixed || k == p->max_cycles - 1) ? 1 : 0;
+        st.launch = k * sc.lpc;
+        if (!sc.mg) {
+            const CycleRole role{k == 0, true, true};
+            ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] {
+                return launch_cycle(p->N, p->C, p->nu_pre + p->nu_post, a, st, single, role, s);
+            }));
             continue;
         }
-        c.sweeps = p->nu_pre;
-        c.closes = false;
-        ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] { return launch_cycle(c, s); }));
-        const acseg_status v = enqueue_correction(ctx, p, m, L, ws, bufs, c.slot, fixed, k * lpc + lpre, s);
+        const CycleRole pre{k == 0, true, false};
+        ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] { return launch_cycle(p->N, p->C, p->nu_pre, a, st, single, pre, s); }));
+        const acseg_status v = enqueue_correction(ctx, p, m, L, ws, bufs, st.slot, sc.fixed, k * sc.lpc + sc.lpre, s);
         if (v != ACSEG_OK) return v;
-        c.sweeps = p->nu_post;
-        c.launch0 = k * lpc + lpre;
-        c.step_first = false;
-        c.opens = false;
-        c.closes = true;
-        ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] { return launch_cycle(c, s); }));
+        st.launch = k * sc.lpc + sc.lpre;
+        const CycleRole post{false, false, true};
+        ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] { return launch_cycle(p->N, p->C, p->nu_post, a, st, single, post, s); }));
     }
+    const StepEndArgs e{p->max_cycles, sc.lpc};
     ACSEG_TRY(timed(ctx, kFamOther, s, [&] {
-        return launch_step_end(p->N, p->C, p->W, p->H, ctl, c.res_part, c.cm_part, L.part_stride,
-                               p->max_cycles, lpc, c.slot, (float)p->tol, tot_next, s);
+        return launch_step_end(p->N, p->C, a, st, e, nullptr, nullptr, 0, s);
     }));
     return ACSEG_OK;
 }
@@ -460,6 +487,83 @@ acseg_status read_stats(acseg_ctx* ctx, const Layout& L, void* ws, hipStream_t s
     else if (c.empty_steps || c.empty_now)
         st->status = ACSEG_WARN_EMPTY_PHASE;
     return ACSEG_OK;
+}
+
+// ---- batches ---------------------------------------------------------------
+
+// A batch shares the time loop: every problem must agree on these.
+bool same_schedule(const acseg_problem& a, const acseg_problem& b) {
+    return a.steps == b.steps && a.nu_pre == b.nu_pre && a.nu_post == b.nu_post &&
+           a.max_cycles == b.max_cycles && a.flags == b.flags;
+}
+
+acseg_status validate_batch(int32_t B, const acseg_problem* ps) {
+    if (B < 1 || B > kMaxBatch || !ps) return ACSEG_ERR_INVALID_ARG;
+    for (int b = 0; b < B; ++b) {
+        const acseg_status v = validate(&ps[b], true);
+        if (v != ACSEG_OK) return v;
+        if (!same_schedule(ps[0], ps[b])) return ACSEG_ERR_INVALID_ARG;
+        if ((ps[b].flags & ACSEG_FLAG_STORE_CHECKPOINTS) != 0u) return ACSEG_ERR_INVALID_ARG;
+        if (plan_of(&ps[b]).L != 1) return ACSEG_ERR_UNSUPPORTED;
+    }
+    return ACSEG_OK;
+}
+
+// Batch workspace: descriptor table, work lists, group image lists, then one
+// single-image region per image.
+struct BatchLayout {
+    size_t descs = 0, work = 0, imgs = 0;
+    std::vector<size_t> region;
+    std::vector<Layout> L;
+    size_t total = 0;
+    size_t table_bytes = 0;  // descs .. imgs, uploaded in one copy
+    int nwork = 0;
+};
+
+int batch_work_slots(int N, const acseg_problem* ps, int B, const std::vector<int>& members) {
+    (void)N;
+    int64_t T = 0;
+    for (int b : members) T += cycle_tiles(ps[b].N, ps[b].W, ps[b].H);
+    (void)B;
+    return (int)(((T + kXcd - 1) / kXcd) * kXcd);
+}
+
+// Images grouped by (N, C), in order of first appearance.
+std::vector<std::vector<int>> batch_groups(int32_t B, const acseg_problem* ps) {
+    std::vector<std::vector<int>> g;
+    for (int b = 0; b < B; ++b) {
+        bool placed = false;
+        for (auto& m : g)
+            if (ps[m[0]].N == ps[b].N && ps[m[0]].C == ps[b].C) {
+                m.push_back(b);
+                placed = true;
+                break;
+            }
+        if (!placed) g.push_back({b});
+    }
+    return g;
+}
+
+BatchLayout batch_layout_of(int32_t B, const acseg_problem* ps) {
+    BatchLayout bl;
+    const auto groups = batch_groups(B, ps);
+    for (const auto& m : groups) bl.nwork += batch_work_slots(ps[m[0]].N, ps, B, m);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    bl.descs = take(sizeof(CycleArgs) * B);
+    bl.work = take(sizeof(int2) * (size_t)bl.nwork);
+    bl.imgs = take(sizeof(int) * B);
+    bl.table_bytes = off;
+    for (int b = 0; b < B; ++b) {
+        bl.L.push_back(layout_of(&ps[b]));
+        bl.region.push_back(take(bl.L.back().total));
+    }
+    bl.total = off;
+    return bl;
 }
 
 }  // namespace
@@ -508,6 +612,11 @@ acseg_status acseg_destroy(acseg_ctx* ctx) {
     }
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->host_ctl) (void)hipHostFree(ctx->host_ctl);
+    if (ctx->stage_ev) {
+        (void)hipEventSynchronize(ctx->stage_ev);
+        (void)hipEventDestroy(ctx->stage_ev);
+    }
+    if (ctx->stage) (void)hipHostFree(ctx->stage);
     delete ctx;
     return ACSEG_OK;
 }
@@ -575,7 +684,7 @@ acseg_status acseg_step(acseg_ctx* ctx, const acseg_problem* p, const float* ima
     const double* cp = c_prev ? cprev : nullptr;
     v = enqueue_means(p, image, u_in, L, ws, cp, c64, c_out, tot, s);
     if (v != ACSEG_OK) return v;
-    v = enqueue_step(ctx, p, cf, image, bufs, L, ws, 0, tot, cp, c64, nullptr, tot + kCmeansMaxM, s);
+    v = enqueue_step(ctx, p, cf, image, bufs, L, ws, 0, 0, 0, c_prev ? 2 : -1, s);
     if (v != ACSEG_OK) return v;
     ACSEG_TRY(launch_copy_current(bufs, ctl, u_out, nu, s));
     return read_stats(ctx, L, ws, s, stats);
@@ -603,9 +712,7 @@ acseg_status acseg_solve(acseg_ctx* ctx, const acseg_problem* p, const float* im
     if (v != ACSEG_OK) return v;
     for (int n = 0; n < p->steps; ++n) {
         const int a = n & 1, b = a ^ 1;
-        v = enqueue_step(ctx, p, cf, image, bufs, L, ws, n, tot + a * kCmeansMaxM,
-                         n > 0 ? c64 + b * kNC : nullptr, c64 + a * kNC, nullptr,
-                         tot + b * kCmeansMaxM, s);
+        v = enqueue_step(ctx, p, cf, image, bufs, L, ws, n, a, a, n > 0 ? b : -1, s);
         if (v != ACSEG_OK) return v;
         if (ckpt) ACSEG_TRY(launch_copy_current(bufs, ctl, checkpoints + (n + 1) * nu, nu, s));
     }
@@ -616,6 +723,144 @@ acseg_status acseg_solve(acseg_ctx* ctx, const acseg_problem* p, const float* im
                                         nullptr, c_out, s));
     }
     return read_stats(ctx, L, ws, s, stats);
+}
+
+acseg_status acseg_batch_workspace_size(int32_t B, const acseg_problem* ps, size_t* bytes) {
+    if (!bytes) return ACSEG_ERR_INVALID_ARG;
+    const acseg_status v = validate_batch(B, ps);
+    if (v != ACSEG_OK) return v;
+    *bytes = batch_layout_of(B, ps).total;
+    return ACSEG_OK;
+}
+
+acseg_status acseg_solve_batched(acseg_ctx* ctx, int32_t B, const acseg_problem* ps,
+                                 const float* const* images, float* const* us,
+                                 float* const* c_outs, acseg_stats* stats, void* ws,
+                                 size_t ws_bytes, void* stream) {
+    acseg_status v = validate_batch(B, ps);
+    if (v != ACSEG_OK) return v;
+    if (!ctx || !images || !us) return ACSEG_ERR_INVALID_ARG;
+    for (int b = 0; b < B; ++b)
+        if (!images[b] || !us[b]) return ACSEG_ERR_INVALID_ARG;
+    const BatchLayout bl = batch_layout_of(B, ps);
+    if (!ws || ((uintptr_t)ws % kAlign) != 0 || ws_bytes < bl.total) return ACSEG_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    char* base = static_cast<char*>(ws);
+
+    // ---- descriptor table, work lists and group lists, built on the host
+    if (ctx->stage_ev) ACSEG_TRY(hipEventSynchronize(ctx->stage_ev));  // the last upload is done
+    if (ctx->stage_bytes < bl.table_bytes) {
+        if (ctx->stage) ACSEG_TRY(hipHostFree(ctx->stage));
+        ctx->stage = nullptr;
+        ctx->stage_bytes = 0;
+        ACSEG_TRY(hipHostMalloc(&ctx->stage, bl.table_bytes, hipHostMallocDefault));
+        ctx->stage_bytes = bl.table_bytes;
+    }
+    if (!ctx->stage_ev) ACSEG_TRY(hipEventCreateWithFlags(&ctx->stage_ev, hipEventDisableTiming));
+    char* hs = static_cast<char*>(ctx->stage);
+    memset(hs, 0, bl.table_bytes);
+    CycleArgs* hdesc = reinterpret_cast<CycleArgs*>(hs + bl.descs);
+    int2* hwork = reinterpret_cast<int2*>(hs + bl.work);
+    int* himgs = reinterpret_cast<int*>(hs + bl.imgs);
+    std::vector<Coefs> cfs(B);
+    std::vector<Bufs> bufs(B);
+    for (int b = 0; b < B; ++b) {
+        void* wsb = base + bl.region[b];
+        cfs[b] = coefs_of(&ps[b]);
+        bufs[b] = Bufs{{us[b], at<float>(wsb, bl.L[b].ubuf), us[b]}};
+        hdesc[b] = cycle_args_of(&ps[b], cfs[b], images[b], bufs[b], bl.L[b], wsb);
+    }
+    struct Group {
+        int N, C, work0, nwork, img0, nimg;
+    };
+    std::vector<Group> groups;
+    {
+        int w0 = 0, i0 = 0;
+        for (const auto& m : batch_groups(B, ps)) {
+            Group g{ps[m[0]].N, ps[m[0]].C, w0, batch_work_slots(ps[m[0]].N, ps, B, m), i0, (int)m.size()};
+            // concatenated tiles of the group, dealt to the XCDs in contiguous bands
+            std::vector<int2> tiles;
+            for (int b : m)
+                for (int t = 0; t < hdesc[b].ntiles; ++t) tiles.push_back(make_int2(b, t));
+            const int tpx = g.nwork / kXcd;
+            for (int k = 0; k < g.nwork; ++k) {
+                const int gt = (k % kXcd) * tpx + k / kXcd;
+                hwork[w0 + k] = gt < (int)tiles.size() ? tiles[gt] : make_int2(-1, 0);
+            }
+            for (int j = 0; j < g.nimg; ++j) himgs[i0 + j] = m[j];
+            w0 += g.nwork;
+            i0 += g.nimg;
+            groups.push_back(g);
+        }
+    }
+    ACSEG_TRY(hipMemcpyAsync(base, hs, bl.table_bytes, hipMemcpyHostToDevice, s));
+    ACSEG_TRY(hipEventRecord(ctx->stage_ev, s));
+    const CycleArgs* ddesc = reinterpret_cast<const CycleArgs*>(base + bl.descs);
+    const int2* dwork = reinterpret_cast<const int2*>(base + bl.work);
+    const int* dimgs = reinterpret_cast<const int*>(base + bl.imgs);
+
+    // ---- colour means of every u^0
+    for (int b = 0; b < B; ++b) {
+        void* wsb = base + bl.region[b];
+        const Layout& L = bl.L[b];
+        ACSEG_TRY(launch_ctl_init(at<Ctl>(wsb, L.ctl), 0, s));
+        v = enqueue_means(&ps[b], images[b], us[b], L, wsb, nullptr, at<double>(wsb, L.c64) + kNC,
+                          (ps[b].steps == 0 && c_outs) ? c_outs[b] : nullptr, at<double>(wsb, L.tot), s);
+        if (v != ACSEG_OK) return v;
+    }
+
+    // ---- the time loop, one launch per cycle and group
+    const acseg_problem& p0 = ps[0];
+    const Schedule sc = schedule_of(&p0);
+    const int sweeps = p0.nu_pre + p0.nu_post;
+    for (int n = 0; n < p0.steps; ++n) {
+        const int a = n & 1, bsel = a ^ 1;
+        CycleStep st{};
+        st.slot = a;
+        st.fixed = sc.fixed ? 1 : 0;
+        st.store_rhs = sc.store_rhs ? 1 : 0;
+        st.tot_sel = a;
+        st.c64_sel = a;
+        st.prev_sel = n > 0 ? bsel : -1;
+        for (const Group& g : groups) {
+            const CycleGrid grid{ddesc, dwork + g.work0, g.nwork};
+            const CycleArgs& any = hdesc[himgs[g.img0]];
+            for (int k = 0; k < p0.max_cycles; ++k) {
+                st.cycle = k;
+                st.cm = (!sc.fixed || k == p0.max_cycles - 1) ? 1 : 0;
+                st.launch = k * sc.lpc;
+                const CycleRole role{k == 0, true, true};
+                ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] {
+                    return launch_cycle(g.N, g.C, sweeps, any, st, grid, role, s);
+                }));
+            }
+            const StepEndArgs e{p0.max_cycles, sc.lpc};
+            ACSEG_TRY(timed(ctx, kFamOther, s, [&] {
+                return launch_step_end(g.N, g.C, any, st, e, ddesc, dimgs + g.img0, g.nimg, s);
+            }));
+        }
+    }
+
+    // ---- results
+    for (int b = 0; b < B; ++b) {
+        void* wsb = base + bl.region[b];
+        const Layout& L = bl.L[b];
+        Ctl* ctl = at<Ctl>(wsb, L.ctl);
+        const int64_t nu = (int64_t)ps[b].N * ps[b].W * ps[b].H;
+        ACSEG_TRY(launch_copy_current(bufs[b], ctl, us[b], nu, s));
+        if (c_outs && c_outs[b] && p0.steps > 0) {
+            const int a = p0.steps & 1, bsel = a ^ 1;
+            ACSEG_TRY(launch_means_from_tot(ps[b].N, ps[b].C, at<double>(wsb, L.tot) + a * kCmeansMaxM,
+                                            at<double>(wsb, L.c64) + bsel * kNC, ctl, nullptr,
+                                            c_outs[b], s));
+        }
+    }
+    if (stats)
+        for (int b = 0; b < B; ++b) {
+            v = read_stats(ctx, bl.L[b], base + bl.region[b], s, &stats[b]);
+            if (v != ACSEG_OK) return v;
+        }
+    return ACSEG_OK;
 }
 
 acseg_status acseg_labels(acseg_ctx* ctx, const acseg_problem* p, const float* u, const float* c,

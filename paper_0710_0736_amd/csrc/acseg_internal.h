@@ -87,46 +87,86 @@ hipError_t launch_cmeans_finish(int N, int C, int W, int H, const double* partia
 
 // ---- launchers (kernels_cycle.hip) ---------------------------------------
 
-// One smoothing cycle of the current time step: `sweeps` red-black projected
-// block Gauss-Seidel sweeps (launches of at most two).  The step's first
-// launch builds the right-hand side from u^n (= bufs[ctl->cur]), the image
-// and c64 (stored to `rhs` when later launches need it); every closing launch
-// writes per-tile residual partials and, with `cm`, colour-mean partials of
-// its output.  Unless `fixed`, a cycle first checks the previous cycle's
-// residual and the rest of the step is skipped once it is <= tol.
-struct CycleLaunch {
-    int N, C, W, H;
-    int sweeps, cycle, slot;
-    int launch0;              // launch index (within the step) of this call's first launch
-    bool opens;               // this call opens the cycle (convergence check)
-    bool closes;              // this call closes the cycle (residual, colour-mean partials)
-    bool step_first;          // this call's first launch opens the step (builds the rhs)
-    bool fixed, store_rhs, cm;
+// ---- smoothing cycles and the end of a step (kernels_cycle.hip) -----------
+
+constexpr int kXcd = 8;  // XCDs of an MI355X: workgroup id mod 8 selects the XCD
+constexpr int kCmeansMaxM = 8 * 4 + 8 + 4 + 2;  // colour-mean sums per set, N <= 8, C <= 4
+constexpr int kNC = 8 * 4;                       // stride of one set of means
+
+// Per image, constant over a solve.
+struct CycleArgs {
     Bufs bufs;
     Ctl* ctl;
-    const float* image;
-    const double* tot;        // reduced colour-mean sums of u^n [cmeans_width]
-    const double* c_prev64;   // previous means for empty phases, or NULL
-    double* c64;              // out: the means of u^n
-    float* c_out;             // out (float), or NULL
-    float* rhs;
-    float* res_part;          // [2][part_stride]
-    double* cm_part;          // [2][cmeans_width][part_stride]
+    const float* image;       // [C][H][W]
+    double* tot;              // colour-mean sums, two sets [2][kCmeansMaxM]
+    double* c64;              // colour means, three sets [3][kNC]
+    float* c_out;             // out (float) by the step's first launch, or NULL
+    float* rhs;               // rhs' [N][H][W]: written by the first launch if store_rhs, else read
+    float* res_part;          // [2][part_stride]        row = cycle & 1
+    double* cm_part;          // [2][M][part_stride]     row = cycle & 1
     int part_stride;
     LevelCoef coef;
     RhsCoef rc;
     float tol;
+    int W, H;
+    int tiles_x, ntiles, tiles_per_xcd;
 };
+
+// Per launch.
+struct CycleStep {
+    int slot;       // control slot of this step (step index & 1)
+    int cycle;      // cycle index within the step
+    int first;      // this launch opens the cycle
+    int launch;     // launch index within the step (buffer parity)
+    int fixed;      // no convergence checks
+    int store_rhs;
+    int cm;         // closing launch accumulates colour-mean partials
+    int tot_sel;    // sums of u^n in tot set tot_sel; the step's end writes set tot_sel ^ 1
+    int c64_sel;    // the step's first launch writes the means of u^n to c64 set c64_sel
+    int prev_sel;   // previous means (empty phases) in c64 set prev_sel, or -1
+};
+
+// What a run of smoothing launches is within its step and cycle.
+struct CycleRole {
+    bool step_first;  // the first launch opens the step: it builds the right-hand side
+    bool opens;       // the first launch opens the cycle: convergence check
+    bool closes;      // the last launch closes the cycle: residual and colour-mean partials
+};
+
+// Where a launch's tiles come from: one image (descs == NULL) or a batch.
+struct CycleGrid {
+    const CycleArgs* descs;
+    const int2* work;
+    int nwork;
+};
+
+struct StepEndArgs {
+    int max_cycles, launches_per_cycle;
+};
+
+// A cycle's tiles are 64 x cycle_tile_rows(N) nodes.
+int cycle_tile_rows(int N);
 int cycle_launches(int sweeps);
 int cycle_tiles(int N, int W, int H);
-hipError_t launch_cycle(const CycleLaunch& c, hipStream_t s);
+// Fill the lattice / tiling fields of a (W, H, tiles_x, ntiles, tiles_per_xcd).
+void cycle_tiling(int N, int W, int H, CycleArgs* a);
 
-// End of a time step: the reduced colour-mean sums of the new iterate into
-// tot_next, the step's residual and cycle count, the buffer holding the
-// iterate, statistics; re-arms control slot slot ^ 1.
-hipError_t launch_step_end(int N, int C, int W, int H, Ctl* ctl, const float* res_part,
-                           const double* cm_part, int part_stride, int max_cycles,
-                           int launches_per_cycle, int slot, float tol, double* tot_next,
+// `sweeps` red-black projected block Gauss-Seidel sweeps of the current time
+// step (launches of at most two).  The step's first launch builds the
+// right-hand side from u^n (= bufs[ctl->cur]), the image and the colour-mean
+// sums (stored to `rhs` when later launches need it); a closing launch writes
+// per-tile residual partials and, with `cm`, colour-mean partials of its
+// output.  Unless `fixed`, a cycle's first launch checks the previous cycle's
+// residual and the rest of the step is skipped once it is <= tol.
+hipError_t launch_cycle(int N, int C, int sweeps, const CycleArgs& a, const CycleStep& st,
+                        const CycleGrid& g, CycleRole role, hipStream_t s);
+
+// End of a time step: the reduced colour-mean sums of the new iterate into tot
+// set st.tot_sel ^ 1, the step's residual and cycle count, the buffer holding
+// the iterate, statistics; re-arms control slot st.slot ^ 1.  With descs, for
+// the images imgs[0..nimg) of a batch.
+hipError_t launch_step_end(int N, int C, const CycleArgs& a, const CycleStep& st,
+                           const StepEndArgs& e, const CycleArgs* descs, const int* imgs, int nimg,
                            hipStream_t s);
 
 // One workgroup: colour means from reduced sums tot (empty phases keep

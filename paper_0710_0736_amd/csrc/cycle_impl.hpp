@@ -33,33 +33,7 @@ namespace acseg {
 
 __host__ __device__ constexpr int cycle_ty(int N) { return N <= 3 ? 32 : 16; }
 constexpr int kTX = 64;
-constexpr int kXcd = 8;
 
-struct CycleArgs {
-    Bufs bufs;
-    Ctl* ctl;
-    const float* image;       // [C][H][W]
-    const double* tot;        // colour-mean sums of u^n [M] (step's first launch)
-    const double* c_prev64;   // previous step's means (empty phases), or NULL
-    double* c64;              // out, block 0 of the first launch: the means of u^n
-    float* c_out;             // out (float), or NULL
-    float* rhs;               // rhs' [N][H][W]: written by the first launch if store_rhs, else read
-    float* res_part;          // [2][part_stride]        row = cycle & 1
-    double* cm_part;          // [2][M][part_stride]     row = cycle & 1
-    int part_stride;
-    LevelCoef coef;
-    RhsCoef rc;
-    float tol;
-    int slot;                 // control slot of this step (step index & 1)
-    int cycle;                // cycle index within the step
-    int first;                // this launch opens the cycle
-    int launch;               // launch index within the step (buffer parity)
-    int fixed;                // no convergence checks
-    int store_rhs;
-    int cm;                   // closing launch accumulates colour-mean partials
-    int W, H;
-    int tiles_x, ntiles, tiles_per_xcd;
-};
 
 constexpr int kCycT = 512;  // threads of a cycle workgroup (8 wave64)
 
@@ -85,8 +59,11 @@ __device__ __forceinline__ float block_max_t(float v, float* sh /* >= T/kWave */
     return r;
 }
 
+// One cycle launch on one tile.  The convergence check (a cycle's first
+// launch, adaptive schedules) is done by every workgroup of the image; the
+// one owning tile 0 records it.
 template <int N, int C, int K, bool FIRST, bool RESID>
-__global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
+__device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& st, int tile) {
     constexpr int T = kCycT;
     constexpr int TX = kTX, TY = cycle_ty(N);
     constexpr int R = 2 * K + (RESID ? 1 : 0);
@@ -118,29 +95,27 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
     __shared__ int flag;
 
     Ctl* ctl = a.ctl;
-    StepSlot* slot = &ctl->step[a.slot];
-    if (!a.fixed) {
+    StepSlot* slot = &ctl->step[st.slot];
+    if (!st.fixed) {
         if (slot->done) return;  // uniform: an earlier cycle of this step converged
-        if (a.first && a.cycle > 0) {
-            const float* prev = a.res_part + ((a.cycle - 1) & 1) * a.part_stride;
+        if (st.first && st.cycle > 0) {
+            const float* prev = a.res_part + ((st.cycle - 1) & 1) * a.part_stride;
             float r = 0.f;
             for (int b = threadIdx.x; b < a.ntiles; b += T) r = fmaxf(r, prev[b]);
             r = block_max_t<T>(r, red);
             if (threadIdx.x == 0) flag = !(r > a.tol);
             __syncthreads();
             if (flag) {
-                if (blockIdx.x == 0 && threadIdx.x == 0) {
+                if (tile == 0 && threadIdx.x == 0) {
                     slot->done = 1;
-                    slot->cycles = a.cycle;
+                    slot->cycles = st.cycle;
                     slot->resid = r;
                 }
                 return;
             }
         }
     }
-    const int tile = (blockIdx.x % kXcd) * a.tiles_per_xcd + blockIdx.x / kXcd;
-    if (tile >= a.ntiles) return;
-    const int cur = iterate_buf(ctl->cur, a.launch);
+    const int cur = iterate_buf(ctl->cur, st.launch);
     const int W = a.W, H = a.H;
     const int64_t P = (int64_t)W * H;
     // per-plane base pointers (uniform), 32-bit node indices
@@ -237,7 +212,7 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
             const int idx = threadIdx.x + q * T;
             const int oy = idx / TX, ox = idx - oy * TX;
             const int gx = x0 + R + ox, gy = y0 + R + oy;
-            on[q] = a.cm && gx < W && gy < H;
+            on[q] = st.cm && gx < W && gy < H;
             const int g = on[q] ? gy * W + gx : 0;
 #pragma unroll
             for (int k = 0; k < C; ++k) {
@@ -250,10 +225,12 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
     // the colour-mean sums of u^n (and the previous means, for empty phases)
     // join the burst: one value per thread of the first wave
     constexpr int NT = M + N * C;
+    const double* tot = a.tot + st.tot_sel * kCmeansMaxM;
+    const double* c_prev64 = st.prev_sel >= 0 ? a.c64 + st.prev_sel * kNC : nullptr;
     if (FIRST && threadIdx.x < NT) {
         const int t = threadIdx.x;
         const bool prev = t >= M;
-        const double* src = prev ? (a.c_prev64 ? a.c_prev64 : a.tot) : a.tot;
+        const double* src = prev ? (c_prev64 ? c_prev64 : tot) : tot;
         tsh[t] = src[prev ? t - M : t];
     }
 
@@ -283,19 +260,19 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
 #pragma unroll
                 for (int k = 0; k < C; ++k) {
                     const double c = has_mass ? tsh[i * C + k] / S
-                                              : (a.c_prev64 ? tsh[M + i * C + k]
-                                                            : tsh[N * C + N + k] / area);
+                                              : (c_prev64 ? tsh[M + i * C + k]
+                                                          : tsh[N * C + N + k] / area);
                     cs[i * C + k] = c;
                     q2 += c * c;
-                    if (blockIdx.x == 0) {
-                        a.c64[i * C + k] = c;
+                    if (tile == 0) {
+                        a.c64[st.c64_sel * kNC + i * C + k] = c;
                         if (a.c_out) a.c_out[i * C + k] = (float)c;
                     }
                 }
                 cs2[i] = q2;
             }
             const bool any_empty = __any(empty);
-            if (blockIdx.x == 0 && i == 0) {
+            if (tile == 0 && i == 0) {
                 if (any_empty) ctl->empty_steps += 1;
                 if (tsh[M - 1] > 0.0) ctl->nonfinite = 1;
             }
@@ -335,7 +312,7 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
 #pragma unroll
                     for (int i = 0; i < N; ++i) {
                         rv[i] = (float)(r[i] - rmax);
-                        if (a.store_rhs && rad == 0) const_cast<float*>(rhsp[i])[gy * W + gx] = rv[i];
+                        if (st.store_rhs && rad == 0) const_cast<float*>(rhsp[i])[gy * W + gx] = rv[i];
                     }
                 } else {
 #pragma unroll
@@ -421,10 +398,10 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
     if (!RESID) return;
 
     // ---- per-tile residual and colour-mean partials of the output
-    const int row = a.cycle & 1;
+    const int row = st.cycle & 1;
     const float bm = block_max_t<T>(res, red);
     if (threadIdx.x == 0) a.res_part[row * a.part_stride + tile] = bm;
-    if (!a.cm) return;
+    if (!st.cm) return;
     float acc[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) acc[q] = 0.f;
@@ -470,6 +447,28 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
     }
 }
 
+// One image: tiles in XCD-aware order (the workgroups of one XCD, id mod 8,
+// own a contiguous band of tiles).
+template <int N, int C, int K, bool FIRST, bool RESID>
+__global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a, CycleStep st) {
+    const int tile = (blockIdx.x % kXcd) * a.tiles_per_xcd + blockIdx.x / kXcd;
+    if (tile >= a.ntiles) return;
+    cycle_tile<N, C, K, FIRST, RESID>(a, st, tile);
+}
+
+// A batch of images with the same N and C: work[] lists (image, tile) of
+// every tile of the batch, already in XCD-aware order (image -1: nothing to
+// do); the per-image constants are read from the descriptor table.
+template <int N, int C, int K, bool FIRST, bool RESID>
+__global__ __launch_bounds__(kCycT) void k_cycle_batch(const CycleArgs* __restrict__ descs,
+                                                       const int2* __restrict__ work, int nwork,
+                                                       CycleStep st) {
+    if ((int)blockIdx.x >= nwork) return;
+    const int2 wv = work[blockIdx.x];
+    if (wv.x < 0) return;
+    cycle_tile<N, C, K, FIRST, RESID>(descs[wv.x], st, wv.y);
+}
+
 // ---------------------------------------------------------------------------
 // End of a time step, M + 1 workgroups.  Workgroup q < M sums row q of the
 // last cycle's colour-mean partials over the tiles (fixed order, so the
@@ -480,26 +479,15 @@ __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a) {
 // step after next.
 // ---------------------------------------------------------------------------
 
-struct StepEndArgs {
-    Ctl* ctl;
-    const float* res_part;
-    const double* cm_part;
-    double* tot_next;
-    int part_stride, ntiles;
-    int max_cycles, launches_per_cycle;
-    int slot;
-    float tol;
-};
-
 template <int N, int C>
-__global__ __launch_bounds__(kBlock) void k_step_end(StepEndArgs a) {
+__device__ __forceinline__ void step_end(const CycleArgs& a, const CycleStep& st, const StepEndArgs& e) {
     constexpr int M = N * C + N + C + 2;
     __shared__ float red[kBlock / kWave];
     __shared__ double shd[kBlock / kWave];
     Ctl* ctl = a.ctl;
-    StepSlot* slot = &ctl->step[a.slot];
+    StepSlot* slot = &ctl->step[st.slot];
     const int done = slot->done;
-    const int cycles = done ? slot->cycles : a.max_cycles;
+    const int cycles = done ? slot->cycles : e.max_cycles;
     if ((int)blockIdx.x < M) {
         const int q = blockIdx.x;
         const double* row = a.cm_part + ((int64_t)((cycles - 1) & 1) * M + q) * a.part_stride;
@@ -511,7 +499,7 @@ __global__ __launch_bounds__(kBlock) void k_step_end(StepEndArgs a) {
         if (threadIdx.x == 0) {
             double s = 0.0;
             for (int w = 0; w < kBlock / kWave; ++w) s += shd[w];
-            a.tot_next[q] = s;
+            a.tot[(st.tot_sel ^ 1) * kCmeansMaxM + q] = s;
         }
         return;
     }
@@ -519,103 +507,123 @@ __global__ __launch_bounds__(kBlock) void k_step_end(StepEndArgs a) {
     if (done) {
         resid = slot->resid;
     } else {
-        const float* last = a.res_part + ((a.max_cycles - 1) & 1) * a.part_stride;
+        const float* last = a.res_part + ((e.max_cycles - 1) & 1) * a.part_stride;
         float r = 0.f;
         for (int b = threadIdx.x; b < a.ntiles; b += kBlock) r = fmaxf(r, last[b]);
         resid = block_max(r, red);
     }
     if (threadIdx.x != 0) return;
-    ctl->cur = iterate_buf(ctl->cur, cycles * a.launches_per_cycle);
+    ctl->cur = iterate_buf(ctl->cur, cycles * e.launches_per_cycle);
     ctl->resid = resid;
     ctl->cycles_total += cycles;
     ctl->cycles_max = cycles > ctl->cycles_max ? cycles : ctl->cycles_max;
     if (resid > a.tol) ctl->steps_unconv += 1;
     ctl->max_resid = fmaxf(ctl->max_resid, resid);
     ctl->steps_done += 1;
-    StepSlot* next = &ctl->step[a.slot ^ 1];
+    StepSlot* next = &ctl->step[st.slot ^ 1];
     next->done = 0;
     next->cycles = 0;
     next->resid = 0.f;
 }
 
+template <int N, int C>
+__global__ __launch_bounds__(kBlock) void k_step_end(CycleArgs a, CycleStep st, StepEndArgs e) {
+    step_end<N, C>(a, st, e);
+}
+
+// blockIdx.y: position in imgs[] (the images of one batch group)
+template <int N, int C>
+__global__ __launch_bounds__(kBlock) void k_step_end_batch(const CycleArgs* __restrict__ descs,
+                                                           const int* __restrict__ imgs, CycleStep st,
+                                                           StepEndArgs e) {
+    step_end<N, C>(descs[imgs[blockIdx.y]], st, e);
+}
+
 int cycle_launches(int sweeps);
 
 template <int N, int C, int K, bool FIRST, bool RESID>
-hipError_t run_cycle(CycleArgs a, hipStream_t s) {
+hipError_t run_cycle(const CycleArgs& a, const CycleStep& st, const CycleGrid& g, hipStream_t s) {
     constexpr int lds = cycle_lds_bytes<N, K, RESID>();
     static_assert(lds <= 65536, "tile does not fit in 64 KiB of LDS");
-    hipLaunchKernelGGL((k_cycle<N, C, K, FIRST, RESID>), dim3(a.tiles_per_xcd * kXcd), dim3(kCycT),
-                       lds, s, a);
+    if (g.descs)
+        hipLaunchKernelGGL((k_cycle_batch<N, C, K, FIRST, RESID>), dim3(g.nwork), dim3(kCycT), lds, s,
+                           g.descs, g.work, g.nwork, st);
+    else
+        hipLaunchKernelGGL((k_cycle<N, C, K, FIRST, RESID>), dim3(a.tiles_per_xcd * kXcd), dim3(kCycT),
+                           lds, s, a, st);
     return hipGetLastError();
 }
 
-// What a run of smoothing launches is within its step and cycle.
-struct CycleRole {
-    bool step_first;  // the first launch opens the step: it builds the right-hand side
-    bool opens;       // the first launch opens the cycle: convergence check
-    bool closes;      // the last launch closes the cycle: residual and colour-mean partials
-};
-
 // `sweeps` sweeps in launches of at most two.
 template <int N, int C>
-hipError_t run_cycle_nc(int sweeps, CycleArgs a, CycleRole role, hipStream_t s) {
+hipError_t run_cycle_nc(int sweeps, const CycleArgs& a, CycleStep st, const CycleGrid& g, CycleRole role,
+                        hipStream_t s) {
     const int nl = cycle_launches(sweeps);
-    const int base = a.launch;
+    const int base = st.launch;
     hipError_t e = hipSuccess;
     for (int k = 0; k < nl && e == hipSuccess; ++k) {
         const int kk = (k < nl - 1 || sweeps % 2 == 0) ? 2 : 1;
         const bool last = role.closes && k == nl - 1;
         const bool first = role.step_first && k == 0;
-        a.first = role.opens && k == 0;
-        a.launch = base + k;
+        st.first = role.opens && k == 0;
+        st.launch = base + k;
         if (kk == 2) {
             if (first)
-                e = last ? run_cycle<N, C, 2, true, true>(a, s) : run_cycle<N, C, 2, true, false>(a, s);
+                e = last ? run_cycle<N, C, 2, true, true>(a, st, g, s) : run_cycle<N, C, 2, true, false>(a, st, g, s);
             else
-                e = last ? run_cycle<N, C, 2, false, true>(a, s) : run_cycle<N, C, 2, false, false>(a, s);
+                e = last ? run_cycle<N, C, 2, false, true>(a, st, g, s) : run_cycle<N, C, 2, false, false>(a, st, g, s);
         } else {
             if (first)
-                e = last ? run_cycle<N, C, 1, true, true>(a, s) : run_cycle<N, C, 1, true, false>(a, s);
+                e = last ? run_cycle<N, C, 1, true, true>(a, st, g, s) : run_cycle<N, C, 1, true, false>(a, st, g, s);
             else
-                e = last ? run_cycle<N, C, 1, false, true>(a, s) : run_cycle<N, C, 1, false, false>(a, s);
+                e = last ? run_cycle<N, C, 1, false, true>(a, st, g, s) : run_cycle<N, C, 1, false, false>(a, st, g, s);
         }
     }
     return e;
 }
 
 template <int N, int C>
-hipError_t run_step_end_nc(const StepEndArgs& a, hipStream_t s) {
+hipError_t run_step_end_nc(const CycleArgs& a, const CycleStep& st, const StepEndArgs& e,
+                           const CycleArgs* descs, const int* imgs, int nimg, hipStream_t s) {
     constexpr int M = N * C + N + C + 2;
-    hipLaunchKernelGGL((k_step_end<N, C>), dim3(M + 1), dim3(kBlock), 0, s, a);
+    if (descs)
+        hipLaunchKernelGGL((k_step_end_batch<N, C>), dim3(M + 1, nimg), dim3(kBlock), 0, s, descs, imgs, st, e);
+    else
+        hipLaunchKernelGGL((k_step_end<N, C>), dim3(M + 1), dim3(kBlock), 0, s, a, st, e);
     return hipGetLastError();
 }
 
 // Per-N entry points, each instantiated in its own translation unit.
 template <int N>
-hipError_t cycle_for_n(int C, int sweeps, const CycleArgs& a, CycleRole role, hipStream_t s) {
+hipError_t cycle_for_n(int C, int sweeps, const CycleArgs& a, const CycleStep& st, const CycleGrid& g,
+                       CycleRole role, hipStream_t s) {
     switch (C) {
-        case 1: return run_cycle_nc<N, 1>(sweeps, a, role, s);
-        case 2: return run_cycle_nc<N, 2>(sweeps, a, role, s);
-        case 3: return run_cycle_nc<N, 3>(sweeps, a, role, s);
-        case 4: return run_cycle_nc<N, 4>(sweeps, a, role, s);
+        case 1: return run_cycle_nc<N, 1>(sweeps, a, st, g, role, s);
+        case 2: return run_cycle_nc<N, 2>(sweeps, a, st, g, role, s);
+        case 3: return run_cycle_nc<N, 3>(sweeps, a, st, g, role, s);
+        case 4: return run_cycle_nc<N, 4>(sweeps, a, st, g, role, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int N>
-hipError_t step_end_for_n(int C, const StepEndArgs& a, hipStream_t s) {
+hipError_t step_end_for_n(int C, const CycleArgs& a, const CycleStep& st, const StepEndArgs& e,
+                          const CycleArgs* descs, const int* imgs, int nimg, hipStream_t s) {
     switch (C) {
-        case 1: return run_step_end_nc<N, 1>(a, s);
-        case 2: return run_step_end_nc<N, 2>(a, s);
-        case 3: return run_step_end_nc<N, 3>(a, s);
-        case 4: return run_step_end_nc<N, 4>(a, s);
+        case 1: return run_step_end_nc<N, 1>(a, st, e, descs, imgs, nimg, s);
+        case 2: return run_step_end_nc<N, 2>(a, st, e, descs, imgs, nimg, s);
+        case 3: return run_step_end_nc<N, 3>(a, st, e, descs, imgs, nimg, s);
+        case 4: return run_step_end_nc<N, 4>(a, st, e, descs, imgs, nimg, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-#define ACSEG_CYCLE_EXTERN(n)                                                                   \
-    extern template hipError_t cycle_for_n<n>(int, int, const CycleArgs&, CycleRole, hipStream_t); \
-    extern template hipError_t step_end_for_n<n>(int, const StepEndArgs&, hipStream_t);
+#define ACSEG_CYCLE_EXTERN(n)                                                                  \
+    extern template hipError_t cycle_for_n<n>(int, int, const CycleArgs&, const CycleStep&,      \
+                                              const CycleGrid&, CycleRole, hipStream_t);         \
+    extern template hipError_t step_end_for_n<n>(int, const CycleArgs&, const CycleStep&,        \
+                                                 const StepEndArgs&, const CycleArgs*, const int*, \
+                                                 int, hipStream_t);
 ACSEG_CYCLE_EXTERN(2)
 ACSEG_CYCLE_EXTERN(3)
 ACSEG_CYCLE_EXTERN(4)

@@ -2,6 +2,8 @@
 #include "cycle_impl.hpp"
 
 namespace acseg {
-template hipError_t cycle_for_n<3>(int, int, const CycleArgs&, CycleRole, hipStream_t);
-template hipError_t step_end_for_n<3>(int, const StepEndArgs&, hipStream_t);
+template hipError_t cycle_for_n<3>(int, int, const CycleArgs&, const CycleStep&, const CycleGrid&,
+                                    CycleRole, hipStream_t);
+template hipError_t step_end_for_n<3>(int, const CycleArgs&, const CycleStep&, const StepEndArgs&,
+                                       const CycleArgs*, const int*, int, hipStream_t);
 }  // namespace acseg

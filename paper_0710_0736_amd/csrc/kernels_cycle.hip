@@ -5,75 +5,47 @@
 
 namespace acseg {
 
+int cycle_tile_rows(int N) { return cycle_ty(N); }
+
 int cycle_launches(int sweeps) { return (sweeps + 1) / 2; }
 
 int cycle_tiles(int N, int W, int H) {
     return ((W + kTX - 1) / kTX) * ((H + cycle_ty(N) - 1) / cycle_ty(N));
 }
 
-hipError_t launch_cycle(const CycleLaunch& c, hipStream_t s) {
-    CycleArgs a{};
-    a.bufs = c.bufs;
-    a.ctl = c.ctl;
-    a.image = c.image;
-    a.tot = c.tot;
-    a.c_prev64 = c.c_prev64;
-    a.c64 = c.c64;
-    a.c_out = c.c_out;
-    a.rhs = c.rhs;
-    a.res_part = c.res_part;
-    a.cm_part = c.cm_part;
-    a.part_stride = c.part_stride;
-    a.coef = c.coef;
-    a.rc = c.rc;
-    a.tol = c.tol;
-    a.slot = c.slot;
-    a.cycle = c.cycle;
-    a.launch = c.launch0;
-    a.fixed = c.fixed ? 1 : 0;
-    a.store_rhs = c.store_rhs ? 1 : 0;
-    a.cm = c.cm ? 1 : 0;
-    a.W = c.W;
-    a.H = c.H;
-    a.tiles_x = (c.W + kTX - 1) / kTX;
-    a.ntiles = cycle_tiles(c.N, c.W, c.H);
-    a.tiles_per_xcd = (a.ntiles + kXcd - 1) / kXcd;
-    const CycleRole role{c.step_first, c.opens, c.closes};
-    switch (c.N) {
-        case 2: return cycle_for_n<2>(c.C, c.sweeps, a, role, s);
-        case 3: return cycle_for_n<3>(c.C, c.sweeps, a, role, s);
-        case 4: return cycle_for_n<4>(c.C, c.sweeps, a, role, s);
-        case 5: return cycle_for_n<5>(c.C, c.sweeps, a, role, s);
-        case 6: return cycle_for_n<6>(c.C, c.sweeps, a, role, s);
-        case 7: return cycle_for_n<7>(c.C, c.sweeps, a, role, s);
-        case 8: return cycle_for_n<8>(c.C, c.sweeps, a, role, s);
+void cycle_tiling(int N, int W, int H, CycleArgs* a) {
+    a->W = W;
+    a->H = H;
+    a->tiles_x = (W + kTX - 1) / kTX;
+    a->ntiles = cycle_tiles(N, W, H);
+    a->tiles_per_xcd = (a->ntiles + kXcd - 1) / kXcd;
+}
+
+hipError_t launch_cycle(int N, int C, int sweeps, const CycleArgs& a, const CycleStep& st,
+                        const CycleGrid& g, CycleRole role, hipStream_t s) {
+    switch (N) {
+        case 2: return cycle_for_n<2>(C, sweeps, a, st, g, role, s);
+        case 3: return cycle_for_n<3>(C, sweeps, a, st, g, role, s);
+        case 4: return cycle_for_n<4>(C, sweeps, a, st, g, role, s);
+        case 5: return cycle_for_n<5>(C, sweeps, a, st, g, role, s);
+        case 6: return cycle_for_n<6>(C, sweeps, a, st, g, role, s);
+        case 7: return cycle_for_n<7>(C, sweeps, a, st, g, role, s);
+        case 8: return cycle_for_n<8>(C, sweeps, a, st, g, role, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_step_end(int N, int C, int W, int H, Ctl* ctl, const float* res_part,
-                           const double* cm_part, int part_stride, int max_cycles,
-                           int launches_per_cycle, int slot, float tol, double* tot_next,
+hipError_t launch_step_end(int N, int C, const CycleArgs& a, const CycleStep& st,
+                           const StepEndArgs& e, const CycleArgs* descs, const int* imgs, int nimg,
                            hipStream_t s) {
-    StepEndArgs a{};
-    a.ctl = ctl;
-    a.res_part = res_part;
-    a.cm_part = cm_part;
-    a.tot_next = tot_next;
-    a.part_stride = part_stride;
-    a.ntiles = cycle_tiles(N, W, H);
-    a.max_cycles = max_cycles;
-    a.launches_per_cycle = launches_per_cycle;
-    a.slot = slot;
-    a.tol = tol;
     switch (N) {
-        case 2: return step_end_for_n<2>(C, a, s);
-        case 3: return step_end_for_n<3>(C, a, s);
-        case 4: return step_end_for_n<4>(C, a, s);
-        case 5: return step_end_for_n<5>(C, a, s);
-        case 6: return step_end_for_n<6>(C, a, s);
-        case 7: return step_end_for_n<7>(C, a, s);
-        case 8: return step_end_for_n<8>(C, a, s);
+        case 2: return step_end_for_n<2>(C, a, st, e, descs, imgs, nimg, s);
+        case 3: return step_end_for_n<3>(C, a, st, e, descs, imgs, nimg, s);
+        case 4: return step_end_for_n<4>(C, a, st, e, descs, imgs, nimg, s);
+        case 5: return step_end_for_n<5>(C, a, st, e, descs, imgs, nimg, s);
+        case 6: return step_end_for_n<6>(C, a, st, e, descs, imgs, nimg, s);
+        case 7: return step_end_for_n<7>(C, a, st, e, descs, imgs, nimg, s);
+        case 8: return step_end_for_n<8>(C, a, st, e, descs, imgs, nimg, s);
         default: return hipErrorInvalidValue;
     }
 }

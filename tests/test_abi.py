@@ -77,3 +77,35 @@ def test_generators_are_deterministic():
     assert img.dtype == np.float32 and u0.dtype == np.float32
     assert np.abs(u0.sum(0) - 1).max() < 1e-6 and u0.min() > 0
     assert set(np.unique(lab)) <= set(range(4))
+
+
+def _batch_code(problems):
+    n = ctypes.c_size_t()
+    arr = (acseg._Problem * max(1, len(problems)))(*[p.c() for p in problems])
+    return acseg.lib().acseg_batch_workspace_size(len(problems), arr, ctypes.byref(n)), n.value
+
+
+def test_batch_validation_codes():
+    a, b = base_problem(), base_problem(W=96, H=33, N=3, C=1, lam=10.0)
+    code, size = _batch_code([a, b])
+    assert code == acseg.OK and size > acseg.workspace_size(a) + acseg.workspace_size(b)
+    assert _batch_code([])[0] == acseg.ERR_INVALID_ARG
+    assert _batch_code([a, base_problem(steps=6)])[0] == acseg.ERR_INVALID_ARG
+    assert _batch_code([a, base_problem(max_cycles=7)])[0] == acseg.ERR_INVALID_ARG
+    assert _batch_code([a, base_problem(nu_post=2)])[0] == acseg.ERR_INVALID_ARG
+    ck = base_problem(flags=acseg.FLAG_STORE_CHECKPOINTS)
+    assert _batch_code([ck])[0] == acseg.ERR_INVALID_ARG
+    assert _batch_code([a, base_problem(levels=2)])[0] == acseg.ERR_UNSUPPORTED
+    assert _batch_code([a, base_problem(N=9)])[0] == acseg.ERR_UNSUPPORTED
+
+
+def test_multigrid_validation_codes():
+    n = ctypes.c_size_t()
+    for kw, code in [(dict(levels=3, nu_pre=0, nu_post=2), acseg.ERR_UNSUPPORTED),
+                     (dict(levels=3, nu_pre=2, nu_post=0), acseg.ERR_UNSUPPORTED),
+                     (dict(levels=3), acseg.OK), (dict(levels=0), acseg.OK),
+                     (dict(levels=1, nu_pre=0, nu_post=2), acseg.OK)]:
+        p = base_problem(**kw)
+        assert acseg.lib().acseg_workspace_size(ctypes.byref(p.c()), ctypes.byref(n)) == code, kw
+    # the multigrid hierarchy needs its own buffers
+    assert acseg.workspace_size(base_problem(levels=3)) > acseg.workspace_size(base_problem(levels=1))

@@ -1,0 +1,69 @@
+"""The batched solve against one-image solves.
+
+Every image of a batch runs the same kernels on the same tiles with its own
+convergence control, and every reduction has a fixed order, so each result
+must be bit-identical to the one-image solve of the same problem.  The
+one-image solve itself is held to the oracle by test_gpu_parity.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_0710_0736_amd import acseg, synth
+from test_gpu_parity import cuda
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [  # W, H, N, C, lambda, seed
+    (96, 80, 4, 3, 100.0, 1), (37, 53, 3, 3, 50.0, 2), (150, 64, 2, 1, 100.0, 3),
+    (64, 64, 4, 3, 20.0, 4), (200, 120, 3, 3, 100.0, 5), (70, 130, 4, 3, 100.0, 6),
+]
+
+
+def make_batch(pixel: bool, steps: int, max_cycles: int, flags: int = 0):
+    problems, images, u0s = [], [], []
+    for (W, H, N, C, lam, seed) in SPECS:
+        base = synth.pixel_twin(synth.VORONOI1024) if pixel else synth.VORONOI1024
+        w = base.scaled(W, H, N=N, lam=lam)
+        img, u0, _ = w.make(seed)
+        if C == 1:
+            img = img.mean(axis=0, keepdims=True)
+        problems.append(acseg.Problem.from_workload(w, C=C, levels=1, steps=steps, tol=1e-6,
+                                                    max_cycles=max_cycles, flags=flags))
+        images.append(cuda(img))
+        u0s.append(cuda(u0))
+    return problems, images, u0s
+
+
+@pytest.mark.parametrize("pixel,fixed", [(False, False), (False, True), (True, False)])
+def test_batched_equals_single(pixel, fixed):
+    steps = 3 if pixel else 6
+    flags = acseg.FLAG_FIXED_CYCLES if fixed else 0
+    problems, images, u0s = make_batch(pixel, steps, 4 if fixed else 300, flags)
+    singles = []
+    for p, im, u0 in zip(problems, images, u0s):
+        u, c, st, _ = acseg.solve(p, im, u0.clone())
+        singles.append((u, c, st))
+    us = [u0.clone() for u0 in u0s]
+    us, cs, sts = acseg.solve_batched(problems, images, us)
+    torch.cuda.synchronize()
+    for b, (u, c, st) in enumerate(singles):
+        assert torch.equal(us[b], u), b
+        assert torch.equal(cs[b], c), b
+        assert sts[b] == st, (b, sts[b], st)
+    if pixel:  # the images converge after different cycle counts
+        assert len({st["cycles_total"] for _, _, st in singles}) > 1
+
+
+def test_batch_of_one_full_size_image_and_repeat_calls():
+    w = synth.VORONOI1024
+    img, u0, _ = w.make(0)
+    p = acseg.Problem.from_workload(w, levels=1, steps=4, max_cycles=1, flags=acseg.FLAG_FIXED_CYCLES)
+    I, U0 = cuda(img), cuda(u0)
+    u_s, c_s, st_s, _ = acseg.solve(p, I, U0.clone())
+    for _ in range(2):  # the descriptor upload of one call must not disturb the next
+        us, cs, sts = acseg.solve_batched([p, p], [I, I], [U0.clone(), U0.clone()])
+        torch.cuda.synchronize()
+        for b in range(2):
+            assert torch.equal(us[b], u_s) and torch.equal(cs[b], c_s)
+            assert sts[b]["final_residual"] == st_s["final_residual"]
