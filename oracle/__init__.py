@@ -101,6 +101,9 @@ def lib():
         L.orc_energy.restype = ctypes.c_double
         L.orc_labels.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp,
                                  ctypes.POINTER(ctypes.c_uint8), dp, dp]
+        L.orc_adjoint_solve.argtypes = [pp, dp, dp, dp]
+        L.orc_adjoint_step.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_backward.argtypes = [pp, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -242,3 +245,39 @@ def labels(u, c):
     lib().orc_labels(N, C, H, W, _p(u), _p(c), lab.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                      _p(comp), _p(rnd))
     return lab, comp, rnd
+
+
+def adjoint_solve(P: Params, unext, ubar):
+    """z = (T H T)^+ T ubar with the free sets of unext (the gradient at b)."""
+    unext, ubar = _d(unext), _d(ubar)
+    z = np.empty_like(ubar)
+    if lib().orc_adjoint_solve(ctypes.byref(P.c()), _p(unext), _p(ubar), _p(z)) < 0:
+        raise ValueError("bad parameters")
+    return z
+
+
+def adjoint_step(P: Params, I, un, unext, ubar_next, c_prev=None):
+    """One step backwards: returns (ubar_n, Ibar, grads [lambda, eps, tau], cbar [N][C])."""
+    I, un, unext, ubar_next = _d(I), _d(un), _d(unext), _d(ubar_next)
+    ubar_n = np.empty_like(un)
+    Ibar = np.zeros_like(I)
+    grads = np.zeros(3)
+    cbar = np.empty((P.N, P.C))
+    cp = None if c_prev is None else _d(c_prev)
+    if lib().orc_adjoint_step(ctypes.byref(P.c()), _p(I), _p(un), _p(cp), _p(unext), _p(ubar_next),
+                              _p(ubar_n), _p(Ibar), _p(grads), _p(cbar)):
+        raise ValueError("bad parameters")
+    return ubar_n, Ibar, grads, cbar
+
+
+def backward(P: Params, steps: int, I, traj, ubar_T):
+    """Backwards through a trajectory u^0..u^steps; returns (Ibar, grads, cbar, ubar0)."""
+    I, traj, ubar_T = _d(I), _d(traj), _d(ubar_T)
+    Ibar = np.empty_like(I)
+    grads = np.empty(3)
+    cbar = np.empty((max(steps, 1), P.N, P.C))
+    ubar0 = np.empty_like(ubar_T)
+    if lib().orc_backward(ctypes.byref(P.c()), steps, _p(I), _p(traj), _p(ubar_T), _p(Ibar),
+                          _p(grads), _p(cbar), _p(ubar0)):
+        raise ValueError("bad parameters")
+    return Ibar, grads, cbar[:steps], ubar0
