@@ -240,6 +240,28 @@ acseg_status acseg_energy(acseg_ctx *ctx, const acseg_problem *p, const float *i
                           void *stream);
 
 /*
+ * Gradients of a loss L(u^steps) through a solve (the derivative of the
+ * discrete time steps of eq. alpha; the paper does not differentiate them).
+ * checkpoints: float[steps+1][N][H][W], u^0..u^steps of an acseg_solve of p
+ * (ACSEG_FLAG_STORE_CHECKPOINTS); grad_uT: float[N][H][W] = dL/du^steps.
+ * Outputs (device): grad_image float[C][H][W] = dL/dI; grad_u0
+ * float[N][H][W] = dL/du^0 (may be NULL); grad_params double[3] = dL/dlambda,
+ * dL/deps at fixed tau, dL/dtau; grad_c float[steps][N][C] = dL/dc^n, the
+ * gradient at the colour means used by step n (may be NULL).  Each step's
+ * derivative holds the free sets {i : u^{n+1}_pi > 0} fixed (components at 0
+ * count as active) and treats the kept mean of an empty phase as a constant.
+ * The per-step linear solves are red-black sweeps to a relative change of
+ * max(tol, 2e-7), at most max(4, 2 max_cycles) sweeps (stats count steps that
+ * hit the cap as not converged, and the sweeps as cycles).  Workspace from
+ * acseg_backward_workspace_size.
+ */
+acseg_status acseg_backward_workspace_size(const acseg_problem *p, size_t *bytes);
+acseg_status acseg_backward(acseg_ctx *ctx, const acseg_problem *p, const float *image,
+                            const float *checkpoints, const float *grad_uT, float *grad_image,
+                            float *grad_u0, double *grad_params, float *grad_c,
+                            acseg_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Kernel timing (profiling aid).  While enabled on a context, the calls
  * acseg_step and acseg_solve bracket each kernel family they enqueue with HIP
  * events on the call's stream; acseg_timing_read waits for those events, adds

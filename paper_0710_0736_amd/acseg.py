@@ -113,6 +113,8 @@ def lib():
         L.acseg_step.argtypes = [vp, pp, vp, vp, vp, vp, vp, sp, vp, sz, vp]
         L.acseg_solve.argtypes = [vp, pp, vp, vp, vp, vp, sp, vp, sz, vp]
         L.acseg_labels.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp]
+        L.acseg_backward_workspace_size.argtypes = [pp, ctypes.POINTER(sz)]
+        L.acseg_backward.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp, vp, sp, vp, sz, vp]
         L.acseg_batch_workspace_size.argtypes = [ctypes.c_int32, pp, ctypes.POINTER(sz)]
         L.acseg_solve_batched.argtypes = [vp, ctypes.c_int32, pp, ctypes.POINTER(vp),
                                           ctypes.POINTER(vp), ctypes.POINTER(vp), sp, vp, sz, vp]
@@ -305,6 +307,66 @@ def solve_batched(problems, images, us, want_stats: bool = True, c_out: bool = T
                                      st if want_stats else None, _ptr(ws), ws.numel(), _stream()),
            "acseg_solve_batched")
     return us, cs, ([_stats_dict(x) for x in st] if want_stats else None)
+
+
+def backward(p: Problem, image: torch.Tensor, checkpoints: torch.Tensor, grad_uT: torch.Tensor,
+             want_stats: bool = True):
+    """Gradients of L(u^steps) given dL/du^steps and the checkpoints of a solve.
+
+    Returns (grad_image [C][H][W], grad_u0 [N][H][W], grad_params float64 [3]
+    (lambda, eps at fixed tau, tau), grad_c [steps][N][C], stats or None).
+    """
+    _need(image, (p.C, p.H, p.W), name="image")
+    _need(checkpoints, (p.steps + 1, p.N, p.H, p.W), name="checkpoints")
+    _need(grad_uT, (p.N, p.H, p.W), name="grad_uT")
+    dev = image.device
+    gI = torch.empty_like(image)
+    gu0 = torch.empty_like(grad_uT)
+    gp = torch.empty(3, dtype=torch.float64, device=dev)
+    gc = torch.empty((max(p.steps, 1), p.N, p.C), dtype=torch.float32, device=dev)
+    n = ctypes.c_size_t()
+    _check(lib().acseg_backward_workspace_size(ctypes.byref(p.c()), ctypes.byref(n)),
+           "backward_workspace_size")
+    ws = _ws_cache.get(("backward", dev))
+    if ws is None or ws.numel() < n.value:
+        ws = torch.empty(max(n.value, 1), dtype=torch.uint8, device=dev)
+        _ws_cache[("backward", dev)] = ws
+    st = _Stats()
+    _check(lib().acseg_backward(ctx(dev.index), ctypes.byref(p.c()), _ptr(image), _ptr(checkpoints),
+                                _ptr(grad_uT), _ptr(gI), _ptr(gu0), _ptr(gp), _ptr(gc),
+                                ctypes.byref(st) if want_stats else None, _ptr(ws), ws.numel(),
+                                _stream()), "acseg_backward")
+    return gI, gu0, gp, gc[:p.steps], (_stats_dict(st) if want_stats else None)
+
+
+class SegmentFn(torch.autograd.Function):
+    """u^steps of a solve as a differentiable function of (image, u0, lambda, eps, tau).
+
+    ``SegmentFn.apply(image, u0, lam, eps, tau, problem)``: lam, eps and tau
+    are scalar tensors (they replace the problem's values); the gradient with
+    respect to eps is taken at fixed tau.  The backward pass runs the library's
+    adjoint from the checkpoints stored by the forward pass.
+    """
+
+    @staticmethod
+    def forward(fctx, image, u0, lam, eps, tau, problem: Problem):
+        p = replace(problem, lam=float(lam), eps=float(eps), tau=float(tau))
+        img = image.detach().contiguous()
+        u = u0.detach().clone().contiguous()
+        u, _, _, ck = solve(p, img, u, checkpoints=True, want_stats=False, c_out=False)
+        fctx.save_for_backward(img, ck)
+        fctx.p = p
+        fctx.scalars = (lam, eps, tau)
+        return u
+
+    @staticmethod
+    def backward(fctx, grad_u):
+        img, ck = fctx.saved_tensors
+        gI, gu0, gp, _, _ = backward(fctx.p, img, ck, grad_u.contiguous().float(), want_stats=False)
+        outs = []
+        for k, t in enumerate(fctx.scalars):
+            outs.append(gp[k].to(t.device, t.dtype) if isinstance(t, torch.Tensor) else None)
+        return (gI, gu0, *outs, None)
 
 
 def labels(p: Problem, u: torch.Tensor, c: torch.Tensor):

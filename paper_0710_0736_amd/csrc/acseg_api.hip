@@ -566,6 +566,37 @@ BatchLayout batch_layout_of(int32_t B, const acseg_problem* ps) {
     return bl;
 }
 
+// ---- backward ---------------------------------------------------------------
+
+struct BackLayout {
+    size_t ctl = 0, actl = 0, c64 = 0, tot = 0, part_cm = 0, part_adj = 0, part_f = 0, cbar = 0;
+    size_t z = 0, ub0 = 0, ub1 = 0, total = 0;
+};
+
+BackLayout back_layout_of(const acseg_problem* p) {
+    BackLayout L;
+    const size_t n = (size_t)p->W * p->H, S = (size_t)std::max(p->steps, 1);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L.ctl = take(sizeof(Ctl));
+    L.actl = take(sizeof(AdjCtl));
+    L.c64 = take(sizeof(double) * S * kNC);
+    L.tot = take(sizeof(double) * S * kCmeansMaxM);
+    L.part_cm = take(sizeof(double) * (size_t)kCmeansBlocks * kCmeansMaxM);
+    L.part_adj = take(sizeof(double) * (size_t)kMgBlocks * (3 + kNC));
+    L.part_f = take(sizeof(float) * 2 * kMgBlocks);
+    L.cbar = take(sizeof(double) * kNC);
+    L.z = take(sizeof(float) * p->N * n);
+    L.ub0 = take(sizeof(float) * p->N * n);
+    L.ub1 = take(sizeof(float) * p->N * n);
+    L.total = off;
+    return L;
+}
+
 }  // namespace
 
 extern "C" {
@@ -870,6 +901,100 @@ acseg_status acseg_labels(acseg_ctx* ctx, const acseg_problem* p, const float* u
     if (!ctx || !u || !c) return ACSEG_ERR_INVALID_ARG;
     return hip_status(launch_labels(p->N, p->C, p->W, p->H, u, c, labels, composite, rounded,
                                     (hipStream_t)stream));
+}
+
+acseg_status acseg_backward_workspace_size(const acseg_problem* p, size_t* bytes) {
+    if (!bytes) return ACSEG_ERR_INVALID_ARG;
+    const acseg_status v = validate(p, true);
+    if (v != ACSEG_OK) return v;
+    *bytes = back_layout_of(p).total;
+    return ACSEG_OK;
+}
+
+acseg_status acseg_backward(acseg_ctx* ctx, const acseg_problem* p, const float* image,
+                            const float* checkpoints, const float* grad_uT, float* grad_image,
+                            float* grad_u0, double* grad_params, float* grad_c,
+                            acseg_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+    acseg_status v = validate(p, true);
+    if (v != ACSEG_OK) return v;
+    if (!ctx || !image || !checkpoints || !grad_uT || !grad_image || !grad_params)
+        return ACSEG_ERR_INVALID_ARG;
+    const BackLayout L = back_layout_of(p);
+    if (!ws || ((uintptr_t)ws % kAlign) != 0 || ws_bytes < L.total) return ACSEG_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const int N = p->N, C = p->C, W = p->W, H = p->H;
+    const int64_t n = (int64_t)W * H, nu = (int64_t)N * n;
+    Ctl* ctl = at<Ctl>(ws, L.ctl);
+    AdjCtl* actl = at<AdjCtl>(ws, L.actl);
+    double* c64 = at<double>(ws, L.c64);
+    double* tot = at<double>(ws, L.tot);
+    ACSEG_TRY(launch_ctl_init(ctl, 0, s));
+    ACSEG_TRY(launch_adj_init(actl, grad_params, s));
+    ACSEG_TRY(launch_fill(grad_image, (int64_t)C * n, 0.f, s));
+    // the means of every step, recomputed from the checkpoints
+    for (int st = 0; st < p->steps; ++st) {
+        const float* u = checkpoints + st * nu;
+        const Bufs bufs{{u, u, u}};
+        double* part = at<double>(ws, L.part_cm);
+        ACSEG_TRY(launch_cmeans(N, C, W, H, image, u, bufs, ctl, part, s));
+        ACSEG_TRY(launch_cmeans_finish(N, C, W, H, part, ctl, st > 0 ? c64 + (st - 1) * kNC : nullptr,
+                                       c64 + st * kNC, nullptr, tot + st * kCmeansMaxM, s));
+    }
+    AdjArgs a{};
+    a.ctl = ctl;
+    a.actl = actl;
+    a.image = image;
+    a.z = at<float>(ws, L.z);
+    a.Ibar = grad_image;
+    a.grads = grad_params;
+    a.cbar64 = at<double>(ws, L.cbar);
+    a.part_f = at<float>(ws, L.part_f);
+    a.part_d = at<double>(ws, L.part_adj);
+    a.coef = coefs_of(p).fine;
+    const float dA[4] = {4.f, 2.f, 1.f, 1.f};
+    for (int k = 0; k < 4; ++k) a.diagA[k] = dA[k];
+    a.h2 = p->h * p->h;
+    a.inv_h2 = (float)(1.0 / a.h2);
+    a.rtol = (float)std::max(p->tol, 2e-7);
+    a.eps = p->eps;
+    a.tau = p->tau;
+    a.lambda = p->lambda;
+    a.W = W;
+    a.H = H;
+    a.nblocks = adj_half_blocks(W, H);
+    a.nblocks_acc = adj_accum_blocks(W, H);
+    a.max_sweeps = std::min(4000, std::max(4, 2 * p->max_cycles));
+    float* ubuf[2] = {at<float>(ws, L.ub0), at<float>(ws, L.ub1)};
+    const float* ub = grad_uT;
+    for (int st = p->steps - 1; st >= 0; --st) {
+        a.u0 = checkpoints + st * nu;
+        a.u1 = checkpoints + (st + 1) * nu;
+        a.ub = ub;
+        a.ub_out = ubuf[st & 1];
+        a.c64 = c64 + st * kNC;
+        a.tot = tot + st * kCmeansMaxM;
+        a.cbar_out = grad_c ? grad_c + (int64_t)st * N * C : nullptr;
+        for (int sw = 0; sw < a.max_sweeps; ++sw) {
+            ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_adj(N, C, kAdjHalf, a, 0, sw, s); }));
+            ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_adj(N, C, kAdjHalf, a, 1, sw, s); }));
+        }
+        ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjAccum, a, 0, 0, s); }));
+        ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjReduce, a, 0, 0, s); }));
+        ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjMeans, a, 0, 0, s); }));
+        ub = a.ub_out;
+    }
+    if (grad_u0) ACSEG_TRY(hipMemcpyAsync(grad_u0, ub, sizeof(float) * nu, hipMemcpyDeviceToDevice, s));
+    if (!stats) return ACSEG_OK;
+    ACSEG_TRY(hipMemcpyAsync(ctx->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    ACSEG_TRY(hipStreamSynchronize(s));
+    const Ctl& c = *ctx->host_ctl;
+    memset(stats, 0, sizeof(*stats));
+    stats->steps_done = c.steps_done;
+    stats->cycles_total = c.cycles_total;
+    stats->cycles_max = c.cycles_max;
+    stats->steps_not_converged = c.steps_unconv;
+    stats->status = c.nonfinite ? ACSEG_ERR_NONFINITE : (c.steps_unconv ? ACSEG_WARN_NOT_CONVERGED : ACSEG_OK);
+    return ACSEG_OK;
 }
 
 acseg_status acseg_energy(acseg_ctx* ctx, const acseg_problem* p, const float* image,

@@ -244,6 +244,47 @@ hipError_t launch_coarse_tail(int N, const TailArgs& a, size_t lds_bytes, hipStr
 hipError_t launch_transfer(int planes, int dir, const float* src, float* dst, int Wf, int Hf,
                            hipStream_t s);
 
+// ---- launchers (kernels_adjoint.hip): gradients through the time steps ------
+
+struct AdjCtl {
+    int done;    // the current adjoint solve converged
+    int sweeps;  // after this many sweeps
+    int pad[2];
+};
+
+enum AdjOp { kAdjHalf = 0, kAdjAccum, kAdjReduce, kAdjMeans };
+
+// Step s backwards: u0 = u^s, u1 = u^{s+1}, ub = dL/du^{s+1}; out: ub_out =
+// dL/du^s; accumulated: Ibar, grads (lambda, eps, tau); cbar of the step.
+struct AdjArgs {
+    Ctl* ctl;
+    AdjCtl* actl;
+    const float* image;
+    const float* u0;
+    const float* u1;
+    const float* ub;
+    float* ub_out;
+    float* z;             // [N][H][W]
+    float* Ibar;          // [C][H][W]
+    double* grads;        // [3]
+    const double* c64;    // means of u^s [N][C]
+    const double* tot;    // colour-mean sums of u^s (mass-weight units)
+    double* cbar64;       // [N][C]
+    float* cbar_out;      // [N][C] or NULL
+    float* part_f;        // [2][kMgBlocks]
+    double* part_d;       // [kMgBlocks][3 + N C]
+    LevelCoef coef;       // finest level
+    float diagA[4];       // stiffness diagonal per node class
+    float inv_h2, rtol;
+    double h2, eps, tau, lambda;
+    int W, H, nblocks, nblocks_acc, max_sweeps;
+};
+
+int adj_half_blocks(int W, int H);
+int adj_accum_blocks(int W, int H);
+hipError_t launch_adj(int N, int C, int op, const AdjArgs& a, int colour, int sweep, hipStream_t s);
+hipError_t launch_adj_init(AdjCtl* ac, double* grads, hipStream_t s);
+
 // Initialise a control block (cur = initial buffer index).
 hipError_t launch_ctl_init(Ctl* ctl, int cur, hipStream_t s);
 

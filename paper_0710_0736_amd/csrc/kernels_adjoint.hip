@@ -1,0 +1,310 @@
+// kernels_adjoint.hip -- gradients of a segmentation through its time steps.
+//
+// The paper does not differentiate its scheme; this is the derivative of the
+// discrete step map of eq. alpha.  With the free sets I_p = {i : u^{n+1}_pi > 0}
+// held fixed, u^{n+1} minimises the step's quadratic over
+// {u_pi = 0 outside I_p, sum_{I_p} u_pi = 1}, so for a loss gradient ubar at
+// u^{n+1} the gradient at the right-hand side b is z = (T H T)^+ T ubar, T the
+// node-wise tangent projection (zero outside I_p, minus the mean over I_p;
+// zero when |I_p| <= 1).  z is found by red-black block Gauss-Seidel on
+//     z_p = T_p (ubar_p / (h^2 D_p) + kappa_p sum_q c_pq z_q)
+// (the nodal minimiser of z.H z / 2 - ubar.z on the range of T_p, in the
+// scaled units of the smoother), stopped when a sweep changes z by at most
+// rtol max|z|.  The chain rule then runs through
+//     b_pi = M_p [(1/tau + 2/eps) un_pi - lambda F_pi],  F_pi = sum_k (I_pk - c_ik)^2,
+//     c_ik = S_ik / S_i,  H = M/tau + eps A,
+// with M_p = h^2 w_p; an empty phase's (kept) mean is a constant.
+#include <algorithm>
+
+#include "acseg_internal.h"
+
+namespace acseg {
+
+namespace {
+
+__device__ __forceinline__ float nbs(const float* __restrict__ v, int W, int H, int x, int y, int64_t p) {
+    const float h = (x > 0 ? v[p - 1] : 0.f) + (x < W - 1 ? v[p + 1] : 0.f);
+    const float vv = (y > 0 ? v[p - W] : 0.f) + (y < H - 1 ? v[p + W] : 0.f);
+    return edge_w_h(y, H) * h + edge_w_v(x, W) * vv;
+}
+
+__device__ __forceinline__ float block_max_f(float v, float* sh) {
+    v = wave_max(v);
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    float r = sh[0];
+    for (int w = 1; w < kBlock / kWave; ++w) r = fmaxf(r, sh[w]);
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) r += sh[w];
+    __syncthreads();
+    return r;
+}
+
+// One half-sweep of the adjoint solve.  The red half-sweep of every sweep
+// after the first first checks the previous sweep's partials (max |dz|,
+// max |z|) and skips the rest of the solve once they meet rtol.
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_adj_half(AdjArgs a, int colour, int sweep) {
+    __shared__ float sh[kBlock / kWave];
+    AdjCtl* ac = a.actl;
+    if (ac->done) return;
+    if (colour == 0 && sweep > 1) {  // sweep 0 compared its black values with unset memory
+        float dz = 0.f, zm = 0.f;
+        for (int b = threadIdx.x; b < a.nblocks; b += kBlock) {
+            dz = fmaxf(dz, a.part_f[b]);
+            zm = fmaxf(zm, a.part_f[kMgBlocks + b]);
+        }
+        dz = block_max_f(dz, sh);
+        zm = block_max_f(zm, sh);
+        if (!(dz > a.rtol * zm)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                ac->done = 1;
+                ac->sweeps = sweep;
+            }
+            return;
+        }
+    }
+    const int W = a.W, H = a.H, hw = (W + 1) / 2;
+    const int64_t n = (int64_t)W * H, nh = (int64_t)hw * H;
+    const float* __restrict__ u1 = a.u1;
+    float dzm = 0.f, zmax = 0.f;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < nh; t += (int64_t)gridDim.x * kBlock) {
+        const int y = (int)(t / hw), j = (int)(t - (int64_t)y * hw);
+        const int x = 2 * j + ((y + colour) & 1);
+        if (x >= W) continue;
+        const int64_t p = (int64_t)y * W + x;
+        const int cls = node_class(x, y, W, H);
+        const float kap = sel4(a.coef.kappa, cls), rs = sel4(a.coef.inv_d, cls) * a.inv_h2;
+        float yv[N];
+        int k = 0;
+        float s = 0.f;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            float v = a.ub[i * n + p] * rs;
+            if (!(sweep == 0 && colour == 0)) v += kap * nbs(a.z + i * n, W, H, x, y, p);
+            yv[i] = v;
+            if (u1[i * n + p] > 0.f) {
+                s += v;
+                ++k;
+            }
+        }
+        const float mean = k > 0 ? s / (float)k : 0.f;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const float zn = (k >= 2 && u1[i * n + p] > 0.f) ? yv[i] - mean : 0.f;
+            if (colour == 1) {
+                dzm = fmaxf(dzm, fabsf(zn - a.z[i * n + p]));
+                zmax = fmaxf(zmax, fabsf(zn));
+            }
+            a.z[i * n + p] = zn;
+        }
+    }
+    if (colour == 1) {
+        // the black half-sweep closes a sweep: its change bounds the sweep's
+        // (the red values it read were just written)
+        const float d = block_max_f(dzm, sh);
+        const float m = block_max_f(zmax, sh);
+        if (threadIdx.x == 0) {
+            a.part_f[blockIdx.x] = d;
+            a.part_f[kMgBlocks + blockIdx.x] = m;
+        }
+    }
+}
+
+// The black half-sweep's change bounds the sweep's residual: the red values
+// of the sweep were computed from the previous black ones, so with those
+// reproduced to |dz| the red nodes are consistent to kappa-weighted |dz|.
+
+// Direct terms of the chain rule at every node; block partials of
+// dL/dlambda, dL/deps, dL/dtau and cbar_ik.
+template <int N, int C>
+__global__ __launch_bounds__(kBlock) void k_adj_accum(AdjArgs a) {
+    constexpr int Q = 3 + N * C;
+    __shared__ double sh[kBlock / kWave];
+    const int W = a.W, H = a.H;
+    const int64_t n = (int64_t)W * H;
+    const double* c = a.c64;
+    double acc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] = 0.0;
+    const double h2 = a.h2, tau = a.tau, eps = a.eps, lam = a.lambda;
+    const double aa = 1.0 / tau + 2.0 / eps;
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += (int64_t)gridDim.x * kBlock) {
+        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+        const int cls = node_class(x, y, W, H);
+        const double Mp = h2 * mass_w(cls);
+        const float ast = sel4(a.diagA, cls);
+        float Ik[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) Ik[k] = a.image[k * n + p];
+        float ib[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) ib[k] = 0.f;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const double z = a.z[i * n + p];
+            const double un = a.u0[i * n + p];
+            const double u1 = a.u1[i * n + p];
+            const double Au1 = (double)ast * u1 - (double)nbs(a.u1 + i * n, W, H, x, y, p);
+            double F = 0.0;
+            double d[C];
+#pragma unroll
+            for (int k = 0; k < C; ++k) {
+                d[k] = (double)Ik[k] - c[i * C + k];
+                F += d[k] * d[k];
+            }
+            a.ub_out[i * n + p] = (float)(aa * Mp * z);
+            acc[0] += z * (-Mp * F);
+            acc[1] += z * (-2.0 / (eps * eps)) * Mp * un - z * Au1;
+            acc[2] += (-z * Mp * un + z * Mp * u1) / (tau * tau);
+            const double Fbar = -lam * Mp * z;
+#pragma unroll
+            for (int k = 0; k < C; ++k) {
+                ib[k] += (float)(2.0 * Fbar * d[k]);
+                acc[3 + i * C + k] += -2.0 * Fbar * d[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < C; ++k) a.Ibar[k * n + p] += ib[k];
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const double t = block_sum(acc[q], sh);
+        if (threadIdx.x == 0) a.part_d[(int64_t)blockIdx.x * Q + q] = t;
+    }
+}
+
+// One workgroup: the partials into grads (accumulated) and cbar of the step.
+template <int N, int C>
+__global__ __launch_bounds__(kBlock) void k_adj_reduce(AdjArgs a) {
+    constexpr int Q = 3 + N * C;
+    __shared__ double sh[kBlock / kWave][Q];
+    __shared__ double tot[Q];
+    reduce_rows<Q>(a.part_d, a.nblocks_acc, tot, sh);
+    if (threadIdx.x < 3) a.grads[threadIdx.x] += tot[threadIdx.x];
+    if (threadIdx.x < N * C) {
+        a.cbar64[threadIdx.x] = tot[3 + threadIdx.x];
+        if (a.cbar_out) a.cbar_out[threadIdx.x] = (float)tot[3 + threadIdx.x];
+    }
+    if (threadIdx.x == 0) {
+        AdjCtl* ac = a.actl;
+        Ctl* ctl = a.ctl;
+        const int sw = ac->done ? ac->sweeps : a.max_sweeps;
+        ctl->cycles_total += sw;
+        ctl->cycles_max = sw > ctl->cycles_max ? sw : ctl->cycles_max;
+        if (!ac->done) ctl->steps_unconv += 1;
+        ctl->steps_done += 1;
+        ac->done = 0;
+        ac->sweeps = 0;
+    }
+}
+
+// The colour means' share: c_ik = S_ik / S_i.
+template <int N, int C>
+__global__ __launch_bounds__(kBlock) void k_adj_means(AdjArgs a) {
+    const int W = a.W, H = a.H;
+    const int64_t n = (int64_t)W * H;
+    constexpr int NC = N * C;
+    const double* tot = a.tot;  // S_ik [N*C], S_i [N], sum w I [C], area, flag (mass-weight units)
+    const double area = tot[NC + N + C];
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += (int64_t)gridDim.x * kBlock) {
+        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+        const double w = mass_w(node_class(x, y, W, H));
+        double ib[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) ib[k] = 0.0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const double S = tot[NC + i];
+            if (!(S > 1e-12 * area)) continue;
+            const double un = a.u0[i * n + p];
+            double du = 0.0;
+#pragma unroll
+            for (int k = 0; k < C; ++k) {
+                const double cb = a.cbar64[i * C + k];
+                ib[k] += cb * w * un / S;
+                du += cb * w * ((double)a.image[k * n + p] - a.c64[i * C + k]) / S;
+            }
+            a.ub_out[i * n + p] += (float)du;
+        }
+#pragma unroll
+        for (int k = 0; k < C; ++k) a.Ibar[k * n + p] += (float)ib[k];
+    }
+}
+
+__global__ void k_adj_init(AdjCtl* ac, double* grads) {
+    if (threadIdx.x == 0) {
+        ac->done = 0;
+        ac->sweeps = 0;
+        grads[0] = grads[1] = grads[2] = 0.0;
+    }
+}
+
+int adj_blocks(int64_t work) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>((work + kBlock - 1) / kBlock, kMgBlocks));
+}
+
+template <int N, int C>
+hipError_t adj_nc(int op, const AdjArgs& a, int colour, int sweep, hipStream_t s) {
+    const int64_t n = (int64_t)a.W * a.H;
+    switch (op) {
+        case kAdjHalf:
+            hipLaunchKernelGGL((k_adj_half<N>), dim3(a.nblocks), dim3(kBlock), 0, s, a, colour, sweep);
+            break;
+        case kAdjAccum:
+            hipLaunchKernelGGL((k_adj_accum<N, C>), dim3(a.nblocks_acc), dim3(kBlock), 0, s, a);
+            break;
+        case kAdjReduce: hipLaunchKernelGGL((k_adj_reduce<N, C>), dim3(1), dim3(kBlock), 0, s, a); break;
+        case kAdjMeans:
+            hipLaunchKernelGGL((k_adj_means<N, C>), dim3(adj_blocks(n)), dim3(kBlock), 0, s, a);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t adj_n(int C, int op, const AdjArgs& a, int colour, int sweep, hipStream_t s) {
+    switch (C) {
+        case 1: return adj_nc<N, 1>(op, a, colour, sweep, s);
+        case 2: return adj_nc<N, 2>(op, a, colour, sweep, s);
+        case 3: return adj_nc<N, 3>(op, a, colour, sweep, s);
+        case 4: return adj_nc<N, 4>(op, a, colour, sweep, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int adj_half_blocks(int W, int H) { return adj_blocks((int64_t)(W + 1) / 2 * H); }
+int adj_accum_blocks(int W, int H) { return adj_blocks((int64_t)W * H); }
+
+hipError_t launch_adj(int N, int C, int op, const AdjArgs& a, int colour, int sweep, hipStream_t s) {
+    switch (N) {
+        case 2: return adj_n<2>(C, op, a, colour, sweep, s);
+        case 3: return adj_n<3>(C, op, a, colour, sweep, s);
+        case 4: return adj_n<4>(C, op, a, colour, sweep, s);
+        case 5: return adj_n<5>(C, op, a, colour, sweep, s);
+        case 6: return adj_n<6>(C, op, a, colour, sweep, s);
+        case 7: return adj_n<7>(C, op, a, colour, sweep, s);
+        case 8: return adj_n<8>(C, op, a, colour, sweep, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_adj_init(AdjCtl* ac, double* grads, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_init, dim3(1), dim3(kWave), 0, s, ac, grads);
+    return hipGetLastError();
+}
+
+}  // namespace acseg
