@@ -74,45 +74,68 @@ __device__ __forceinline__ double mass_w(int cls) {
     return cls == 0 ? 1.0 : (cls == 1 ? 0.5 : (cls == 2 ? (1.0 / 3.0) : (1.0 / 6.0)));
 }
 
+// Sorting networks (descending), N <= 8: pairs (i, j), i < j, after which
+// s[i] >= s[j].  Each was checked exhaustively on 0/1 inputs.
+template <int N> struct SortNet;
+template <> struct SortNet<2> { static constexpr int n = 1; static constexpr int p[1][2] = {{0, 1}}; };
+template <> struct SortNet<3> { static constexpr int n = 3; static constexpr int p[3][2] = {{0, 2}, {0, 1}, {1, 2}}; };
+template <> struct SortNet<4> {
+    static constexpr int n = 5;
+    static constexpr int p[5][2] = {{0, 1}, {2, 3}, {0, 2}, {1, 3}, {1, 2}};
+};
+template <> struct SortNet<5> {
+    static constexpr int n = 9;
+    static constexpr int p[9][2] = {{0, 1}, {3, 4}, {2, 4}, {2, 3}, {0, 3}, {0, 2}, {1, 4}, {1, 3}, {1, 2}};
+};
+template <> struct SortNet<6> {
+    static constexpr int n = 12;
+    static constexpr int p[12][2] = {{1, 2}, {4, 5}, {0, 2}, {3, 5}, {0, 1}, {3, 4},
+                                     {2, 5}, {0, 3}, {1, 4}, {2, 4}, {1, 3}, {2, 3}};
+};
+template <> struct SortNet<7> {
+    static constexpr int n = 16;
+    static constexpr int p[16][2] = {{1, 2}, {3, 4}, {5, 6}, {0, 2}, {3, 5}, {4, 6}, {0, 1}, {4, 5},
+                                     {2, 6}, {0, 4}, {1, 5}, {0, 3}, {2, 5}, {1, 3}, {2, 4}, {2, 3}};
+};
+template <> struct SortNet<8> {
+    static constexpr int n = 19;
+    static constexpr int p[19][2] = {{0, 2}, {1, 3}, {4, 6}, {5, 7}, {0, 4}, {1, 5}, {2, 6},
+                                     {3, 7}, {0, 1}, {2, 3}, {4, 5}, {6, 7}, {2, 4}, {3, 5},
+                                     {1, 4}, {3, 6}, {1, 2}, {3, 4}, {5, 6}};
+};
+
 // Euclidean projection of v onto the Gibbs simplex, in registers.
 //
-// The correction loop of Section "Gibbs Space Constraint Pseudocode" in
-// threshold form: all free components are shifted by one common theta chosen
-// so that they sum to one; every free component that would go negative is
-// fixed at zero and leaves the free set; repeat (at most N - 1 removals).
-// Values are first taken relative to the largest component, so every value
-// is <= 0 and the sum s of the free ones too; then theta = (s - 1)/k < 0, the
-// largest component (now exactly 0) is never removed, and the threshold
-// arithmetic stays well conditioned in FP32.
+// The correction loop of Section "Gibbs Space Constraint Pseudocode" ends at
+// x_i = max(v_i - theta, 0) with theta the common shift that makes the free
+// components sum to one.  Here theta is found without the loop, by the
+// sort-based characterisation of the same projection (Held, Wolfe & Crowder
+// 1974; Duchi et al. 2008): with s the values sorted in descending order and
+// S_k the sum of the k largest, theta = max_k (S_k - 1) / k (each candidate
+// is a lower bound of theta, and the one at the number of free components is
+// theta itself).  Values are taken relative to the largest one, so the sums
+// are of non-positive numbers and stay well conditioned in FP32.
 template <int N>
 __device__ __forceinline__ void project_simplex(float (&v)[N]) {
-    float vmax = v[0];
+    float s[N];
 #pragma unroll
-    for (int i = 1; i < N; ++i) vmax = fmaxf(vmax, v[i]);
-    float s = 0.f;
+    for (int i = 0; i < N; ++i) s[i] = v[i];
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-        v[i] -= vmax;
-        s += v[i];
+    for (int c = 0; c < SortNet<N>::n; ++c) {
+        const int i = SortNet<N>::p[c][0], j = SortNet<N>::p[c][1];
+        const float a = s[i], b = s[j];
+        s[i] = fmaxf(a, b);
+        s[j] = fminf(a, b);
     }
-    float theta = (s - 1.0f) * (1.0f / (float)N);
-    unsigned freem = (1u << N) - 1u;
+    const float vmax = s[0];
+    float S = 0.f, theta = -1.0f;  // k = 1: the largest value alone
 #pragma unroll
-    for (int r = 0; r < N - 1; ++r) {
-        unsigned out = 0u;
-#pragma unroll
-        for (int i = 0; i < N; ++i)
-            if (((freem >> i) & 1u) && v[i] < theta) out |= 1u << i;
-        if (out == 0u) break;
-        freem &= ~out;
-        s = 0.f;
-#pragma unroll
-        for (int i = 0; i < N; ++i)
-            if ((freem >> i) & 1u) s += v[i];
-        theta = (s - 1.0f) * __builtin_amdgcn_rcpf((float)__popc(freem));
+    for (int k = 2; k <= N; ++k) {
+        S += s[k - 1] - vmax;
+        theta = fmaxf(theta, (S - 1.0f) * (1.0f / (float)k));
     }
 #pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = ((freem >> i) & 1u) ? fmaxf(v[i] - theta, 0.f) : 0.f;
+    for (int i = 0; i < N; ++i) v[i] = fmaxf((v[i] - vmax) - theta, 0.f);
 }
 
 // ---------------------------------------------------------------------------
@@ -122,6 +145,23 @@ __device__ __forceinline__ void project_simplex(float (&v)[N]) {
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Sum over the 64 lanes of a wave in a fixed order (data-parallel-primitive
+// moves: within quads, rotations within rows of 16, then row broadcasts); the
+// total is exact in lane 63 only.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+__device__ __forceinline__ float wave_sum_last(float v) {
+    v += dpp_f<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]: every lane holds its quad's sum
+    v += dpp_f<0x124, 0xF>(v);  // row_ror:4
+    v += dpp_f<0x128, 0xF>(v);  // row_ror:8: every lane holds its row's sum
+    v += dpp_f<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_f<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
     return v;
 }
 
