@@ -80,17 +80,12 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
     constexpr int M = N * C + N + C + 2;
     constexpr int NHALF = 2 * K + (RESID ? 1 : 0);
     constexpr int kOut = 255;      // "radius" of a node outside the image: never updated
-    // colour-mean rows reduced per LDS pass (each row: T + 1 floats)
-    constexpr int QCH = (cycle_lds_bytes<N, K, RESID>() / (4 * (T + 1))) < M
-                            ? (cycle_lds_bytes<N, K, RESID>() / (4 * (T + 1)))
-                            : M;
-    static_assert(!RESID || QCH >= 1, "staging area too small for one reduction row");
     constexpr int PARTS = T / kWave;  // partial sums per row
     extern __shared__ float lds[];
     __shared__ float red[T / kWave];
     __shared__ double cs[N * C];
     __shared__ double cs2[N];
-    __shared__ double part[M][PARTS];
+    __shared__ float wsum[PARTS][M];
     __shared__ double tsh[M + N * C];
     __shared__ int flag;
 
@@ -135,9 +130,8 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
     const int x0 = tx * TX - R, y0 = ty * TY - R;  // LDS origin; x0 + y0 is even
 
     // ---- one burst of global loads: u of the staged region in row order
-    //      (coalesced), the image (first launch) or stored right-hand side of
-    //      the owned pairs, and the image of the owned output nodes for the
-    //      colour-mean partials
+    //      (coalesced), and the image (first launch) or stored right-hand side
+    //      of the owned pairs
     constexpr int NS = (LX * LY + T - 1) / T;
     float ust[NS][N];
 #pragma unroll
@@ -203,23 +197,6 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
             }
         }
         pk[m] = packed;
-    }
-    float Io[NO][C];
-    bool on[NO];
-    if (RESID) {
-#pragma unroll
-        for (int q = 0; q < NO; ++q) {
-            const int idx = threadIdx.x + q * T;
-            const int oy = idx / TX, ox = idx - oy * TX;
-            const int gx = x0 + R + ox, gy = y0 + R + oy;
-            on[q] = st.cm && gx < W && gy < H;
-            const int g = on[q] ? gy * W + gx : 0;
-#pragma unroll
-            for (int k = 0; k < C; ++k) {
-                const float t = imgp[k][g];
-                Io[q][k] = on[q] ? t : 0.f;
-            }
-        }
     }
 
     // the colour-mean sums of u^n (and the previous means, for empty phases)
@@ -332,10 +309,28 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
         }
     }
 
+    float Io[NO][C];  // image of the owned output nodes (closing launch), loaded before the last half-sweep
+    bool on[NO];
+
     // ---- red-black half-sweeps on the shrinking region
     float res = 0.f;
     for (int s = 0; s < NHALF; ++s) {
         const int r = R - 1 - s;
+        if (RESID && s == NHALF - 1) {
+#pragma unroll
+            for (int q = 0; q < NO; ++q) {
+                const int idx = threadIdx.x + q * T;
+                const int oy = idx / TX, ox = idx - oy * TX;
+                const int gx = x0 + R + ox, gy = y0 + R + oy;
+                on[q] = st.cm && gx < W && gy < H;
+                const int g = on[q] ? gy * W + gx : 0;
+#pragma unroll
+                for (int k = 0; k < C; ++k) {
+                    const float t = imgp[k][g];
+                    Io[q][k] = on[q] ? t : 0.f;
+                }
+            }
+        }
         __syncthreads();
         if ((s & 1) == 0) {  // red: the first node of every pair
 #pragma unroll
@@ -421,28 +416,18 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
         for (int k = 0; k < C; ++k) acc[N * C + N + k] += w * Io[q][k];
         acc[N * C + N + C] += w;
     }
-    // block sum in a fixed order: QCH rows at a time, every thread's partials
-    // into padded LDS rows (the staging area is free now); each wave adds 64
-    // entries of a row in float64, then M threads add the wave sums
+    // block sum in a fixed order: each wave sums its lanes in FP32 (128 nodes),
+    // then M threads add the T / 64 wave sums in FP64
 #pragma unroll
-    for (int q0 = 0; q0 < M; q0 += QCH) {
-#pragma unroll
-        for (int q = 0; q < QCH; ++q)
-            if (q0 + q < M) lds[q * (T + 1) + threadIdx.x] = acc[q0 + q];
-        __syncthreads();
-        for (int t = threadIdx.x; t < QCH * PARTS; t += T) {
-            const int q = t / PARTS, h = t - q * PARTS;
-            if (q0 + q >= M) continue;
-            const float* rowp = lds + q * (T + 1) + h * kWave;
-            double v = 0.0;
-            for (int k = 0; k < kWave; ++k) v += (double)rowp[k];
-            part[q0 + q][h] = v;
-        }
-        __syncthreads();
+    for (int q = 0; q < M; ++q) {
+        const float t = wave_sum_last(acc[q]);
+        if (threadIdx.x % kWave == kWave - 1) wsum[threadIdx.x / kWave][q] = t;
     }
+    __syncthreads();
     if (threadIdx.x < M) {
         double t = 0.0;
-        for (int h = 0; h < PARTS; ++h) t += part[threadIdx.x][h];
+#pragma unroll
+        for (int h = 0; h < PARTS; ++h) t += (double)wsum[h][threadIdx.x];
         a.cm_part[((int64_t)row * M + threadIdx.x) * a.part_stride + tile] = t;
     }
 }
