@@ -40,10 +40,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "segmentations/s at 1024² N=4 (batched vs plain); smoother GB/s vs HBM peak"
 HBM_PEAK_GBS = 8000.0
-# DRAM bytes per k_cycle launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled
-# by the copy-kernel factor (profiles/k_cycle_voronoi1024_n4_pmc.md); None
-# until measured on the current kernel.
-TRAFFIC = {}
+# DRAM bytes per smoothing launch, (workload, images per launch) -> bytes:
+# rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
+# same counter reads for a 256 MiB device copy (FETCH x 2.000, WRITE x 1.000);
+# see profiles/k_cycle_voronoi1024_n4_batch8_traffic.md.  Must be re-measured
+# whenever the kernel changes (absent: null).
+TRAFFIC = {
+    ("voronoi1024_n4", 8): 378.07e6,
+    ("voronoi1024_n4", 1): 63.43e6,
+}
 
 
 def log(msg):
@@ -198,7 +203,7 @@ def main():
             cycles if fixed else st_run["cycles_total"] / w.steps, fixed)
         achieved = bytes_per_launch / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get((w.name, B)),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": (int(TRAFFIC[(w.name, B)]) if (w.name, B) in TRAFFIC else None),
                 "kernel": ("k_cycle_batch" if B > 1 else "k_cycle") +
                           " (time step: rhs + 2 red-black sweeps in LDS + residual + colour-mean partials)",
                 "images_per_launch": B,
