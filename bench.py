@@ -80,24 +80,157 @@ def copy_calibration(mib: int, reps: int):
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "reps": reps}), flush=True)
 
 
+def run_hetero(args):
+    """256 images of independent sizes and phase counts: one batched solve vs one call per image."""
+    import torch
+    from paper_0710_0736_amd import acseg, synth
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ws = synth.batch_workloads(args.hetero)
+    made = [w.make(b) for b, w in enumerate(ws)]
+    imgs = [torch.from_numpy(m[0]).to(dev) for m in made]
+    u0s = [torch.from_numpy(m[1]).to(dev) for m in made]
+    us = [torch.empty_like(u) for u in u0s]
+    nodes = sum(w.W * w.H for w in ws)
+    probs = [acseg.Problem.from_workload(w, C=3, levels=1, max_cycles=args.max_cycles) for w in ws]
+    cycles = 1
+    for b in range(len(ws)):  # the slowest time step of any image fixes the schedule
+        us[b].copy_(u0s[b])
+        _, _, st, _ = acseg.solve(probs[b], imgs[b], us[b])
+        if st["status"] != acseg.OK:
+            raise RuntimeError(f"calibration solve of image {b} did not converge: {st}")
+        cycles = max(cycles, st["cycles_max"])
+    probs = [acseg.Problem(**{**p.__dict__, "max_cycles": cycles, "flags": acseg.FLAG_FIXED_CYCLES})
+             for p in probs]
+
+    def one_by_one():
+        for b in range(len(ws)):
+            us[b].copy_(u0s[b])
+            acseg.solve(probs[b], imgs[b], us[b], want_stats=False, c_out=False)
+
+    def batched():
+        for b in range(len(ws)):
+            us[b].copy_(u0s[b])
+        acseg.solve_batched(probs, imgs, us, want_stats=False, c_out=False)
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    k = max(1, args.steps // 4)
+    t_plain = timed(one_by_one, k)
+    t_batch = timed(batched, k)
+    for b in range(len(ws)):
+        us[b].copy_(u0s[b])
+    _, _, sts = acseg.solve_batched(probs, imgs, us)
+    bad = [x for x in sts if x["status"] != acseg.OK]
+    if bad:
+        raise RuntimeError(f"batched schedule did not converge: {bad[0]}")
+    out = {"metric": "images/s, heterogeneous batch (batched vs one call per image)",
+           "value": round(len(ws) / t_batch, 2), "unit": "images/s", "n_gpus": 1, "steps": k,
+           "warmup": 1, "ms_per_step": round(t_batch * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "plain": {"value": round(len(ws) / t_plain, 2), "unit": "images/s",
+                     "ms_per_batch": round(t_plain * 1e3, 3)},
+           "config": {"workload": f"hetero{len(ws)}", "images": len(ws), "nodes": nodes,
+                      "N": sorted({w.N for w in ws}), "time_steps": ws[0].steps,
+                      "cycles_per_step": cycles, "sweeps_per_cycle": 2},
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
+def run_adjoint(args):
+    """Forward solve with checkpoints, then gradients of a squared-error loss."""
+    import torch
+    from paper_0710_0736_amd import acseg, synth
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = synth.WORKLOADS["voronoi512_n4"]
+    img_np, u0_np, lab = w.make(0)
+    I = torch.from_numpy(img_np).to(dev)
+    U0 = torch.from_numpy(u0_np).to(dev)
+    y = torch.from_numpy(np.stack([(lab == i) for i in range(w.N)]).astype(np.float32)).to(dev)
+    p = acseg.Problem.from_workload(w, C=3, levels=1, max_cycles=args.max_cycles)
+    st = {}
+
+    def forward():
+        u, _, s, ck = acseg.solve(p, I, U0.clone(), checkpoints=True, want_stats=False, c_out=False)
+        return u, ck
+
+    def both():
+        u, ck = forward()
+        return acseg.backward(p, I, ck, 2 * (u - y), want_stats=False)
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    k = max(2, args.steps)
+    t_f = timed(forward, k)
+    t_fb = timed(both, k)
+    u, ck = forward()
+    _, _, _, _, bst = acseg.backward(p, I, ck, 2 * (u - y))
+    out = {"metric": "adjoint: forward+backward time per segmentation (voronoi512_n4)",
+           "value": round(t_fb * 1e3, 3), "unit": "ms", "n_gpus": 1, "steps": k, "warmup": 1,
+           "ms_per_step": round(t_fb * 1e3, 3), "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "forward_ms": round(t_f * 1e3, 3), "backward_ms": round((t_fb - t_f) * 1e3, 3),
+           "backward_over_forward": round((t_fb - t_f) / t_f, 2),
+           "config": {"workload": w.name, "W": w.W, "H": w.H, "N": w.N, "time_steps": w.steps,
+                      "adjoint_sweeps_total": bst["cycles_total"], "adjoint_sweeps_max": bst["cycles_max"],
+                      "status": bst["status"]},
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20, help="segmentations timed")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="voronoi1024_n4")
+    ap.add_argument("--pixel-units", action="store_true",
+                    help="the workload's pixel-unit twin (h = 1, eps = 2, tau = 4)")
+    ap.add_argument("--levels", type=int, default=1,
+                    help="multigrid levels (1: Gauss-Seidel cycles only, 0: automatic)")
+    ap.add_argument("--max-cycles", type=int, default=20, help="cycle budget per time step")
+    ap.add_argument("--nu", type=int, nargs=2, default=(1, 1), metavar=("PRE", "POST"),
+                    help="smoothing sweeps before / after the coarse correction")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="only time a forward solve with checkpoints and the backward pass "
+                         "(voronoi512_n4: 512^2, N = 4, 20 steps)")
     ap.add_argument("--batch", type=int, default=8,
                     help="images per batched solve (seeds 0..B-1, same shape); 1 = plain only")
     ap.add_argument("--schedule", choices=["fixed", "adaptive"], default="fixed",
                     help="fixed: every time step runs the cycle count found sufficient in a "
                          "calibration solve; adaptive: stop at the residual on the device")
-    ap.add_argument("--cpu-sample-steps", type=int, default=6,
-                    help="time steps of the oracle run for the CPU baseline")
+    ap.add_argument("--cpu-sample-steps", type=int, default=0,
+                    help="time steps of the oracle run for the CPU baseline (0: about 6 steps of "
+                         "a 1024^2 N=4 image's work, at least 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB on the device (profiler counter calibration)")
+    ap.add_argument("--hetero", type=int, default=0, metavar="B",
+                    help="only time a batch of B images of independent sizes (64..1024) and "
+                         "phase counts (2..6), batched vs one call per image")
     args = ap.parse_args()
+    if args.hetero:
+        run_hetero(args)
+        return
+    if args.adjoint:
+        run_adjoint(args)
+        return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration, max(1, args.steps))
         return
@@ -111,9 +244,14 @@ def main():
     from paper_0710_0736_amd import acseg, synth
 
     w = synth.WORKLOADS[args.workload]
+    if args.pixel_units:
+        w = synth.pixel_twin(w)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     B = max(1, args.batch)
+    if args.levels != 1 and B > 1:
+        log("[bench] the batched solve runs Gauss-Seidel cycles only: --levels != 1 uses --batch 1")
+        B = 1
     made = [w.make(seed) for seed in range(B)]
     img_np, u0_np, _ = made[0]
     C = img_np.shape[0]
@@ -123,7 +261,8 @@ def main():
     us = [torch.empty_like(u0) for u0 in u0s]
     img, u0, u = imgs[0], u0s[0], us[0]
 
-    base = acseg.Problem.from_workload(w, C=C, levels=1, nu_pre=1, nu_post=1, max_cycles=20)
+    base = acseg.Problem.from_workload(w, C=C, levels=args.levels, nu_pre=args.nu[0],
+                                       nu_post=args.nu[1], max_cycles=args.max_cycles)
 
     # calibration: how many cycles does the slowest time step of any image need?
     cycles = 1
@@ -216,7 +355,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle as orc
         P = orc.Params.from_workload(w, C=C, tol=w.tol)
-        k = args.cpu_sample_steps
+        k = args.cpu_sample_steps or max(1, min(w.steps, round(6 * (1024 * 1024 * 4) / (n * w.N))))
         t0c = time.perf_counter()
         orc.solve(P, k, img_np, u0_np, keep_trajectory=False)
         tc = time.perf_counter() - t0c
