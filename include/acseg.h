@@ -252,8 +252,10 @@ acseg_status acseg_energy(acseg_ctx *ctx, const acseg_problem *p, const float *i
  * count as active) and treats the kept mean of an empty phase as a constant.
  * The per-step linear solves are red-black sweeps to a relative change of
  * max(tol, 2e-7), at most max(4, 2 max_cycles) sweeps (stats count steps that
- * hit the cap as not converged, and the sweeps as cycles).  Workspace from
- * acseg_backward_workspace_size.
+ * hit the cap as not converged, and the sweeps as cycles).  The sweeps are
+ * enqueued in chunks of 4, 8, ... 64; between chunks the call waits for the
+ * stream to read the convergence flag, so it returns with the work done.
+ * Workspace from acseg_backward_workspace_size.
  */
 acseg_status acseg_backward_workspace_size(const acseg_problem *p, size_t *bytes);
 acseg_status acseg_backward(acseg_ctx *ctx, const acseg_problem *p, const float *image,

@@ -29,6 +29,7 @@ struct acseg_ctx {
     int device = 0;
     int cu_count = 0;
     Ctl* host_ctl = nullptr;  // pinned, for statistics read-back
+    AdjCtl* host_actl = nullptr;  // pinned, for the adjoint's convergence flag
     bool timing = false;
     std::vector<hipEvent_t> pool;
     std::vector<TimedRec> recs;
@@ -263,6 +264,7 @@ acseg_status enqueue_correction(acseg_ctx* ctx, const acseg_problem* p, const Mg
     f.ctl = ctl;
     f.rhs = at<float>(ws, L.rhs);
     f.gt = at<float>(ws, L.mg_gt);
+    f.r1 = at<float>(ws, L.mg_r[1]);
     f.v1 = at<float>(ws, L.mg_v[1]);
     f.part = at<double>(ws, L.mg_part);
     f.coef = m.coef[0];
@@ -282,7 +284,7 @@ acseg_status enqueue_correction(acseg_ctx* ctx, const acseg_problem* p, const Mg
         a.dst = dst;
         a.aux = aux;
         a.res = res;
-        a.coef = m.coef[l];
+        a.coef = op == kCoarseResidRestrict ? m.coef[l - 1] : m.coef[l];
         a.W = m.W[l];
         a.H = m.H[l];
         a.Wf = m.W[l - 1];
@@ -293,11 +295,13 @@ acseg_status enqueue_correction(acseg_ctx* ctx, const acseg_problem* p, const Mg
         a.fixed = f.fixed;
         return timed(ctx, kFamMg, s, [&] { return launch_mg_coarse(N, op, a, s); });
     };
-    auto sweeps = [&](int l, int count, bool zero) -> hipError_t {
+    // count sweeps on level l: from v = 0 (zero), or after adding the prolonged
+    // correction vc of level l + 1 (folded into the first red half-sweep)
+    auto sweeps = [&](int l, int count, bool zero, const float* vc) -> hipError_t {
         float* v = at<float>(ws, L.mg_v[l]);
         const float* r = at<float>(ws, L.mg_r[l]);
         for (int k = 0; k < count; ++k) {
-            hipError_t e = coarse(kCoarseHalf, l, r, v, nullptr, nullptr, 0, zero && k == 0);
+            hipError_t e = coarse(kCoarseHalf, l, r, v, k == 0 ? vc : nullptr, nullptr, 0, zero && k == 0);
             if (e == hipSuccess) e = coarse(kCoarseHalf, l, r, v, nullptr, nullptr, 1, 0);
             if (e != hipSuccess) return e;
         }
@@ -306,18 +310,15 @@ acseg_status enqueue_correction(acseg_ctx* ctx, const acseg_problem* p, const Mg
     auto fine = [&](int op) { return timed(ctx, kFamMg, s, [&] { return launch_mg_fine(N, op, f, s); }); };
 
     // truncated defect, restricted to level 1
-    ACSEG_TRY(fine(kMgDefect));
-    ACSEG_TRY(coarse(kCoarseRestrict, 1, f.gt, at<float>(ws, L.mg_r[1]), nullptr, nullptr, 0, 0));
+    ACSEG_TRY(fine(kMgDefectRestrict));
     // down: levels 1 .. tail-1 in global memory
     const int last_global = std::min(m.tail, m.L) - 1;  // deepest level solved by global kernels
     for (int l = 1; l <= last_global; ++l) {
         const bool coarsest = l == m.L - 1;
-        ACSEG_TRY(sweeps(l, coarsest ? kCoarseSweeps : p->nu_pre, true));
+        ACSEG_TRY(sweeps(l, coarsest ? kCoarseSweeps : p->nu_pre, true, nullptr));
         if (coarsest) break;
-        ACSEG_TRY(coarse(kCoarseResid, l, at<float>(ws, L.mg_r[l]), nullptr, at<float>(ws, L.mg_v[l]),
-                         at<float>(ws, L.mg_res[l]), 0, 0));
-        ACSEG_TRY(coarse(kCoarseRestrict, l + 1, at<float>(ws, L.mg_res[l]),
-                         at<float>(ws, L.mg_r[l + 1]), nullptr, nullptr, 0, 0));
+        ACSEG_TRY(coarse(kCoarseResidRestrict, l + 1, at<float>(ws, L.mg_r[l]), at<float>(ws, L.mg_r[l + 1]),
+                         at<float>(ws, L.mg_v[l]), nullptr, 0, 0));
     }
     if (m.tail < m.L) {
         TailArgs t{};
@@ -348,12 +349,8 @@ acseg_status enqueue_correction(acseg_ctx* ctx, const acseg_problem* p, const Mg
         ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_coarse_tail(N, t, bytes, s); }));
     }
     // up: prolongate and post-smooth levels tail-1 .. 1
-    for (int l = std::min(m.tail, m.L - 1) - 1; l >= 1; --l) {
-        if (l == m.L - 1) continue;
-        ACSEG_TRY(coarse(kCoarseProlongAdd, l + 1, at<float>(ws, L.mg_v[l + 1]), at<float>(ws, L.mg_v[l]),
-                         nullptr, nullptr, 0, 0));
-        ACSEG_TRY(sweeps(l, p->nu_post, false));
-    }
+    for (int l = std::min(m.tail, m.L - 1) - 1; l >= 1; --l)
+        ACSEG_TRY(sweeps(l, p->nu_post, false, at<float>(ws, L.mg_v[l + 1])));
     // direction, line search, update
     ACSEG_TRY(fine(kMgDir));
     ACSEG_TRY(fine(kMgWhw));
@@ -627,7 +624,9 @@ acseg_status acseg_create(int device, acseg_ctx** out) {
     acseg_ctx* c = new acseg_ctx();
     c->device = device;
     if (hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
-        hipHostMalloc((void**)&c->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&c->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->host_actl, sizeof(AdjCtl), hipHostMallocDefault) != hipSuccess) {
+        if (c->host_ctl) (void)hipHostFree(c->host_ctl);
         delete c;
         return ACSEG_ERR_HIP;
     }
@@ -643,6 +642,7 @@ acseg_status acseg_destroy(acseg_ctx* ctx) {
     }
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->host_ctl) (void)hipHostFree(ctx->host_ctl);
+    if (ctx->host_actl) (void)hipHostFree(ctx->host_actl);
     if (ctx->stage_ev) {
         (void)hipEventSynchronize(ctx->stage_ev);
         (void)hipEventDestroy(ctx->stage_ev);
@@ -974,9 +974,26 @@ acseg_status acseg_backward(acseg_ctx* ctx, const acseg_problem* p, const float*
         a.c64 = c64 + st * kNC;
         a.tot = tot + st * kCmeansMaxM;
         a.cbar_out = grad_c ? grad_c + (int64_t)st * N * C : nullptr;
-        for (int sw = 0; sw < a.max_sweeps; ++sw) {
+        // sweeps in chunks of growing length; between chunks the host reads the
+        // convergence flag (one small copy and wait per chunk) instead of
+        // enqueueing the whole budget of mostly no-op launches
+        int sw = 0, chunk = 4;
+        while (sw < a.max_sweeps) {
+            const int end = std::min(a.max_sweeps, sw + chunk);
+            for (; sw < end; ++sw) {
+                ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_adj(N, C, kAdjHalf, a, 0, sw, s); }));
+                ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_adj(N, C, kAdjHalf, a, 1, sw, s); }));
+            }
+            if (sw >= a.max_sweeps) break;
+            // the convergence test of the next sweep, done here: one red half-sweep
+            // launch whose check sets the flag, then the flag read back
             ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_adj(N, C, kAdjHalf, a, 0, sw, s); }));
+            ACSEG_TRY(hipMemcpyAsync(ctx->host_actl, actl, sizeof(AdjCtl), hipMemcpyDeviceToHost, s));
+            ACSEG_TRY(hipStreamSynchronize(s));
+            if (ctx->host_actl->done) break;
             ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_adj(N, C, kAdjHalf, a, 1, sw, s); }));
+            ++sw;
+            chunk = std::min(64, chunk * 2);
         }
         ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjAccum, a, 0, 0, s); }));
         ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjReduce, a, 0, 0, s); }));

@@ -181,15 +181,16 @@ constexpr int kTailSide = 64;     // levels with both sides <= this run in the L
 constexpr int kMaxTail = 8;       // levels in the LDS tail
 constexpr int kCoarseSweeps = 8;  // red-black sweeps on the coarsest level
 
-enum MgOp { kMgDefect = 0, kMgDir, kMgWhw, kMgAlpha, kMgUpdate };
+enum MgOp { kMgDefectRestrict = 0, kMgDir, kMgWhw, kMgAlpha, kMgUpdate };
 
 // Fine-level passes.  The iterate is bufs[iterate_buf(ctl->cur, launch)] and
-// is updated in place; gt holds the truncated defect, then the direction.
+// is updated in place; gt holds the direction w.
 struct MgArgs {
     Bufs bufs;
     Ctl* ctl;
     const float* rhs;   // stored right-hand side [N][H][W]
     float* gt;          // [N][H][W]
+    float* r1;          // restricted truncated defect on level 1 [N][Hc][Wc]
     const float* v1;    // correction on level 1 [N][Hc][Wc]
     double* part;       // [2][kMgBlocks]: <g~,w> and <w,Hw> partials
     LevelCoef coef;     // finest level
@@ -197,13 +198,17 @@ struct MgArgs {
     int slot, fixed, launch, nblocks;
 };
 
-enum CoarseOp { kCoarseRestrict = 0, kCoarseProlongAdd, kCoarseHalf, kCoarseResid };
+enum CoarseOp { kCoarseRestrict = 0, kCoarseProlongAdd, kCoarseHalf, kCoarseResid, kCoarseResidRestrict };
 
 // One coarse-level pass on level (W, H); (Wf, Hf) is the next finer level.
-//   restrict:     dst[W x H] = P^T src[Wf x Hf]
-//   prolong_add:  dst[Wf x Hf] += P src[W x H]
-//   half:         red (colour 0) / black half-sweep of H v = src on dst = v
-//   resid:        res = src - H aux
+//   restrict:       dst[W x H] = P^T src[Wf x Hf]
+//   prolong_add:    dst[Wf x Hf] += P src[W x H]
+//   half:           red (colour 0) / black half-sweep of H v = src on dst = v;
+//                   with aux (the next coarser level's v), the neighbours are
+//                   read as v + P aux (a red half-sweep after prolongation)
+//   resid:          res = src - H aux
+//   resid_restrict: dst[W x H] = P^T (src - H_f aux) on the finer level (Wf, Hf),
+//                   coef of the finer level
 struct CoarseArgs {
     const Ctl* ctl;
     const float* src;

@@ -50,10 +50,11 @@ __device__ __forceinline__ float prolong_at(const float* __restrict__ vc, int Wc
     return 0.5f * (r0[0] + r0[Wc + 1]);
 }
 
-// (P^T rf) at coarse node (X, Y): the weights of prolong_at, gathered.
-__device__ __forceinline__ float restrict_at(const float* __restrict__ rf, int Wf, int Hf, int Wc,
-                                             int Hc, int X, int Y) {
-    float s = 0.f;
+// Visit the fine nodes that prolong_at lets coarse node (X, Y) reach, with
+// their weights: f(x, y, weight).  The transpose of the prolongation is the
+// weighted sum of a fine field over these visits.
+template <class F>
+__device__ __forceinline__ void for_restrict(int Wf, int Hf, int Wc, int Hc, int X, int Y, F&& f) {
 #pragma unroll
     for (int db = -1; db <= 1; ++db) {
         const int b = 2 * Y + db;
@@ -67,9 +68,16 @@ __device__ __forceinline__ float restrict_at(const float* __restrict__ rf, int W
             const float wt = (da == 0 && db == 0) ? 1.f : 0.5f;
             const int xn = (a == 2 * Wc - 2 && a + 1 < Wf) ? 2 : 1;
             for (int yy = 0; yy < yn; ++yy)
-                for (int xx = 0; xx < xn; ++xx) s += wt * rf[(int64_t)(b + yy) * Wf + a + xx];
+                for (int xx = 0; xx < xn; ++xx) f(a + xx, b + yy, wt);
         }
     }
+}
+
+// (P^T rf) at coarse node (X, Y).
+__device__ __forceinline__ float restrict_at(const float* __restrict__ rf, int Wf, int Hf, int Wc,
+                                             int Hc, int X, int Y) {
+    float s = 0.f;
+    for_restrict(Wf, Hf, Wc, Hc, X, Y, [&](int x, int y, float wt) { s += wt * rf[(int64_t)y * Wf + x]; });
     return s;
 }
 
@@ -79,6 +87,44 @@ __device__ __forceinline__ float nb_sum(const float* __restrict__ v, int W, int 
     const float h = (x > 0 ? v[p - 1] : 0.f) + (x < W - 1 ? v[p + 1] : 0.f);
     const float vv = (y > 0 ? v[p - W] : 0.f) + (y < H - 1 ? v[p + W] : 0.f);
     return edge_w_h(y, H) * h + edge_w_v(x, W) * vv;
+}
+
+// nb_sum of v + P vc (vc on the coarse lattice Wc x Hc of this one).
+__device__ __forceinline__ float nb_sum_prolonged(const float* __restrict__ v, const float* __restrict__ vc,
+                                                  int W, int H, int Wc, int Hc, int x, int y, int64_t p) {
+    const float l = x > 0 ? v[p - 1] + prolong_at(vc, Wc, Hc, x - 1, y) : 0.f;
+    const float r = x < W - 1 ? v[p + 1] + prolong_at(vc, Wc, Hc, x + 1, y) : 0.f;
+    const float d = y > 0 ? v[p - W] + prolong_at(vc, Wc, Hc, x, y - 1) : 0.f;
+    const float u = y < H - 1 ? v[p + W] + prolong_at(vc, Wc, Hc, x, y + 1) : 0.f;
+    return edge_w_h(y, H) * (l + r) + edge_w_v(x, W) * (d + u);
+}
+
+// The truncated defect g~_p = T_I (D (y_p(u) - u_p)) of node (x, y), N values.
+template <int N>
+__device__ __forceinline__ void trunc_defect(const MgArgs& a, const float* __restrict__ u, int x, int y,
+                                             float (&g)[N]) {
+    const int W = a.W, H = a.H;
+    const int64_t n = (int64_t)W * H, p = (int64_t)y * W + x;
+    const int cls = node_class(x, y, W, H);
+    const float kap = sel4(a.coef.kappa, cls), D = sel4(a.coef.d, cls);
+    bool fr[N];
+    float s = 0.f;
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const float* ui = u + i * n;
+        const float uc = ui[p];
+        const float yv = a.rhs[i * n + p] + kap * nb_sum(ui, W, H, x, y, p);
+        g[i] = D * (yv - uc);
+        fr[i] = uc > 0.f;
+        if (fr[i]) {
+            s += g[i];
+            ++k;
+        }
+    }
+    const float mean = k > 0 ? s / (float)k : 0.f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) g[i] = (k >= 2 && fr[i]) ? g[i] - mean : 0.f;
 }
 
 __device__ __forceinline__ bool step_done(const MgArgs& a) {
@@ -100,40 +146,31 @@ __device__ __forceinline__ double block_sum_d(double v, double* sh /* kBlock/kWa
 // Finest level
 // ---------------------------------------------------------------------------
 
-// 1. g~ = T_I (D (y(u) - u)) into a.gt.
+// 1-2. r_1 = P^T g~, coarse node by coarse node (the defect of a fine node is
+// recomputed for each coarse node it reaches).
 template <int N>
-__global__ __launch_bounds__(kBlock) void k_mg_defect(MgArgs a) {
+__global__ __launch_bounds__(kBlock) void k_mg_defect_restrict(MgArgs a) {
     if (step_done(a)) return;
     const float* __restrict__ u = a.bufs.b[iterate_buf(a.ctl->cur, a.launch)];
-    const int W = a.W, H = a.H;
-    const int64_t n = (int64_t)W * H;
-    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += (int64_t)gridDim.x * kBlock) {
-        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
-        const int cls = node_class(x, y, W, H);
-        const float kap = sel4(a.coef.kappa, cls), D = sel4(a.coef.d, cls);
-        float g[N];
-        bool fr[N];
-        float s = 0.f;
-        int k = 0;
+    const int Wc = a.Wc, Hc = a.Hc;
+    const int64_t nc = (int64_t)Wc * Hc;
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < nc; p += (int64_t)gridDim.x * kBlock) {
+        const int Y = (int)(p / Wc), X = (int)(p - (int64_t)Y * Wc);
+        float r[N];
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const float* ui = u + i * n;
-            const float uc = ui[p];
-            const float yv = a.rhs[i * n + p] + kap * nb_sum(ui, W, H, x, y, p);
-            g[i] = D * (yv - uc);
-            fr[i] = uc > 0.f;
-            if (fr[i]) {
-                s += g[i];
-                ++k;
-            }
-        }
-        const float mean = k > 0 ? s / (float)k : 0.f;
+        for (int i = 0; i < N; ++i) r[i] = 0.f;
+        for_restrict(a.W, a.H, Wc, Hc, X, Y, [&](int x, int y, float wt) {
+            float g[N];
+            trunc_defect<N>(a, u, x, y, g);
 #pragma unroll
-        for (int i = 0; i < N; ++i) a.gt[i * n + p] = (k >= 2 && fr[i]) ? g[i] - mean : 0.f;
+            for (int i = 0; i < N; ++i) r[i] += wt * g[i];
+        });
+#pragma unroll
+        for (int i = 0; i < N; ++i) a.r1[i * nc + p] = r[i];
     }
 }
 
-// 4a. w = Pi(u + T_I P v_1) - u into a.gt (over g~), block partials of <g~, w>.
+// 4a. w = Pi(u + T_I P v_1) - u into a.gt, block partials of <g~, w> (g~ recomputed).
 template <int N>
 __global__ __launch_bounds__(kBlock) void k_mg_dir(MgArgs a) {
     __shared__ double sh[kBlock / kWave];
@@ -156,6 +193,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_dir(MgArgs a) {
                 ++k;
             }
         }
+        float g[N];
+        trunc_defect<N>(a, u, x, y, g);
         float w[N];
         if (k >= 2) {
             const float mean = s / (float)k;
@@ -171,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_dir(MgArgs a) {
         }
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            gw += (double)a.gt[i * n + p] * (double)w[i];
+            gw += (double)g[i] * (double)w[i];
             a.gt[i * n + p] = w[i];
         }
     }
@@ -272,10 +311,15 @@ __global__ __launch_bounds__(kBlock) void k_lin_half(CoarseArgs a) {
         const int64_t p = (int64_t)y * W + x;
         const int cls = node_class(x, y, W, H);
         const float kap = sel4(a.coef.kappa, cls), invd = sel4(a.coef.inv_d, cls);
+        const int Wc = (W + 1) / 2, Hc = (H + 1) / 2;
+        const int64_t nc = (int64_t)Wc * Hc;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             float s = a.src[i * n + p] * invd;
-            if (!a.zero) s += kap * nb_sum(a.dst + i * n, W, H, x, y, p);
+            if (a.aux)  // the neighbours' values plus the prolonged coarse correction
+                s += kap * nb_sum_prolonged(a.dst + i * n, a.aux + i * nc, W, H, Wc, Hc, x, y, p);
+            else if (!a.zero)
+                s += kap * nb_sum(a.dst + i * n, W, H, x, y, p);
             a.dst[i * n + p] = s;
         }
     }
@@ -294,6 +338,30 @@ __global__ __launch_bounds__(kBlock) void k_lin_resid(CoarseArgs a) {
         for (int i = 0; i < N; ++i) {
             const float* v = a.aux + i * n;
             a.res[i * n + p] = a.src[i * n + p] - (D * v[p] - a.coef.e2 * nb_sum(v, W, H, x, y, p));
+        }
+    }
+}
+
+// dst (level of (W, H)) = P^T (r - H v) of the finer level (Wf, Hf): src = r,
+// aux = v of the finer level, coef of the finer level in a.coef.
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_resid_restrict(CoarseArgs a) {
+    if (!a.fixed && a.ctl->step[a.slot].done) return;
+    const int Wf = a.Wf, Hf = a.Hf;
+    const int64_t nf = (int64_t)Wf * Hf, nc = (int64_t)a.W * a.H;
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < nc; p += (int64_t)gridDim.x * kBlock) {
+        const int Y = (int)(p / a.W), X = (int)(p - (int64_t)Y * a.W);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const float* v = a.aux + i * nf;
+            const float* r = a.src + i * nf;
+            float s = 0.f;
+            for_restrict(Wf, Hf, a.W, a.H, X, Y, [&](int x, int y, float wt) {
+                const int64_t q = (int64_t)y * Wf + x;
+                const float D = sel4(a.coef.d, node_class(x, y, Wf, Hf));
+                s += wt * (r[q] - (D * v[q] - a.coef.e2 * nb_sum(v, Wf, Hf, x, y, q)));
+            });
+            a.dst[i * nc + p] = s;
         }
     }
 }
@@ -392,7 +460,9 @@ template <int N>
 hipError_t mg_fine(int op, const MgArgs& a, hipStream_t s) {
     const int g = a.nblocks;
     switch (op) {
-        case kMgDefect: hipLaunchKernelGGL((k_mg_defect<N>), dim3(g), dim3(kBlock), 0, s, a); break;
+        case kMgDefectRestrict:
+            hipLaunchKernelGGL((k_mg_defect_restrict<N>), dim3(grid_for((int64_t)a.Wc * a.Hc)), dim3(kBlock), 0, s, a);
+            break;
         case kMgDir: hipLaunchKernelGGL((k_mg_dir<N>), dim3(g), dim3(kBlock), 0, s, a); break;
         case kMgWhw: hipLaunchKernelGGL((k_mg_whw<N>), dim3(g), dim3(kBlock), 0, s, a); break;
         case kMgAlpha: hipLaunchKernelGGL(k_mg_alpha, dim3(1), dim3(kBlock), 0, s, a); break;
@@ -416,6 +486,9 @@ hipError_t mg_coarse(int op, const CoarseArgs& a, hipStream_t s) {
             break;
         case kCoarseResid:
             hipLaunchKernelGGL((k_lin_resid<N>), dim3(grid_for((int64_t)a.W * a.H)), dim3(kBlock), 0, s, a);
+            break;
+        case kCoarseResidRestrict:
+            hipLaunchKernelGGL((k_resid_restrict<N>), dim3(grid_for((int64_t)a.W * a.H)), dim3(kBlock), 0, s, a);
             break;
         default: return hipErrorInvalidValue;
     }
