@@ -204,6 +204,8 @@ def main():
     ap.add_argument("--levels", type=int, default=1,
                     help="multigrid levels (1: Gauss-Seidel cycles only, 0: automatic)")
     ap.add_argument("--max-cycles", type=int, default=20, help="cycle budget per time step")
+    ap.add_argument("--cycles", type=int, default=0,
+                    help="fixed cycles per time step without a calibration solve (0: calibrate)")
     ap.add_argument("--nu", type=int, nargs=2, default=(1, 1), metavar=("PRE", "POST"),
                     help="smoothing sweeps before / after the coarse correction")
     ap.add_argument("--adjoint", action="store_true",
@@ -265,8 +267,8 @@ def main():
                                        nu_post=args.nu[1], max_cycles=args.max_cycles)
 
     # calibration: how many cycles does the slowest time step of any image need?
-    cycles = 1
-    for b in range(B):
+    cycles = max(1, args.cycles)
+    for b in (range(B) if args.cycles == 0 else ()):
         us[b].copy_(u0s[b])
         _, _, st, _ = acseg.solve(base, imgs[b], us[b])
         if st["status"] != acseg.OK:
