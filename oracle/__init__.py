@@ -104,6 +104,8 @@ def lib():
         L.orc_adjoint_solve.argtypes = [pp, dp, dp, dp]
         L.orc_adjoint_step.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
         L.orc_backward.argtypes = [pp, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_backward_c.argtypes = [pp, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_solve_c.argtypes = [pp, ctypes.c_int, dp, dp, dp, dp, dp, sp]
         _lib = L
     return _lib
 
@@ -281,3 +283,27 @@ def backward(P: Params, steps: int, I, traj, ubar_T):
                           _p(grads), _p(cbar), _p(ubar0)):
         raise ValueError("bad parameters")
     return Ibar, grads, cbar[:steps], ubar0
+
+
+def solve_fixed_c(P: Params, steps: int, I, u0, c_fixed, keep_trajectory: bool = True):
+    """``steps`` time steps with the colour means fixed; returns (u_T, traj or None, stats list)."""
+    I, u0, cf = _d(I), _d(u0), _d(c_fixed)
+    u = np.empty_like(u0)
+    traj = np.empty((steps + 1,) + u0.shape) if keep_trajectory else None
+    st = (_Stats * max(steps, 1))()
+    if lib().orc_solve_c(ctypes.byref(P.c()), steps, _p(I), _p(u0), _p(cf), _p(u), _p(traj), st):
+        raise ValueError("bad parameters")
+    return u, traj, [_stats(st[k]) for k in range(steps)]
+
+
+def backward_fixed_c(P: Params, steps: int, I, traj, c_fixed, ubar_T):
+    """Backwards with fixed means; returns (Ibar, grads, cbar [N][C] = dL/dc_fixed, ubar0)."""
+    I, traj, ubar_T, cf = _d(I), _d(traj), _d(ubar_T), _d(c_fixed)
+    Ibar = np.empty_like(I)
+    grads = np.empty(3)
+    cbar = np.empty((P.N, P.C))
+    ubar0 = np.empty_like(ubar_T)
+    if lib().orc_backward_c(ctypes.byref(P.c()), steps, _p(I), _p(traj), _p(cf), _p(ubar_T), _p(Ibar),
+                            _p(grads), _p(cbar), _p(ubar0)):
+        raise ValueError("bad parameters")
+    return Ibar, grads, cbar, ubar0

@@ -788,6 +788,42 @@ int orc_solve(const orc_params *P, int steps, const double *I, const double *u0,
 }
 
 /*
+ * As orc_solve, with the colour means fixed to c_fixed ([N][C]) in every step
+ * instead of recomputed from u^n.
+ */
+int orc_solve_c(const orc_params *P, int steps, const double *I, const double *u0,
+                const double *c_fixed, double *u_out, double *traj, orc_stats *stats)
+{
+    grid_t G[32];
+    int L;
+    if (hierarchy_init(P, G, &L)) return -1;
+    size_t n = (size_t)P->W * P->H, nu = (size_t)P->N * n;
+    double *b = malloc(sizeof(double) * nu);
+    double *cur = malloc(sizeof(double) * nu);
+    double *nxt = malloc(sizeof(double) * nu);
+    memcpy(cur, u0, sizeof(double) * nu);
+    if (traj) memcpy(traj, u0, sizeof(double) * nu);
+    for (int s = 0; s < steps; ++s) {
+        rhs(&G[0], P, I, cur, c_fixed, b);
+        memcpy(nxt, cur, sizeof(double) * nu);
+        orc_stats st;
+        solve_rhs(G, L, P, b, nxt, &st);
+        st.empty_phase = 0;
+        if (stats) stats[s] = st;
+        if (traj) memcpy(traj + (size_t)(s + 1) * nu, nxt, sizeof(double) * nu);
+        double *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    memcpy(u_out, cur, sizeof(double) * nu);
+    free(b);
+    free(cur);
+    free(nxt);
+    hierarchy_free(G, L);
+    return 0;
+}
+
+/*
  * Discrete energy of eq. E on the P1 space with the lumped mass:
  *   parts[0] = eps/2 sum_i u_i.A u_i                       (interface)
  *   parts[1] = 1/eps sum_i sum_p M_p u_pi (1 - u_pi)         (concave potential)
@@ -944,8 +980,9 @@ static int adjoint_solve(const grid_t *g, const orc_params *P, const double *une
  * Ibar += dL/dI, grads[0..2] += dL/dlambda, dL/deps (tau fixed), dL/dtau.
  */
 static int adjoint_step(const grid_t *g, const orc_params *P, const double *I, const double *un,
-                        const double *c_prev, const double *unext, const double *ubar_next,
-                        double *ubar_n, double *Ibar, double *grads, double *cbar, double *z_out)
+                        const double *c_prev, const double *c_fixed, const double *unext,
+                        const double *ubar_next, double *ubar_n, double *Ibar, double *grads,
+                        double *cbar, double *z_out)
 {
     const int N = P->N, C = P->C;
     size_t n = (size_t)g->W * g->H, m = (size_t)N * n;
@@ -953,13 +990,16 @@ static int adjoint_step(const grid_t *g, const orc_params *P, const double *I, c
     double S[ORC_MAX_N];
     unsigned char nonempty[ORC_MAX_N];
     if (C > 4) return -1;
-    colour_means(g, N, C, I, un, c_prev, c);
+    if (c_fixed)
+        memcpy(c, c_fixed, sizeof(double) * N * C);
+    else
+        colour_means(g, N, C, I, un, c_prev, c);
     double area = 0.0;
     for (size_t p = 0; p < n; ++p) area += g->mass[p];
     for (int i = 0; i < N; ++i) {
         S[i] = 0.0;
         for (size_t p = 0; p < n; ++p) S[i] += g->mass[p] * un[i * n + p];
-        nonempty[i] = S[i] > 1e-12 * area;
+        nonempty[i] = !c_fixed && S[i] > 1e-12 * area;  /* fixed means depend on nothing */
     }
     double *z = malloc(sizeof(double) * m);
     adjoint_solve(g, P, unext, ubar_next, z, 1e-14);
@@ -1009,6 +1049,10 @@ static int adjoint_step(const grid_t *g, const orc_params *P, const double *I, c
     return 0;
 }
 
+int orc_backward_c(const orc_params *P, int steps, const double *I, const double *traj,
+                   const double *c_fixed, const double *ubar_T, double *Ibar, double *grads,
+                   double *cbar, double *ubar0);
+
 /* The gradient at b of one step: z = (T H T)^+ T ubar, free sets from unext. */
 int orc_adjoint_solve(const orc_params *P, const double *unext, const double *ubar, double *z)
 {
@@ -1025,7 +1069,7 @@ int orc_adjoint_step(const orc_params *P, const double *I, const double *un, con
 {
     grid_t g;
     if (grid_init(&g, P->W, P->H, P->h)) return -1;
-    int r = adjoint_step(&g, P, I, un, c_prev, unext, ubar_next, ubar_n, Ibar, grads, cbar, NULL);
+    int r = adjoint_step(&g, P, I, un, c_prev, NULL, unext, ubar_next, ubar_n, Ibar, grads, cbar, NULL);
     grid_free(&g);
     return r;
 }
@@ -1039,6 +1083,18 @@ int orc_adjoint_step(const orc_params *P, const double *I, const double *un, con
  */
 int orc_backward(const orc_params *P, int steps, const double *I, const double *traj,
                  const double *ubar_T, double *Ibar, double *grads, double *cbar, double *ubar0)
+{
+    return orc_backward_c(P, steps, I, traj, NULL, ubar_T, Ibar, grads, cbar, ubar0);
+}
+
+/*
+ * As orc_backward; with c_fixed ([N][C], non-NULL) every step used those
+ * means (no colour-mean update), and cbar ([N][C]) receives dL/dc_fixed,
+ * the sum over the steps.
+ */
+int orc_backward_c(const orc_params *P, int steps, const double *I, const double *traj,
+                   const double *c_fixed, const double *ubar_T, double *Ibar, double *grads,
+                   double *cbar, double *ubar0)
 {
     grid_t g;
     if (grid_init(&g, P->W, P->H, P->h)) return -1;
@@ -1054,10 +1110,14 @@ int orc_backward(const orc_params *P, int steps, const double *I, const double *
     memset(Ibar, 0, sizeof(double) * C * n);
     grads[0] = grads[1] = grads[2] = 0.0;
     int r = 0;
+    if (c_fixed && cbar) memset(cbar, 0, sizeof(double) * N * C);
     for (int s = steps - 1; s >= 0 && r == 0; --s) {
         r = adjoint_step(&g, P, I, traj + (size_t)s * m, s > 0 ? cs + (size_t)(s - 1) * N * C : NULL,
-                         traj + (size_t)(s + 1) * m, ub, ub2, Ibar, grads, cb, NULL);
-        if (cbar) memcpy(cbar + (size_t)s * N * C, cb, sizeof(double) * N * C);
+                         c_fixed, traj + (size_t)(s + 1) * m, ub, ub2, Ibar, grads, cb, NULL);
+        if (cbar && c_fixed)
+            for (int q = 0; q < N * C; ++q) cbar[q] += cb[q];
+        else if (cbar)
+            memcpy(cbar + (size_t)s * N * C, cb, sizeof(double) * N * C);
         double *t = ub;
         ub = ub2;
         ub2 = t;

@@ -130,3 +130,39 @@ def test_dot_product_identity_of_one_step():
     ubar_n, _, _, _ = orc.adjoint_step(P, img, u0, u1, wv)
     lhs, rhs_ = (Jv * wv).sum(), (v * ubar_n).sum()
     assert abs(lhs - rhs_) <= 1e-6 * max(1.0, abs(lhs)), (lhs, rhs_)
+
+
+@pytest.mark.parametrize("pixel", [True, False])
+def test_fixed_means_backward_matches_finite_differences(pixel):
+    """With the colour means fixed (an input of the solve), the gradient with
+    respect to them is a true input gradient: pinned by central differences of
+    the forward oracle along every entry."""
+    w, P, img, u0, lab = small(pixel=pixel, seed=6)
+    c_fixed, _ = orc.colour_means(P, img, u0)
+    c_fixed = c_fixed + 0.05  # away from the means of any state
+    y = np.stack([(lab == i).astype(np.float64) for i in range(P.N)])
+
+    def L(Pp=P, I=img, u=u0, c=c_fixed):
+        uT, _, _ = orc.solve_fixed_c(Pp, w.steps, I, u, c, keep_trajectory=False)
+        return ((uT - y) ** 2).sum()
+
+    uT, traj, _ = orc.solve_fixed_c(P, w.steps, img, u0, c_fixed)
+    Ibar, grads, cbar, ubar0 = orc.backward_fixed_c(P, w.steps, img, traj, c_fixed, 2 * (uT - y))
+    d = 1e-6
+    for i in range(P.N):
+        for k in range(P.C):
+            e = np.zeros_like(c_fixed)
+            e[i, k] = d
+            fd = (L(c=c_fixed + e) - L(c=c_fixed - e)) / (2 * d)
+            assert abs(fd - cbar[i, k]) <= 1e-4 * max(abs(fd), 1e-6), (i, k, fd, cbar[i, k])
+    for kk, name in enumerate(["lam", "eps", "tau"]):
+        v = getattr(P, name)
+        fd = (L(Pp=with_(P, **{name: v * (1 + d)})) - L(Pp=with_(P, **{name: v * (1 - d)}))) / (2 * d * v)
+        assert abs(fd - grads[kk]) <= 1e-4 * max(abs(fd), 1e-8 * abs(L())), (name, fd, grads[kk])
+    rng = np.random.default_rng(7)
+    V = rng.choice([-1.0, 1.0], size=img.shape)
+    fd = (L(I=img + d * V) - L(I=img - d * V)) / (2 * d)
+    assert abs(fd - (Ibar * V).sum()) <= 1e-4 * max(abs(fd), 1e-6)
+    Vu = rng.standard_normal(u0.shape)
+    fd = (L(u=u0 + d * Vu) - L(u=u0 - d * Vu)) / (2 * d)
+    assert abs(fd - (ubar0 * Vu).sum()) <= 1e-4 * max(abs(fd), 1e-6)
