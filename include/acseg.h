@@ -76,6 +76,14 @@ typedef int32_t acseg_status;
  * flag, cycles after convergence are enqueued but exit at once on the device.
  */
 #define ACSEG_FLAG_FIXED_CYCLES 2u
+/*
+ * The colour means are an input, the same in every time step, instead of the
+ * means of u^n (eq. VV_fidelity): acseg_solve reads them from c_out (which it
+ * then does not write), acseg_solve_batched from c_outs[b], acseg_step from
+ * c_prev (copied to c_out); all of them must be non-NULL.  acseg_backward
+ * then takes them as c_fixed and returns dL/dc_fixed in grad_c ([N][C]).
+ */
+#define ACSEG_FLAG_FIXED_C 4u
 
 /*
  * One segmentation problem.  Parameters follow eq. E and eq. alpha:
@@ -247,7 +255,9 @@ acseg_status acseg_energy(acseg_ctx *ctx, const acseg_problem *p, const float *i
  * Outputs (device): grad_image float[C][H][W] = dL/dI; grad_u0
  * float[N][H][W] = dL/du^0 (may be NULL); grad_params double[3] = dL/dlambda,
  * dL/deps at fixed tau, dL/dtau; grad_c float[steps][N][C] = dL/dc^n, the
- * gradient at the colour means used by step n (may be NULL).  Each step's
+ * gradient at the colour means used by step n (may be NULL).  With
+ * ACSEG_FLAG_FIXED_C, c_fixed (float[N][C]) are the means of the solve and
+ * grad_c is float[N][C] = dL/dc_fixed; otherwise c_fixed is ignored.  Each step's
  * derivative holds the free sets {i : u^{n+1}_pi > 0} fixed (components at 0
  * count as active) and treats the kept mean of an empty phase as a constant.
  * The per-step linear solves are red-black sweeps to a relative change of
@@ -259,9 +269,10 @@ acseg_status acseg_energy(acseg_ctx *ctx, const acseg_problem *p, const float *i
  */
 acseg_status acseg_backward_workspace_size(const acseg_problem *p, size_t *bytes);
 acseg_status acseg_backward(acseg_ctx *ctx, const acseg_problem *p, const float *image,
-                            const float *checkpoints, const float *grad_uT, float *grad_image,
-                            float *grad_u0, double *grad_params, float *grad_c,
-                            acseg_stats *stats, void *ws, size_t ws_bytes, void *stream);
+                            const float *checkpoints, const float *c_fixed,
+                            const float *grad_uT, float *grad_image, float *grad_u0,
+                            double *grad_params, float *grad_c, acseg_stats *stats, void *ws,
+                            size_t ws_bytes, void *stream);
 
 /*
  * Kernel timing (profiling aid).  While enabled on a context, the calls

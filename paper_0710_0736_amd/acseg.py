@@ -27,6 +27,7 @@ WARN_NOT_CONVERGED = 1
 WARN_EMPTY_PHASE = 2
 FLAG_STORE_CHECKPOINTS = 1
 FLAG_FIXED_CYCLES = 2
+FLAG_FIXED_C = 4
 
 
 class _Problem(ctypes.Structure):
@@ -114,7 +115,7 @@ def lib():
         L.acseg_solve.argtypes = [vp, pp, vp, vp, vp, vp, sp, vp, sz, vp]
         L.acseg_labels.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp]
         L.acseg_backward_workspace_size.argtypes = [pp, ctypes.POINTER(sz)]
-        L.acseg_backward.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp, vp, sp, vp, sz, vp]
+        L.acseg_backward.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp, vp, vp, sp, vp, sz, vp]
         L.acseg_batch_workspace_size.argtypes = [ctypes.c_int32, pp, ctypes.POINTER(sz)]
         L.acseg_solve_batched.argtypes = [vp, ctypes.c_int32, pp, ctypes.POINTER(vp),
                                           ctypes.POINTER(vp), ctypes.POINTER(vp), sp, vp, sz, vp]
@@ -230,8 +231,14 @@ def colour_means(p: Problem, image: torch.Tensor, u: torch.Tensor, c_prev=None):
     return c, _stats_dict(st)
 
 
-def step(p: Problem, image: torch.Tensor, u_in: torch.Tensor, c_prev=None, want_stats=True):
-    """One time step from ``u_in``; returns (u_out, c_used, stats)."""
+def step(p: Problem, image: torch.Tensor, u_in: torch.Tensor, c_prev=None, want_stats=True,
+         c_fixed=None):
+    """One time step from ``u_in``; returns (u_out, c_used, stats).
+
+    With ``c_fixed`` ([N][C]) the step uses those means (FLAG_FIXED_C)."""
+    if c_fixed is not None:
+        p = replace(p, flags=p.flags | FLAG_FIXED_C)
+        c_prev = c_fixed
     _need(image, (p.C, p.H, p.W), name="image")
     _need(u_in, (p.N, p.H, p.W), name="u_in")
     if c_prev is not None:
@@ -248,10 +255,11 @@ def step(p: Problem, image: torch.Tensor, u_in: torch.Tensor, c_prev=None, want_
 
 
 def solve(p: Problem, image: torch.Tensor, u: torch.Tensor, checkpoints: bool = False,
-          want_stats: bool = True, c_out: bool = True):
+          want_stats: bool = True, c_out: bool = True, c_fixed: Optional[torch.Tensor] = None):
     """``p.steps`` time steps; ``u`` (u^0) is overwritten with u^steps.
 
     Returns (u, c [N][C] of the result or None, stats or None, checkpoints or None).
+    With ``c_fixed`` ([N][C]) every step uses those means (FLAG_FIXED_C) and c is c_fixed.
     """
     _need(image, (p.C, p.H, p.W), name="image")
     _need(u, (p.N, p.H, p.W), name="u")
@@ -259,7 +267,12 @@ def solve(p: Problem, image: torch.Tensor, u: torch.Tensor, checkpoints: bool = 
     if checkpoints:
         p = replace(p, flags=p.flags | FLAG_STORE_CHECKPOINTS)
         ck = torch.empty((p.steps + 1, p.N, p.H, p.W), dtype=torch.float32, device=u.device)
-    c = torch.empty((p.N, p.C), dtype=torch.float32, device=u.device) if c_out else None
+    if c_fixed is not None:
+        _need(c_fixed, (p.N, p.C), name="c_fixed")
+        p = replace(p, flags=p.flags | FLAG_FIXED_C)
+        c = c_fixed
+    else:
+        c = torch.empty((p.N, p.C), dtype=torch.float32, device=u.device) if c_out else None
     ws = workspace(p, u.device.index)
     st = _Stats()
     _check(lib().acseg_solve(ctx(u.device.index), ctypes.byref(p.c()), _ptr(image), _ptr(u),
@@ -280,11 +293,15 @@ def batch_workspace_size(problems) -> int:
     return n.value
 
 
-def solve_batched(problems, images, us, want_stats: bool = True, c_out: bool = True):
+def solve_batched(problems, images, us, want_stats: bool = True, c_out: bool = True,
+                  c_fixed=None):
     """One time loop over independent images; every ``us[b]`` is overwritten.
 
-    Returns (us, cs (list of [N][C] or None), stats (list) or None).
+    Returns (us, cs (list of [N][C] or None), stats (list) or None).  With
+    ``c_fixed`` (a list of [N][C]) every step of image b uses c_fixed[b].
     """
+    if c_fixed is not None:
+        problems = [replace(p, flags=p.flags | FLAG_FIXED_C) for p in problems]
     B = len(problems)
     if not (len(images) == len(us) == B) or B == 0:
         raise ValueError("need one image and one field per problem")
@@ -292,7 +309,13 @@ def solve_batched(problems, images, us, want_stats: bool = True, c_out: bool = T
         _need(im, (p.C, p.H, p.W), name="image")
         _need(u, (p.N, p.H, p.W), name="u")
     dev = us[0].device
-    cs = [torch.empty((p.N, p.C), dtype=torch.float32, device=dev) for p in problems] if c_out else None
+    if c_fixed is not None:
+        cs = list(c_fixed)
+        for p, c in zip(problems, cs):
+            _need(c, (p.N, p.C), name="c_fixed")
+        c_out = True
+    else:
+        cs = [torch.empty((p.N, p.C), dtype=torch.float32, device=dev) for p in problems] if c_out else None
     VP = ctypes.c_void_p * B
     ims = VP(*[im.data_ptr() for im in images])
     uus = VP(*[u.data_ptr() for u in us])
@@ -310,12 +333,16 @@ def solve_batched(problems, images, us, want_stats: bool = True, c_out: bool = T
 
 
 def backward(p: Problem, image: torch.Tensor, checkpoints: torch.Tensor, grad_uT: torch.Tensor,
-             want_stats: bool = True):
+             want_stats: bool = True, c_fixed: Optional[torch.Tensor] = None):
     """Gradients of L(u^steps) given dL/du^steps and the checkpoints of a solve.
 
     Returns (grad_image [C][H][W], grad_u0 [N][H][W], grad_params float64 [3]
-    (lambda, eps at fixed tau, tau), grad_c [steps][N][C], stats or None).
+    (lambda, eps at fixed tau, tau), grad_c [steps][N][C] -- or [N][C] =
+    dL/dc_fixed for a solve with fixed means --, stats or None).
     """
+    if c_fixed is not None:
+        _need(c_fixed, (p.N, p.C), name="c_fixed")
+        p = replace(p, flags=p.flags | FLAG_FIXED_C)
     _need(image, (p.C, p.H, p.W), name="image")
     _need(checkpoints, (p.steps + 1, p.N, p.H, p.W), name="checkpoints")
     _need(grad_uT, (p.N, p.H, p.W), name="grad_uT")
@@ -333,40 +360,46 @@ def backward(p: Problem, image: torch.Tensor, checkpoints: torch.Tensor, grad_uT
         _ws_cache[("backward", dev)] = ws
     st = _Stats()
     _check(lib().acseg_backward(ctx(dev.index), ctypes.byref(p.c()), _ptr(image), _ptr(checkpoints),
-                                _ptr(grad_uT), _ptr(gI), _ptr(gu0), _ptr(gp), _ptr(gc),
+                                _ptr(c_fixed), _ptr(grad_uT), _ptr(gI), _ptr(gu0), _ptr(gp), _ptr(gc),
                                 ctypes.byref(st) if want_stats else None, _ptr(ws), ws.numel(),
                                 _stream()), "acseg_backward")
-    return gI, gu0, gp, gc[:p.steps], (_stats_dict(st) if want_stats else None)
+    gcv = gc[0] if c_fixed is not None else gc[:p.steps]
+    return gI, gu0, gp, gcv, (_stats_dict(st) if want_stats else None)
 
 
 class SegmentFn(torch.autograd.Function):
     """u^steps of a solve as a differentiable function of (image, u0, lambda, eps, tau).
 
-    ``SegmentFn.apply(image, u0, lam, eps, tau, problem)``: lam, eps and tau
-    are scalar tensors (they replace the problem's values); the gradient with
-    respect to eps is taken at fixed tau.  The backward pass runs the library's
-    adjoint from the checkpoints stored by the forward pass.
+    ``SegmentFn.apply(image, u0, lam, eps, tau, problem, c_fixed=None)``: lam,
+    eps and tau are scalar tensors (they replace the problem's values); the
+    gradient with respect to eps is taken at fixed tau.  With ``c_fixed``
+    ([N][C]) every step uses those colour means, and they get a gradient too.
+    The backward pass runs the library's adjoint from the checkpoints stored by
+    the forward pass.
     """
 
     @staticmethod
-    def forward(fctx, image, u0, lam, eps, tau, problem: Problem):
+    def forward(fctx, image, u0, lam, eps, tau, problem: Problem, c_fixed=None):
         p = replace(problem, lam=float(lam), eps=float(eps), tau=float(tau))
         img = image.detach().contiguous()
         u = u0.detach().clone().contiguous()
-        u, _, _, ck = solve(p, img, u, checkpoints=True, want_stats=False, c_out=False)
+        cf = None if c_fixed is None else c_fixed.detach().float().contiguous()
+        u, _, _, ck = solve(p, img, u, checkpoints=True, want_stats=False, c_out=False, c_fixed=cf)
         fctx.save_for_backward(img, ck)
         fctx.p = p
+        fctx.cf = cf
         fctx.scalars = (lam, eps, tau)
         return u
 
     @staticmethod
     def backward(fctx, grad_u):
         img, ck = fctx.saved_tensors
-        gI, gu0, gp, _, _ = backward(fctx.p, img, ck, grad_u.contiguous().float(), want_stats=False)
+        gI, gu0, gp, gc, _ = backward(fctx.p, img, ck, grad_u.contiguous().float(), want_stats=False,
+                                      c_fixed=fctx.cf)
         outs = []
         for k, t in enumerate(fctx.scalars):
             outs.append(gp[k].to(t.device, t.dtype) if isinstance(t, torch.Tensor) else None)
-        return (gI, gu0, *outs, None)
+        return (gI, gu0, *outs, None, gc if fctx.cf is not None else None)
 
 
 def labels(p: Problem, u: torch.Tensor, c: torch.Tensor):
@@ -426,3 +459,26 @@ def segment(image: torch.Tensor, N: int, *, lam: float, steps: int, h: Optional[
     u, c, st, _ = solve(p, image.contiguous(), u)
     lab, _, _ = labels(p, u, c)
     return u, c, lab, st
+
+
+def segment_batch(images, Ns, *, lam: float, steps: int, tol: float = 1e-6, seed: int = 0, **kw):
+    """Segment a list of [C][H][W] float32 CUDA images (phase counts ``Ns``, one
+    per image or one for all) in one batched solve, at the unit-square scale of
+    ``segment``.  Returns a list of (u, c, labels, stats)."""
+    from .synth import random_simplex_field
+    if isinstance(Ns, int):
+        Ns = [Ns] * len(images)
+    problems, us, ims = [], [], []
+    for b, (image, N) in enumerate(zip(images, Ns)):
+        C, H, W = image.shape
+        h = 1.0 / (max(W, H) - 1)
+        problems.append(Problem(H=H, W=W, C=C, N=N, h=h, eps=2.0 * h, lam=lam, tau=(2.0 * h) ** 2,
+                                steps=steps, levels=1, tol=tol, **kw))
+        us.append(torch.from_numpy(random_simplex_field(N, H, W, seed + b)).to(image.device))
+        ims.append(image.contiguous())
+    us, cs, sts = solve_batched(problems, ims, us)
+    out = []
+    for p, u, c, st in zip(problems, us, cs, sts):
+        lab, _, _ = labels(p, u, c)
+        out.append((u, c, lab, st))
+    return out

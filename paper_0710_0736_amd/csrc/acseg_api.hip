@@ -79,7 +79,7 @@ acseg_status validate(const acseg_problem* p, bool need_steps) {
     // check) and closes with post-smoothing (residual)
     const int L = p->levels == 0 ? auto_levels(p->W, p->H) : p->levels;
     if (L >= 2 && (p->nu_pre < 1 || p->nu_post < 1)) return ACSEG_ERR_UNSUPPORTED;
-    if ((p->flags & ~(ACSEG_FLAG_STORE_CHECKPOINTS | ACSEG_FLAG_FIXED_CYCLES)) != 0u)
+    if ((p->flags & ~(ACSEG_FLAG_STORE_CHECKPOINTS | ACSEG_FLAG_FIXED_CYCLES | ACSEG_FLAG_FIXED_C)) != 0u)
         return ACSEG_ERR_INVALID_ARG;
     return ACSEG_OK;
 }
@@ -422,7 +422,8 @@ acseg_status enqueue_step(acseg_ctx* ctx, const acseg_problem* p, const Coefs& c
     st.store_rhs = sc.store_rhs ? 1 : 0;
     st.tot_sel = tot_sel;
     st.c64_sel = c64_sel;
-    st.prev_sel = prev_sel;
+    st.fixed_c = (p->flags & ACSEG_FLAG_FIXED_C) != 0u ? 1 : 0;
+    st.prev_sel = st.fixed_c ? 2 : prev_sel;  // fixed means sit in c64 set 2
     const MgPlan m = plan_of(p);
     for (int k = 0; k < p->max_cycles; ++k) {
         st.cycle = k;
@@ -699,7 +700,9 @@ acseg_status acseg_step(acseg_ctx* ctx, const acseg_problem* p, const float* ima
                         acseg_stats* stats, void* ws, size_t ws_bytes, void* stream) {
     acseg_status v = validate(p, false);
     if (v != ACSEG_OK) return v;
-    if (!ctx || !image || !u_in || !u_out || u_in == u_out) return ACSEG_ERR_INVALID_ARG;
+    const bool fixed_c = (p->flags & ACSEG_FLAG_FIXED_C) != 0u;
+    if (!ctx || !image || !u_in || !u_out || u_in == u_out || (fixed_c && !c_prev))
+        return ACSEG_ERR_INVALID_ARG;
     Layout L;
     if ((v = check_ws(p, ws, ws_bytes, &L)) != ACSEG_OK) return v;
     hipStream_t s = (hipStream_t)stream;
@@ -713,10 +716,12 @@ acseg_status acseg_step(acseg_ctx* ctx, const acseg_problem* p, const float* ima
     ACSEG_TRY(launch_ctl_init(ctl, 2, s));
     if (c_prev) ACSEG_TRY(launch_widen(c_prev, cprev, p->N * p->C, s));
     const double* cp = c_prev ? cprev : nullptr;
-    v = enqueue_means(p, image, u_in, L, ws, cp, c64, c_out, tot, s);
+    v = enqueue_means(p, image, u_in, L, ws, cp, c64, fixed_c ? nullptr : c_out, tot, s);
     if (v != ACSEG_OK) return v;
     v = enqueue_step(ctx, p, cf, image, bufs, L, ws, 0, 0, 0, c_prev ? 2 : -1, s);
     if (v != ACSEG_OK) return v;
+    if (fixed_c && c_out)
+        ACSEG_TRY(hipMemcpyAsync(c_out, c_prev, sizeof(float) * p->N * p->C, hipMemcpyDeviceToDevice, s));
     ACSEG_TRY(launch_copy_current(bufs, ctl, u_out, nu, s));
     return read_stats(ctx, L, ws, s, stats);
 }
@@ -727,7 +732,9 @@ acseg_status acseg_solve(acseg_ctx* ctx, const acseg_problem* p, const float* im
     acseg_status v = validate(p, true);
     if (v != ACSEG_OK) return v;
     const bool ckpt = (p->flags & ACSEG_FLAG_STORE_CHECKPOINTS) != 0u;
-    if (!ctx || !image || !u || (ckpt && !checkpoints)) return ACSEG_ERR_INVALID_ARG;
+    const bool fixed_c = (p->flags & ACSEG_FLAG_FIXED_C) != 0u;
+    if (!ctx || !image || !u || (ckpt && !checkpoints) || (fixed_c && !c_out))
+        return ACSEG_ERR_INVALID_ARG;
     Layout L;
     if ((v = check_ws(p, ws, ws_bytes, &L)) != ACSEG_OK) return v;
     hipStream_t s = (hipStream_t)stream;
@@ -738,8 +745,10 @@ acseg_status acseg_solve(acseg_ctx* ctx, const acseg_problem* p, const float* im
     double* tot = at<double>(ws, L.tot);  // [2][kCmeansMaxM]: sums of u^n in set n & 1
     const Bufs bufs{{u, at<float>(ws, L.ubuf), u}};
     ACSEG_TRY(launch_ctl_init(ctl, 0, s));
+    if (fixed_c) ACSEG_TRY(launch_widen(c_out, c64 + 2 * kNC, p->N * p->C, s));
     if (ckpt) ACSEG_TRY(hipMemcpyAsync(checkpoints, u, sizeof(float) * nu, hipMemcpyDeviceToDevice, s));
-    v = enqueue_means(p, image, u, L, ws, nullptr, c64 + kNC, p->steps == 0 ? c_out : nullptr, tot, s);
+    v = enqueue_means(p, image, u, L, ws, nullptr, c64 + kNC,
+                      (p->steps == 0 && !fixed_c) ? c_out : nullptr, tot, s);
     if (v != ACSEG_OK) return v;
     for (int n = 0; n < p->steps; ++n) {
         const int a = n & 1, b = a ^ 1;
@@ -748,7 +757,7 @@ acseg_status acseg_solve(acseg_ctx* ctx, const acseg_problem* p, const float* im
         if (ckpt) ACSEG_TRY(launch_copy_current(bufs, ctl, checkpoints + (n + 1) * nu, nu, s));
     }
     ACSEG_TRY(launch_copy_current(bufs, ctl, u, nu, s));
-    if (c_out && p->steps > 0) {
+    if (c_out && p->steps > 0 && !fixed_c) {
         const int a = p->steps & 1, b = a ^ 1;  // sums of u^steps; means used by the last step
         ACSEG_TRY(launch_means_from_tot(p->N, p->C, tot + a * kCmeansMaxM, c64 + b * kNC, ctl,
                                         nullptr, c_out, s));
@@ -770,9 +779,10 @@ acseg_status acseg_solve_batched(acseg_ctx* ctx, int32_t B, const acseg_problem*
                                  size_t ws_bytes, void* stream) {
     acseg_status v = validate_batch(B, ps);
     if (v != ACSEG_OK) return v;
-    if (!ctx || !images || !us) return ACSEG_ERR_INVALID_ARG;
+    const bool fixed_c = (ps[0].flags & ACSEG_FLAG_FIXED_C) != 0u;
+    if (!ctx || !images || !us || (fixed_c && !c_outs)) return ACSEG_ERR_INVALID_ARG;
     for (int b = 0; b < B; ++b)
-        if (!images[b] || !us[b]) return ACSEG_ERR_INVALID_ARG;
+        if (!images[b] || !us[b] || (fixed_c && !c_outs[b])) return ACSEG_ERR_INVALID_ARG;
     const BatchLayout bl = batch_layout_of(B, ps);
     if (!ws || ((uintptr_t)ws % kAlign) != 0 || ws_bytes < bl.total) return ACSEG_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
@@ -835,8 +845,10 @@ acseg_status acseg_solve_batched(acseg_ctx* ctx, int32_t B, const acseg_problem*
         void* wsb = base + bl.region[b];
         const Layout& L = bl.L[b];
         ACSEG_TRY(launch_ctl_init(at<Ctl>(wsb, L.ctl), 0, s));
+        if (fixed_c) ACSEG_TRY(launch_widen(c_outs[b], at<double>(wsb, L.c64) + 2 * kNC, ps[b].N * ps[b].C, s));
         v = enqueue_means(&ps[b], images[b], us[b], L, wsb, nullptr, at<double>(wsb, L.c64) + kNC,
-                          (ps[b].steps == 0 && c_outs) ? c_outs[b] : nullptr, at<double>(wsb, L.tot), s);
+                          (ps[b].steps == 0 && c_outs && !fixed_c) ? c_outs[b] : nullptr,
+                          at<double>(wsb, L.tot), s);
         if (v != ACSEG_OK) return v;
     }
 
@@ -852,7 +864,8 @@ acseg_status acseg_solve_batched(acseg_ctx* ctx, int32_t B, const acseg_problem*
         st.store_rhs = sc.store_rhs ? 1 : 0;
         st.tot_sel = a;
         st.c64_sel = a;
-        st.prev_sel = n > 0 ? bsel : -1;
+        st.fixed_c = fixed_c ? 1 : 0;
+        st.prev_sel = fixed_c ? 2 : (n > 0 ? bsel : -1);
         for (const Group& g : groups) {
             const CycleGrid grid{ddesc, dwork + g.work0, g.nwork};
             const CycleArgs& any = hdesc[himgs[g.img0]];
@@ -879,7 +892,7 @@ acseg_status acseg_solve_batched(acseg_ctx* ctx, int32_t B, const acseg_problem*
         Ctl* ctl = at<Ctl>(wsb, L.ctl);
         const int64_t nu = (int64_t)ps[b].N * ps[b].W * ps[b].H;
         ACSEG_TRY(launch_copy_current(bufs[b], ctl, us[b], nu, s));
-        if (c_outs && c_outs[b] && p0.steps > 0) {
+        if (c_outs && c_outs[b] && p0.steps > 0 && !fixed_c) {
             const int a = p0.steps & 1, bsel = a ^ 1;
             ACSEG_TRY(launch_means_from_tot(ps[b].N, ps[b].C, at<double>(wsb, L.tot) + a * kCmeansMaxM,
                                             at<double>(wsb, L.c64) + bsel * kNC, ctl, nullptr,
@@ -912,12 +925,14 @@ acseg_status acseg_backward_workspace_size(const acseg_problem* p, size_t* bytes
 }
 
 acseg_status acseg_backward(acseg_ctx* ctx, const acseg_problem* p, const float* image,
-                            const float* checkpoints, const float* grad_uT, float* grad_image,
-                            float* grad_u0, double* grad_params, float* grad_c,
-                            acseg_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+                            const float* checkpoints, const float* c_fixed,
+                            const float* grad_uT, float* grad_image, float* grad_u0,
+                            double* grad_params, float* grad_c, acseg_stats* stats, void* ws,
+                            size_t ws_bytes, void* stream) {
     acseg_status v = validate(p, true);
     if (v != ACSEG_OK) return v;
-    if (!ctx || !image || !checkpoints || !grad_uT || !grad_image || !grad_params)
+    const bool fixed_c = (p->flags & ACSEG_FLAG_FIXED_C) != 0u;
+    if (!ctx || !image || !checkpoints || !grad_uT || !grad_image || !grad_params || (fixed_c && !c_fixed))
         return ACSEG_ERR_INVALID_ARG;
     const BackLayout L = back_layout_of(p);
     if (!ws || ((uintptr_t)ws % kAlign) != 0 || ws_bytes < L.total) return ACSEG_ERR_WORKSPACE;
@@ -931,8 +946,12 @@ acseg_status acseg_backward(acseg_ctx* ctx, const acseg_problem* p, const float*
     ACSEG_TRY(launch_ctl_init(ctl, 0, s));
     ACSEG_TRY(launch_adj_init(actl, grad_params, s));
     ACSEG_TRY(launch_fill(grad_image, (int64_t)C * n, 0.f, s));
+    if (fixed_c) {
+        ACSEG_TRY(launch_widen(c_fixed, c64, N * C, s));
+        if (grad_c) ACSEG_TRY(launch_fill(grad_c, (int64_t)N * C, 0.f, s));
+    }
     // the means of every step, recomputed from the checkpoints
-    for (int st = 0; st < p->steps; ++st) {
+    for (int st = 0; st < (fixed_c ? 0 : p->steps); ++st) {
         const float* u = checkpoints + st * nu;
         const Bufs bufs{{u, u, u}};
         double* part = at<double>(ws, L.part_cm);
@@ -971,9 +990,10 @@ acseg_status acseg_backward(acseg_ctx* ctx, const acseg_problem* p, const float*
         a.u1 = checkpoints + (st + 1) * nu;
         a.ub = ub;
         a.ub_out = ubuf[st & 1];
-        a.c64 = c64 + st * kNC;
+        a.c64 = fixed_c ? c64 : c64 + st * kNC;
         a.tot = tot + st * kCmeansMaxM;
-        a.cbar_out = grad_c ? grad_c + (int64_t)st * N * C : nullptr;
+        a.cbar_out = grad_c ? (fixed_c ? grad_c : grad_c + (int64_t)st * N * C) : nullptr;
+        a.cbar_accumulate = fixed_c ? 1 : 0;
         // sweeps in chunks of growing length; between chunks the host reads the
         // convergence flag (one small copy and wait per chunk) instead of
         // enqueueing the whole budget of mostly no-op launches
@@ -997,7 +1017,8 @@ acseg_status acseg_backward(acseg_ctx* ctx, const acseg_problem* p, const float*
         }
         ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjAccum, a, 0, 0, s); }));
         ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjReduce, a, 0, 0, s); }));
-        ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjMeans, a, 0, 0, s); }));
+        if (!fixed_c)  // fixed means depend on neither u^n nor the image
+            ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjMeans, a, 0, 0, s); }));
         ub = a.ub_out;
     }
     if (grad_u0) ACSEG_TRY(hipMemcpyAsync(grad_u0, ub, sizeof(float) * nu, hipMemcpyDeviceToDevice, s));

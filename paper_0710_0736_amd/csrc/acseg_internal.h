@@ -124,6 +124,7 @@ struct CycleStep {
     int tot_sel;    // sums of u^n in tot set tot_sel; the step's end writes set tot_sel ^ 1
     int c64_sel;    // the step's first launch writes the means of u^n to c64 set c64_sel
     int prev_sel;   // previous means (empty phases) in c64 set prev_sel, or -1
+    int fixed_c;    // the means of every step are c64 set prev_sel (not recomputed)
 };
 
 // What a run of smoothing launches is within its step and cycle.
@@ -276,6 +277,7 @@ struct AdjArgs {
     const double* tot;    // colour-mean sums of u^s (mass-weight units)
     double* cbar64;       // [N][C]
     float* cbar_out;      // [N][C] or NULL
+    int cbar_accumulate;  // add cbar to cbar_out (fixed means) instead of storing it
     float* part_f;        // [2][kMgBlocks]
     double* part_d;       // [kMgBlocks][3 + N C]
     LevelCoef coef;       // finest level

@@ -231,8 +231,9 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
             if (i < N) {
                 const double area = tsh[N * C + N + C];
                 const double S = tsh[N * C + i];
-                const bool has_mass = S > 1e-12 * area;
-                empty = !has_mass;
+                // fixed means: the caller's, in the previous-means slot
+                const bool has_mass = !st.fixed_c && S > 1e-12 * area;
+                empty = !st.fixed_c && !has_mass;
                 double q2 = 0.0;
 #pragma unroll
                 for (int k = 0; k < C; ++k) {

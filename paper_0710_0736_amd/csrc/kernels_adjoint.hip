@@ -194,7 +194,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_reduce(AdjArgs a) {
     if (threadIdx.x < 3) a.grads[threadIdx.x] += tot[threadIdx.x];
     if (threadIdx.x < N * C) {
         a.cbar64[threadIdx.x] = tot[3 + threadIdx.x];
-        if (a.cbar_out) a.cbar_out[threadIdx.x] = (float)tot[3 + threadIdx.x];
+        if (a.cbar_out) {
+            if (a.cbar_accumulate)
+                a.cbar_out[threadIdx.x] += (float)tot[3 + threadIdx.x];
+            else
+                a.cbar_out[threadIdx.x] = (float)tot[3 + threadIdx.x];
+        }
     }
     if (threadIdx.x == 0) {
         AdjCtl* ac = a.actl;

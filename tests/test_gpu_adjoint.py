@@ -11,7 +11,7 @@ import torch
 
 import oracle as orc
 from paper_0710_0736_amd import acseg, synth
-from test_gpu_parity import cuda, host
+from test_gpu_parity import GATE_U, cuda, host
 
 pytestmark = pytest.mark.gpu
 
@@ -70,3 +70,42 @@ def test_segment_function_autograd():
     assert torch.equal(uT.detach(), u)
     assert torch.allclose(I.grad, gI) and torch.allclose(U0.grad, gu0)
     assert torch.allclose(torch.stack([lam.grad, eps.grad, tau.grad]), gp.cpu())
+
+
+@pytest.mark.parametrize("pixel", [False, True])
+def test_fixed_means_forward_and_backward(pixel):
+    w, p, img, u0, y = setup(pixel, 48, 40, 3, 3, 5, 1500 if pixel else 50)
+    P = orc.Params.from_workload(w, C=3, tol=1e-12, levels=1)
+    c0, _ = orc.colour_means(P, img, u0)
+    cf = (c0 + 0.05).astype(np.float32)
+    I = cuda(img)
+    u, c, st, ck = acseg.solve(p, I, cuda(u0), checkpoints=True, c_fixed=cuda(cf))
+    torch.cuda.synchronize()
+    assert st["status"] == acseg.OK, st
+    assert np.array_equal(host(c), cf.astype(np.float64))  # an input, untouched
+    ckh = host(ck)
+    for n in range(p.steps):  # every step with the fixed means, from the GPU's own state
+        u_ref, _, _ = orc.solve_fixed_c(P, 1, img, ckh[n], cf, keep_trajectory=False)
+        assert np.abs(ckh[n + 1] - u_ref).max() <= GATE_U, n
+    gT = 2 * (u - cuda(y))
+    gI, gu0, gp, gc, bst = acseg.backward(p, I, ck, gT, c_fixed=cuda(cf))
+    torch.cuda.synchronize()
+    assert gc.shape == (3, 3) and bst["status"] == acseg.OK
+    Ibar, grads, cbar, ubar0 = orc.backward_fixed_c(P, p.steps, img, ckh, cf, host(gT))
+    assert rel_err(host(gI), Ibar) <= 2e-3
+    assert rel_err(host(gu0), ubar0) <= 2e-3
+    assert rel_err(host(gc), cbar) <= 2e-3
+    g = gp.cpu().numpy()
+    for k in range(3):
+        assert abs(g[k] - grads[k]) <= 2e-3 * abs(grads[k]) + 1e-9, (k, g[k], grads[k])
+
+
+def test_fixed_means_batched_equals_single():
+    w, p, img, u0, y = setup(False, 64, 48, 3, 4, 6, 50)
+    P = orc.Params.from_workload(w, C=3, tol=1e-12, levels=1)
+    cf = cuda(orc.colour_means(P, img, u0)[0] + 0.03)
+    u_s, _, st_s, _ = acseg.solve(p, cuda(img), cuda(u0), c_fixed=cf)
+    us, cs, sts = acseg.solve_batched([p, p], [cuda(img)] * 2, [cuda(u0), cuda(u0)], c_fixed=[cf, cf])
+    torch.cuda.synchronize()
+    assert torch.equal(us[0], u_s) and torch.equal(us[1], u_s)
+    assert sts[0] == st_s

@@ -67,3 +67,17 @@ def test_batch_of_one_full_size_image_and_repeat_calls():
         for b in range(2):
             assert torch.equal(us[b], u_s) and torch.equal(cs[b], c_s)
             assert sts[b]["final_residual"] == st_s["final_residual"]
+
+
+def test_segment_and_segment_batch_agree():
+    ims = []
+    for (W, H, N, seed) in [(80, 64, 3, 11), (50, 70, 4, 12)]:
+        w = synth.VORONOI1024.scaled(W, H, N=N)
+        img, _, _ = w.make(seed)
+        ims.append((cuda(img), N))
+    res = acseg.segment_batch([im for im, _ in ims], [N for _, N in ims], lam=100.0, steps=5, seed=3)
+    for b, (im, N) in enumerate(ims):
+        u, c, lab, st = acseg.segment(im, N, lam=100.0, steps=5, seed=3 + b, levels=1)
+        torch.cuda.synchronize()
+        assert st["status"] == acseg.OK and res[b][3]["status"] == acseg.OK
+        assert torch.equal(res[b][0], u) and torch.equal(res[b][2], lab)
