@@ -62,7 +62,9 @@ __device__ __forceinline__ float block_max_t(float v, float* sh /* >= T/kWave */
 // One cycle launch on one tile.  The convergence check (a cycle's first
 // launch, adaptive schedules) is done by every workgroup of the image; the
 // one owning tile 0 records it.
-template <int N, int C, int K, bool FIRST, bool RESID>
+// INT: the staged region lies strictly inside the image, so every staged node
+// is an interior node (class 0, unit edge weights) and no bounds test is needed.
+template <int N, int C, int K, bool FIRST, bool RESID, bool INT>
 __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& st, int tile) {
     constexpr int T = kCycT;
     constexpr int TX = kTX, TY = cycle_ty(N);
@@ -139,7 +141,7 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
         const int idx = threadIdx.x + q * T;
         const int ly = idx / LX, lx = idx - ly * LX;
         const int gx = x0 + lx, gy = y0 + ly;
-        const bool in = idx < LX * LY && gx >= 0 && gx < W && gy >= 0 && gy < H;
+        const bool in = idx < LX * LY && (INT || (gx >= 0 && gx < W && gy >= 0 && gy < H));
         const int g = in ? gy * W + gx : 0;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
@@ -163,7 +165,7 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
         for (int e = 0; e < 2; ++e) {
             const int lx = 2 * j + odd + e;
             const int gx = x0 + lx, gy = y0 + ly;
-            const bool in = pi < NP && gx >= 0 && gx < W && gy >= 0 && gy < H && lx < LX;
+            const bool in = pi < NP && lx < LX && (INT || (gx >= 0 && gx < W && gy >= 0 && gy < H));
             const int dx = max(max(R - lx, lx - (R + TX - 1)), 0);
             const int dy = max(max(R - ly, ly - (R + TY - 1)), 0);
             const int rad = in ? max(dx, dy) : kOut;
@@ -178,7 +180,9 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
                 v[q] = need ? t : 0.f;
             }
             float kh = 0.f, kv = 0.f;
-            if (in) {
+            if (INT) {
+                kh = kv = in ? uniform_f(a.coef.kappa[0]) : 0.f;
+            } else if (in) {
                 const float kap = sel4(a.coef.kappa, node_class(gx, gy, W, H));
                 kh = kap * edge_w_h(gy, H);
                 kv = kap * edge_w_v(gx, W);
@@ -274,7 +278,7 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
                     const int pi = threadIdx.x + m * T;
                     const int ly = pi / LXH, j = pi - ly * LXH;
                     const int gx = x0 + 2 * j + (ly & 1) + e, gy = y0 + ly;
-                    const double wd = sel4d(a.rc.wd, node_class(gx, gy, W, H));
+                    const double wd = INT ? uniform_d(a.rc.wd[0]) : sel4d(a.rc.wd, node_class(gx, gy, W, H));
                     double r[N];
                     double rmax = -1e300;
 #pragma unroll
@@ -323,7 +327,7 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
                 const int idx = threadIdx.x + q * T;
                 const int oy = idx / TX, ox = idx - oy * TX;
                 const int gx = x0 + R + ox, gy = y0 + R + oy;
-                on[q] = st.cm && gx < W && gy < H;
+                on[q] = st.cm && (INT || (gx < W && gy < H));
                 const int g = on[q] ? gy * W + gx : 0;
 #pragma unroll
                 for (int k = 0; k < C; ++k) {
@@ -383,7 +387,7 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
         const int gx = x0 + R + ox, gy = y0 + R + oy;
         const int lx = R + ox, ly = R + oy;
         const int li = ly * RW + (lx & 1) * HL + (lx >> 1);
-        const bool o = gx < W && gy < H;
+        const bool o = INT || (gx < W && gy < H);
         const int g = o ? gy * W + gx : 0;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
@@ -405,7 +409,7 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
     for (int q = 0; q < NO; ++q) {
         const int idx = threadIdx.x + q * T;
         const int oy = idx / TX, ox = idx - oy * TX;
-        const float w = on[q] ? (float)mass_w(node_class(x0 + R + ox, y0 + R + oy, W, H)) : 0.f;
+        const float w = on[q] ? (INT ? 1.f : (float)mass_w(node_class(x0 + R + ox, y0 + R + oy, W, H))) : 0.f;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const float wu = w * uo[q][i];
@@ -435,11 +439,28 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
 
 // One image: tiles in XCD-aware order (the workgroups of one XCD, id mod 8,
 // own a contiguous band of tiles).
+// Whether the staged region of a tile lies strictly inside the image.
+template <int N, int K, bool RESID>
+__device__ __forceinline__ bool tile_interior(const CycleArgs& a, int tile) {
+    constexpr int R = 2 * K + (RESID ? 1 : 0);
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int x0 = tx * kTX - R, y0 = ty * cycle_ty(N) - R;
+    return x0 >= 1 && y0 >= 1 && x0 + kTX + 2 * R <= a.W - 1 && y0 + cycle_ty(N) + 2 * R <= a.H - 1;
+}
+
+template <int N, int C, int K, bool FIRST, bool RESID>
+__device__ __forceinline__ void cycle_tile_any(const CycleArgs& a, const CycleStep& st, int tile) {
+    if (tile_interior<N, K, RESID>(a, tile))
+        cycle_tile<N, C, K, FIRST, RESID, true>(a, st, tile);
+    else
+        cycle_tile<N, C, K, FIRST, RESID, false>(a, st, tile);
+}
+
 template <int N, int C, int K, bool FIRST, bool RESID>
 __global__ __launch_bounds__(kCycT) void k_cycle(CycleArgs a, CycleStep st) {
     const int tile = (blockIdx.x % kXcd) * a.tiles_per_xcd + blockIdx.x / kXcd;
     if (tile >= a.ntiles) return;
-    cycle_tile<N, C, K, FIRST, RESID>(a, st, tile);
+    cycle_tile_any<N, C, K, FIRST, RESID>(a, st, tile);
 }
 
 // A batch of images with the same N and C: work[] lists (image, tile) of
@@ -452,7 +473,7 @@ __global__ __launch_bounds__(kCycT) void k_cycle_batch(const CycleArgs* __restri
     if ((int)blockIdx.x >= nwork) return;
     const int2 wv = work[blockIdx.x];
     if (wv.x < 0) return;
-    cycle_tile<N, C, K, FIRST, RESID>(descs[wv.x], st, wv.y);
+    cycle_tile_any<N, C, K, FIRST, RESID>(descs[wv.x], st, wv.y);
 }
 
 // ---------------------------------------------------------------------------
