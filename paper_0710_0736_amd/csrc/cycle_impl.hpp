@@ -85,9 +85,10 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
     constexpr int PARTS = T / kWave;  // partial sums per row
     extern __shared__ float lds[];
     __shared__ float red[T / kWave];
-    __shared__ double cs[N * C];
-    __shared__ double cs2[N];
-    __shared__ float wsum[PARTS][M];
+    __shared__ double cs[N * C];  // 2 lambda c_ik (first launch of a step)
+    __shared__ double cs2[N];     // -lambda |c_i|^2
+    constexpr int MD = N * C + N;  // colour-mean sums that change with u
+    __shared__ float wsum[PARTS][MD];
     __shared__ double tsh[M + N * C];
     __shared__ int flag;
 
@@ -244,14 +245,14 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
                     const double c = has_mass ? tsh[i * C + k] / S
                                               : (c_prev64 ? tsh[M + i * C + k]
                                                           : tsh[N * C + N + k] / area);
-                    cs[i * C + k] = c;
+                    cs[i * C + k] = 2.0 * a.rc.lambda * c;  // 2 lambda c_ik
                     q2 += c * c;
                     if (tile == 0) {
                         a.c64[st.c64_sel * kNC + i * C + k] = c;
                         if (a.c_out) a.c_out[i * C + k] = (float)c;
                     }
                 }
-                cs2[i] = q2;
+                cs2[i] = -a.rc.lambda * q2;  // -lambda |c_i|^2
             }
             const bool any_empty = __any(empty);
             if (tile == 0 && i == 0) {
@@ -279,21 +280,25 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
                     const int ly = pi / LXH, j = pi - ly * LXH;
                     const int gx = x0 + 2 * j + (ly & 1) + e, gy = y0 + ly;
                     const double wd = INT ? uniform_d(a.rc.wd[0]) : sel4d(a.rc.wd, node_class(gx, gy, W, H));
+                    const double ra = uniform_d(a.rc.a);
+                    double Ik[C];
+#pragma unroll
+                    for (int k = 0; k < C; ++k) Ik[k] = (double)(e == 0 ? pv0[m][k] : pv1[m][k]);
+                    // t_i = (1/tau + 2/eps) u_i + lambda (2 c_i.I - |c_i|^2); rhs'_i = (w/D)(t_i - max_j t_j)
                     double r[N];
                     double rmax = -1e300;
 #pragma unroll
                     for (int i = 0; i < N; ++i) {
-                        double ci = 0.0;
-#pragma unroll
-                        for (int k = 0; k < C; ++k)
-                            ci += cs[i * C + k] * (double)(e == 0 ? pv0[m][k] : pv1[m][k]);
                         const double ui = (double)lds[i * PL + (e == 0 ? c0[m] : c0[m] + (((pk[m] >> 16) & 1) ? 1 - HL : HL))];
-                        r[i] = wd * (a.rc.a * ui + a.rc.lambda * (2.0 * ci - cs2[i]));
-                        rmax = fmax(rmax, r[i]);
+                        double t = fma(ra, ui, cs2[i]);
+#pragma unroll
+                        for (int k = 0; k < C; ++k) t = fma(cs[i * C + k], Ik[k], t);
+                        r[i] = t;
+                        rmax = fmax(rmax, t);
                     }
 #pragma unroll
                     for (int i = 0; i < N; ++i) {
-                        rv[i] = (float)(r[i] - rmax);
+                        rv[i] = (float)(wd * (r[i] - rmax));
                         if (st.store_rhs && rad == 0) const_cast<float*>(rhsp[i])[gy * W + gx] = rv[i];
                     }
                 } else {
@@ -402,9 +407,11 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
     const float bm = block_max_t<T>(res, red);
     if (threadIdx.x == 0) a.res_part[row * a.part_stride + tile] = bm;
     if (!st.cm) return;
-    float acc[M];
+    // the sums that depend on u: S_ik = sum w u_i I_k and S_i = sum w u_i (the
+    // image-only ones do not change from step to step)
+    float acc[MD];
 #pragma unroll
-    for (int q = 0; q < M; ++q) acc[q] = 0.f;
+    for (int q = 0; q < MD; ++q) acc[q] = 0.f;
 #pragma unroll
     for (int q = 0; q < NO; ++q) {
         const int idx = threadIdx.x + q * T;
@@ -417,23 +424,20 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
 #pragma unroll
             for (int k = 0; k < C; ++k) acc[i * C + k] += wu * Io[q][k];
         }
-#pragma unroll
-        for (int k = 0; k < C; ++k) acc[N * C + N + k] += w * Io[q][k];
-        acc[N * C + N + C] += w;
     }
     // block sum in a fixed order: each wave sums its lanes in FP32 (128 nodes),
-    // then M threads add the T / 64 wave sums in FP64
+    // then MD threads add the T / 64 wave sums in FP64
 #pragma unroll
-    for (int q = 0; q < M; ++q) {
+    for (int q = 0; q < MD; ++q) {
         const float t = wave_sum_last(acc[q]);
         if (threadIdx.x % kWave == kWave - 1) wsum[threadIdx.x / kWave][q] = t;
     }
     __syncthreads();
-    if (threadIdx.x < M) {
+    if (threadIdx.x < MD) {
         double t = 0.0;
 #pragma unroll
         for (int h = 0; h < PARTS; ++h) t += (double)wsum[h][threadIdx.x];
-        a.cm_part[((int64_t)row * M + threadIdx.x) * a.part_stride + tile] = t;
+        a.cm_part[((int64_t)row * MD + threadIdx.x) * a.part_stride + tile] = t;
     }
 }
 
@@ -477,27 +481,28 @@ __global__ __launch_bounds__(kCycT) void k_cycle_batch(const CycleArgs* __restri
 }
 
 // ---------------------------------------------------------------------------
-// End of a time step, M + 1 workgroups.  Workgroup q < M sums row q of the
-// last cycle's colour-mean partials over the tiles (fixed order, so the
-// result is deterministic) into tot_next[q]: the sums of the new iterate.
-// Workgroup M takes the step's residual (the last cycle's, unless a cycle
-// kernel found convergence earlier), moves `cur` to the buffer holding the
-// iterate, folds the statistics and re-arms the other control slot for the
-// step after next.
+// End of a time step, MD + 1 workgroups (MD = N C + N).  Workgroup q < MD
+// sums row q of the last cycle's colour-mean partials over the tiles (fixed
+// order, so the result is deterministic) into the next set of sums: those of
+// the new iterate.  Workgroup MD carries the image-only sums over, takes the
+// step's residual (the last cycle's, unless a cycle kernel found convergence
+// earlier), moves `cur` to the buffer holding the iterate, folds the
+// statistics and re-arms the other control slot for the step after next.
 // ---------------------------------------------------------------------------
 
 template <int N, int C>
 __device__ __forceinline__ void step_end(const CycleArgs& a, const CycleStep& st, const StepEndArgs& e) {
     constexpr int M = N * C + N + C + 2;
+    constexpr int MD = N * C + N;  // rows reduced; the image-only sums are carried over
     __shared__ float red[kBlock / kWave];
     __shared__ double shd[kBlock / kWave];
     Ctl* ctl = a.ctl;
     StepSlot* slot = &ctl->step[st.slot];
     const int done = slot->done;
     const int cycles = done ? slot->cycles : e.max_cycles;
-    if ((int)blockIdx.x < M) {
+    if ((int)blockIdx.x < MD) {
         const int q = blockIdx.x;
-        const double* row = a.cm_part + ((int64_t)((cycles - 1) & 1) * M + q) * a.part_stride;
+        const double* row = a.cm_part + ((int64_t)((cycles - 1) & 1) * MD + q) * a.part_stride;
         double t = 0.0;
         for (int b = threadIdx.x; b < a.ntiles; b += kBlock) t += row[b];
         t = wave_sum(t);
@@ -510,6 +515,8 @@ __device__ __forceinline__ void step_end(const CycleArgs& a, const CycleStep& st
         }
         return;
     }
+    if (threadIdx.x < M - MD)  // sum w I_k, sum w and the image flag: constants of the solve
+        a.tot[(st.tot_sel ^ 1) * kCmeansMaxM + MD + threadIdx.x] = a.tot[st.tot_sel * kCmeansMaxM + MD + threadIdx.x];
     float resid;
     if (done) {
         resid = slot->resid;
@@ -592,11 +599,11 @@ hipError_t run_cycle_nc(int sweeps, const CycleArgs& a, CycleStep st, const Cycl
 template <int N, int C>
 hipError_t run_step_end_nc(const CycleArgs& a, const CycleStep& st, const StepEndArgs& e,
                            const CycleArgs* descs, const int* imgs, int nimg, hipStream_t s) {
-    constexpr int M = N * C + N + C + 2;
+    constexpr int MD = N * C + N;
     if (descs)
-        hipLaunchKernelGGL((k_step_end_batch<N, C>), dim3(M + 1, nimg), dim3(kBlock), 0, s, descs, imgs, st, e);
+        hipLaunchKernelGGL((k_step_end_batch<N, C>), dim3(MD + 1, nimg), dim3(kBlock), 0, s, descs, imgs, st, e);
     else
-        hipLaunchKernelGGL((k_step_end<N, C>), dim3(M + 1), dim3(kBlock), 0, s, a, st, e);
+        hipLaunchKernelGGL((k_step_end<N, C>), dim3(MD + 1), dim3(kBlock), 0, s, a, st, e);
     return hipGetLastError();
 }
 
