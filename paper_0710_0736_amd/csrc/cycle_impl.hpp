@@ -37,11 +37,64 @@ constexpr int kTX = 64;
 
 constexpr int kCycT = 512;  // threads of a cycle workgroup (8 wave64)
 
-// Dynamic LDS of one cycle launch: the staged planes.
+// LDS holds the staged field node-major: the N components of a node are
+// contiguous, padded to NP(N) floats so that a node is read or written with
+// one to three vector accesses (float4 for N = 4 and 8).
+__host__ __device__ constexpr int node_pad(int N) { return N <= 2 ? 2 : (N <= 4 ? 4 : (N <= 6 ? 6 : 8)); }
+
+template <int N>
+__device__ __forceinline__ void lds_get(const float* __restrict__ L, int slot, float (&v)[N]) {
+    constexpr int P = node_pad(N);
+    const float* p = L + slot * P;
+    if constexpr (P % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < P / 4; ++k) {
+            const float4 t = reinterpret_cast<const float4*>(p)[k];
+            if (4 * k + 0 < N) v[4 * k + 0] = t.x;
+            if (4 * k + 1 < N) v[4 * k + 1] = t.y;
+            if (4 * k + 2 < N) v[4 * k + 2] = t.z;
+            if (4 * k + 3 < N) v[4 * k + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < P / 2; ++k) {
+            const float2 t = reinterpret_cast<const float2*>(p)[k];
+            if (2 * k + 0 < N) v[2 * k + 0] = t.x;
+            if (2 * k + 1 < N) v[2 * k + 1] = t.y;
+        }
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void lds_put(float* __restrict__ L, int slot, const float (&v)[N]) {
+    constexpr int P = node_pad(N);
+    float* p = L + slot * P;
+    if constexpr (P % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < P / 4; ++k) {
+            float4 t;
+            t.x = 4 * k + 0 < N ? v[4 * k + 0] : 0.f;
+            t.y = 4 * k + 1 < N ? v[4 * k + 1] : 0.f;
+            t.z = 4 * k + 2 < N ? v[4 * k + 2] : 0.f;
+            t.w = 4 * k + 3 < N ? v[4 * k + 3] : 0.f;
+            reinterpret_cast<float4*>(p)[k] = t;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < P / 2; ++k) {
+            float2 t;
+            t.x = 2 * k + 0 < N ? v[2 * k + 0] : 0.f;
+            t.y = 2 * k + 1 < N ? v[2 * k + 1] : 0.f;
+            reinterpret_cast<float2*>(p)[k] = t;
+        }
+    }
+}
+
+// Dynamic LDS of one cycle launch: the staged field.
 template <int N, int K, bool RESID>
 __host__ __device__ constexpr int cycle_lds_bytes() {
     constexpr int R = 2 * K + (RESID ? 1 : 0);
-    return N * (cycle_ty(N) + 2 * R) * ((kTX + 2 * R) / 2 + 1) * 2 * 4;
+    return node_pad(N) * (cycle_ty(N) + 2 * R) * ((kTX + 2 * R) / 2 + 1) * 2 * 4;
 }
 
 template <int T>
@@ -73,7 +126,6 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
     constexpr int LXH = LX / 2;    // pairs per row
     constexpr int HL = LXH + 1;    // half-row length in LDS (one spare slot)
     constexpr int RW = 2 * HL;     // LDS row stride
-    constexpr int PL = LY * RW;    // LDS plane stride
     constexpr int NP = LXH * LY;   // pairs in the staged region
     constexpr int MP = (NP + T - 1) / T;
     constexpr int NO = TX * TY / T;  // output nodes per thread
@@ -223,8 +275,7 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
         if (idx >= LX * LY) continue;
         const int ly = idx / LX, lx = idx - ly * LX;
         const int li = ly * RW + (lx & 1) * HL + (lx >> 1);
-#pragma unroll
-        for (int i = 0; i < N; ++i) lds[i * PL + li] = ust[q][i];
+        lds_put<N>(lds, li, ust[q]);
     }
     __syncthreads();  // u and the sums staged
     if (FIRST) {
@@ -287,9 +338,11 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
                     // t_i = (1/tau + 2/eps) u_i + lambda (2 c_i.I - |c_i|^2); rhs'_i = (w/D)(t_i - max_j t_j)
                     double r[N];
                     double rmax = -1e300;
+                    float un[N];
+                    lds_get<N>(lds, e == 0 ? c0[m] : c0[m] + (((pk[m] >> 16) & 1) ? 1 - HL : HL), un);
 #pragma unroll
                     for (int i = 0; i < N; ++i) {
-                        const double ui = (double)lds[i * PL + (e == 0 ? c0[m] : c0[m] + (((pk[m] >> 16) & 1) ? 1 - HL : HL))];
+                        const double ui = (double)un[i];
                         double t = fma(ra, ui, cs2[i]);
 #pragma unroll
                         for (int k = 0; k < C; ++k) t = fma(cs[i * C + k], Ik[k], t);
@@ -347,20 +400,21 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
             for (int m = 0; m < MP; ++m) {
                 if ((pk[m] & 255) > r) continue;
                 const int cb = c0[m] + (((pk[m] >> 16) & 1) ? 1 - HL : HL);
-                float v[N];
+                float v[N], a0[N], a1[N], a2[N], a3[N];
+                lds_get<N>(lds, cb - 1, a0);
+                lds_get<N>(lds, cb, a1);
+                lds_get<N>(lds, c0[m] - RW, a2);
+                lds_get<N>(lds, c0[m] + RW, a3);
 #pragma unroll
-                for (int i = 0; i < N; ++i) {
-                    const float* L = lds + i * PL;
-                    v[i] = rr0[m][i] + kh0[m] * (L[cb - 1] + L[cb]) +
-                           kv0[m] * (L[c0[m] - RW] + L[c0[m] + RW]);
-                }
+                for (int i = 0; i < N; ++i) v[i] = rr0[m][i] + kh0[m] * (a0[i] + a1[i]) + kv0[m] * (a2[i] + a3[i]);
                 project_simplex<N>(v);
                 if (RESID && s == NHALF - 1) {
+                    float o[N];
+                    lds_get<N>(lds, c0[m], o);
 #pragma unroll
-                    for (int i = 0; i < N; ++i) res = fmaxf(res, fabsf(v[i] - lds[i * PL + c0[m]]));
+                    for (int i = 0; i < N; ++i) res = fmaxf(res, fabsf(v[i] - o[i]));
                 } else {
-#pragma unroll
-                    for (int i = 0; i < N; ++i) lds[i * PL + c0[m]] = v[i];
+                    lds_put<N>(lds, c0[m], v);
                 }
             }
         } else {  // black: the second node of every pair
@@ -368,16 +422,15 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
             for (int m = 0; m < MP; ++m) {
                 if (((pk[m] >> 8) & 255) > r) continue;
                 const int cb = c0[m] + (((pk[m] >> 16) & 1) ? 1 - HL : HL);
-                float v[N];
+                float v[N], a0[N], a1[N], a2[N], a3[N];
+                lds_get<N>(lds, c0[m], a0);
+                lds_get<N>(lds, c0[m] + 1, a1);
+                lds_get<N>(lds, cb - RW, a2);
+                lds_get<N>(lds, cb + RW, a3);
 #pragma unroll
-                for (int i = 0; i < N; ++i) {
-                    const float* L = lds + i * PL;
-                    v[i] = rr1[m][i] + kh1[m] * (L[c0[m]] + L[c0[m] + 1]) +
-                           kv1[m] * (L[cb - RW] + L[cb + RW]);
-                }
+                for (int i = 0; i < N; ++i) v[i] = rr1[m][i] + kh1[m] * (a0[i] + a1[i]) + kv1[m] * (a2[i] + a3[i]);
                 project_simplex<N>(v);
-#pragma unroll
-                for (int i = 0; i < N; ++i) lds[i * PL + cb] = v[i];
+                lds_put<N>(lds, cb, v);
             }
         }
     }
@@ -394,11 +447,10 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
         const int li = ly * RW + (lx & 1) * HL + (lx >> 1);
         const bool o = INT || (gx < W && gy < H);
         const int g = o ? gy * W + gx : 0;
+        lds_get<N>(lds, li, uo[q]);
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            uo[q][i] = lds[i * PL + li];
+        for (int i = 0; i < N; ++i)
             if (o) dstp[i][g] = uo[q][i];
-        }
     }
     if (!RESID) return;
 
