@@ -132,10 +132,11 @@ __device__ __forceinline__ void project_simplex(float (&v)[N]) {
 #pragma unroll
     for (int k = 2; k <= N; ++k) {
         S += s[k - 1] - vmax;
-        theta = fmaxf(theta, (S - 1.0f) * (1.0f / (float)k));
+        theta = fmaxf(theta, fmaf(S, 1.0f / (float)k, -1.0f / (float)k));
     }
+    const float thr = vmax + theta;  // the shift in the original values
 #pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = fmaxf((v[i] - vmax) - theta, 0.f);
+    for (int i = 0; i < N; ++i) v[i] = fmaxf(v[i] - thr, 0.f);
 }
 
 // ---------------------------------------------------------------------------
@@ -162,6 +163,23 @@ __device__ __forceinline__ float wave_sum_last(float v) {
     v += dpp_f<0x128, 0xF>(v);  // row_ror:8: every lane holds its row's sum
     v += dpp_f<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
     v += dpp_f<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+// Sum over the 4 lanes of each quad (every lane of the quad holds it).
+__device__ __forceinline__ float quad_sum(float v) {
+    v += dpp_f<0xB1, 0xF>(v);
+    v += dpp_f<0x4E, 0xF>(v);
+    return v;
+}
+
+// Sum over each half-wave (32 lanes) in a fixed order; exact in lanes 31 and 63.
+__device__ __forceinline__ float half_wave_sum_last(float v) {
+    v += dpp_f<0xB1, 0xF>(v);
+    v += dpp_f<0x4E, 0xF>(v);
+    v += dpp_f<0x124, 0xF>(v);
+    v += dpp_f<0x128, 0xF>(v);
+    v += dpp_f<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
     return v;
 }
 

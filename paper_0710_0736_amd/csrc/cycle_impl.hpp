@@ -134,13 +134,11 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
     constexpr int M = N * C + N + C + 2;
     constexpr int NHALF = 2 * K + (RESID ? 1 : 0);
     constexpr int kOut = 255;      // "radius" of a node outside the image: never updated
-    constexpr int PARTS = T / kWave;  // partial sums per row
     extern __shared__ float lds[];
     __shared__ float red[T / kWave];
     __shared__ double cs[N * C];  // 2 lambda c_ik (first launch of a step)
     __shared__ double cs2[N];     // -lambda |c_i|^2
     constexpr int MD = N * C + N;  // colour-mean sums that change with u
-    __shared__ float wsum[PARTS][MD];
     __shared__ double tsh[M + N * C];
     __shared__ int flag;
 
@@ -477,19 +475,31 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
             for (int k = 0; k < C; ++k) acc[i * C + k] += wu * Io[q][k];
         }
     }
-    // block sum in a fixed order: each wave sums its lanes in FP32 (128 nodes),
-    // then MD threads add the T / 64 wave sums in FP64
+    // block sum in a fixed order, in FP32: quads first (data-parallel moves),
+    // one lane per quad into LDS (the staging area is free: the residual's
+    // block reduction has synchronised the reads of the field), then 32 lanes
+    // per sum add four quad sums each and reduce across their half-wave
+    constexpr int NQ = T / 4;  // quads per workgroup
+    static_assert(MD * NQ * 4 <= cycle_lds_bytes<N, K, RESID>(), "quad sums must fit in the staging area");
+    static_assert(NQ == 32 * 4, "a half-wave of lanes covers the quads of one sum");
+    float* qs = lds;  // [MD][NQ]
 #pragma unroll
     for (int q = 0; q < MD; ++q) {
-        const float t = wave_sum_last(acc[q]);
-        if (threadIdx.x % kWave == kWave - 1) wsum[threadIdx.x / kWave][q] = t;
+        const float t = quad_sum(acc[q]);
+        if ((threadIdx.x & 3) == 0) qs[q * NQ + (threadIdx.x >> 2)] = t;
     }
     __syncthreads();
-    if (threadIdx.x < MD) {
-        double t = 0.0;
 #pragma unroll
-        for (int h = 0; h < PARTS; ++h) t += (double)wsum[h][threadIdx.x];
-        a.cm_part[((int64_t)row * MD + threadIdx.x) * a.part_stride + tile] = t;
+    for (int pass = 0; pass < (MD * 32 + T - 1) / T; ++pass) {
+        const int t = threadIdx.x + pass * T;
+        const int q = t >> 5, seg = t & 31;  // sum q, quads 4 seg .. 4 seg + 3
+        float v = 0.f;
+        if (q < MD) {
+            const float* r4 = qs + q * NQ + 4 * seg;
+            v = (r4[0] + r4[1]) + (r4[2] + r4[3]);
+        }
+        v = half_wave_sum_last(v);
+        if (seg == 31 && q < MD) a.cm_part[((int64_t)row * MD + q) * a.part_stride + tile] = (double)v;
     }
 }
 
