@@ -84,6 +84,16 @@ typedef int32_t acseg_status;
  * then takes them as c_fixed and returns dL/dc_fixed in grad_c ([N][C]).
  */
 #define ACSEG_FLAG_FIXED_C 4u
+/*
+ * Adaptive schedules (no ACSEG_FLAG_FIXED_CYCLES) enqueue the cycles of a time
+ * step in chunks (the first as long as the previous step needed, then growing)
+ * and read the step's convergence flag back between chunks, so acseg_step and
+ * acseg_solve wait for the stream while they run.  With this flag they instead
+ * enqueue all max_cycles cycles of every step at once, which exit on the
+ * device after convergence (no host wait; each skipped launch still costs a
+ * few microseconds).  acseg_solve_batched always works this way.
+ */
+#define ACSEG_FLAG_NO_HOST_WAIT 8u
 
 /*
  * One segmentation problem.  Parameters follow eq. E and eq. alpha:

@@ -28,6 +28,7 @@ WARN_EMPTY_PHASE = 2
 FLAG_STORE_CHECKPOINTS = 1
 FLAG_FIXED_CYCLES = 2
 FLAG_FIXED_C = 4
+FLAG_NO_HOST_WAIT = 8
 
 
 class _Problem(ctypes.Structure):

@@ -30,6 +30,8 @@ struct acseg_ctx {
     int cu_count = 0;
     Ctl* host_ctl = nullptr;  // pinned, for statistics read-back
     AdjCtl* host_actl = nullptr;  // pinned, for the adjoint's convergence flag
+    StepSlot* host_slot = nullptr;  // pinned, for a step's convergence flag
+    int cycle_hint = 2;             // cycles of the first chunk of an adaptive step
     bool timing = false;
     std::vector<hipEvent_t> pool;
     std::vector<TimedRec> recs;
@@ -79,7 +81,8 @@ acseg_status validate(const acseg_problem* p, bool need_steps) {
     // check) and closes with post-smoothing (residual)
     const int L = p->levels == 0 ? auto_levels(p->W, p->H) : p->levels;
     if (L >= 2 && (p->nu_pre < 1 || p->nu_post < 1)) return ACSEG_ERR_UNSUPPORTED;
-    if ((p->flags & ~(ACSEG_FLAG_STORE_CHECKPOINTS | ACSEG_FLAG_FIXED_CYCLES | ACSEG_FLAG_FIXED_C)) != 0u)
+    if ((p->flags & ~(ACSEG_FLAG_STORE_CHECKPOINTS | ACSEG_FLAG_FIXED_CYCLES | ACSEG_FLAG_FIXED_C |
+                      ACSEG_FLAG_NO_HOST_WAIT)) != 0u)
         return ACSEG_ERR_INVALID_ARG;
     return ACSEG_OK;
 }
@@ -425,7 +428,7 @@ acseg_status enqueue_step(acseg_ctx* ctx, const acseg_problem* p, const Coefs& c
     st.fixed_c = (p->flags & ACSEG_FLAG_FIXED_C) != 0u ? 1 : 0;
     st.prev_sel = st.fixed_c ? 2 : prev_sel;  // fixed means sit in c64 set 2
     const MgPlan m = plan_of(p);
-    for (int k = 0; k < p->max_cycles; ++k) {
+    auto cycle = [&](int k) -> acseg_status {
         st.cycle = k;
         st.cm = (!sc.fixed || k == p->max_cycles - 1) ? 1 : 0;
         st.launch = k * sc.lpc;
@@ -434,7 +437,7 @@ acseg_status enqueue_step(acseg_ctx* ctx, const acseg_problem* p, const Coefs& c
             ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] {
                 return launch_cycle(p->N, p->C, p->nu_pre + p->nu_post, a, st, single, role, s);
             }));
-            continue;
+            return ACSEG_OK;
         }
         const CycleRole pre{k == 0, true, false};
         ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] { return launch_cycle(p->N, p->C, p->nu_pre, a, st, single, pre, s); }));
@@ -443,6 +446,34 @@ acseg_status enqueue_step(acseg_ctx* ctx, const acseg_problem* p, const Coefs& c
         st.launch = k * sc.lpc + sc.lpre;
         const CycleRole post{false, false, true};
         ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] { return launch_cycle(p->N, p->C, p->nu_post, a, st, single, post, s); }));
+        return ACSEG_OK;
+    };
+    const bool chunked = !sc.fixed && (p->flags & ACSEG_FLAG_NO_HOST_WAIT) == 0u;
+    ctx->host_slot->done = 0;
+    if (!chunked) {
+        for (int k = 0; k < p->max_cycles; ++k) {
+            const acseg_status v = cycle(k);
+            if (v != ACSEG_OK) return v;
+        }
+    } else {
+        // chunks of cycles; after each, a convergence test whose flag the host reads
+        int k = 0, chunk = std::max(1, std::min(ctx->cycle_hint, p->max_cycles));
+        while (k < p->max_cycles) {
+            const int end = std::min(p->max_cycles, k + chunk);
+            for (; k < end; ++k) {
+                const acseg_status v = cycle(k);
+                if (v != ACSEG_OK) return v;
+            }
+            if (k >= p->max_cycles) break;
+            ACSEG_TRY(launch_step_check(a, st.slot, k, s));
+            ACSEG_TRY(hipMemcpyAsync(ctx->host_slot, &a.ctl->step[st.slot], sizeof(StepSlot),
+                                     hipMemcpyDeviceToHost, s));
+            ACSEG_TRY(hipStreamSynchronize(s));
+            if (ctx->host_slot->done) break;
+            chunk = std::min(2 * chunk, 64);
+        }
+        // the next step starts with as many cycles as this one needed
+        ctx->cycle_hint = std::max(1, ctx->host_slot->done ? ctx->host_slot->cycles : k);
     }
     const StepEndArgs e{p->max_cycles, sc.lpc};
     ACSEG_TRY(timed(ctx, kFamOther, s, [&] {
@@ -626,8 +657,10 @@ acseg_status acseg_create(int device, acseg_ctx** out) {
     c->device = device;
     if (hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
         hipHostMalloc((void**)&c->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&c->host_actl, sizeof(AdjCtl), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&c->host_actl, sizeof(AdjCtl), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->host_slot, sizeof(StepSlot), hipHostMallocDefault) != hipSuccess) {
         if (c->host_ctl) (void)hipHostFree(c->host_ctl);
+        if (c->host_actl) (void)hipHostFree(c->host_actl);
         delete c;
         return ACSEG_ERR_HIP;
     }
@@ -644,6 +677,7 @@ acseg_status acseg_destroy(acseg_ctx* ctx) {
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->host_ctl) (void)hipHostFree(ctx->host_ctl);
     if (ctx->host_actl) (void)hipHostFree(ctx->host_actl);
+    if (ctx->host_slot) (void)hipHostFree(ctx->host_slot);
     if (ctx->stage_ev) {
         (void)hipEventSynchronize(ctx->stage_ev);
         (void)hipEventDestroy(ctx->stage_ev);

@@ -162,6 +162,9 @@ void cycle_tiling(int N, int W, int H, CycleArgs* a);
 hipError_t launch_cycle(int N, int C, int sweeps, const CycleArgs& a, const CycleStep& st,
                         const CycleGrid& g, CycleRole role, hipStream_t s);
 
+// Convergence test after `cycles` cycles of the step in control slot `slot`.
+hipError_t launch_step_check(const CycleArgs& a, int slot, int cycles, hipStream_t s);
+
 // End of a time step: the reduced colour-mean sums of the new iterate into tot
 // set st.tot_sel ^ 1, the step's residual and cycle count, the buffer holding
 // the iterate, statistics; re-arms control slot st.slot ^ 1.  With descs, for

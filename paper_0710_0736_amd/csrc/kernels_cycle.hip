@@ -21,6 +21,28 @@ void cycle_tiling(int N, int W, int H, CycleArgs* a) {
     a->tiles_per_xcd = (a->ntiles + kXcd - 1) / kXcd;
 }
 
+// Convergence test after `cycles` cycles of a step (one workgroup): the
+// largest per-tile residual of the last cycle against tol; marks the step done.
+__global__ __launch_bounds__(kBlock) void k_step_check(CycleArgs a, int slot_idx, int cycles) {
+    __shared__ float red[kBlock / kWave];
+    StepSlot* slot = &a.ctl->step[slot_idx];
+    if (slot->done) return;
+    const float* last = a.res_part + ((cycles - 1) & 1) * a.part_stride;
+    float r = 0.f;
+    for (int b = threadIdx.x; b < a.ntiles; b += kBlock) r = fmaxf(r, last[b]);
+    r = block_max(r, red);
+    if (threadIdx.x == 0 && !(r > a.tol)) {
+        slot->done = 1;
+        slot->cycles = cycles;
+        slot->resid = r;
+    }
+}
+
+hipError_t launch_step_check(const CycleArgs& a, int slot, int cycles, hipStream_t s) {
+    hipLaunchKernelGGL(k_step_check, dim3(1), dim3(kBlock), 0, s, a, slot, cycles);
+    return hipGetLastError();
+}
+
 hipError_t launch_cycle(int N, int C, int sweeps, const CycleArgs& a, const CycleStep& st,
                         const CycleGrid& g, CycleRole role, hipStream_t s) {
     switch (N) {

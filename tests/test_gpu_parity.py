@@ -248,3 +248,18 @@ def test_reported_residual_is_the_natural_residual(sweeps):
     rho = orc.residual(P, b, ug)
     assert rho > 1e-3  # genuinely unconverged
     assert abs(st["final_residual"] - rho) <= 1e-5 * max(1.0, rho) + 2e-6, (st["final_residual"], rho)
+
+
+@pytest.mark.parametrize("levels", [1, 0])
+def test_adaptive_chunks_equal_device_only_schedule(levels):
+    """Adaptive steps enqueued in chunks with a host read of the convergence
+    flag, and all cycles enqueued with exits on the device, compute the same."""
+    w = synth.pixel_twin(synth.VORONOI1024, 80)
+    img, u0, _ = w.make(12)
+    p = gpu_problem(w, steps=4, levels=levels, max_cycles=300)
+    u_a, c_a, st_a, _ = acseg.solve(p, cuda(img), cuda(u0))
+    p2 = acseg.Problem(**{**p.__dict__, "flags": acseg.FLAG_NO_HOST_WAIT})
+    u_b, c_b, st_b, _ = acseg.solve(p2, cuda(img), cuda(u0))
+    torch.cuda.synchronize()
+    assert st_a["status"] == acseg.OK and st_a == st_b, (st_a, st_b)
+    assert torch.equal(u_a, u_b) and torch.equal(c_a, c_b)
