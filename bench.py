@@ -70,14 +70,24 @@ def smoother_bytes_per_launch(N: int, C: int, n: int, sweeps: int, cycles: int, 
 
 
 def copy_calibration(mib: int, reps: int):
+    """A plain device copy of a known size: bytes for counter calibration, and
+    the copy's own bandwidth (read + written bytes / time) as the attainable
+    streaming rate."""
     import torch
     n = mib * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda:0")
     b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(reps):
         b.copy_(a)
+    e1.record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "reps": reps}), flush=True)
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "reps": reps,
+                      "ms_per_copy": round(ms, 4), "GB_per_s": round(8 * n / ms / 1e6, 1)}), flush=True)
 
 
 def run_hetero(args):

@@ -125,7 +125,8 @@ def test_first_step_parity(w):
 
 
 @pytest.mark.parametrize("shape,N,C", [((65, 37), 3, 1), ((2, 2), 2, 3), ((3, 130), 4, 2),
-                                       ((129, 66), 8, 4), ((70, 33), 5, 3)])
+                                       ((129, 66), 8, 4), ((70, 33), 5, 3), ((200, 150), 3, 3),
+                                       ((160, 100), 6, 2), ((140, 90), 7, 1)])
 def test_ragged_shapes(shape, N, C):
     W, H = shape
     w = synth.Workload("ragged", W, H, N, "voronoi", 0.1, 40.0, 1, 0, 1e-6, pixel_units=True)
