@@ -97,6 +97,8 @@ typedef int32_t acseg_status;
 
 /*
  * One segmentation problem.  Parameters follow eq. E and eq. alpha:
+ *   H, W    lattice rows and columns; each >= 2 and W * H <= 2^30
+ *   C, N    image channels (1..ACSEG_MAX_C) and phases (ACSEG_MIN_N..ACSEG_MAX_N)
  *   h       lattice spacing (node (x,y) sits at (x h, y h)); > 0
  *   eps     interface parameter epsilon; > 0
  *   lambda  fitting weight; >= 0

@@ -68,7 +68,7 @@ bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 acseg_status validate(const acseg_problem* p, bool need_steps) {
     if (!p) return ACSEG_ERR_INVALID_ARG;
     if (p->W < 2 || p->H < 2 || p->C < 1 || p->N < 1) return ACSEG_ERR_INVALID_ARG;
-    if ((int64_t)p->W * p->H > ((int64_t)1 << 31)) return ACSEG_ERR_INVALID_ARG;
+    if ((int64_t)p->W * p->H > ((int64_t)1 << 30)) return ACSEG_ERR_INVALID_ARG;  // 32-bit byte offsets per plane
     if (p->N < ACSEG_MIN_N || p->N > ACSEG_MAX_N || p->C > ACSEG_MAX_C) return ACSEG_ERR_UNSUPPORTED;
     if (!finite_pos(p->h) || !finite_pos(p->eps) || !finite_pos(p->tau)) return ACSEG_ERR_INVALID_ARG;
     if (!isfinite(p->lambda) || p->lambda < 0.0) return ACSEG_ERR_INVALID_ARG;

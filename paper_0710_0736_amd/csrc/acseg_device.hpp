@@ -24,6 +24,22 @@ namespace acseg {
 constexpr int kBlock = 256;  // threads per workgroup (4 wave64)
 constexpr int kWave = 64;
 
+// Global memory through address space 1.  A pointer read from a descriptor
+// table is generic, and an access through it becomes a flat instruction with
+// a 64-bit vector address of its own (two VALU operations per access, and a
+// count on the LDS counter too).  Through these helpers the access is a
+// global instruction addressed as a uniform base in scalar registers plus a
+// 32-bit byte offset, which all planes of a field share.  Element index
+// i < 2^30 (the lattice limit).
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) char gchar;
+__device__ __forceinline__ float gload(const float* base, uint32_t i) {
+    return *(const gfloat*)((const gchar*)base + (i << 2));
+}
+__device__ __forceinline__ void gstore(float* base, uint32_t i, float v) {
+    *(gfloat*)((gchar*)base + (i << 2)) = v;
+}
+
 // Node class: 0 interior, 1 edge, 2 corner (0,0)/(W-1,H-1), 3 corner (W-1,0)/(0,H-1).
 __device__ __forceinline__ int node_class(int x, int y, int W, int H) {
     const int bx = (x == 0) | (x == W - 1);

@@ -178,7 +178,8 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
             }
         }
     }
-    const int cur = iterate_buf(ctl->cur, st.launch);
+    // uniform: the plane bases then live in scalar registers
+    const int cur = __builtin_amdgcn_readfirstlane(iterate_buf(ctl->cur, st.launch));
     const int W = a.W, H = a.H;
     const int64_t P = (int64_t)W * H;
     // per-plane base pointers (uniform), 32-bit node indices
@@ -208,10 +209,10 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
         const int ly = idx / LX, lx = idx - ly * LX;
         const int gx = x0 + lx, gy = y0 + ly;
         const bool in = idx < LX * LY && (INT || (gx >= 0 && gx < W && gy >= 0 && gy < H));
-        const int g = in ? gy * W + gx : 0;
+        const uint32_t g = in ? (uint32_t)(gy * W + gx) : 0u;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            const float t = srcp[i][g];
+            const float t = gload(srcp[i], g);
             ust[q][i] = in ? t : 0.f;
         }
     }
@@ -236,13 +237,13 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
             const int dy = max(max(R - ly, ly - (R + TY - 1)), 0);
             const int rad = in ? max(dx, dy) : kOut;
             const bool need = rad <= R - 1;  // some half-sweep updates this node
-            const int g = need ? gy * W + gx : 0;
+            const uint32_t g = need ? (uint32_t)(gy * W + gx) : 0u;
             // unconditional loads (index 0 is always valid): no branch between
             // the loads of the burst
             float v[NV];
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
-                const float t = FIRST ? imgp[q][g] : rhsp[q][g];
+                const float t = gload(FIRST ? imgp[q] : rhsp[q], g);
                 v[q] = need ? t : 0.f;
             }
             float kh = 0.f, kv = 0.f;
@@ -365,7 +366,7 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
 #pragma unroll
                     for (int i = 0; i < N; ++i) {
                         rv[i] = (float)(wd * (r[i] - rmax));
-                        if (st.store_rhs && rad == 0) const_cast<float*>(rhsp[i])[gy * W + gx] = rv[i];
+                        if (st.store_rhs && rad == 0) gstore(const_cast<float*>(rhsp[i]), (uint32_t)(gy * W + gx), rv[i]);
                     }
                 } else {
 #pragma unroll
@@ -399,10 +400,10 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
                 const int oy = idx / TX, ox = idx - oy * TX;
                 const int gx = x0 + R + ox, gy = y0 + R + oy;
                 on[q] = st.cm && (INT || (gx < W && gy < H));
-                const int g = on[q] ? gy * W + gx : 0;
+                const uint32_t g = on[q] ? (uint32_t)(gy * W + gx) : 0u;
 #pragma unroll
                 for (int k = 0; k < C; ++k) {
-                    const float t = imgp[k][g];
+                    const float t = gload(imgp[k], g);
                     Io[q][k] = on[q] ? t : 0.f;
                 }
             }
@@ -459,11 +460,11 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
         const int lx = R + ox, ly = R + oy;
         const int li = ly * RW + (lx & 1) * HL + (lx >> 1);
         const bool o = INT || (gx < W && gy < H);
-        const int g = o ? gy * W + gx : 0;
+        const uint32_t g = o ? (uint32_t)(gy * W + gx) : 0u;
         lds_get<N>(lds, li, uo[q]);
 #pragma unroll
         for (int i = 0; i < N; ++i)
-            if (o) dstp[i][g] = uo[q][i];
+            if (o) gstore(dstp[i], g, uo[q][i]);
     }
     if (!RESID) return;
 

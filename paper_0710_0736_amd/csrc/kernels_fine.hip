@@ -42,7 +42,7 @@ template <int N, int C>
 __global__ __launch_bounds__(kBlock) void k_cmeans(CmeansArgs a) {
     constexpr int M = N * C + N + C + 2;  // S_ik, S_i, SI_k, Sw, non-finite count
     __shared__ double sh[kBlock / kWave][M];
-    const float* u = a.u ? a.u : a.bufs.b[a.ctl->cur];
+    const float* u = a.u ? a.u : a.bufs.b[__builtin_amdgcn_readfirstlane(a.ctl->cur)];
     const int64_t n = (int64_t)a.W * a.H;
     double acc[M];
 #pragma unroll
@@ -128,7 +128,7 @@ __global__ void k_ctl_init(Ctl* ctl, int cur) {
 
 __global__ __launch_bounds__(kBlock) void k_copy_current(Bufs bufs, const Ctl* ctl, float* dst,
                                                          int64_t count) {
-    const float* src = bufs.b[ctl->cur];
+    const float* src = bufs.b[__builtin_amdgcn_readfirstlane(ctl->cur)];
     if (src == dst) return;
     for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < count;
          t += (int64_t)gridDim.x * kBlock)

@@ -151,7 +151,7 @@ __device__ __forceinline__ double block_sum_d(double v, double* sh /* kBlock/kWa
 template <int N>
 __global__ __launch_bounds__(kBlock) void k_mg_defect_restrict(MgArgs a) {
     if (step_done(a)) return;
-    const float* __restrict__ u = a.bufs.b[iterate_buf(a.ctl->cur, a.launch)];
+    const float* __restrict__ u = a.bufs.b[__builtin_amdgcn_readfirstlane(iterate_buf(a.ctl->cur, a.launch))];
     const int Wc = a.Wc, Hc = a.Hc;
     const int64_t nc = (int64_t)Wc * Hc;
     for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < nc; p += (int64_t)gridDim.x * kBlock) {
@@ -175,7 +175,7 @@ template <int N>
 __global__ __launch_bounds__(kBlock) void k_mg_dir(MgArgs a) {
     __shared__ double sh[kBlock / kWave];
     if (step_done(a)) return;
-    const float* __restrict__ u = a.bufs.b[iterate_buf(a.ctl->cur, a.launch)];
+    const float* __restrict__ u = a.bufs.b[__builtin_amdgcn_readfirstlane(iterate_buf(a.ctl->cur, a.launch))];
     const int W = a.W, H = a.H, Wc = a.Wc, Hc = a.Hc;
     const int64_t n = (int64_t)W * H, nc = (int64_t)Wc * Hc;
     double gw = 0.0;
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_update(MgArgs a) {
     if (step_done(a)) return;
     const float alpha = (float)a.ctl->alpha;
     if (alpha == 0.f) return;
-    float* __restrict__ u = const_cast<float*>(a.bufs.b[iterate_buf(a.ctl->cur, a.launch)]);
+    float* __restrict__ u = const_cast<float*>(a.bufs.b[__builtin_amdgcn_readfirstlane(iterate_buf(a.ctl->cur, a.launch))]);
     const int64_t total = (int64_t)N * a.W * a.H;
     for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total; t += (int64_t)gridDim.x * kBlock)
         u[t] = fmaxf(u[t] + alpha * a.gt[t], 0.f);
