@@ -205,6 +205,7 @@ Coefs coefs_of(const acseg_problem* p) {
         c.fine.inv_d[k] = (float)(1.0 / D);
         c.fine.d[k] = (float)D;
         c.rhs.wd[k] = w[k] / D;
+        c.rhs.wda[k] = (float)(w[k] / D * (1.0 / p->tau + 2.0 / p->eps));
     }
     c.fine.e2 = (float)e2;
     c.rhs.a = 1.0 / p->tau + 2.0 / p->eps;

@@ -129,30 +129,60 @@ template <> struct SortNet<8> {
 // 1974; Duchi et al. 2008): with s the values sorted in descending order and
 // S_k the sum of the k largest, theta = max_k (S_k - 1) / k (each candidate
 // is a lower bound of theta, and the one at the number of free components is
-// theta itself).  Values are taken relative to the largest one, so the sums
-// are of non-positive numbers and stay well conditioned in FP32.
-template <int N>
+// theta itself).  Two phases have the closed form x_0 = (1 + v_0 - v_1) / 2
+// clipped to [0, 1], x_1 = 1 - x_0.
+//
+// CENTRED: the sums are taken relative to the largest value, which keeps
+// them well conditioned for inputs of any magnitude.  The sweep of the solver
+// calls it with CENTRED = false: its largest component is of order one (the
+// right-hand side, shifted per node so that its largest component lies in
+// [0, (w/D)(1/tau + 2/eps)], plus neighbour terms in [0, 1)), so every
+// component that can be free lies within one of it, and the plain sums are
+// as well conditioned.
+// Components of the result lie in [0, 1], so max(v_i - theta, 0) is a clamp
+// to [0, 1], which folds into the subtraction.
+__device__ __forceinline__ float clamp01(float x) { return __builtin_amdgcn_fmed3f(x, 0.f, 1.f); }
+
+template <int N, bool CENTRED = true>
 __device__ __forceinline__ void project_simplex(float (&v)[N]) {
-    float s[N];
+    if constexpr (N == 2) {
+        const float x0 = clamp01(fmaf(v[0] - v[1], 0.5f, 0.5f));
+        v[0] = x0;
+        v[1] = 1.f - x0;
+        return;
+    } else {
+        float s[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) s[i] = v[i];
+        for (int i = 0; i < N; ++i) s[i] = v[i];
 #pragma unroll
-    for (int c = 0; c < SortNet<N>::n; ++c) {
-        const int i = SortNet<N>::p[c][0], j = SortNet<N>::p[c][1];
-        const float a = s[i], b = s[j];
-        s[i] = fmaxf(a, b);
-        s[j] = fminf(a, b);
+        for (int c = 0; c < SortNet<N>::n; ++c) {
+            const int i = SortNet<N>::p[c][0], j = SortNet<N>::p[c][1];
+            const float a = s[i], b = s[j];
+            s[i] = fmaxf(a, b);
+            s[j] = fminf(a, b);
+        }
+        float thr;
+        if constexpr (CENTRED) {
+            const float vmax = s[0];
+            float S = 0.f, theta = -1.0f;  // k = 1: the largest value alone
+#pragma unroll
+            for (int k = 2; k <= N; ++k) {
+                S += s[k - 1] - vmax;
+                theta = fmaxf(theta, fmaf(S, 1.0f / (float)k, -1.0f / (float)k));
+            }
+            thr = vmax + theta;  // the shift in the original values
+        } else {
+            float T = s[0] - 1.f;  // S_k - 1, accumulated
+            thr = T;
+#pragma unroll
+            for (int k = 2; k <= N; ++k) {
+                T += s[k - 1];
+                thr = fmaxf(thr, T * (1.0f / (float)k));
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = clamp01(v[i] - thr);
     }
-    const float vmax = s[0];
-    float S = 0.f, theta = -1.0f;  // k = 1: the largest value alone
-#pragma unroll
-    for (int k = 2; k <= N; ++k) {
-        S += s[k - 1] - vmax;
-        theta = fmaxf(theta, fmaf(S, 1.0f / (float)k, -1.0f / (float)k));
-    }
-    const float thr = vmax + theta;  // the shift in the original values
-#pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = fmaxf(v[i] - thr, 0.f);
 }
 
 // ---------------------------------------------------------------------------

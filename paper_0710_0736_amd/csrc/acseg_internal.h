@@ -62,6 +62,7 @@ struct RhsCoef {
     double wd[4];   // w / D per node class
     double a;       // 1/tau + 2/eps
     double lambda;
+    float wda[4];   // (w / D)(1/tau + 2/eps) per node class (< 1 when eps > 0.71 h)
 };
 
 constexpr int kCmeansBlocks = 128;  // workgroups of the colour-mean pass

@@ -52,9 +52,8 @@ __host__ __device__ constexpr int node_pad(int N) {
 __host__ __device__ constexpr int cycle_min_waves(int N) { return N == 6 ? 6 : 1; }
 
 template <int N>
-__device__ __forceinline__ void lds_get(const float* __restrict__ L, int slot, float (&v)[N]) {
+__device__ __forceinline__ void lds_ld(const float* __restrict__ p, float (&v)[N]) {
     constexpr int P = node_pad(N);
-    const float* p = L + slot * P;
     if constexpr (P % 2 == 1) {
 #pragma unroll
         for (int k = 0; k < N; ++k) v[k] = p[k];
@@ -78,9 +77,8 @@ __device__ __forceinline__ void lds_get(const float* __restrict__ L, int slot, f
 }
 
 template <int N>
-__device__ __forceinline__ void lds_put(float* __restrict__ L, int slot, const float (&v)[N]) {
+__device__ __forceinline__ void lds_st(float* __restrict__ p, const float (&v)[N]) {
     constexpr int P = node_pad(N);
-    float* p = L + slot * P;
     if constexpr (P % 2 == 1) {
 #pragma unroll
         for (int k = 0; k < N; ++k) p[k] = v[k];
@@ -103,6 +101,16 @@ __device__ __forceinline__ void lds_put(float* __restrict__ L, int slot, const f
             reinterpret_cast<float2*>(p)[k] = t;
         }
     }
+}
+
+template <int N>
+__device__ __forceinline__ void lds_get(const float* __restrict__ L, int slot, float (&v)[N]) {
+    lds_ld<N>(L + slot * node_pad(N), v);
+}
+
+template <int N>
+__device__ __forceinline__ void lds_put(float* __restrict__ L, int slot, const float (&v)[N]) {
+    lds_st<N>(L + slot * node_pad(N), v);
 }
 
 // Dynamic LDS of one cycle launch: the staged field.
@@ -218,16 +226,29 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
     }
     constexpr int NV = FIRST ? C : N;
     float pv0[MP][NV], pv1[MP][NV];
-    int c0[MP];      // LDS slot of the red node; the black one follows from it
-    int pk[MP];      // rad0 | rad1 << 8 | odd row << 16
+    // LDS addresses of each owned pair, so that every access of a sweep is an
+    // immediate offset from one of them: the red node sits at yr + RW, its
+    // neighbours at xr + {0, 1} (left, right) and yr + {0, 2 RW} (up, down);
+    // the black node sits at zb + RW, its neighbours at yr + RW + {0, 1} and
+    // zb + {0, 2 RW} (in slots of NPD floats; the rows beyond the staged
+    // region that the outermost ring points to are never accessed)
+    constexpr int NPD = node_pad(N);
+    float* xr[MP];
+    float* yr[MP];
+    float* zb[MP];
+    int pk[MP];      // rad0 | rad1 << 8
     float kh0[MP], kv0[MP], kh1[MP], kv1[MP];
 #pragma unroll
     for (int m = 0; m < MP; ++m) {
         const int pi = threadIdx.x + m * T;
         const int ly = pi / LXH, j = pi - ly * LXH;
         const int odd = ly & 1;
-        c0[m] = ly * RW + odd * HL + j;
-        int packed = odd << 16;
+        const int c0 = ly * RW + odd * HL + j;       // red node
+        const int cb = c0 + (odd ? 1 - HL : HL);     // black node
+        xr[m] = lds + (cb - 1) * NPD;
+        yr[m] = lds + (c0 - RW) * NPD;
+        zb[m] = lds + (cb - RW) * NPD;
+        int packed = 0;
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int lx = 2 * j + odd + e;
@@ -240,12 +261,10 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
             const uint32_t g = need ? (uint32_t)(gy * W + gx) : 0u;
             // unconditional loads (index 0 is always valid): no branch between
             // the loads of the burst
+            // (read only for nodes that a half-sweep updates: no mask)
             float v[NV];
 #pragma unroll
-            for (int q = 0; q < NV; ++q) {
-                const float t = gload(FIRST ? imgp[q] : rhsp[q], g);
-                v[q] = need ? t : 0.f;
-            }
+            for (int q = 0; q < NV; ++q) v[q] = gload(FIRST ? imgp[q] : rhsp[q], g);
             float kh = 0.f, kv = 0.f;
             if (INT) {
                 kh = kv = in ? uniform_f(a.coef.kappa[0]) : 0.f;
@@ -337,35 +356,40 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
             float rv[N];
             const int rad = (pk[m] >> (8 * e)) & 255;
             if (FIRST) {
-                // rhs'_i = w[(1/tau + 2/eps) u_i - lambda F_i(c)] / D in float64, with
-                // F_i = |I|^2 - 2 c_i.I + |c_i|^2 (the common |I|^2 dropped), shifted
-                // so that max_i rhs'_i = 0
+                // rhs'_i = (w/D)[(1/tau + 2/eps) u_i - lambda F_i(c)] with
+                // F_i = |I|^2 - 2 c_i.I + |c_i|^2, up to a constant per node (which
+                // leaves the projection unchanged): the colour part
+                // g_i = lambda (2 c_i.I - |c_i|^2) in float64, shifted by its largest
+                // value (its terms, of size lambda |c|^2, cancel), plus the mass part
+                // (w/D)(1/tau + 2/eps) u_i in float32.  The largest component of rhs'
+                // lies in [0, (w/D)(1/tau + 2/eps)], below one when eps > 0.71 h.
                 if (rad <= R - 1) {
                     const int pi = threadIdx.x + m * T;
                     const int ly = pi / LXH, j = pi - ly * LXH;
                     const int gx = x0 + 2 * j + (ly & 1) + e, gy = y0 + ly;
-                    const double wd = INT ? uniform_d(a.rc.wd[0]) : sel4d(a.rc.wd, node_class(gx, gy, W, H));
-                    const double ra = uniform_d(a.rc.a);
+                    const int cls = INT ? 0 : node_class(gx, gy, W, H);
+                    const double wd = INT ? uniform_d(a.rc.wd[0]) : sel4d(a.rc.wd, cls);
+                    const float wda = INT ? uniform_f(a.rc.wda[0]) : sel4(a.rc.wda, cls);
                     double Ik[C];
 #pragma unroll
                     for (int k = 0; k < C; ++k) Ik[k] = (double)(e == 0 ? pv0[m][k] : pv1[m][k]);
-                    // t_i = (1/tau + 2/eps) u_i + lambda (2 c_i.I - |c_i|^2); rhs'_i = (w/D)(t_i - max_j t_j)
-                    double r[N];
-                    double rmax = -1e300;
-                    float un[N];
-                    lds_get<N>(lds, e == 0 ? c0[m] : c0[m] + (((pk[m] >> 16) & 1) ? 1 - HL : HL), un);
+                    double gc[N];
 #pragma unroll
                     for (int i = 0; i < N; ++i) {
-                        const double ui = (double)un[i];
-                        double t = fma(ra, ui, cs2[i]);
+                        double t = cs2[i];
 #pragma unroll
                         for (int k = 0; k < C; ++k) t = fma(cs[i * C + k], Ik[k], t);
-                        r[i] = t;
-                        rmax = fmax(rmax, t);
+                        gc[i] = t;
                     }
+                    double gmax = gc[0];
+#pragma unroll
+                    for (int i = 1; i < N; ++i) gmax = fmax(gmax, gc[i]);
+                    const double off = -wd * gmax;
+                    float un[N];
+                    lds_ld<N>((e == 0 ? yr[m] : zb[m]) + RW * NPD, un);
 #pragma unroll
                     for (int i = 0; i < N; ++i) {
-                        rv[i] = (float)(wd * (r[i] - rmax));
+                        rv[i] = fmaf(wda, un[i], (float)fma(wd, gc[i], off));
                         if (st.store_rhs && rad == 0) gstore(const_cast<float*>(rhsp[i]), (uint32_t)(gy * W + gx), rv[i]);
                     }
                 } else {
@@ -413,38 +437,36 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
 #pragma unroll
             for (int m = 0; m < MP; ++m) {
                 if ((pk[m] & 255) > r) continue;
-                const int cb = c0[m] + (((pk[m] >> 16) & 1) ? 1 - HL : HL);
                 float v[N], a0[N], a1[N], a2[N], a3[N];
-                lds_get<N>(lds, cb - 1, a0);
-                lds_get<N>(lds, cb, a1);
-                lds_get<N>(lds, c0[m] - RW, a2);
-                lds_get<N>(lds, c0[m] + RW, a3);
+                lds_ld<N>(xr[m], a0);
+                lds_ld<N>(xr[m] + NPD, a1);
+                lds_ld<N>(yr[m], a2);
+                lds_ld<N>(yr[m] + 2 * RW * NPD, a3);
 #pragma unroll
                 for (int i = 0; i < N; ++i) v[i] = rr0[m][i] + kh0[m] * (a0[i] + a1[i]) + kv0[m] * (a2[i] + a3[i]);
-                project_simplex<N>(v);
+                project_simplex<N, false>(v);
                 if (RESID && s == NHALF - 1) {
                     float o[N];
-                    lds_get<N>(lds, c0[m], o);
+                    lds_ld<N>(yr[m] + RW * NPD, o);
 #pragma unroll
                     for (int i = 0; i < N; ++i) res = fmaxf(res, fabsf(v[i] - o[i]));
                 } else {
-                    lds_put<N>(lds, c0[m], v);
+                    lds_st<N>(yr[m] + RW * NPD, v);
                 }
             }
         } else {  // black: the second node of every pair
 #pragma unroll
             for (int m = 0; m < MP; ++m) {
                 if (((pk[m] >> 8) & 255) > r) continue;
-                const int cb = c0[m] + (((pk[m] >> 16) & 1) ? 1 - HL : HL);
                 float v[N], a0[N], a1[N], a2[N], a3[N];
-                lds_get<N>(lds, c0[m], a0);
-                lds_get<N>(lds, c0[m] + 1, a1);
-                lds_get<N>(lds, cb - RW, a2);
-                lds_get<N>(lds, cb + RW, a3);
+                lds_ld<N>(yr[m] + RW * NPD, a0);
+                lds_ld<N>(yr[m] + (RW + 1) * NPD, a1);
+                lds_ld<N>(zb[m], a2);
+                lds_ld<N>(zb[m] + 2 * RW * NPD, a3);
 #pragma unroll
                 for (int i = 0; i < N; ++i) v[i] = rr1[m][i] + kh1[m] * (a0[i] + a1[i]) + kv1[m] * (a2[i] + a3[i]);
-                project_simplex<N>(v);
-                lds_put<N>(lds, cb, v);
+                project_simplex<N, false>(v);
+                lds_st<N>(zb[m] + RW * NPD, v);
             }
         }
     }
