@@ -46,8 +46,8 @@ HBM_PEAK_GBS = 8000.0
 # see profiles/k_cycle_voronoi1024_n4_batch8_traffic.md.  Must be re-measured
 # whenever the kernel changes (absent: null).
 TRAFFIC = {
-    ("voronoi1024_n4", 8): 377.03e6,
-    ("voronoi1024_n4", 1): 63.57e6,
+    ("voronoi1024_n4", 8): 375.50e6,
+    ("voronoi1024_n4", 1): 63.67e6,
 }
 
 

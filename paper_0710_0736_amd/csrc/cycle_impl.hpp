@@ -39,9 +39,8 @@ constexpr int kCycT = 512;  // threads of a cycle workgroup (8 wave64)
 
 // LDS holds the staged field node-major: the N components of a node are
 // contiguous, padded to NP(N) floats so that a node is read or written with
-// one to three vector accesses (float4 for N = 4 and 8). N = 3 is the
-// exception: a 3-float stride read with dword accesses runs the fused kernel
-// 2.3x faster on gfx950 than a 16-byte stride read with b96/b128 accesses.
+// one to three vector accesses (float4 for N = 4 and 8). N = 3 takes a
+// 3-float stride with dword accesses, 2% faster than a 16-byte stride.
 __host__ __device__ constexpr int node_pad(int N) {
     return N <= 2 ? 2 : (N == 3 ? 3 : (N <= 4 ? 4 : (N <= 6 ? 6 : 8)));
 }
@@ -157,7 +156,9 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
     constexpr int M = N * C + N + C + 2;
     constexpr int NHALF = 2 * K + (RESID ? 1 : 0);
     constexpr int kOut = 255;      // "radius" of a node outside the image: never updated
-    extern __shared__ float lds[];
+    // 16-byte aligned: the staged field is read and written with b128 accesses,
+    // and the static arrays before it need not end on a 16-byte boundary
+    extern __shared__ __attribute__((aligned(16))) float lds[];
     __shared__ float red[T / kWave];
     __shared__ double cs[N * C];  // 2 lambda c_ik (first launch of a step)
     __shared__ double cs2[N];     // -lambda |c_i|^2

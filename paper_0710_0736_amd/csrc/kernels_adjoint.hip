@@ -22,9 +22,11 @@ namespace acseg {
 
 namespace {
 
-__device__ __forceinline__ float nbs(const float* __restrict__ v, int W, int H, int x, int y, int64_t p) {
-    const float h = (x > 0 ? v[p - 1] : 0.f) + (x < W - 1 ? v[p + 1] : 0.f);
-    const float vv = (y > 0 ? v[p - W] : 0.f) + (y < H - 1 ? v[p + W] : 0.f);
+// Weighted neighbour sum of node p = y W + x of one plane (32-bit offsets
+// from the plane's base; the lattice holds at most 2^30 nodes).
+__device__ __forceinline__ float nbs(const float* __restrict__ v, int W, int H, int x, int y, uint32_t p) {
+    const float h = (x > 0 ? gload(v, p - 1) : 0.f) + (x < W - 1 ? gload(v, p + 1) : 0.f);
+    const float vv = (y > 0 ? gload(v, p - W) : 0.f) + (y < H - 1 ? gload(v, p + W) : 0.f);
     return edge_w_h(y, H) * h + edge_w_v(x, W) * vv;
 }
 
@@ -75,25 +77,37 @@ __global__ __launch_bounds__(kBlock) void k_adj_half(AdjArgs a, int colour, int 
         }
     }
     const int W = a.W, H = a.H, hw = (W + 1) / 2;
-    const int64_t n = (int64_t)W * H, nh = (int64_t)hw * H;
-    const float* __restrict__ u1 = a.u1;
+    const int64_t n = (int64_t)W * H;
+    const int nh = hw * H;
+    // per-plane bases (uniform), 32-bit node offsets
+    const float* ubp[N];
+    const float* u1p[N];
+    float* zp[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        ubp[i] = a.ub + i * n;
+        u1p[i] = a.u1 + i * n;
+        zp[i] = a.z + i * n;
+    }
     float dzm = 0.f, zmax = 0.f;
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < nh; t += (int64_t)gridDim.x * kBlock) {
-        const int y = (int)(t / hw), j = (int)(t - (int64_t)y * hw);
+    for (int t = blockIdx.x * kBlock + threadIdx.x; t < nh; t += gridDim.x * kBlock) {
+        const int y = t / hw, j = t - y * hw;
         const int x = 2 * j + ((y + colour) & 1);
         if (x >= W) continue;
-        const int64_t p = (int64_t)y * W + x;
+        const uint32_t p = (uint32_t)(y * W + x);
         const int cls = node_class(x, y, W, H);
         const float kap = sel4(a.coef.kappa, cls), rs = sel4(a.coef.inv_d, cls) * a.inv_h2;
         float yv[N];
+        bool fr[N];
         int k = 0;
         float s = 0.f;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            float v = a.ub[i * n + p] * rs;
-            if (!(sweep == 0 && colour == 0)) v += kap * nbs(a.z + i * n, W, H, x, y, p);
+            float v = gload(ubp[i], p) * rs;
+            if (!(sweep == 0 && colour == 0)) v += kap * nbs(zp[i], W, H, x, y, p);
             yv[i] = v;
-            if (u1[i * n + p] > 0.f) {
+            fr[i] = gload(u1p[i], p) > 0.f;
+            if (fr[i]) {
                 s += v;
                 ++k;
             }
@@ -101,12 +115,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_half(AdjArgs a, int colour, int 
         const float mean = k > 0 ? s / (float)k : 0.f;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            const float zn = (k >= 2 && u1[i * n + p] > 0.f) ? yv[i] - mean : 0.f;
+            const float zn = (k >= 2 && fr[i]) ? yv[i] - mean : 0.f;
             if (colour == 1) {
-                dzm = fmaxf(dzm, fabsf(zn - a.z[i * n + p]));
+                dzm = fmaxf(dzm, fabsf(zn - gload(zp[i], p)));
                 zmax = fmaxf(zmax, fabsf(zn));
             }
-            a.z[i * n + p] = zn;
+            gstore(zp[i], p, zn);
         }
     }
     if (colour == 1) {
@@ -139,22 +153,23 @@ __global__ __launch_bounds__(kBlock) void k_adj_accum(AdjArgs a) {
     for (int q = 0; q < Q; ++q) acc[q] = 0.0;
     const double h2 = a.h2, tau = a.tau, eps = a.eps, lam = a.lambda;
     const double aa = 1.0 / tau + 2.0 / eps;
-    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += (int64_t)gridDim.x * kBlock) {
-        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+    for (int t = blockIdx.x * kBlock + threadIdx.x; t < (int)n; t += gridDim.x * kBlock) {
+        const int y = t / W, x = t - y * W;
+        const uint32_t p = (uint32_t)t;
         const int cls = node_class(x, y, W, H);
         const double Mp = h2 * mass_w(cls);
         const float ast = sel4(a.diagA, cls);
         float Ik[C];
 #pragma unroll
-        for (int k = 0; k < C; ++k) Ik[k] = a.image[k * n + p];
+        for (int k = 0; k < C; ++k) Ik[k] = gload(a.image + k * n, p);
         float ib[C];
 #pragma unroll
         for (int k = 0; k < C; ++k) ib[k] = 0.f;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            const double z = a.z[i * n + p];
-            const double un = a.u0[i * n + p];
-            const double u1 = a.u1[i * n + p];
+            const double z = gload(a.z + i * n, p);
+            const double un = gload(a.u0 + i * n, p);
+            const double u1 = gload(a.u1 + i * n, p);
             const double Au1 = (double)ast * u1 - (double)nbs(a.u1 + i * n, W, H, x, y, p);
             double F = 0.0;
             double d[C];
@@ -163,7 +178,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_accum(AdjArgs a) {
                 d[k] = (double)Ik[k] - c[i * C + k];
                 F += d[k] * d[k];
             }
-            a.ub_out[i * n + p] = (float)(aa * Mp * z);
+            gstore(a.ub_out + i * n, p, (float)(aa * Mp * z));
             acc[0] += z * (-Mp * F);
             acc[1] += z * (-2.0 / (eps * eps)) * Mp * un - z * Au1;
             acc[2] += (-z * Mp * un + z * Mp * u1) / (tau * tau);
@@ -175,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_accum(AdjArgs a) {
             }
         }
 #pragma unroll
-        for (int k = 0; k < C; ++k) a.Ibar[k * n + p] += ib[k];
+        for (int k = 0; k < C; ++k) gstore(a.Ibar + k * n, p, gload(a.Ibar + k * n, p) + ib[k]);
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -222,8 +237,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_means(AdjArgs a) {
     constexpr int NC = N * C;
     const double* tot = a.tot;  // S_ik [N*C], S_i [N], sum w I [C], area, flag (mass-weight units)
     const double area = tot[NC + N + C];
-    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += (int64_t)gridDim.x * kBlock) {
-        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+    for (int t = blockIdx.x * kBlock + threadIdx.x; t < (int)n; t += gridDim.x * kBlock) {
+        const int y = t / W, x = t - y * W;
+        const uint32_t p = (uint32_t)t;
         const double w = mass_w(node_class(x, y, W, H));
         double ib[C];
 #pragma unroll
@@ -232,18 +248,18 @@ __global__ __launch_bounds__(kBlock) void k_adj_means(AdjArgs a) {
         for (int i = 0; i < N; ++i) {
             const double S = tot[NC + i];
             if (!(S > 1e-12 * area)) continue;
-            const double un = a.u0[i * n + p];
+            const double un = gload(a.u0 + i * n, p);
             double du = 0.0;
 #pragma unroll
             for (int k = 0; k < C; ++k) {
                 const double cb = a.cbar64[i * C + k];
                 ib[k] += cb * w * un / S;
-                du += cb * w * ((double)a.image[k * n + p] - a.c64[i * C + k]) / S;
+                du += cb * w * ((double)gload(a.image + k * n, p) - a.c64[i * C + k]) / S;
             }
-            a.ub_out[i * n + p] += (float)du;
+            gstore(a.ub_out + i * n, p, gload(a.ub_out + i * n, p) + (float)du);
         }
 #pragma unroll
-        for (int k = 0; k < C; ++k) a.Ibar[k * n + p] += (float)ib[k];
+        for (int k = 0; k < C; ++k) gstore(a.Ibar + k * n, p, gload(a.Ibar + k * n, p) + (float)ib[k]);
     }
 }
 

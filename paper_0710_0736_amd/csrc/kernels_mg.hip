@@ -396,7 +396,7 @@ __device__ void tail_sweeps(float* v, const float* r, int W, int H, const LevelC
 
 __global__ __launch_bounds__(kTailThreads) void k_coarse_tail(TailArgs a) {
     if (!a.fixed && a.ctl->step[a.slot].done) return;
-    extern __shared__ float lds[];
+    extern __shared__ __attribute__((aligned(16))) float lds[];
     const int i = blockIdx.x;  // component
     const TailLevel* lv = a.lv;
     float* res = lds + a.off_res;
