@@ -43,11 +43,13 @@ HBM_PEAK_GBS = 8000.0
 # DRAM bytes per smoothing launch, (workload, images per launch) -> bytes:
 # rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
 # same counter reads for a 256 MiB device copy (FETCH x 2.000, WRITE x 1.000);
-# see profiles/k_cycle_voronoi1024_n4_batch8_traffic.md.  Must be re-measured
-# whenever the kernel changes (absent: null).
+# see profiles/k_cycle_voronoi1024_n4_batch8_traffic.md.  Measured on the
+# fixed one-cycle schedule of the default run (keyed by workload, batch,
+# cycles per step, levels, sweeps per cycle); must be re-measured whenever
+# the kernel changes (absent: null).
 TRAFFIC = {
-    ("voronoi1024_n4", 8): 375.50e6,
-    ("voronoi1024_n4", 1): 63.67e6,
+    ("voronoi1024_n4", 8, 1, 1, 2): 375.50e6,
+    ("voronoi1024_n4", 1, 1, 1, 2): 63.67e6,
 }
 
 
@@ -353,8 +355,9 @@ def main():
             w.N, C, n, prob.nu_pre + prob.nu_post,
             cycles if fixed else st_run["cycles_total"] / w.steps, fixed)
         achieved = bytes_per_launch / avg_s / 1e9
+        tkey = (w.name, B, cycles, prob.levels, prob.nu_pre + prob.nu_post)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": (int(TRAFFIC[(w.name, B)]) if (w.name, B) in TRAFFIC else None),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": (int(TRAFFIC[tkey]) if fixed and tkey in TRAFFIC else None),
                 "kernel": ("k_cycle_batch" if B > 1 else "k_cycle") +
                           " (time step: rhs + 2 red-black sweeps in LDS + residual + colour-mean partials)",
                 "images_per_launch": B,
