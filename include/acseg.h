@@ -185,6 +185,50 @@ acseg_status acseg_transfer(acseg_ctx *ctx, int32_t direction, int32_t planes, i
                             int32_t Hf, const float *src, float *dst, void *stream);
 
 /*
+ * Image data on a refined lattice (Section "Data Projection"; the refinement
+ * of the pixel grid in Section "Determination of Natural Scales"): r uniform
+ * refinements of a W x H pixel lattice give Wf = (W - 1) 2^r + 1 by Hf = (H - 1) 2^r + 1
+ * nodes of spacing h / 2^r, pixel (x, y) sitting on node (x 2^r, y 2^r).
+ * Every node that a refinement creates takes the value of one of its
+ * neighbours, never an interpolated one (no new gradients): here the value of
+ * the pixel at or below-left of it, so node (X, Y) holds pixel
+ * (X >> r, Y >> r).  The automatic multigrid hierarchy of the refined lattice
+ * passes through the pixel lattice.
+ *   src  float[planes][H][W] (device), dst float[planes][Hf][Wf] (device);
+ *        they must not overlap.
+ *   0 <= r <= 8, W, H >= 2, Wf * Hf <= 2^30; ACSEG_ERR_INVALID_ARG otherwise.
+ */
+acseg_status acseg_refine(acseg_ctx *ctx, int32_t planes, int32_t W, int32_t H, int32_t r,
+                          const float *src, float *dst, void *stream);
+
+/*
+ * The values of a field on the refined lattice of acseg_refine at the pixel
+ * nodes: dst[c][y][x] = src[c][y 2^r][x 2^r], src float[planes][Hf][Wf], dst
+ * float[planes][H][W] (device, not overlapping).  Same limits as acseg_refine.
+ * Sampling the phase fields and taking their labels gives the segmentation at
+ * the pixels.
+ */
+acseg_status acseg_sample(acseg_ctx *ctx, int32_t planes, int32_t W, int32_t H, int32_t r,
+                          const float *src, float *dst, void *stream);
+
+/*
+ * Colour-space pre-pass (Section "Two Dimensional Examples", multi-channel
+ * data: the model takes any colour space and number of channels, and L*a*b*
+ * with the luminosity ignored is suggested in place of RGB).  rgb
+ * float[3][count] holds sRGB values in [0, 1] (IEC 61966-2-1 transfer curve
+ * and primaries, D65 white); dst gets CIE 1976 L*a*b* divided by 100:
+ *   ACSEG_LAB  dst float[3][count] = (L*, a*, b*) / 100, so the first channel lies in [0, 1];
+ *   ACSEG_AB   dst float[2][count] = (a*, b*) / 100 (luminosity dropped).
+ * The white point is the image of RGB (1, 1, 1), so white and every grey
+ * map to a* = b* = 0.  Device pointers; rgb and dst must not overlap.
+ * ACSEG_ERR_INVALID_ARG for count < 0 or an unknown kind.
+ */
+#define ACSEG_LAB 0
+#define ACSEG_AB 1
+acseg_status acseg_colour_space(acseg_ctx *ctx, int32_t kind, int64_t count, const float *rgb,
+                                float *dst, void *stream);
+
+/*
  * Colour means of eq. VV_fidelity with the lumped mass (one node per pixel):
  *   c_ik = sum_p M_p u_pi I_pk / sum_p M_p u_pi,   c: float[N][C].
  * A phase whose mass is below 1e-12 of the domain area keeps c_prev[i] (if

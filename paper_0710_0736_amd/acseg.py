@@ -111,6 +111,11 @@ def lib():
         L.acseg_project_simplex.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp]
         L.acseg_transfer.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32, vp, vp, vp]
+        L.acseg_refine.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   vp, vp, vp]
+        L.acseg_sample.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   vp, vp, vp]
+        L.acseg_colour_space.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp]
         L.acseg_colour_means.argtypes = [vp, pp, vp, vp, vp, vp, sp, vp, sz, vp]
         L.acseg_step.argtypes = [vp, pp, vp, vp, vp, vp, vp, sp, vp, sz, vp]
         L.acseg_solve.argtypes = [vp, pp, vp, vp, vp, vp, sp, vp, sz, vp]
@@ -216,6 +221,48 @@ def restrict(vf: torch.Tensor) -> torch.Tensor:
     _check(lib().acseg_transfer(ctx(vf.device.index), 1, planes, Wf, Hf, _ptr(vf), _ptr(vc),
                                 _stream()), "acseg_transfer")
     return vc
+
+
+def refined_sides(W: int, H: int, r: int):
+    """(Wf, Hf) of r uniform refinements of a W x H pixel lattice."""
+    return ((W - 1) << r) + 1, ((H - 1) << r) + 1
+
+
+def refine(src: torch.Tensor, r: int) -> torch.Tensor:
+    """Piecewise-constant data on r refinements: [planes][H][W] -> [planes][Hf][Wf]."""
+    planes, H, W = src.shape
+    _need(src, (planes, H, W), name="src")
+    Wf, Hf = refined_sides(W, H, r)
+    dst = torch.empty((planes, Hf, Wf), dtype=torch.float32, device=src.device)
+    _check(lib().acseg_refine(ctx(src.device.index), planes, W, H, r, _ptr(src), _ptr(dst), _stream()),
+           "acseg_refine")
+    return dst
+
+
+def sample(src: torch.Tensor, W: int, H: int, r: int) -> torch.Tensor:
+    """Values of a refined field at the pixel nodes: [planes][Hf][Wf] -> [planes][H][W]."""
+    planes = src.shape[0]
+    Wf, Hf = refined_sides(W, H, r)
+    _need(src, (planes, Hf, Wf), name="src")
+    dst = torch.empty((planes, H, W), dtype=torch.float32, device=src.device)
+    _check(lib().acseg_sample(ctx(src.device.index), planes, W, H, r, _ptr(src), _ptr(dst), _stream()),
+           "acseg_sample")
+    return dst
+
+
+LAB, AB = 0, 1
+
+
+def colour_space(rgb: torch.Tensor, kind: int = LAB) -> torch.Tensor:
+    """sRGB [3][...] in [0, 1] -> L*a*b* / 100 ([3][...]) or a*b* / 100 ([2][...])."""
+    if rgb.shape[0] != 3:
+        raise ValueError("rgb must have 3 channels")
+    _need(rgb, tuple(rgb.shape), name="rgb")
+    count = rgb[0].numel()
+    dst = torch.empty((3 if kind == LAB else 2, *rgb.shape[1:]), dtype=torch.float32, device=rgb.device)
+    _check(lib().acseg_colour_space(ctx(rgb.device.index), kind, count, _ptr(rgb), _ptr(dst), _stream()),
+           "acseg_colour_space")
+    return dst
 
 
 def colour_means(p: Problem, image: torch.Tensor, u: torch.Tensor, c_prev=None):

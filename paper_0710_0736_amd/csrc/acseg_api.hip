@@ -711,6 +711,36 @@ acseg_status acseg_transfer(acseg_ctx* ctx, int32_t direction, int32_t planes, i
     return hip_status(launch_transfer(planes, direction, src, dst, Wf, Hf, (hipStream_t)stream));
 }
 
+// Sizes of the refined lattice of acseg_refine / acseg_sample, or false when
+// out of range.
+static bool refined_sides(int32_t W, int32_t H, int32_t r, int64_t* Wf, int64_t* Hf) {
+    if (W < 2 || H < 2 || r < 0 || r > 8) return false;
+    *Wf = ((int64_t)(W - 1) << r) + 1;
+    *Hf = ((int64_t)(H - 1) << r) + 1;
+    return *Wf * *Hf <= ((int64_t)1 << 30);
+}
+
+acseg_status acseg_refine(acseg_ctx* ctx, int32_t planes, int32_t W, int32_t H, int32_t r, const float* src,
+                          float* dst, void* stream) {
+    int64_t Wf, Hf;
+    if (!ctx || planes < 1 || !src || !dst || !refined_sides(W, H, r, &Wf, &Hf)) return ACSEG_ERR_INVALID_ARG;
+    return hip_status(launch_refine(planes, W, H, r, src, dst, (hipStream_t)stream));
+}
+
+acseg_status acseg_sample(acseg_ctx* ctx, int32_t planes, int32_t W, int32_t H, int32_t r, const float* src,
+                          float* dst, void* stream) {
+    int64_t Wf, Hf;
+    if (!ctx || planes < 1 || !src || !dst || !refined_sides(W, H, r, &Wf, &Hf)) return ACSEG_ERR_INVALID_ARG;
+    return hip_status(launch_sample(planes, W, H, r, src, dst, (hipStream_t)stream));
+}
+
+acseg_status acseg_colour_space(acseg_ctx* ctx, int32_t kind, int64_t count, const float* rgb, float* dst,
+                                void* stream) {
+    if (!ctx || (kind != ACSEG_LAB && kind != ACSEG_AB) || count < 0 || (count > 0 && (!rgb || !dst)))
+        return ACSEG_ERR_INVALID_ARG;
+    return hip_status(launch_lab(kind == ACSEG_AB, count, rgb, dst, (hipStream_t)stream));
+}
+
 acseg_status acseg_colour_means(acseg_ctx* ctx, const acseg_problem* p, const float* image,
                                 const float* u, const float* c_prev, float* c_out,
                                 acseg_stats* stats, void* ws, size_t ws_bytes, void* stream) {

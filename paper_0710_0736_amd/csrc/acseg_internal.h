@@ -254,6 +254,11 @@ hipError_t launch_coarse_tail(int N, const TailArgs& a, size_t lds_bytes, hipStr
 hipError_t launch_transfer(int planes, int dir, const float* src, float* dst, int Wf, int Hf,
                            hipStream_t s);
 
+// ---- data on refined lattices, colour spaces (kernels_data.hip) -----------
+hipError_t launch_refine(int planes, int W, int H, int r, const float* src, float* dst, hipStream_t s);
+hipError_t launch_sample(int planes, int W, int H, int r, const float* src, float* dst, hipStream_t s);
+hipError_t launch_lab(int ab_only, int64_t count, const float* rgb, float* dst, hipStream_t s);
+
 // ---- launchers (kernels_adjoint.hip): gradients through the time steps ------
 
 struct AdjCtl {

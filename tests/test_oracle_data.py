@@ -1,0 +1,91 @@
+"""Pins of the data pre-pass oracle (no GPU).
+
+* refinement: the rule of Section "Data Projection" checked node by node (every
+  node a refinement creates equals one of its lattice neighbours; old nodes
+  keep their values; no new values appear), lattice sizes and their nesting
+  into the multigrid hierarchy, and sampling as its left inverse;
+* colour space: invariants of CIE L*a*b* (white -> L* = 100, a* = b* = 0;
+  black -> 0; every grey -> a* = b* = 0; L* increasing along the greys),
+  continuity of both piecewise definitions at their knots, and the published
+  L*a*b* of the sRGB primaries.
+"""
+import numpy as np
+import pytest
+
+from oracle import data as od
+
+NEIGHBOURS = [(-1, -1), (-1, 0), (-1, 1), (0, -1), (0, 1), (1, -1), (1, 0), (1, 1)]
+
+
+@pytest.mark.parametrize("W,H,P", [(2, 2, 1), (5, 3, 2), (7, 9, 3)])
+def test_refine_once_follows_the_injection_rule(W, H, P):
+    rng = np.random.default_rng(W * H)
+    a = rng.integers(0, 1000, size=(P, H, W)).astype(np.float64)  # distinct-ish values
+    f = od.refine_once(a)
+    assert f.shape == (P, 2 * H - 1, 2 * W - 1)
+    assert np.array_equal(f[:, ::2, ::2], a)
+    for c in range(P):
+        for Y in range(2 * H - 1):
+            for X in range(2 * W - 1):
+                if X % 2 == 0 and Y % 2 == 0:
+                    continue
+                # a created node carries the value of one of its lattice neighbours
+                vals = [f[c, Y + dy, X + dx] for dy, dx in NEIGHBOURS
+                        if 0 <= Y + dy < 2 * H - 1 and 0 <= X + dx < 2 * W - 1]
+                assert f[c, Y, X] in vals, (c, X, Y)
+    assert set(np.unique(f)) <= set(np.unique(a))
+
+
+@pytest.mark.parametrize("W,H,r", [(2, 2, 0), (3, 2, 1), (6, 5, 3), (17, 9, 2)])
+def test_refine_sizes_nesting_and_sampling(W, H, r):
+    rng = np.random.default_rng(r)
+    a = rng.random((2, H, W))
+    f = od.refine(a, r)
+    Wf, Hf = (W - 1) * 2 ** r + 1, (H - 1) * 2 ** r + 1
+    assert f.shape == (2, Hf, Wf)
+    # the multigrid coarsening ceil(side / 2) of the refined lattice reaches the pixel lattice
+    w, h = Wf, Hf
+    for _ in range(r):
+        w, h = (w + 1) // 2, (h + 1) // 2
+    assert (w, h) == (W, H)
+    assert np.array_equal(od.sample(f, r), a)
+    # piecewise constant: node (X, Y) holds pixel (X >> r, Y >> r)
+    Y, X = np.mgrid[0:Hf, 0:Wf]
+    assert np.array_equal(f, a[:, Y >> r, X >> r])
+
+
+def test_lab_white_black_and_greys():
+    g = np.linspace(0.0, 1.0, 101)
+    rgb = np.stack([g, g, g])
+    lab = od.srgb_to_lab(rgb) * 100.0
+    assert abs(lab[0, -1] - 100.0) < 1e-9 and np.abs(lab[1:, -1]).max() < 1e-9
+    assert np.abs(lab[:, 0]).max() < 1e-9
+    assert np.abs(lab[1:]).max() < 1e-9
+    assert np.all(np.diff(lab[0]) > 0)
+    ab = od.srgb_to_lab(rgb, ab_only=True)
+    assert ab.shape == (2, 101) and np.array_equal(ab, lab[1:] / 100.0)
+
+
+def test_lab_piecewise_definitions_are_continuous_at_their_knots():
+    k = 0.04045  # the sRGB transfer curve's knot
+    assert abs(k / 12.92 - ((k + 0.055) / 1.055) ** 2.4) < 1e-7
+    lo, hi = od.srgb_to_linear([k, k + 1e-9])
+    assert abs(hi - lo) < 1e-8
+    d = 6.0 / 29.0  # the CIE companding knot: value and slope match
+    t = d ** 3
+    assert abs(od.cie_f(t) - od.cie_f(t * (1 + 1e-9))) < 1e-8
+    slope_lin = 1.0 / (3 * d * d)
+    slope_cbrt = (1.0 / 3.0) * t ** (-2.0 / 3.0)
+    assert abs(slope_lin - slope_cbrt) < 1e-9
+
+
+def test_lab_of_the_srgb_primaries():
+    # L*a*b* (D65) of pure sRGB red, green and blue as tabulated in the
+    # colour-science literature; the 4-digit matrix keeps them within 0.05
+    ref = {(1, 0, 0): (53.24, 80.09, 67.20), (0, 1, 0): (87.73, -86.18, 83.18),
+           (0, 0, 1): (32.30, 79.19, -107.86)}
+    for rgb, want in ref.items():
+        got = od.srgb_to_lab(np.array(rgb, dtype=np.float64).reshape(3, 1))[:, 0] * 100.0
+        assert np.abs(got - np.array(want)).max() < 0.05, (rgb, got)
+    # middle grey: the transfer curve maps 0.5 to 0.2140 (linear light)
+    assert abs(od.srgb_to_linear(0.5) - 0.2140) < 1e-4
