@@ -57,9 +57,16 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def smoother_bytes_per_launch(N: int, C: int, n: int, sweeps: int, cycles: int, fixed: bool) -> float:
+def launches_per_cycle(levels: int, nu_pre: int, nu_post: int) -> int:
+    """k_cycle launches per cycle: up to two sweeps per launch; a multigrid
+    cycle smooths before and after its coarse correction in separate launches."""
+    if levels == 1:
+        return (nu_pre + nu_post + 1) // 2
+    return (nu_pre + 1) // 2 + (nu_post + 1) // 2
+
+
+def smoother_bytes_per_launch(N: int, C: int, n: int, lpc: int, cycles: int, fixed: bool) -> float:
     """Algorithmic bytes of one k_cycle launch, averaged over a time step."""
-    lpc = (sweeps + 1) // 2
     launches = cycles * lpc
     store_rhs = not (fixed and cycles == 1 and lpc == 1)
     first = 4 * (2 * N + C) + (4 * N if store_rhs else 0)
@@ -156,6 +163,84 @@ def run_hetero(args):
     print(json.dumps(out), flush=True)
 
 
+def run_refined(args):
+    """Segmentation on a refined lattice: pixel data refined r times by
+    piecewise-constant injection, the solve on the refined lattice, the phase
+    fields sampled back at the pixels and labelled there."""
+    import torch
+    from paper_0710_0736_amd import acseg, synth
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    r, Wp, N, C, steps = args.refine, args.refine_pixels, 4, 3, 50
+    Wf, Hf = acseg.refined_sides(Wp, Wp, r)
+    img_np, _ = synth.voronoi_image(Wp, Wp, N, 0.1, seed=0, channels=C)
+    Ip = torch.from_numpy(img_np).to(dev)
+    U0 = torch.from_numpy(synth.random_simplex_field(N, Hf, Wf, seed=0)).to(dev)
+    u = torch.empty_like(U0)
+    h = 1.0 / (1 << r)   # the pixel is the unit of length
+    eps = 0.5            # half a pixel: 2^(r-1) refined nodes
+    base = acseg.Problem(H=Hf, W=Wf, C=C, N=N, h=h, eps=eps, lam=100.0, tau=eps * eps, steps=steps,
+                         levels=args.levels, tol=1e-6, nu_pre=args.nu[0], nu_post=args.nu[1],
+                         max_cycles=args.max_cycles)
+    pix = acseg.Problem(H=Wp, W=Wp, C=C, N=N, h=1.0, eps=eps, lam=100.0, tau=eps * eps, steps=steps)
+    If = acseg.refine(Ip, r)
+    u.copy_(U0)
+    _, _, st, _ = acseg.solve(base, If, u)
+    if st["status"] != acseg.OK:
+        raise RuntimeError(f"calibration solve did not converge: {st}")
+    cycles = max(1, st["cycles_max"])
+    prob = acseg.Problem(**{**base.__dict__, "max_cycles": cycles, "flags": acseg.FLAG_FIXED_CYCLES})
+    log(f"[bench] refined: {Wp}^2 pixels, r={r} -> {Wf}x{Hf} nodes, levels={prob.levels}, "
+        f"cycles/step<={cycles}")
+
+    def segment():
+        Ifine = acseg.refine(Ip, r)
+        u.copy_(U0)
+        _, c, _, _ = acseg.solve(prob, Ifine, u, want_stats=False)
+        return acseg.labels(pix, acseg.sample(u, Wp, Wp, r), c)
+
+    for _ in range(args.warmup):
+        segment()
+    torch.cuda.synchronize()
+    k = max(1, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(k):
+        segment()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / k
+    u.copy_(U0)
+    _, _, st_run, _ = acseg.solve(prob, If, u)
+    if st_run["status"] != acseg.OK:
+        raise RuntimeError(f"benchmark schedule did not converge: {st_run}")
+    acseg.timing_enable(True)
+    acseg.timing_read()
+    segment()
+    torch.cuda.synchronize()
+    tm = acseg.timing_read()
+    acseg.timing_enable(False)
+    launches, total_ms = tm["smooth"]
+    avg_s = total_ms / launches / 1e3
+    bpl = smoother_bytes_per_launch(N, C, Wf * Hf, launches_per_cycle(prob.levels, prob.nu_pre, prob.nu_post),
+                                    cycles, True)
+    achieved = bpl / avg_s / 1e9
+    out = {"metric": "segmentations/s on a refined lattice (refine + solve + sample + labels)",
+           "value": round(1.0 / t, 3), "unit": "segmentations/s", "n_gpus": 1, "steps": k,
+           "warmup": args.warmup, "ms_per_step": round(t * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"voronoi{Wp}_n{N}_refined{r}", "pixels": Wp * Wp, "r": r, "W": Wf, "H": Hf,
+                      "N": N, "C": C, "h": h, "eps": eps, "tau": eps * eps, "lambda": 100.0,
+                      "time_steps": steps, "levels": prob.levels,
+                      "sweeps_per_cycle": prob.nu_pre + prob.nu_post, "cycles_per_step_max": cycles,
+                      "cycles_total": st_run["cycles_total"], "final_residual": st_run["final_residual"]},
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_cycle",
+                        "bytes_per_launch": int(bpl), "avg_launch_us": round(avg_s * 1e6, 2),
+                        "launches": launches,
+                        "per_family_ms": {kk: round(v[1], 4) for kk, v in tm.items()}},
+           "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def run_adjoint(args):
     """Forward solve with checkpoints, then gradients of a squared-error loss."""
     import torch
@@ -238,7 +323,14 @@ def main():
     ap.add_argument("--hetero", type=int, default=0, metavar="B",
                     help="only time a batch of B images of independent sizes (64..1024) and "
                          "phase counts (2..6), batched vs one call per image")
+    ap.add_argument("--refine", type=int, default=0, metavar="R",
+                    help="only time segmentation on R uniform refinements of a pixel image "
+                         "(--refine-pixels square, N = 4, eps half a pixel)")
+    ap.add_argument("--refine-pixels", type=int, default=128)
     args = ap.parse_args()
+    if args.refine:
+        run_refined(args)
+        return
     if args.hetero:
         run_hetero(args)
         return
@@ -352,7 +444,7 @@ def main():
         avg_s = total_ms / launches / 1e3
         fixed = args.schedule == "fixed"
         bytes_per_launch = B * smoother_bytes_per_launch(
-            w.N, C, n, prob.nu_pre + prob.nu_post,
+            w.N, C, n, launches_per_cycle(prob.levels, prob.nu_pre, prob.nu_post),
             cycles if fixed else st_run["cycles_total"] / w.steps, fixed)
         achieved = bytes_per_launch / avg_s / 1e9
         tkey = (w.name, B, cycles, prob.levels, prob.nu_pre + prob.nu_post)
