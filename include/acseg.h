@@ -212,6 +212,22 @@ acseg_status acseg_sample(acseg_ctx *ctx, int32_t planes, int32_t W, int32_t H, 
                           const float *src, float *dst, void *stream);
 
 /*
+ * The image as the standard (consistent) mass matrix sees it (Section "Data
+ * Projection": fidelity terms assembled with M_pq = (eta_p, eta_q) instead of
+ * the lumped mass):  dst_p = (M I)_p / m_p per channel, m_p = sum_q M_pq, on
+ * the lattice of the solver (cells split along (x,y)-(x+1,y+1)).  Inside the
+ * lattice this is I_p / 2 plus 1/12 of the six neighbours sharing a triangle.
+ * With consistent-mass fitting, the right-hand side of every phase at node p
+ * differs from the lumped one on dst by a term that is the same for all
+ * phases, and the colour means equal the lumped means on dst; so the solver
+ * run on dst computes the consistent-mass segmentation.
+ *   src, dst  float[planes][H][W] (device), not overlapping; W, H >= 2,
+ *   W * H <= 2^30, planes >= 1 (ACSEG_ERR_INVALID_ARG otherwise).
+ */
+acseg_status acseg_mass_average(acseg_ctx *ctx, int32_t planes, int32_t W, int32_t H,
+                                const float *src, float *dst, void *stream);
+
+/*
  * Colour-space pre-pass (Section "Two Dimensional Examples", multi-channel
  * data: the model takes any colour space and number of channels, and L*a*b*
  * with the luminosity ignored is suggested in place of RGB).  rgb

@@ -81,3 +81,34 @@ def srgb_to_lab(rgb, ab_only: bool = False) -> np.ndarray:
     b = 200.0 * (fy - fz)
     out = np.stack([a, b]) if ab_only else np.stack([L, a, b])
     return out / 100.0
+
+
+def mass_matrix(W: int, H: int, h: float = 1.0):
+    """Consistent P1 mass matrix M_pq = (eta_p, eta_q) of the W x H lattice, every
+    cell split along its (x, y)-(x+1, y+1) diagonal (Section "Data Projection",
+    the standard mass matrix).  Assembled element by element: a triangle of
+    area |T| adds |T|/6 to each diagonal entry of its vertices and |T|/12 to
+    each pair.  Returns a scipy CSR matrix over nodes p = y W + x."""
+    import scipy.sparse as sp
+    rows, cols, vals = [], [], []
+    area = h * h / 2.0
+    for cy in range(H - 1):
+        for cx in range(W - 1):
+            for tri in (((cx, cy), (cx + 1, cy), (cx + 1, cy + 1)),
+                        ((cx, cy), (cx, cy + 1), (cx + 1, cy + 1))):
+                for a in tri:
+                    for b in tri:
+                        rows.append(a[1] * W + a[0])
+                        cols.append(b[1] * W + b[0])
+                        vals.append(area / 6.0 if a == b else area / 12.0)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(W * H, W * H))
+
+
+def mass_average(img: np.ndarray, h: float = 1.0) -> np.ndarray:
+    """The image as the consistent mass matrix sees it: (M I)_p / m_p per channel,
+    with m_p = sum_q M_pq the lumped mass."""
+    img = np.asarray(img, dtype=np.float64)
+    C, H, W = img.shape
+    M = mass_matrix(W, H, h)
+    m = np.asarray(M.sum(axis=1)).ravel()
+    return np.stack([(M @ img[k].ravel()) / m for k in range(C)]).reshape(C, H, W)

@@ -116,6 +116,7 @@ def lib():
         L.acseg_sample.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                    vp, vp, vp]
         L.acseg_colour_space.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp]
+        L.acseg_mass_average.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
         L.acseg_colour_means.argtypes = [vp, pp, vp, vp, vp, vp, sp, vp, sz, vp]
         L.acseg_step.argtypes = [vp, pp, vp, vp, vp, vp, vp, sp, vp, sz, vp]
         L.acseg_solve.argtypes = [vp, pp, vp, vp, vp, vp, sp, vp, sz, vp]
@@ -247,6 +248,16 @@ def sample(src: torch.Tensor, W: int, H: int, r: int) -> torch.Tensor:
     dst = torch.empty((planes, H, W), dtype=torch.float32, device=src.device)
     _check(lib().acseg_sample(ctx(src.device.index), planes, W, H, r, _ptr(src), _ptr(dst), _stream()),
            "acseg_sample")
+    return dst
+
+
+def mass_average(img: torch.Tensor) -> torch.Tensor:
+    """(M I) / m per channel: run the solver on it for consistent-mass fitting."""
+    planes, H, W = img.shape
+    _need(img, (planes, H, W), name="img")
+    dst = torch.empty_like(img)
+    _check(lib().acseg_mass_average(ctx(img.device.index), planes, W, H, _ptr(img), _ptr(dst), _stream()),
+           "acseg_mass_average")
     return dst
 
 

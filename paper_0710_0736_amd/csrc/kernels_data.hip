@@ -1,5 +1,6 @@
-// kernels_data.hip -- image data on refined lattices, and the colour-space
-// pre-pass.  All three are one pass over the data (HBM bound).
+// kernels_data.hip -- image data on refined lattices, the consistent-mass view
+// of the image, and the colour-space pre-pass.  Each is one pass over the data
+// (HBM bound).
 #include <algorithm>
 
 #include "acseg_internal.h"
@@ -76,6 +77,49 @@ __global__ __launch_bounds__(kBlock) void k_lab(const float* __restrict__ rgb, f
     }
 }
 
+// The image as the consistent P1 mass matrix sees it: (M I)_p / m_p, every
+// lattice cell split along its (x,y)-(x+1,y+1) diagonal.  A triangle T at node
+// p with other vertices a, b adds |T|/12 (2 I_p + I_a + I_b) to (M I)_p and
+// |T|/3 to the lumped mass m_p, so (M I)_p / m_p is the sum over the n_T
+// triangles at p of (2 I_p + I_a + I_b), divided by 4 n_T (6 triangles inside;
+// fewer on the boundary, at least one).  One workgroup per row.
+__global__ __launch_bounds__(kBlock) void k_mass_avg(const float* __restrict__ src, float* __restrict__ dst,
+                                                     int W, int H, int planes) {
+    const int64_t n = (int64_t)W * H;
+    const int64_t rows = (int64_t)H * planes;
+    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int c = (int)(row / H), y = (int)(row - (int64_t)c * H);
+        const float* s = src + c * n;
+        float* d = dst + c * n + (int64_t)y * W;
+        const float* r0 = s + (int64_t)y * W;            // row y
+        const float* rd = y > 0 ? r0 - W : r0;           // row y - 1 (read only when it exists)
+        const float* ru = y < H - 1 ? r0 + W : r0;       // row y + 1
+        for (int x = threadIdx.x; x < W; x += kBlock) {
+            const bool L = x > 0, R = x < W - 1, D = y > 0, U = y < H - 1;
+            const float ip2 = 2.f * r0[x];
+            float acc = 0.f;
+            int nt = 0;
+            if (L && D) {  // cell (x-1, y-1): both triangles have p as their (x+1, y+1) corner
+                acc += (ip2 + rd[x - 1] + rd[x]) + (ip2 + rd[x - 1] + r0[x - 1]);
+                nt += 2;
+            }
+            if (R && D) {  // cell (x, y-1): triangle (x, y-1), (x, y), (x+1, y)
+                acc += ip2 + rd[x] + r0[x + 1];
+                nt += 1;
+            }
+            if (L && U) {  // cell (x-1, y): triangle (x-1, y), (x, y), (x, y+1)
+                acc += ip2 + r0[x - 1] + ru[x];
+                nt += 1;
+            }
+            if (R && U) {  // cell (x, y): both triangles have p as their (x, y) corner
+                acc += (ip2 + r0[x + 1] + ru[x + 1]) + (ip2 + ru[x] + ru[x + 1]);
+                nt += 2;
+            }
+            d[x] = acc / (float)(4 * nt);
+        }
+    }
+}
+
 int row_blocks(int64_t rows) { return (int)std::max<int64_t>(1, std::min<int64_t>(rows, kRowBlocks)); }
 
 }  // namespace
@@ -91,6 +135,12 @@ hipError_t launch_sample(int planes, int W, int H, int r, const float* src, floa
     const int Wf = ((W - 1) << r) + 1, Hf = ((H - 1) << r) + 1;
     hipLaunchKernelGGL(k_sample, dim3(row_blocks((int64_t)H * planes)), dim3(kBlock), 0, s, src, dst, W, H, r,
                        Wf, Hf, planes);
+    return hipGetLastError();
+}
+
+hipError_t launch_mass_avg(int planes, int W, int H, const float* src, float* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_mass_avg, dim3(row_blocks((int64_t)H * planes)), dim3(kBlock), 0, s, src, dst, W, H,
+                       planes);
     return hipGetLastError();
 }
 

@@ -117,3 +117,50 @@ def test_refined_step_and_pixel_labels_match_oracle():
     s = np.sort(up_r, axis=0)
     decided = (s[-1] - s[-2]) > 1e-3
     assert ((up_g.argmax(0) != up_r.argmax(0)) & decided).sum() <= 1e-3 * decided.size + 0.5
+
+
+@pytest.mark.parametrize("W,H,P", [(2, 2, 1), (5, 3, 2), (130, 67, 3), (257, 9, 1)])
+def test_mass_average_matches_oracle(W, H, P):
+    rng = np.random.default_rng(W * H + P)
+    img = rng.random((P, H, W)).astype(np.float32)
+    got = host(acseg.mass_average(cuda(img)))
+    ref = od.mass_average(img.astype(np.float64), 1.0)
+    assert np.abs(got - ref).max() < 1e-6
+
+
+def test_mass_average_rejects_bad_sizes():
+    L = acseg.lib()
+    x = torch.zeros(16, device=DEV)
+    cx, p = acseg.ctx(0), x.data_ptr()
+    assert L.acseg_mass_average(cx, 1, 1, 4, p, p, None) == acseg.ERR_INVALID_ARG
+    assert L.acseg_mass_average(cx, 0, 2, 2, p, p, None) == acseg.ERR_INVALID_ARG
+    assert L.acseg_mass_average(cx, 1, 32769, 32769, p, p, None) == acseg.ERR_INVALID_ARG
+
+
+def test_consistent_mass_step_matches_oracle():
+    """A GPU step on the mass average against the oracle's consistent-mass step,
+    assembled from its definition (means u_i.M I / u_i.M 1, gradient lambda M F_i)."""
+    W, H, N, C, h = 61, 43, 3, 3, 1.0
+    kw = dict(H=H, W=W, C=C, N=N, h=h, eps=2 * h, lam=40.0, tau=(2 * h) ** 2)
+    P = orc.Params(levels=0, tol=1e-12, **kw)
+    img, _ = synth.voronoi_image(W, H, N, 0.1, seed=8, channels=C)
+    img64 = img.astype(np.float64)
+    un = synth.random_simplex_field(N, H, W, seed=9).astype(np.float32)
+    un64 = un.astype(np.float64)
+    M = od.mass_matrix(W, H, h)
+    m = np.asarray(M.sum(axis=1)).ravel()
+    MI = np.stack([M @ img64[k].ravel() for k in range(C)])
+    c = np.array([[un64[i].ravel() @ MI[k] / (un64[i].ravel() @ m) for k in range(C)] for i in range(N)])
+    a = 1.0 / P.tau + 2.0 / P.eps
+    b = np.stack([(m * a * un64[i].ravel()
+                   - P.lam * (M @ sum((img64[k] - c[i, k]) ** 2 for k in range(C)).ravel())).reshape(H, W)
+                  for i in range(N)])
+    u_ref, st_ref = orc.solve_qp(P, b, un64)
+    assert st_ref["converged"]
+    p = acseg.Problem(steps=1, levels=1, tol=1e-6, max_cycles=400, **kw)
+    Ia = acseg.mass_average(cuda(img))
+    u_g, c_g, st = acseg.step(p, Ia, cuda(un))
+    torch.cuda.synchronize()
+    assert st["final_residual"] <= 1e-6, st
+    assert np.abs(host(c_g) - c).max() < 1e-5
+    assert np.abs(host(u_g) - u_ref).max() <= 1e-4

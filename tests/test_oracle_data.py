@@ -89,3 +89,59 @@ def test_lab_of_the_srgb_primaries():
         assert np.abs(got - np.array(want)).max() < 0.05, (rgb, got)
     # middle grey: the transfer curve maps 0.5 to 0.2140 (linear light)
     assert abs(od.srgb_to_linear(0.5) - 0.2140) < 1e-4
+
+
+def test_mass_matrix_and_mass_average():
+    W, H, h = 7, 5, 0.4
+    M = od.mass_matrix(W, H, h).toarray()
+    assert np.allclose(M, M.T)
+    assert np.linalg.eigvalsh(M).min() > 0
+    # row sums: the lumped mass h^2 w of the node classes (interior 1, edge 1/2,
+    # corners (0,0)/(W-1,H-1) 1/3, the other two 1/6); total = domain area
+    m = M.sum(axis=1).reshape(H, W) / h ** 2
+    assert np.allclose(m[1:-1, 1:-1], 1.0) and np.allclose(m[0, 1:-1], 0.5) and np.allclose(m[1:-1, 0], 0.5)
+    assert np.isclose(m[0, 0], 1 / 3) and np.isclose(m[-1, -1], 1 / 3)
+    assert np.isclose(m[0, -1], 1 / 6) and np.isclose(m[-1, 0], 1 / 6)
+    assert np.isclose(M.sum(), ((W - 1) * h) * ((H - 1) * h))
+    # constants are kept everywhere, linear functions at every interior node
+    # (the six triangles around it are symmetric about it)
+    Y, X = np.mgrid[0:H, 0:W].astype(np.float64)
+    img = np.stack([np.full((H, W), 0.3), 0.2 * X - 0.1 * Y + 0.05])
+    av = od.mass_average(img, h)
+    assert np.allclose(av[0], 0.3)
+    assert np.allclose(av[1][1:-1, 1:-1], img[1][1:-1, 1:-1])
+    assert not np.allclose(av[1], img[1])  # the boundary sees a one-sided average
+
+
+def test_consistent_mass_fitting_is_the_lumped_solver_on_the_mass_average():
+    """Consistent-mass fitting (gradient lambda M F_i, means u_i.M I / u_i.M 1) gives
+    the same step as the lumped oracle on I~ = M I / m: the right-hand sides differ
+    by a term common to all phases at each node, and the means agree."""
+    import oracle as orc
+    from paper_0710_0736_amd import synth
+    W, H, N, C, h = 9, 7, 3, 2, 0.3
+    P = orc.Params(H=H, W=W, C=C, N=N, h=h, eps=2 * h, lam=20.0, tau=(2 * h) ** 2, levels=1, tol=1e-12)
+    rng = np.random.default_rng(5)
+    img = rng.random((C, H, W))
+    un = synth.random_simplex_field(N, H, W, seed=6).astype(np.float64)
+    M = od.mass_matrix(W, H, h)
+    m = np.asarray(M.sum(axis=1)).ravel()
+    # consistent-mass means and right-hand side, from their definitions
+    MI = np.stack([M @ img[k].ravel() for k in range(C)])
+    c_cons = np.array([[un[i].ravel() @ MI[k] / (un[i].ravel() @ m) for k in range(C)] for i in range(N)])
+    a = 1.0 / P.tau + 2.0 / P.eps
+    b_cons = np.empty((N, H, W))
+    for i in range(N):
+        F = sum((img[k] - c_cons[i, k]) ** 2 for k in range(C)).ravel()
+        b_cons[i] = (m * a * un[i].ravel() - P.lam * (M @ F)).reshape(H, W)
+    # the lumped oracle on the mass average
+    Ia = od.mass_average(img, h)
+    c_red, _ = orc.colour_means(P, Ia, un)
+    assert np.abs(c_red - c_cons).max() < 1e-12
+    b_red = orc.rhs(P, Ia, un, c_red)
+    d = b_cons - b_red
+    assert np.abs(d - d[0:1]).max() < 1e-10 * np.abs(b_cons).max()
+    u_cons, s1 = orc.solve_qp(P, b_cons, un)
+    u_red, s2 = orc.solve_qp(P, b_red, un)
+    assert s1["converged"] and s2["converged"]
+    assert np.abs(u_cons - u_red).max() < 1e-9
