@@ -327,6 +327,8 @@ def main():
                     help="only time segmentation on R uniform refinements of a pixel image "
                          "(--refine-pixels square, N = 4, eps half a pixel)")
     ap.add_argument("--refine-pixels", type=int, default=128)
+    ap.add_argument("--consistent-mass", action="store_true",
+                    help="fitting with the consistent mass matrix (the solver runs on M I / m)")
     args = ap.parse_args()
     if args.refine:
         run_refined(args)
@@ -370,11 +372,15 @@ def main():
     base = acseg.Problem.from_workload(w, C=C, levels=args.levels, nu_pre=args.nu[0],
                                        nu_post=args.nu[1], max_cycles=args.max_cycles)
 
+    # consistent-mass fitting: the solver runs on M I / m, computed per segmentation
+    # into a fixed buffer per image
+    avg = {id(x): torch.empty_like(x) for x in imgs}
+    prep = (lambda x: acseg.mass_average(x, out=avg[id(x)])) if args.consistent_mass else (lambda x: x)
     # calibration: how many cycles does the slowest time step of any image need?
     cycles = max(1, args.cycles)
     for b in (range(B) if args.cycles == 0 else ()):
         us[b].copy_(u0s[b])
-        _, _, st, _ = acseg.solve(base, imgs[b], us[b])
+        _, _, st, _ = acseg.solve(base, prep(imgs[b]), us[b])
         if st["status"] != acseg.OK:
             raise RuntimeError(f"calibration solve did not converge: {st}")
         cycles = max(cycles, st["cycles_max"])
@@ -388,15 +394,16 @@ def main():
 
     def segment():
         u.copy_(u0)
-        _, c, _, _ = acseg.solve(prob, img, u, want_stats=False)
+        _, c, _, _ = acseg.solve(prob, prep(img), u, want_stats=False)
         return acseg.labels(prob, u, c)
 
     probs = [prob] * B
 
     def segment_batch():
+        ims = [prep(x) for x in imgs]
         for b in range(B):
             us[b].copy_(u0s[b])
-        _, cs, _ = acseg.solve_batched(probs, imgs, us, want_stats=False)
+        _, cs, _ = acseg.solve_batched(probs, ims, us, want_stats=False)
         return [acseg.labels(prob, us[b], cs[b]) for b in range(B)]
 
     def timed(fn, k):
@@ -419,13 +426,13 @@ def main():
 
     # the timed schedule converges: check it once with statistics
     u.copy_(u0)
-    _, _, st_run, _ = acseg.solve(prob, img, u)
+    _, _, st_run, _ = acseg.solve(prob, prep(img), u)
     if st_run["status"] != acseg.OK:
         raise RuntimeError(f"benchmark schedule did not converge: {st_run}")
     if B > 1:
         for b in range(B):
             us[b].copy_(u0s[b])
-        _, _, sts = acseg.solve_batched(probs, imgs, us)
+        _, _, sts = acseg.solve_batched(probs, [prep(x) for x in imgs], us)
         bad = [x for x in sts if x["status"] != acseg.OK]
         if bad:
             raise RuntimeError(f"batched schedule did not converge: {bad[0]}")
@@ -447,7 +454,8 @@ def main():
             w.N, C, n, launches_per_cycle(prob.levels, prob.nu_pre, prob.nu_post),
             cycles if fixed else st_run["cycles_total"] / w.steps, fixed)
         achieved = bytes_per_launch / avg_s / 1e9
-        tkey = (w.name, B, cycles, prob.levels, prob.nu_pre + prob.nu_post)
+        tkey = (w.name + ("_consistent_mass" if args.consistent_mass else ""), B, cycles, prob.levels,
+                prob.nu_pre + prob.nu_post)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": (int(TRAFFIC[tkey]) if fixed and tkey in TRAFFIC else None),
                 "kernel": ("k_cycle_batch" if B > 1 else "k_cycle") +
@@ -488,7 +496,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "batch": B, "W": w.W, "H": w.H, "N": w.N, "C": C,
+        "config": {"workload": w.name + ("_consistent_mass" if args.consistent_mass else ""), "batch": B,
+                   "W": w.W, "H": w.H, "N": w.N, "C": C,
                    "time_steps": w.steps, "lambda": w.lam, "h": w.h, "eps": w.eps, "tau": w.tau,
                    "tol": w.tol, "levels": prob.levels, "sweeps_per_cycle": prob.nu_pre + prob.nu_post,
                    "schedule": args.schedule, "cycles_per_step_max": cycles,

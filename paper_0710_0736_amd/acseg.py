@@ -251,11 +251,12 @@ def sample(src: torch.Tensor, W: int, H: int, r: int) -> torch.Tensor:
     return dst
 
 
-def mass_average(img: torch.Tensor) -> torch.Tensor:
+def mass_average(img: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """(M I) / m per channel: run the solver on it for consistent-mass fitting."""
     planes, H, W = img.shape
     _need(img, (planes, H, W), name="img")
-    dst = torch.empty_like(img)
+    dst = torch.empty_like(img) if out is None else out
+    _need(dst, (planes, H, W), name="out")
     _check(lib().acseg_mass_average(ctx(img.device.index), planes, W, H, _ptr(img), _ptr(dst), _stream()),
            "acseg_mass_average")
     return dst
