@@ -55,6 +55,24 @@ def test_batched_equals_single(pixel, fixed):
         assert len({st["cycles_total"] for _, _, st in singles}) > 1
 
 
+def test_bench_configuration_eight_full_size_images():
+    """The launch shape of the benchmark: 8 full-size headline images (seeds
+    0..7) in one batched solve on the fixed one-cycle schedule, each
+    bit-identical to its single-image solve (whose parity with the oracle is
+    tested at full size)."""
+    w = synth.VORONOI1024
+    p = acseg.Problem.from_workload(w, levels=1, steps=3, max_cycles=1, flags=acseg.FLAG_FIXED_CYCLES)
+    made = [w.make(s) for s in range(8)]
+    images = [cuda(m[0]) for m in made]
+    u0s = [cuda(m[1]) for m in made]
+    us, cs, sts = acseg.solve_batched([p] * 8, images, [u.clone() for u in u0s])
+    torch.cuda.synchronize()
+    for b in range(8):
+        u, c, st, _ = acseg.solve(p, images[b], u0s[b].clone())
+        assert torch.equal(us[b], u) and torch.equal(cs[b], c), b
+        assert sts[b]["status"] == acseg.OK and sts[b] == st, (b, sts[b], st)
+
+
 def test_batch_of_one_full_size_image_and_repeat_calls():
     w = synth.VORONOI1024
     img, u0, _ = w.make(0)

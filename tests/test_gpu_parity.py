@@ -177,6 +177,29 @@ def test_full_size_headline_step():
     assert st["cycles_max"] <= 10
 
 
+def test_full_size_hbm_resident_step():
+    """The 4096^2, N = 8 workload at full size, one step in the launch shape the
+    benchmark times.  The oracle's step is too slow here, so the checks are
+    ones that hold at any size: feasibility at every node, the colour means
+    against the oracle's, and the oracle's float64 natural residual of the GPU
+    result for the oracle's right-hand side (the step's QP is strictly convex,
+    so a small residual pins its unique minimiser)."""
+    w = synth.VORONOI4096
+    img, u0, _ = w.make(0)
+    P = orc_params(w, levels=0)
+    c_ref, _ = orc.colour_means(P, img, u0)
+    p = gpu_problem(w, max_cycles=1, flags=acseg.FLAG_FIXED_CYCLES)
+    u_g, c_g, st = acseg.step(p, cuda(img), cuda(u0))
+    torch.cuda.synchronize()
+    assert st["status"] == acseg.OK and st["final_residual"] <= GPU_TOL, st
+    assert np.abs(host(c_g) - c_ref).max() < 1e-5
+    ug = u_g.cpu().numpy()
+    del u_g
+    assert ug.min() >= 0 and np.abs(ug.sum(0, dtype=np.float64) - 1).max() < 1e-5
+    b = orc.rhs(P, img, u0, c_ref)
+    assert orc.residual(P, b, ug) <= 2.5 * GPU_TOL
+
+
 def test_labels_composite_energy():
     w = synth.VORONOI1024.scaled(160, 120)
     img, u0, _ = w.make(4)
