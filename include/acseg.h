@@ -73,7 +73,11 @@ typedef int32_t acseg_status;
  * Every time step runs exactly max_cycles cycles instead of stopping at the
  * first cycle whose residual is <= tol.  The residual after the last cycle
  * still decides whether the step counts as converged (stats).  Without this
- * flag, cycles after convergence are enqueued but exit at once on the device.
+ * flag a step stops at convergence (see ACSEG_FLAG_NO_HOST_WAIT).
+ * With this flag and stats == NULL, acseg_solve enqueues only kernels and
+ * device-to-device copies on its stream (no host reads, no memsets), so the
+ * call can be captured in a HIP graph and replayed.  acseg_solve_batched
+ * uploads host-built descriptor tables on every call and is not capturable.
  */
 #define ACSEG_FLAG_FIXED_CYCLES 2u
 /*
