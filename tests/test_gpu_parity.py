@@ -5,7 +5,8 @@ Gates (per step, from the oracle's state rounded to float32):
     the oracle's float64 evaluation of the GPU result);
   * max |u_gpu - u_oracle| <= 1e-4;
   * argmax labels differ on <= 0.1% of the pixels where the oracle's two
-    largest phases are more than 1e-4 apart.
+    largest phases are more than 1e-4 apart, and each such difference lies
+    on an interface of the oracle's labels (a 4-neighbour with another label).
 Smaller pieces (projection, colour means, energy, labels) are compared
 element by element with float32-level tolerances.
 """
@@ -31,12 +32,27 @@ def host(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
+def interface_nodes(labels):
+    """Nodes with a lattice neighbour (4-neighbourhood) of another label."""
+    e = np.zeros(labels.shape, bool)
+    dx = labels[:, 1:] != labels[:, :-1]
+    dy = labels[1:, :] != labels[:-1, :]
+    e[:, 1:] |= dx
+    e[:, :-1] |= dx
+    e[1:, :] |= dy
+    e[:-1, :] |= dy
+    return e
+
+
 def label_gate(u_gpu, u_ref):
+    """(mismatches where the oracle's top two phases differ by > 1e-4, nodes,
+    all mismatches); decided mismatches must also lie on the oracle's interfaces."""
     s = np.sort(u_ref, axis=0)
     gap = s[-1] - s[-2]
     lg, lr = u_gpu.argmax(0), u_ref.argmax(0)
     decided = gap > 1e-4
     bad = (lg != lr) & decided
+    assert not (bad & ~interface_nodes(lr)).any(), "a decided label mismatch away from any interface"
     return bad.sum(), decided.size, (lg != lr).sum()
 
 
