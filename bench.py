@@ -505,6 +505,11 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    # absolute smoothing rate: full-image red-black sweeps of the finest lattice per
+    # second (and the node updates they make)
+    sweeps = B * args.steps * st_run["cycles_total"] * (prob.nu_pre + prob.nu_post) / elapsed
+    out["sweeps_per_s"] = round(sweeps, 1)
+    out["node_sweeps_per_s"] = round(sweeps * n, 1)
     print(json.dumps(out), flush=True)
 
 
