@@ -600,7 +600,7 @@ BatchLayout batch_layout_of(int32_t B, const acseg_problem* ps) {
 
 struct BackLayout {
     size_t ctl = 0, actl = 0, c64 = 0, tot = 0, part_cm = 0, part_adj = 0, part_f = 0, cbar = 0;
-    size_t z = 0, ub0 = 0, ub1 = 0, total = 0;
+    size_t z = 0, z2 = 0, ub0 = 0, ub1 = 0, total = 0;
 };
 
 BackLayout back_layout_of(const acseg_problem* p) {
@@ -618,9 +618,10 @@ BackLayout back_layout_of(const acseg_problem* p) {
     L.tot = take(sizeof(double) * S * kCmeansMaxM);
     L.part_cm = take(sizeof(double) * (size_t)kCmeansBlocks * kCmeansMaxM);
     L.part_adj = take(sizeof(double) * (size_t)kMgBlocks * (3 + kNC));
-    L.part_f = take(sizeof(float) * 2 * kMgBlocks);
+    L.part_f = take(sizeof(float) * 4 * kMgBlocks);
     L.cbar = take(sizeof(double) * kNC);
     L.z = take(sizeof(float) * p->N * n);
+    L.z2 = take(sizeof(float) * p->N * n);
     L.ub0 = take(sizeof(float) * p->N * n);
     L.ub1 = take(sizeof(float) * p->N * n);
     L.total = off;
@@ -1036,6 +1037,7 @@ acseg_status acseg_backward(acseg_ctx* ctx, const acseg_problem* p, const float*
     a.actl = actl;
     a.image = image;
     a.z = at<float>(ws, L.z);
+    a.z2 = at<float>(ws, L.z2);
     a.Ibar = grad_image;
     a.grads = grad_params;
     a.cbar64 = at<double>(ws, L.cbar);
@@ -1052,7 +1054,7 @@ acseg_status acseg_backward(acseg_ctx* ctx, const acseg_problem* p, const float*
     a.lambda = p->lambda;
     a.W = W;
     a.H = H;
-    a.nblocks = adj_half_blocks(W, H);
+    a.nblocks = adj_sweep_blocks(W, H);
     a.nblocks_acc = adj_accum_blocks(W, H);
     a.max_sweeps = std::min(4000, std::max(4, 2 * p->max_cycles));
     float* ubuf[2] = {at<float>(ws, L.ub0), at<float>(ws, L.ub1)};
@@ -1072,18 +1074,15 @@ acseg_status acseg_backward(acseg_ctx* ctx, const acseg_problem* p, const float*
         int sw = 0, chunk = 4;
         while (sw < a.max_sweeps) {
             const int end = std::min(a.max_sweeps, sw + chunk);
-            for (; sw < end; ++sw) {
-                ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_adj(N, C, kAdjHalf, a, 0, sw, s); }));
-                ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_adj(N, C, kAdjHalf, a, 1, sw, s); }));
-            }
+            for (; sw < end; ++sw)
+                ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_adj(N, C, kAdjSweep, a, 0, sw, s); }));
             if (sw >= a.max_sweeps) break;
-            // the convergence test of the next sweep, done here: one red half-sweep
-            // launch whose check sets the flag, then the flag read back
-            ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_adj(N, C, kAdjHalf, a, 0, sw, s); }));
+            // the next sweep's launch tests convergence first (and sweeps only if
+            // not converged); then the flag is read back
+            ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_adj(N, C, kAdjSweep, a, 0, sw, s); }));
             ACSEG_TRY(hipMemcpyAsync(ctx->host_actl, actl, sizeof(AdjCtl), hipMemcpyDeviceToHost, s));
             ACSEG_TRY(hipStreamSynchronize(s));
             if (ctx->host_actl->done) break;
-            ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_adj(N, C, kAdjHalf, a, 1, sw, s); }));
             ++sw;
             chunk = std::min(64, chunk * 2);
         }

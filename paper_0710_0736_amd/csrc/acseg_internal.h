@@ -268,7 +268,7 @@ struct AdjCtl {
     int pad[2];
 };
 
-enum AdjOp { kAdjHalf = 0, kAdjAccum, kAdjReduce, kAdjMeans };
+enum AdjOp { kAdjSweep = 0, kAdjAccum, kAdjReduce, kAdjMeans };
 
 // Step s backwards: u0 = u^s, u1 = u^{s+1}, ub = dL/du^{s+1}; out: ub_out =
 // dL/du^s; accumulated: Ibar, grads (lambda, eps, tau); cbar of the step.
@@ -280,7 +280,8 @@ struct AdjArgs {
     const float* u1;
     const float* ub;
     float* ub_out;
-    float* z;             // [N][H][W]
+    float* z;             // [N][H][W], z of the sweeps of one parity
+    float* z2;            // [N][H][W], the other parity
     float* Ibar;          // [C][H][W]
     double* grads;        // [3]
     const double* c64;    // means of u^s [N][C]
@@ -288,7 +289,7 @@ struct AdjArgs {
     double* cbar64;       // [N][C]
     float* cbar_out;      // [N][C] or NULL
     int cbar_accumulate;  // add cbar to cbar_out (fixed means) instead of storing it
-    float* part_f;        // [2][kMgBlocks]
+    float* part_f;        // [2 sweep parities][2][kMgBlocks]: max |dz|, max |z| per workgroup
     double* part_d;       // [kMgBlocks][3 + N C]
     LevelCoef coef;       // finest level
     float diagA[4];       // stiffness diagonal per node class
@@ -297,7 +298,7 @@ struct AdjArgs {
     int W, H, nblocks, nblocks_acc, max_sweeps;
 };
 
-int adj_half_blocks(int W, int H);
+int adj_sweep_blocks(int W, int H);
 int adj_accum_blocks(int W, int H);
 hipError_t launch_adj(int N, int C, int op, const AdjArgs& a, int colour, int sweep, hipStream_t s);
 hipError_t launch_adj_init(AdjCtl* ac, double* grads, hipStream_t s);

@@ -52,19 +52,43 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return r;
 }
 
-// One half-sweep of the adjoint solve.  The red half-sweep of every sweep
-// after the first first checks the previous sweep's partials (max |dz|,
-// max |z|) and skips the rest of the solve once they meet rtol.
+// One red-black sweep of the adjoint solve per launch, tile by tile in LDS.
+// A tile of 64 x 8 nodes stages z with a halo of 2: the red nodes within
+// distance 1 of the tile are updated from the staged (old) black values, then
+// the tile's black nodes from those reds, so the tile ends as one global
+// red-black sweep leaves it.  Sweep s reads z from buffer s & 1 (a.z, a.z2)
+// and writes the other, so tiles never see each other's new values.  Every
+// sweep after the second first checks the previous sweep's partials (max |dz|
+// over its black nodes, max |z|; two sets, by sweep parity) and skips the rest
+// of the solve once they meet rtol.  Per node the arithmetic is that of the
+// two half-sweeps it replaces.
+constexpr int kAdjTX = 64, kAdjTY = 8, kAdjR = 2;
+constexpr int kAdjLX = kAdjTX + 2 * kAdjR, kAdjLY = kAdjTY + 2 * kAdjR;
+
+__host__ __device__ inline int adj_tiles(int W, int H) {
+    return ((W + kAdjTX - 1) / kAdjTX) * ((H + kAdjTY - 1) / kAdjTY);
+}
+
+// Weighted neighbour sum of staged node (lx, ly) = lattice node (x, y).
+__device__ __forceinline__ float nbs_tile(const float (&zl)[kAdjLY][kAdjLX], int W, int H, int x, int y, int lx,
+                                          int ly) {
+    const float h = (x > 0 ? zl[ly][lx - 1] : 0.f) + (x < W - 1 ? zl[ly][lx + 1] : 0.f);
+    const float vv = (y > 0 ? zl[ly - 1][lx] : 0.f) + (y < H - 1 ? zl[ly + 1][lx] : 0.f);
+    return edge_w_h(y, H) * h + edge_w_v(x, W) * vv;
+}
+
 template <int N>
-__global__ __launch_bounds__(kBlock) void k_adj_half(AdjArgs a, int colour, int sweep) {
+__global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs a, int sweep) {
     __shared__ float sh[kBlock / kWave];
+    __shared__ float zl[N][kAdjLY][kAdjLX];
     AdjCtl* ac = a.actl;
     if (ac->done) return;
-    if (colour == 0 && sweep > 1) {  // sweep 0 compared its black values with unset memory
+    if (sweep > 1) {  // sweep 0 compared its black values with unset memory
+        const float* prev = a.part_f + ((sweep - 1) & 1) * 2 * kMgBlocks;
         float dz = 0.f, zm = 0.f;
         for (int b = threadIdx.x; b < a.nblocks; b += kBlock) {
-            dz = fmaxf(dz, a.part_f[b]);
-            zm = fmaxf(zm, a.part_f[kMgBlocks + b]);
+            dz = fmaxf(dz, prev[b]);
+            zm = fmaxf(zm, prev[kMgBlocks + b]);
         }
         dz = block_max_f(dz, sh);
         zm = block_max_f(zm, sh);
@@ -76,62 +100,83 @@ __global__ __launch_bounds__(kBlock) void k_adj_half(AdjArgs a, int colour, int 
             return;
         }
     }
-    const int W = a.W, H = a.H, hw = (W + 1) / 2;
+    const int W = a.W, H = a.H;
     const int64_t n = (int64_t)W * H;
-    const int nh = hw * H;
-    // per-plane bases (uniform), 32-bit node offsets
-    const float* ubp[N];
-    const float* u1p[N];
-    float* zp[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        ubp[i] = a.ub + i * n;
-        u1p[i] = a.u1 + i * n;
-        zp[i] = a.z + i * n;
-    }
+    const float* zin = (sweep & 1) ? a.z2 : a.z;
+    float* zout = (sweep & 1) ? a.z : a.z2;
+    const int tiles_x = (W + kAdjTX - 1) / kAdjTX;
+    const int ntiles = adj_tiles(W, H);
     float dzm = 0.f, zmax = 0.f;
-    for (int t = blockIdx.x * kBlock + threadIdx.x; t < nh; t += gridDim.x * kBlock) {
-        const int y = t / hw, j = t - y * hw;
-        const int x = 2 * j + ((y + colour) & 1);
-        if (x >= W) continue;
-        const uint32_t p = (uint32_t)(y * W + x);
-        const int cls = node_class(x, y, W, H);
-        const float kap = sel4(a.coef.kappa, cls), rs = sel4(a.coef.inv_d, cls) * a.inv_h2;
-        float yv[N];
-        bool fr[N];
-        int k = 0;
-        float s = 0.f;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int x0 = (tile % tiles_x) * kAdjTX - kAdjR, y0 = (tile / tiles_x) * kAdjTY - kAdjR;
+        __syncthreads();  // the previous tile's reads of zl are done
+        for (int q = threadIdx.x; q < kAdjLX * kAdjLY; q += kBlock) {
+            const int ly = q / kAdjLX, lx = q - ly * kAdjLX;
+            const int gx = x0 + lx, gy = y0 + ly;
+            const bool in = sweep > 0 && gx >= 0 && gx < W && gy >= 0 && gy < H;
+            const uint32_t g = in ? (uint32_t)(gy * W + gx) : 0u;
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            float v = gload(ubp[i], p) * rs;
-            if (!(sweep == 0 && colour == 0)) v += kap * nbs(zp[i], W, H, x, y, p);
-            yv[i] = v;
-            fr[i] = gload(u1p[i], p) > 0.f;
-            if (fr[i]) {
-                s += v;
-                ++k;
+            for (int i = 0; i < N; ++i) {
+                const float t = gload(zin + i * n, g);
+                zl[i][ly][lx] = in ? t : 0.f;
             }
         }
-        const float mean = k > 0 ? s / (float)k : 0.f;
+        __syncthreads();
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const float zn = (k >= 2 && fr[i]) ? yv[i] - mean : 0.f;
-            if (colour == 1) {
-                dzm = fmaxf(dzm, fabsf(zn - gload(zp[i], p)));
-                zmax = fmaxf(zmax, fabsf(zn));
+        for (int colour = 0; colour < 2; ++colour) {
+            // red: the nodes within distance 1 of the tile, 33 per staged row;
+            // black: the tile's own nodes, 32 per row
+            const int lo = colour == 0 ? 1 : kAdjR;
+            const int per_row = colour == 0 ? (kAdjTX + 2) / 2 : kAdjTX / 2;
+            const int rows = colour == 0 ? kAdjTY + 2 : kAdjTY;
+            for (int q = threadIdx.x; q < per_row * rows; q += kBlock) {
+                const int r = q / per_row, k = q - r * per_row;
+                const int ly = lo + r, gy = y0 + ly;
+                const int gx0 = x0 + lo;
+                const int gx = gx0 + 2 * k + ((gx0 + gy + colour) & 1);
+                const int lx = gx - x0;
+                if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;
+                const uint32_t p = (uint32_t)(gy * W + gx);
+                const int cls = node_class(gx, gy, W, H);
+                const float kap = sel4(a.coef.kappa, cls), rs = sel4(a.coef.inv_d, cls) * a.inv_h2;
+                float yv[N];
+                bool fr[N];
+                int kf = 0;
+                float sum = 0.f;
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    float v = gload(a.ub + i * n, p) * rs;
+                    if (!(sweep == 0 && colour == 0)) v += kap * nbs_tile(zl[i], W, H, gx, gy, lx, ly);
+                    yv[i] = v;
+                    fr[i] = gload(a.u1 + i * n, p) > 0.f;
+                    if (fr[i]) {
+                        sum += v;
+                        ++kf;
+                    }
+                }
+                const float mean = kf > 0 ? sum / (float)kf : 0.f;
+                const bool own = lx >= kAdjR && lx < kAdjR + kAdjTX && ly >= kAdjR && ly < kAdjR + kAdjTY;
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    const float zn = (kf >= 2 && fr[i]) ? yv[i] - mean : 0.f;
+                    if (colour == 1) {
+                        dzm = fmaxf(dzm, fabsf(zn - zl[i][ly][lx]));
+                        zmax = fmaxf(zmax, fabsf(zn));
+                    } else {
+                        zl[i][ly][lx] = zn;  // reds are read only by the black half
+                    }
+                    if (own) gstore(zout + i * n, p, zn);
+                }
             }
-            gstore(zp[i], p, zn);
+            __syncthreads();
         }
     }
-    if (colour == 1) {
-        // the black half-sweep closes a sweep: its change bounds the sweep's
-        // (the red values it read were just written)
-        const float d = block_max_f(dzm, sh);
-        const float m = block_max_f(zmax, sh);
-        if (threadIdx.x == 0) {
-            a.part_f[blockIdx.x] = d;
-            a.part_f[kMgBlocks + blockIdx.x] = m;
-        }
+    const float d = block_max_f(dzm, sh);
+    const float m = block_max_f(zmax, sh);
+    if (threadIdx.x == 0) {
+        float* cur = a.part_f + (sweep & 1) * 2 * kMgBlocks;
+        cur[blockIdx.x] = d;
+        cur[kMgBlocks + blockIdx.x] = m;
     }
 }
 
@@ -153,6 +198,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_accum(AdjArgs a) {
     for (int q = 0; q < Q; ++q) acc[q] = 0.0;
     const double h2 = a.h2, tau = a.tau, eps = a.eps, lam = a.lambda;
     const double aa = 1.0 / tau + 2.0 / eps;
+    // z after the last completed sweep: sweep s wrote buffer (s + 1) & 1
+    const int done_sweeps = a.actl->done ? a.actl->sweeps : a.max_sweeps;
+    const float* zf = (done_sweeps & 1) ? a.z2 : a.z;
     for (int t = blockIdx.x * kBlock + threadIdx.x; t < (int)n; t += gridDim.x * kBlock) {
         const int y = t / W, x = t - y * W;
         const uint32_t p = (uint32_t)t;
@@ -167,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_accum(AdjArgs a) {
         for (int k = 0; k < C; ++k) ib[k] = 0.f;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            const double z = gload(a.z + i * n, p);
+            const double z = gload(zf + i * n, p);
             const double un = gload(a.u0 + i * n, p);
             const double u1 = gload(a.u1 + i * n, p);
             const double Au1 = (double)ast * u1 - (double)nbs(a.u1 + i * n, W, H, x, y, p);
@@ -279,8 +327,8 @@ template <int N, int C>
 hipError_t adj_nc(int op, const AdjArgs& a, int colour, int sweep, hipStream_t s) {
     const int64_t n = (int64_t)a.W * a.H;
     switch (op) {
-        case kAdjHalf:
-            hipLaunchKernelGGL((k_adj_half<N>), dim3(a.nblocks), dim3(kBlock), 0, s, a, colour, sweep);
+        case kAdjSweep:
+            hipLaunchKernelGGL((k_adj_sweep<N>), dim3(a.nblocks), dim3(kBlock), 0, s, a, sweep);
             break;
         case kAdjAccum:
             hipLaunchKernelGGL((k_adj_accum<N, C>), dim3(a.nblocks_acc), dim3(kBlock), 0, s, a);
@@ -307,7 +355,7 @@ hipError_t adj_n(int C, int op, const AdjArgs& a, int colour, int sweep, hipStre
 
 }  // namespace
 
-int adj_half_blocks(int W, int H) { return adj_blocks((int64_t)(W + 1) / 2 * H); }
+int adj_sweep_blocks(int W, int H) { return std::min(adj_tiles(W, H), kMgBlocks); }
 int adj_accum_blocks(int W, int H) { return adj_blocks((int64_t)W * H); }
 
 hipError_t launch_adj(int N, int C, int op, const AdjArgs& a, int colour, int sweep, hipStream_t s) {
