@@ -65,7 +65,7 @@ struct RhsCoef {
     float wda[4];   // (w / D)(1/tau + 2/eps) per node class (< 1 when eps > 0.71 h)
 };
 
-constexpr int kCmeansBlocks = 128;  // workgroups of the colour-mean pass
+constexpr int kCmeansBlocks = 1024;  // workgroups of the colour-mean pass (every CU busy)
 constexpr int kRhsBlocks = 512;     // workgroups of the right-hand-side pass
 
 // ---- launchers (kernels_fine.hip) ----------------------------------------
