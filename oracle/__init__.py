@@ -30,7 +30,7 @@ class _Params(ctypes.Structure):
                 ("lam", ctypes.c_double), ("tau", ctypes.c_double), ("levels", ctypes.c_int32),
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("coarse_sweeps", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("tol", ctypes.c_double)]
+                ("ssc", ctypes.c_int32), ("tol", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -56,12 +56,13 @@ class Params:
     coarse_sweeps: int = 20
     max_cycles: int = 100000
     tol: float = 1e-10
+    ssc: bool = False        # cycles = the paper's subspace correction over all basis functions
 
     def c(self) -> _Params:
         d = asdict(self)
         return _Params(d["H"], d["W"], d["C"], d["N"], d["h"], d["eps"], d["lam"], d["tau"],
                        d["levels"], d["nu_pre"], d["nu_post"], d["coarse_sweeps"],
-                       d["max_cycles"], 0, d["tol"])
+                       d["max_cycles"], int(d["ssc"]), d["tol"])
 
     @classmethod
     def from_workload(cls, w, C: int = 3, **kw) -> "Params":
@@ -106,6 +107,8 @@ def lib():
         L.orc_backward.argtypes = [pp, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp]
         L.orc_backward_c.argtypes = [pp, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp]
         L.orc_solve_c.argtypes = [pp, ctypes.c_int, dp, dp, dp, dp, dp, sp]
+        L.orc_basis.argtypes = [pp, ctypes.c_int, ctypes.c_int, dp]
+        L.orc_ssc_update.argtypes = [pp, ctypes.c_int, ctypes.c_int, dp, dp]
         _lib = L
     return _lib
 
@@ -194,6 +197,25 @@ def apply_H(P: Params, v) -> np.ndarray:
     out = np.empty_like(v)
     lib().orc_apply_H(ctypes.byref(P.c()), _p(v), _p(out))
     return out
+
+
+def basis(P: Params, level: int, q: int) -> np.ndarray:
+    """Basis function of node q (row-major) of ``level`` (0 = finest) on the
+    finest lattice, [H][W] (Section "Multigrid Solution")."""
+    eta = np.empty((P.H, P.W))
+    if lib().orc_basis(ctypes.byref(P.c()), level, q, _p(eta)):
+        raise ValueError("bad level or node")
+    return eta
+
+
+def ssc_update(P: Params, level: int, q: int, b, u):
+    """One subspace correction of u along one basis function; returns
+    (u_new, raised) where ``raised`` flags a rise of the step objective."""
+    u = _d(u).copy()
+    r = lib().orc_ssc_update(ctypes.byref(P.c()), level, q, _p(_d(b)), _p(u))
+    if r < 0:
+        raise ValueError("bad level or node")
+    return u, bool(r)
 
 
 def solve_qp(P: Params, b, u_init):

@@ -31,12 +31,18 @@
  *     multigrid correction with an exact line search (Section "Multigrid
  *     Solution"; truncation as motivated at the start of the Gibbs-constraint
  *     section), iterated until the natural residual meets the tolerance;
+ *   - the paper's own multilevel iteration (Section "Multigrid Solution"):
+ *     successive subspace correction over the basis functions of every level,
+ *     seen on the finest lattice, from the coarsest level to the finest, each
+ *     correction kept on the simplices by the Gibbs correction with the
+ *     function's own lower bound;
  *   - the discrete energy of eq. E and the composite / rounded composite of
  *     Section "Post-processing".
  *
  * Data layout: node (x, y) of a W x H lattice has flat index p = y*W + x;
  * phase fields are [N][H*W], images [C][H*W], all double.
  */
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -51,7 +57,7 @@ typedef struct {
     int32_t nu_pre, nu_post;
     int32_t coarse_sweeps; /* Gauss-Seidel sweeps on the coarsest level */
     int32_t max_cycles;
-    int32_t pad;
+    int32_t ssc;           /* 1: cycles are the paper's subspace correction over all basis functions */
     double tol;            /* on the natural residual (max norm) */
 } orc_params;
 
@@ -576,6 +582,209 @@ static int mg_cycle(const grid_t *G, int L, const orc_params *P, const double *b
 }
 
 /* ------------------------------------------------------------------------ */
+/* Successive subspace correction over the basis functions of every level     */
+/* (Section "Multigrid Solution"; Gibbs correction of Section "Gibbs Space    */
+/* Constraint Pseudocode")                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* A basis function of some level seen on the finest lattice: its nonzero values. */
+typedef struct {
+    int count;
+    int *idx;     /* finest-lattice node indices where eta > 0 */
+    double *val;  /* eta at those nodes */
+} basis_fn;
+
+/*
+ * eta for node q of level l (0 = finest): the unit vector of node q prolonged
+ * level by level down to level 0 (all basis functions of all levels are
+ * projected onto the finest grid).
+ */
+static int basis_build(const grid_t *G, int l, int q, basis_fn *f)
+{
+    size_t m = (size_t)G[l].W * G[l].H;
+    double *a = calloc(m, sizeof(double));
+    if (!a) return -1;
+    a[q] = 1.0;
+    for (int k = l; k > 0; --k) {
+        size_t mf = (size_t)G[k - 1].W * G[k - 1].H;
+        double *fine = malloc(sizeof(double) * mf);
+        if (!fine) {
+            free(a);
+            return -1;
+        }
+        prolong(&G[k - 1], &G[k], 1, a, fine);
+        free(a);
+        a = fine;
+        m = mf;
+    }
+    f->count = 0;
+    for (size_t p = 0; p < m; ++p) f->count += a[p] > 0.0;
+    f->idx = malloc(sizeof(int) * (f->count ? f->count : 1));
+    f->val = malloc(sizeof(double) * (f->count ? f->count : 1));
+    if (!f->idx || !f->val) {
+        free(a);
+        return -1;
+    }
+    int k = 0;
+    for (size_t p = 0; p < m; ++p)
+        if (a[p] > 0.0) {
+            f->idx[k] = (int)p;
+            f->val[k] = a[p];
+            ++k;
+        }
+    free(a);
+    return 0;
+}
+
+typedef struct {
+    int L;
+    int count[32];     /* functions per level */
+    basis_fn *fn[32];  /* [level][node of that level, row-major] */
+} basis_set;
+
+static void basis_set_free(basis_set *B)
+{
+    for (int l = 0; l < B->L; ++l) {
+        if (!B->fn[l]) continue;
+        for (int q = 0; q < B->count[l]; ++q) {
+            free(B->fn[l][q].idx);
+            free(B->fn[l][q].val);
+        }
+        free(B->fn[l]);
+        B->fn[l] = NULL;
+    }
+}
+
+static int basis_set_init(const grid_t *G, int L, basis_set *B)
+{
+    memset(B, 0, sizeof(*B));
+    B->L = L;
+    for (int l = 0; l < L; ++l) {
+        B->count[l] = G[l].W * G[l].H;
+        B->fn[l] = calloc((size_t)B->count[l], sizeof(basis_fn));
+        if (!B->fn[l]) {
+            basis_set_free(B);
+            return -1;
+        }
+        for (int q = 0; q < B->count[l]; ++q)
+            if (basis_build(G, l, q, &B->fn[l][q])) {
+                basis_set_free(B);
+                return -1;
+            }
+    }
+    return 0;
+}
+
+/*
+ * alpha = the point of {sum alpha = 0, alpha_i >= -m_i} nearest to a (the
+ * Gibbs correction with lower bounds): start from a made to sum to zero; raise
+ * every component below its bound to the bound, take the total raise equally
+ * from the components not yet fixed, and repeat until none is below.  Each
+ * round recomputes the free components from a with the one common shift that
+ * makes the total zero, which is the same as subtracting the raises round by
+ * round but keeps the sum exactly zero.
+ */
+static void bounded_correction(int N, const double *a, const double *m, double *alpha)
+{
+    unsigned char free_[ORC_MAX_N];
+    for (int i = 0; i < N; ++i) free_[i] = 1;
+    for (;;) {
+        double s = 0.0;
+        int nfree = 0;
+        for (int i = 0; i < N; ++i) {
+            if (free_[i]) {
+                s += a[i];
+                ++nfree;
+            } else {
+                s -= m[i];
+            }
+        }
+        for (int i = 0; i < N; ++i) alpha[i] = free_[i] ? a[i] - s / nfree : -m[i];
+        int nlow = 0;
+        for (int i = 0; i < N; ++i)
+            if (free_[i] && alpha[i] < -m[i]) {
+                free_[i] = 0;
+                ++nlow;
+            }
+        if (nlow == 0 || nlow == nfree) break;
+    }
+    for (int i = 0; i < N; ++i)
+        if (alpha[i] < -m[i]) alpha[i] = -m[i];
+}
+
+/*
+ * One subspace correction along basis function eta (eq. alpha, with the
+ * stiffness sign and time step as read above): u <- u + alpha eta with alpha
+ * minimising J(u + alpha eta) over the alpha that keep every node on its
+ * simplex.  J is isotropic in alpha (curvature eta.H eta for every phase), so
+ * that minimiser is the nearest feasible point to the unconstrained one
+ * g / (eta.H eta), g_i = eta.(b_i - H u_i); feasibility is sum alpha = 0 and
+ * u_pi + alpha_i eta_p >= 0 on the support, i.e. alpha_i >= -m_i with
+ * m_i = min_p u_pi / eta_p (the bound at which the lowest value becomes
+ * zero).  `scratch` is a zeroed [H*W] field, left zeroed.  Returns 1 if J
+ * rose (never expected).
+ */
+static int ssc_update(const grid_t *g, const orc_params *P, const double *b, double *u,
+                      const basis_fn *f, double *scratch)
+{
+    const int N = P->N;
+    const size_t n = (size_t)g->W * g->H;
+    double gi[ORC_MAX_N], mi[ORC_MAX_N], a[ORC_MAX_N], alpha[ORC_MAX_N];
+    for (int k = 0; k < f->count; ++k) scratch[f->idx[k]] = f->val[k];
+    double D = 0.0;
+    for (int k = 0; k < f->count; ++k) {
+        int p = f->idx[k], x = p % g->W, y = p / g->W;
+        D += f->val[k] * (g->mass[p] / P->tau * f->val[k] + P->eps * stiff_apply(g, scratch, x, y));
+    }
+    for (int k = 0; k < f->count; ++k) scratch[f->idx[k]] = 0.0;
+    for (int i = 0; i < N; ++i) {
+        const double *ui = u + i * n;
+        gi[i] = 0.0;
+        mi[i] = INFINITY;
+        for (int k = 0; k < f->count; ++k) {
+            int p = f->idx[k], x = p % g->W, y = p / g->W;
+            double r = b[i * n + p] - (g->mass[p] / P->tau * ui[p] + P->eps * stiff_apply(g, ui, x, y));
+            gi[i] += f->val[k] * r;
+            double q = ui[p] / f->val[k];
+            if (q < mi[i]) mi[i] = q;
+        }
+        a[i] = gi[i] / D;
+    }
+    bounded_correction(N, a, mi, alpha);
+    /* J(u + alpha eta) - J(u); alpha is the projection of g / D onto a convex
+       set holding 0, so exactly it is at most -D |alpha|^2 / 2.  The slack
+       covers the rounding of alpha (a few ulps of |a|) times |g|. */
+    double dJ = 0.0, scale = 0.0, gs = 0.0, as = 0.0;
+    for (int i = 0; i < N; ++i) {
+        dJ += 0.5 * D * alpha[i] * alpha[i] - gi[i] * alpha[i];
+        scale += 0.5 * D * alpha[i] * alpha[i] + fabs(gi[i] * alpha[i]);
+        gs += fabs(gi[i]);
+        as += fabs(a[i]) + mi[i];
+        for (int k = 0; k < f->count; ++k) {
+            double v = u[i * n + f->idx[k]] + alpha[i] * f->val[k];
+            u[i * n + f->idx[k]] = v > 0.0 ? v : 0.0;  /* a bound met exactly may round below 0 */
+        }
+    }
+    return dJ > 1e-10 * scale + 8.0 * N * DBL_EPSILON * gs * as;
+}
+
+/*
+ * One iteration: every basis function of every level, from the coarsest level
+ * to the finest, each level's nodes in row-major order.  On the finest level
+ * the functions are the nodal ones, and the update is the projected block
+ * Gauss-Seidel update of that node.  Returns the number of updates that
+ * raised J.
+ */
+static int ssc_iteration(const grid_t *G, const basis_set *B, const orc_params *P, const double *b,
+                         double *u, double *scratch)
+{
+    int bad = 0;
+    for (int l = B->L - 1; l >= 0; --l)
+        for (int q = 0; q < B->count[l]; ++q) bad += ssc_update(&G[0], P, b, u, &B->fn[l][q], scratch);
+    return bad;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Public oracle entry points                                                */
 /* ------------------------------------------------------------------------ */
 
@@ -683,22 +892,39 @@ int orc_apply_H(const orc_params *P, const double *v, double *out)
 /*
  * Solve the step problem for a given right-hand side b, starting from u
  * (overwritten with the result).  Cycles are multigrid cycles when the
- * hierarchy has two or more levels, single Gauss-Seidel sweeps otherwise;
- * they repeat until the natural residual is <= tol or max_cycles is reached.
+ * hierarchy has two or more levels, single Gauss-Seidel sweeps otherwise, or
+ * with P->ssc the subspace-correction iterations over all levels; they repeat
+ * until the natural residual is <= tol or max_cycles is reached.
  */
 static int solve_rhs(const grid_t *G, int L, const orc_params *P, const double *b, double *u,
                      orc_stats *st)
 {
     int cycles = 0, bad = 0;
     double r;
+    basis_set B;
+    double *scratch = NULL;
+    if (P->ssc) {
+        if (basis_set_init(G, L, &B)) return -1;
+        scratch = calloc((size_t)G[0].W * G[0].H, sizeof(double));
+        if (!scratch) {
+            basis_set_free(&B);
+            return -1;
+        }
+    }
     do {
-        if (L >= 2)
+        if (P->ssc)
+            bad += ssc_iteration(G, &B, P, b, u, scratch);
+        else if (L >= 2)
             bad += mg_cycle(G, L, P, b, u);
         else
             gs_sweep(&G[0], P, b, u);
         ++cycles;
         r = natural_residual(&G[0], P, b, u);
     } while (r > P->tol && cycles < P->max_cycles);
+    if (P->ssc) {
+        basis_set_free(&B);
+        free(scratch);
+    }
     if (st) {
         st->cycles = cycles;
         st->converged = r <= P->tol;
@@ -715,9 +941,9 @@ int orc_solve_qp(const orc_params *P, const double *b, double *u, orc_stats *st)
     grid_t G[32];
     int L;
     if (hierarchy_init(P, G, &L)) return -1;
-    solve_rhs(G, L, P, b, u, st);
+    int e = solve_rhs(G, L, P, b, u, st);
     hierarchy_free(G, L);
-    return 0;
+    return e;
 }
 
 /*
@@ -1128,4 +1354,53 @@ int orc_backward_c(const orc_params *P, int steps, const double *I, const double
     free(ub2);
     grid_free(&g);
     return r;
+}
+
+/*
+ * The basis function of node q of level l seen on the finest lattice, written
+ * densely into eta ([H*W] of the finest lattice).  Returns 0, or -1.
+ */
+int orc_basis(const orc_params *P, int l, int q, double *eta)
+{
+    grid_t G[32];
+    int L;
+    if (hierarchy_init(P, G, &L)) return -1;
+    int e = -1;
+    if (l >= 0 && l < L && q >= 0 && q < G[l].W * G[l].H) {
+        basis_fn f;
+        if (!basis_build(G, l, q, &f)) {
+            memset(eta, 0, sizeof(double) * P->W * P->H);
+            for (int k = 0; k < f.count; ++k) eta[f.idx[k]] = f.val[k];
+            free(f.idx);
+            free(f.val);
+            e = 0;
+        }
+    }
+    hierarchy_free(G, L);
+    return e;
+}
+
+/*
+ * One subspace correction of u ([N][H*W], in place) along the basis function
+ * of node q of level l, for the step problem with right-hand side b.
+ * Returns 0, 1 if J rose, or -1.
+ */
+int orc_ssc_update(const orc_params *P, int l, int q, const double *b, double *u)
+{
+    grid_t G[32];
+    int L;
+    if (hierarchy_init(P, G, &L)) return -1;
+    int e = -1;
+    double *scratch = calloc((size_t)P->W * P->H, sizeof(double));
+    if (scratch && l >= 0 && l < L && q >= 0 && q < G[l].W * G[l].H) {
+        basis_fn f;
+        if (!basis_build(G, l, q, &f)) {
+            e = ssc_update(&G[0], P, b, u, &f, scratch);
+            free(f.idx);
+            free(f.val);
+        }
+    }
+    free(scratch);
+    hierarchy_free(G, L);
+    return e;
 }
