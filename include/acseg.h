@@ -98,6 +98,19 @@ typedef int32_t acseg_status;
  * few microseconds).  acseg_solve_batched always works this way.
  */
 #define ACSEG_FLAG_NO_HOST_WAIT 8u
+/*
+ * The coarse correction of a multigrid cycle (levels >= 2) is the paper's own
+ * successive subspace correction (Section "Multigrid Solution", with the
+ * constraint handling of Section "Gibbs Space Constraint Pseudocode") instead
+ * of the truncated correction: after the pre-smoothing sweeps, every basis
+ * function of every coarse level, from the coarsest level to the finest,
+ * moves u by the multiple alpha (one value per phase, summing to zero) of
+ * itself that minimises the step's objective while every node stays on its
+ * simplex, then the post-smoothing sweeps follow.  Same fixed point, usually
+ * many more cycles: a coarse function's step stops where any node of its
+ * support reaches zero.  No effect with one level.
+ */
+#define ACSEG_FLAG_SSC 16u
 
 /*
  * One segmentation problem.  Parameters follow eq. E and eq. alpha:

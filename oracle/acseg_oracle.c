@@ -910,6 +910,16 @@ static int solve_rhs(const grid_t *G, int L, const orc_params *P, const double *
             basis_set_free(&B);
             return -1;
         }
+        /* The corrections sum to zero, so they keep every node's sum: the
+           start must lie on the simplices.  A start read from float32 misses
+           them by rounding; project it node by node (a no-op on the simplices). */
+        size_t n = (size_t)G[0].W * G[0].H;
+        double yv[ORC_MAX_N], xv[ORC_MAX_N];
+        for (size_t p = 0; p < n; ++p) {
+            for (int i = 0; i < P->N; ++i) yv[i] = u[i * n + p];
+            orc_project(P->N, yv, xv);
+            for (int i = 0; i < P->N; ++i) u[i * n + p] = xv[i];
+        }
     }
     do {
         if (P->ssc)

@@ -29,6 +29,7 @@ FLAG_STORE_CHECKPOINTS = 1
 FLAG_FIXED_CYCLES = 2
 FLAG_FIXED_C = 4
 FLAG_NO_HOST_WAIT = 8
+FLAG_SSC = 16
 
 
 class _Problem(ctypes.Structure):

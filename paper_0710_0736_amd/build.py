@@ -11,7 +11,7 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libacseg.so")
 
 SOURCES = ["kernels_fine.hip", "kernels_cycle.hip", "kernels_mg.hip", "kernels_adjoint.hip",
-           "kernels_data.hip", "acseg_api.hip"] + [
+           "kernels_data.hip", "kernels_ssc.hip", "acseg_api.hip"] + [
     f"cycle_n{n}.hip" for n in range(2, 9)]
 
 HIPCC_FLAGS = [

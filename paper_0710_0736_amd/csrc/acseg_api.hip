@@ -82,7 +82,7 @@ acseg_status validate(const acseg_problem* p, bool need_steps) {
     const int L = p->levels == 0 ? auto_levels(p->W, p->H) : p->levels;
     if (L >= 2 && (p->nu_pre < 1 || p->nu_post < 1)) return ACSEG_ERR_UNSUPPORTED;
     if ((p->flags & ~(ACSEG_FLAG_STORE_CHECKPOINTS | ACSEG_FLAG_FIXED_CYCLES | ACSEG_FLAG_FIXED_C |
-                      ACSEG_FLAG_NO_HOST_WAIT)) != 0u)
+                      ACSEG_FLAG_NO_HOST_WAIT | ACSEG_FLAG_SSC)) != 0u)
         return ACSEG_ERR_INVALID_ARG;
     return ACSEG_OK;
 }
@@ -363,6 +363,33 @@ acseg_status enqueue_correction(acseg_ctx* ctx, const acseg_problem* p, const Mg
     return ACSEG_OK;
 }
 
+// The subspace correction over the basis functions of the coarse levels,
+// coarsest first, four parity classes per level (in place on the iterate left
+// by `launch` smoothing launches of the current step).
+acseg_status enqueue_ssc(acseg_ctx* ctx, const acseg_problem* p, const MgPlan& m, const Layout& L,
+                         void* ws, Bufs bufs, int slot, bool fixed, int launch, hipStream_t s) {
+    SscArgs a{};
+    a.bufs = bufs;
+    a.ctl = at<Ctl>(ws, L.ctl);
+    a.rhs = at<float>(ws, L.rhs);
+    a.coef = m.coef[0];
+    a.W = m.W[0];
+    a.H = m.H[0];
+    a.slot = slot;
+    a.fixed = fixed ? 1 : 0;
+    a.launch = launch;
+    for (int l = m.L - 1; l >= 1; --l) {
+        a.Wc = m.W[l];
+        a.Hc = m.H[l];
+        a.sh = l;
+        for (int c = 0; c < 4; ++c) {
+            a.colour = c;
+            ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_ssc(p->N, a, s); }));
+        }
+    }
+    return ACSEG_OK;
+}
+
 // Enqueue time step n on the iterate bufs[ctl->cur] whose reduced colour-mean
 // sums are in `tot`: max_cycles smoothing cycles (after convergence they exit
 // at once unless the schedule is fixed), then the step's end, which leaves the
@@ -442,7 +469,10 @@ acseg_status enqueue_step(acseg_ctx* ctx, const acseg_problem* p, const Coefs& c
         }
         const CycleRole pre{k == 0, true, false};
         ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] { return launch_cycle(p->N, p->C, p->nu_pre, a, st, single, pre, s); }));
-        const acseg_status v = enqueue_correction(ctx, p, m, L, ws, bufs, st.slot, sc.fixed, k * sc.lpc + sc.lpre, s);
+        const acseg_status v =
+            (p->flags & ACSEG_FLAG_SSC) != 0u
+                ? enqueue_ssc(ctx, p, m, L, ws, bufs, st.slot, sc.fixed, k * sc.lpc + sc.lpre, s)
+                : enqueue_correction(ctx, p, m, L, ws, bufs, st.slot, sc.fixed, k * sc.lpc + sc.lpre, s);
         if (v != ACSEG_OK) return v;
         st.launch = k * sc.lpc + sc.lpre;
         const CycleRole post{false, false, true};

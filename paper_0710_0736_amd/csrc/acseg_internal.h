@@ -243,6 +243,22 @@ struct TailArgs {
     int slot, fixed;
 };
 
+// One launch of the subspace correction over the basis functions of one coarse
+// level: level lattice Wc x Hc, spacing 2^sh finest nodes, the functions whose
+// node (X, Y) has X % 2 == colour & 1 and Y % 2 == colour >> 1.  In place on
+// the iterate left by `launch` smoothing launches of the step.
+struct SscArgs {
+    Bufs bufs;
+    const Ctl* ctl;
+    const float* rhs;   // stored right-hand side [N][H][W]
+    LevelCoef coef;     // finest level
+    int W, H;
+    int Wc, Hc, sh, colour;
+    int slot, fixed, launch;
+};
+
+hipError_t launch_ssc(int N, const SscArgs& a, hipStream_t s);
+
 int mg_blocks(int W, int H);
 hipError_t launch_mg_fine(int N, int op, const MgArgs& a, hipStream_t s);
 hipError_t launch_mg_coarse(int N, int op, const CoarseArgs& a, hipStream_t s);
