@@ -305,6 +305,8 @@ def main():
                     help="fixed cycles per time step without a calibration solve (0: calibrate)")
     ap.add_argument("--nu", type=int, nargs=2, default=(1, 1), metavar=("PRE", "POST"),
                     help="smoothing sweeps before / after the coarse correction")
+    ap.add_argument("--ssc", action="store_true",
+                    help="coarse correction = the paper's subspace correction over all basis functions")
     ap.add_argument("--adjoint", action="store_true",
                     help="only time a forward solve with checkpoints and the backward pass "
                          "(voronoi512_n4: 512^2, N = 4, 20 steps)")
@@ -369,8 +371,9 @@ def main():
     us = [torch.empty_like(u0) for u0 in u0s]
     img, u0, u = imgs[0], u0s[0], us[0]
 
+    ssc_flag = acseg.FLAG_SSC if args.ssc else 0
     base = acseg.Problem.from_workload(w, C=C, levels=args.levels, nu_pre=args.nu[0],
-                                       nu_post=args.nu[1], max_cycles=args.max_cycles)
+                                       nu_post=args.nu[1], max_cycles=args.max_cycles, flags=ssc_flag)
 
     # consistent-mass fitting: the solver runs on M I / m, computed per segmentation
     # into a fixed buffer per image
@@ -386,7 +389,7 @@ def main():
         cycles = max(cycles, st["cycles_max"])
     if args.schedule == "fixed":
         prob = acseg.Problem(**{**base.__dict__, "max_cycles": cycles,
-                                "flags": acseg.FLAG_FIXED_CYCLES})
+                                "flags": acseg.FLAG_FIXED_CYCLES | ssc_flag})
     else:
         prob = base
     log(f"[bench] {w.name}: {w.W}x{w.H} N={w.N} C={C} steps={w.steps} tol={w.tol} "
@@ -496,10 +499,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name + ("_consistent_mass" if args.consistent_mass else ""), "batch": B,
+        "config": {"workload": w.name + ("_consistent_mass" if args.consistent_mass else "")
+                               + ("_ssc" if args.ssc and prob.levels != 1 else ""), "batch": B,
                    "W": w.W, "H": w.H, "N": w.N, "C": C,
                    "time_steps": w.steps, "lambda": w.lam, "h": w.h, "eps": w.eps, "tau": w.tau,
                    "tol": w.tol, "levels": prob.levels, "sweeps_per_cycle": prob.nu_pre + prob.nu_post,
+                   "coarse_correction": ("subspace correction" if args.ssc else "truncated") if prob.levels != 1 else None,
                    "schedule": args.schedule, "cycles_per_step_max": cycles,
                    "cycles_total": st_run["cycles_total"], "final_residual": st_run["final_residual"]},
         "roofline": roof,

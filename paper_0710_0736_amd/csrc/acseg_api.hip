@@ -366,6 +366,8 @@ acseg_status enqueue_correction(acseg_ctx* ctx, const acseg_problem* p, const Mg
 // The subspace correction over the basis functions of the coarse levels,
 // coarsest first, four parity classes per level (in place on the iterate left
 // by `launch` smoothing launches of the current step).
+constexpr int kSscChunkLevel = 5;     // levels from which a support spans several workgroups
+constexpr int kSscChunkNodes = 2048;  // box nodes per chunk
 acseg_status enqueue_ssc(acseg_ctx* ctx, const acseg_problem* p, const MgPlan& m, const Layout& L,
                          void* ws, Bufs bufs, int slot, bool fixed, int launch, hipStream_t s) {
     SscArgs a{};
@@ -378,10 +380,19 @@ acseg_status enqueue_ssc(acseg_ctx* ctx, const acseg_problem* p, const MgPlan& m
     a.slot = slot;
     a.fixed = fixed ? 1 : 0;
     a.launch = launch;
+    // chunked two-launch form where supports are large; the partials go to the
+    // truncated correction's defect buffer, unused by this correction
+    double* part = at<double>(ws, L.mg_gt);
+    const size_t part_cap = sizeof(float) * (size_t)p->N * m.W[0] * m.H[0] / ((2 * p->N + 1) * sizeof(double));
     for (int l = m.L - 1; l >= 1; --l) {
         a.Wc = m.W[l];
         a.Hc = m.H[l];
         a.sh = l;
+        const int side = (2 << l) - 1;  // box side of an interior function
+        a.rows = std::max(1, kSscChunkNodes / side);
+        a.chunks = (side + a.rows - 1) / a.rows;
+        const size_t items = (size_t)((a.Wc + 1) / 2) * ((a.Hc + 1) / 2) * a.chunks;
+        a.part = (l >= kSscChunkLevel && items <= part_cap) ? part : nullptr;
         for (int c = 0; c < 4; ++c) {
             a.colour = c;
             ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_ssc(p->N, a, s); }));

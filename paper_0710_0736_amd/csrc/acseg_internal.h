@@ -246,7 +246,8 @@ struct TailArgs {
 // One launch of the subspace correction over the basis functions of one coarse
 // level: level lattice Wc x Hc, spacing 2^sh finest nodes, the functions whose
 // node (X, Y) has X % 2 == colour & 1 and Y % 2 == colour >> 1.  In place on
-// the iterate left by `launch` smoothing launches of the step.
+// the iterate left by `launch` smoothing launches of the step.  With `part`
+// the supports are cut into chunks of `rows` box rows over two launches.
 struct SscArgs {
     Bufs bufs;
     const Ctl* ctl;
@@ -255,6 +256,8 @@ struct SscArgs {
     int W, H;
     int Wc, Hc, sh, colour;
     int slot, fixed, launch;
+    double* part;       // non-NULL: two launches, per-chunk partials [functions * chunks][2N+1]
+    int rows, chunks;   // box rows per chunk, chunks per function
 };
 
 hipError_t launch_ssc(int N, const SscArgs& a, hipStream_t s);

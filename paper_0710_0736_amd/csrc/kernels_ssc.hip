@@ -19,8 +19,12 @@
 // least two finest nodes apart, so no node of one is a 5-point neighbour of a
 // node of the other: the four parity classes of (X, Y) are four launches, and
 // the functions of one launch update in place without touching each other's
-// reads.  One workgroup per function; its threads stride over the support's
-// bounding box, reduce, and every thread applies the same alpha.
+// reads.  One workgroup per function: its threads stride over the support's
+// bounding box, reduce, and every thread applies the same alpha.  On the
+// coarsest levels a class holds few functions with large supports, so there a
+// function's box is cut into chunks of rows: one launch writes each chunk's
+// partial sums, a second one recomputes alpha from all partials of the
+// function (the same order in every workgroup) and updates the chunk.
 //
 // Units as the multigrid path: the level is scaled by 1/h^2 of the finest
 // spacing, the residual is D_p (y_p - u_p) with y_p the smoother's nodal map,
@@ -80,27 +84,154 @@ __device__ __forceinline__ void project_scaled(float (&v)[N], float M) {
     for (int i = 0; i < N; ++i) v[i] = fmaxf(v[i] - thr, 0.f);
 }
 
+// Function f of the launch's parity class and the bounding box of its support.
+struct FunBox {
+    int X, Y, x0, x1, y0, y1, bw;
+};
+
+__device__ __forceinline__ int class_count_x(const SscArgs& a) { return (a.Wc - (a.colour & 1) + 1) >> 1; }
+__device__ __forceinline__ int class_count(const SscArgs& a) {
+    return class_count_x(a) * ((a.Hc - (a.colour >> 1) + 1) >> 1);
+}
+
+__device__ __forceinline__ FunBox fun_box(const SscArgs& a, int f) {
+    const int nx = class_count_x(a), fy = f / nx, sh = a.sh;
+    FunBox b;
+    b.X = (a.colour & 1) + 2 * (f - fy * nx);
+    b.Y = (a.colour >> 1) + 2 * fy;
+    b.x0 = max(0, ((b.X - 1) << sh) + 1);
+    b.x1 = min(a.W - 1, ((b.X + 1) << sh) - 1);
+    b.y0 = max(0, ((b.Y - 1) << sh) + 1);
+    b.y1 = min(a.H - 1, ((b.Y + 1) << sh) - 1);
+    b.bw = b.x1 - b.x0 + 1;
+    return b;
+}
+
+__device__ __forceinline__ float* iterate_of(const SscArgs& a) {
+    return const_cast<float*>(a.bufs.b[__builtin_amdgcn_readfirstlane(iterate_buf(a.ctl->cur, a.launch))]);
+}
+
+// A lane's share (box nodes t0, t0 + stride, ...) of g, Q = eta.H eta and m
+// over box rows [ya, yb].
+template <int N>
+__device__ __forceinline__ void accumulate(const SscArgs& a, const float* u, const FunBox& b, int ya, int yb,
+                                           double (&g)[N], double& q, float (&m)[N], int t0, int stride) {
+    const int W = a.W, H = a.H, sh = a.sh, Wc = a.Wc, Hc = a.Hc;
+    const uint32_t n = (uint32_t)W * (uint32_t)H;
+    const float inv_s = 1.f / (float)(1 << sh);
+    const int nbox = b.bw * (yb - ya + 1);
+    for (int k = t0; k < nbox; k += stride) {
+        const int yy = k / b.bw;
+        const int y = ya + yy, x = b.x0 + (k - yy * b.bw);
+        const float e = hat_at(x, y, b.X, b.Y, sh, Wc, Hc, inv_s);
+        if (e <= 0.f) continue;
+        const int cls = node_class(x, y, W, H);
+        const float D = sel4(a.coef.d, cls), kap = sel4(a.coef.kappa, cls);
+        const float wh = edge_w_h(y, H), wv = edge_w_v(x, W);
+        const float ne = wh * ((x > 0 ? hat_at(x - 1, y, b.X, b.Y, sh, Wc, Hc, inv_s) : 0.f) +
+                               (x < W - 1 ? hat_at(x + 1, y, b.X, b.Y, sh, Wc, Hc, inv_s) : 0.f)) +
+                         wv * ((y > 0 ? hat_at(x, y - 1, b.X, b.Y, sh, Wc, Hc, inv_s) : 0.f) +
+                               (y < H - 1 ? hat_at(x, y + 1, b.X, b.Y, sh, Wc, Hc, inv_s) : 0.f));
+        q += (double)e * (double)(D * e - a.coef.e2 * ne);
+        const uint32_t p = (uint32_t)y * (uint32_t)W + (uint32_t)x;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const float* ui = u + (size_t)i * n;
+            const float uc = gload(ui, p);
+            const float nb = wh * ((x > 0 ? gload(ui, p - 1) : 0.f) + (x < W - 1 ? gload(ui, p + 1) : 0.f)) +
+                             wv * ((y > 0 ? gload(ui, p - W) : 0.f) + (y < H - 1 ? gload(ui, p + W) : 0.f));
+            const float yv = gload(a.rhs + (size_t)i * n, p) + kap * nb;
+            g[i] += (double)e * (double)(D * (yv - uc));
+            m[i] = fminf(m[i], uc / e);
+        }
+    }
+}
+
+// Workgroup reduction in a fixed order; every thread returns the same sums.
+template <int N, int T>
+__device__ __forceinline__ void reduce(double (&g)[N], double& q, float (&m)[N], double (*sh_g)[N + 1],
+                                       float (*sh_m)[N]) {
+    constexpr int kW = T / kWave;
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    q = wave_sum(q);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        g[i] = wave_sum(g[i]);
+        m[i] = wave_min_f(m[i]);
+    }
+    if (lane == 0) {
+        sh_g[wid][N] = q;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            sh_g[wid][i] = g[i];
+            sh_m[wid][i] = m[i];
+        }
+    }
+    __syncthreads();
+    q = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        g[i] = 0.0;
+        m[i] = INFINITY;
+    }
+    for (int w = 0; w < kW; ++w) {
+        q += sh_g[w][N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            g[i] += sh_g[w][i];
+            m[i] = fminf(m[i], sh_m[w][i]);
+        }
+    }
+    __syncthreads();  // the shared partials are reused
+}
+
+// alpha from the reduced sums; false when only alpha = 0 is feasible.
+template <int N>
+__device__ __forceinline__ bool step_of(const double (&g)[N], double q, const float (&m)[N], float (&al)[N]) {
+    float M = 0.f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        al[i] = (float)(g[i] / q) + m[i];
+        M += m[i];
+    }
+    if (!(M > 0.f) || !(q > 0.0)) return false;
+    project_scaled<N>(al, M);
+#pragma unroll
+    for (int i = 0; i < N; ++i) al[i] -= m[i];
+    return true;
+}
+
+// u += alpha eta over box rows [ya, yb] (a lane's share, as in accumulate).
+template <int N>
+__device__ __forceinline__ void apply(const SscArgs& a, float* u, const FunBox& b, int ya, int yb,
+                                      const float (&al)[N], int t0, int stride) {
+    const uint32_t n = (uint32_t)a.W * (uint32_t)a.H;
+    const float inv_s = 1.f / (float)(1 << a.sh);
+    const int nbox = b.bw * (yb - ya + 1);
+    for (int k = t0; k < nbox; k += stride) {
+        const int yy = k / b.bw;
+        const int y = ya + yy, x = b.x0 + (k - yy * b.bw);
+        const float e = hat_at(x, y, b.X, b.Y, a.sh, a.Wc, a.Hc, inv_s);
+        if (e <= 0.f) continue;
+        const uint32_t p = (uint32_t)y * (uint32_t)a.W + (uint32_t)x;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            float* ui = u + (size_t)i * n;
+            gstore(ui, p, fmaxf(fmaf(al[i], e, gload(ui, p)), 0.f));  // a bound met exactly may round below 0
+        }
+    }
+}
+
+// One workgroup per function: sums, alpha and update in one launch.
 template <int N, int T>
 __global__ __launch_bounds__(T) void k_ssc(SscArgs a) {
-    constexpr int kW = T / kWave;
-    __shared__ double sh_g[kW][N + 1];
-    __shared__ float sh_m[kW][N];
+    __shared__ double sh_g[T / kWave][N + 1];
+    __shared__ float sh_m[T / kWave][N];
     if (!a.fixed && a.ctl->step[a.slot].done) return;
-    float* u = const_cast<float*>(a.bufs.b[__builtin_amdgcn_readfirstlane(iterate_buf(a.ctl->cur, a.launch))]);
-    const int W = a.W, H = a.H, Wc = a.Wc, Hc = a.Hc, sh = a.sh;
-    const uint32_t n = (uint32_t)W * (uint32_t)H;
-    const int s = 1 << sh;
-    const float inv_s = 1.f / (float)s;
-    const int cx = a.colour & 1, cy = a.colour >> 1;
-    const int nx = (Wc - cx + 1) >> 1, ny = (Hc - cy + 1) >> 1;
-    const int nfun = nx * ny;
-    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    float* u = iterate_of(a);
+    const int nfun = class_count(a);
     for (int f = blockIdx.x; f < nfun; f += gridDim.x) {
-        const int fy = f / nx;
-        const int X = cx + 2 * (f - fy * nx), Y = cy + 2 * fy;
-        const int x0 = max(0, ((X - 1) << sh) + 1), x1 = min(W - 1, ((X + 1) << sh) - 1);
-        const int y0 = max(0, ((Y - 1) << sh) + 1), y1 = min(H - 1, ((Y + 1) << sh) - 1);
-        const int bw = x1 - x0 + 1, nbox = bw * (y1 - y0 + 1);
+        const FunBox b = fun_box(a, f);
         double g[N], q = 0.0;
         float m[N];
 #pragma unroll
@@ -108,84 +239,126 @@ __global__ __launch_bounds__(T) void k_ssc(SscArgs a) {
             g[i] = 0.0;
             m[i] = INFINITY;
         }
-        for (int k = threadIdx.x; k < nbox; k += T) {
-            const int yy = k / bw;
-            const int y = y0 + yy, x = x0 + (k - yy * bw);
-            const float e = hat_at(x, y, X, Y, sh, Wc, Hc, inv_s);
-            if (e <= 0.f) continue;
-            const int cls = node_class(x, y, W, H);
-            const float D = sel4(a.coef.d, cls), kap = sel4(a.coef.kappa, cls);
-            const float wh = edge_w_h(y, H), wv = edge_w_v(x, W);
-            const float ne = wh * ((x > 0 ? hat_at(x - 1, y, X, Y, sh, Wc, Hc, inv_s) : 0.f) +
-                                   (x < W - 1 ? hat_at(x + 1, y, X, Y, sh, Wc, Hc, inv_s) : 0.f)) +
-                             wv * ((y > 0 ? hat_at(x, y - 1, X, Y, sh, Wc, Hc, inv_s) : 0.f) +
-                                   (y < H - 1 ? hat_at(x, y + 1, X, Y, sh, Wc, Hc, inv_s) : 0.f));
-            q += (double)e * (double)(D * e - a.coef.e2 * ne);
-            const uint32_t p = (uint32_t)y * (uint32_t)W + (uint32_t)x;
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const float* ui = u + (size_t)i * n;
-                const float uc = gload(ui, p);
-                const float nb = wh * ((x > 0 ? gload(ui, p - 1) : 0.f) + (x < W - 1 ? gload(ui, p + 1) : 0.f)) +
-                                 wv * ((y > 0 ? gload(ui, p - W) : 0.f) + (y < H - 1 ? gload(ui, p + W) : 0.f));
-                const float yv = gload(a.rhs + (size_t)i * n, p) + kap * nb;
-                g[i] += (double)e * (double)(D * (yv - uc));
-                m[i] = fminf(m[i], uc / e);
-            }
-        }
-        // workgroup reduction in a fixed order: every thread gets the same sums
-        q = wave_sum(q);
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            g[i] = wave_sum(g[i]);
-            m[i] = wave_min_f(m[i]);
-        }
-        if (lane == 0) {
-            sh_g[wid][N] = q;
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                sh_g[wid][i] = g[i];
-                sh_m[wid][i] = m[i];
-            }
-        }
-        __syncthreads();
-        q = 0.0;
+        accumulate<N>(a, u, b, b.y0, b.y1, g, q, m, threadIdx.x, T);
+        reduce<N, T>(g, q, m, sh_g, sh_m);
+        float al[N];
+        if (!step_of<N>(g, q, m, al)) continue;
+        apply<N>(a, u, b, b.y0, b.y1, al, threadIdx.x, T);
+    }
+}
+
+// Large supports, two launches.  Item = (function, chunk of a.rows box rows),
+// a.chunks chunks per function.  Partials per item: g[N], Q, m[N] (doubles).
+template <int N, int T>
+__global__ __launch_bounds__(T) void k_ssc_part(SscArgs a) {
+    __shared__ double sh_g[T / kWave][N + 1];
+    __shared__ float sh_m[T / kWave][N];
+    if (!a.fixed && a.ctl->step[a.slot].done) return;
+    const float* u = iterate_of(a);
+    const int items = class_count(a) * a.chunks;
+    for (int it = blockIdx.x; it < items; it += gridDim.x) {
+        const int f = it / a.chunks, ch = it - f * a.chunks;
+        const FunBox b = fun_box(a, f);
+        const int ya = b.y0 + ch * a.rows, yb = min(b.y1, ya + a.rows - 1);
+        double g[N], q = 0.0;
+        float m[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             g[i] = 0.0;
             m[i] = INFINITY;
         }
-        for (int w = 0; w < kW; ++w) {
-            q += sh_g[w][N];
+        if (ya <= yb) accumulate<N>(a, u, b, ya, yb, g, q, m, threadIdx.x, T);
+        reduce<N, T>(g, q, m, sh_g, sh_m);
+        if (threadIdx.x == 0) {
+            double* o = a.part + (size_t)it * (2 * N + 1);
 #pragma unroll
             for (int i = 0; i < N; ++i) {
-                g[i] += sh_g[w][i];
-                m[i] = fminf(m[i], sh_m[w][i]);
+                o[i] = g[i];
+                o[N + 1 + i] = (double)m[i];
             }
+            o[N] = q;
         }
-        __syncthreads();  // the shared partials are reused by the next function
-        float al[N], M = 0.f;
+    }
+}
+
+template <int N, int T>
+__global__ __launch_bounds__(T) void k_ssc_apply(SscArgs a) {
+    if (!a.fixed && a.ctl->step[a.slot].done) return;
+    float* u = iterate_of(a);
+    const int items = class_count(a) * a.chunks;
+    for (int it = blockIdx.x; it < items; it += gridDim.x) {
+        const int f = it / a.chunks, ch = it - f * a.chunks;
+        const FunBox b = fun_box(a, f);
+        const int ya = b.y0 + ch * a.rows, yb = min(b.y1, ya + a.rows - 1);
+        if (ya > yb) continue;
+        double g[N], q = 0.0;
+        float m[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            al[i] = (float)(g[i] / q) + m[i];
-            M += m[i];
+            g[i] = 0.0;
+            m[i] = INFINITY;
         }
-        if (!(M > 0.f) || !(q > 0.0)) continue;  // only alpha = 0 is feasible
-        project_scaled<N>(al, M);
-#pragma unroll
-        for (int i = 0; i < N; ++i) al[i] -= m[i];
-        for (int k = threadIdx.x; k < nbox; k += T) {
-            const int yy = k / bw;
-            const int y = y0 + yy, x = x0 + (k - yy * bw);
-            const float e = hat_at(x, y, X, Y, sh, Wc, Hc, inv_s);
-            if (e <= 0.f) continue;
-            const uint32_t p = (uint32_t)y * (uint32_t)W + (uint32_t)x;
+        const double* o = a.part + (size_t)f * a.chunks * (2 * N + 1);
+        for (int c = 0; c < a.chunks; ++c, o += 2 * N + 1) {  // the function's chunks in order
+            q += o[N];
 #pragma unroll
             for (int i = 0; i < N; ++i) {
-                float* ui = u + (size_t)i * n;
-                gstore(ui, p, fmaxf(fmaf(al[i], e, gload(ui, p)), 0.f));  // a bound met exactly may round below 0
+                g[i] += o[i];
+                m[i] = fminf(m[i], (float)o[N + 1 + i]);
             }
         }
+        float al[N];
+        if (!step_of<N>(g, q, m, al)) continue;
+        apply<N>(a, u, b, ya, yb, al, threadIdx.x, T);
+    }
+}
+
+// Small supports: G lanes per function (G divides the wave), 256 / G functions
+// per workgroup, reduced by xor butterflies within the lane group (each lane
+// ends with the same sums: IEEE addition is commutative).  The loop over
+// functions is uniform across the workgroup so every lane takes part in the
+// shuffles; lanes past the last function only contribute zeros.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+template <int G>
+__device__ __forceinline__ float group_min(float v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+template <int N, int G>
+__global__ __launch_bounds__(256) void k_ssc_small(SscArgs a) {
+    constexpr int kPer = 256 / G;
+    if (!a.fixed && a.ctl->step[a.slot].done) return;
+    float* u = iterate_of(a);
+    const int nfun = class_count(a);
+    const int grp = threadIdx.x / G, gl = threadIdx.x % G;
+    for (int f0 = blockIdx.x * kPer; f0 < nfun; f0 += gridDim.x * kPer) {
+        const int f = f0 + grp;
+        const bool valid = f < nfun;
+        const FunBox b = fun_box(a, valid ? f : f0);
+        double g[N], q = 0.0;
+        float m[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            g[i] = 0.0;
+            m[i] = INFINITY;
+        }
+        if (valid) accumulate<N>(a, u, b, b.y0, b.y1, g, q, m, gl, G);
+        q = group_sum<G>(q);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            g[i] = group_sum<G>(g[i]);
+            m[i] = group_min<G>(m[i]);
+        }
+        float al[N];
+        if (!valid || !step_of<N>(g, q, m, al)) continue;
+        apply<N>(a, u, b, b.y0, b.y1, al, gl, G);
     }
 }
 
@@ -194,13 +367,27 @@ hipError_t ssc_launch(const SscArgs& a, hipStream_t s) {
     const int cx = a.colour & 1, cy = a.colour >> 1;
     const int nfun = ((a.Wc - cx + 1) >> 1) * ((a.Hc - cy + 1) >> 1);
     if (nfun <= 0) return hipSuccess;
-    const int blocks = std::min(nfun, 1 << 20);
-    if (a.sh <= 2)
-        hipLaunchKernelGGL((k_ssc<N, 64>), dim3(blocks), dim3(64), 0, s, a);
-    else if (a.sh <= 4)
-        hipLaunchKernelGGL((k_ssc<N, 256>), dim3(blocks), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_ssc<N, 1024>), dim3(blocks), dim3(1024), 0, s, a);
+    if (a.part) {
+        const int items = nfun * a.chunks;
+        const int blocks = std::min(items, 1 << 20);
+        hipLaunchKernelGGL((k_ssc_part<N, 256>), dim3(blocks), dim3(256), 0, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_ssc_apply<N, 256>), dim3(blocks), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+    // box side 2^(sh+1) - 1: 3, 7, 15 nodes for sh = 1, 2, 3
+    if (a.sh == 1) {
+        hipLaunchKernelGGL((k_ssc_small<N, 16>), dim3(std::min((nfun + 15) / 16, 1 << 20)), dim3(256), 0, s, a);
+    } else if (a.sh <= 3) {
+        hipLaunchKernelGGL((k_ssc_small<N, 64>), dim3(std::min((nfun + 3) / 4, 1 << 20)), dim3(256), 0, s, a);
+    } else {
+        const int blocks = std::min(nfun, 1 << 20);
+        if (a.sh == 4)
+            hipLaunchKernelGGL((k_ssc<N, 256>), dim3(blocks), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_ssc<N, 1024>), dim3(blocks), dim3(1024), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -20,8 +20,9 @@ from test_gpu_parity import GATE_U, GPU_TOL, check_step, cuda, gpu_problem, host
 pytestmark = pytest.mark.gpu
 
 
+# (520, 40): six levels, so level 5's supports run in chunks over two launches
 @pytest.mark.parametrize("W,H,N,levels,seed", [(96, 80, 4, 0, 1), (77, 130, 3, 3, 2), (64, 64, 2, 0, 3),
-                                               (90, 70, 6, 2, 4), (45, 33, 8, 0, 5)])
+                                               (90, 70, 6, 2, 4), (45, 33, 8, 0, 5), (520, 40, 3, 0, 7)])
 def test_ssc_step_parity_pixel_units(W, H, N, levels, seed):
     base = synth.pixel_twin(synth.VORONOI1024).scaled(W, H, N=N)
     img, u0, _ = base.make(seed)
