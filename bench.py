@@ -305,6 +305,8 @@ def main():
                     help="fixed cycles per time step without a calibration solve (0: calibrate)")
     ap.add_argument("--nu", type=int, nargs=2, default=(1, 1), metavar=("PRE", "POST"),
                     help="smoothing sweeps before / after the coarse correction")
+    ap.add_argument("--vcycle-levels", type=int, default=8,
+                    help="also time the workload with this many multigrid levels, one image per call (0: skip)")
     ap.add_argument("--ssc", action="store_true",
                     help="coarse correction = the paper's subspace correction over all basis functions")
     ap.add_argument("--adjoint", action="store_true",
@@ -427,6 +429,33 @@ def main():
     else:
         elapsed = elapsed_plain
 
+    # the configuration's own hierarchy (config text: 8-level V-cycles), one image per
+    # call, timed beside the headline: same converged steps, a coarse correction per cycle
+    vcycle = None
+    if args.vcycle_levels and prob.levels == 1 and not args.pixel_units:
+        pv = acseg.Problem(**{**base.__dict__, "levels": args.vcycle_levels, "max_cycles": args.max_cycles})
+        u.copy_(u0)
+        _, _, stv, _ = acseg.solve(pv, prep(img), u)
+        if stv["status"] != acseg.OK:
+            raise RuntimeError(f"V-cycle calibration did not converge: {stv}")
+        pvf = acseg.Problem(**{**pv.__dict__, "max_cycles": stv["cycles_max"],
+                               "flags": acseg.FLAG_FIXED_CYCLES | ssc_flag})
+
+        def segment_v():
+            u.copy_(u0)
+            _, c, _, _ = acseg.solve(pvf, prep(img), u, want_stats=False)
+            return acseg.labels(pvf, u, c)
+
+        tv = timed(segment_v, args.steps)
+        u.copy_(u0)
+        _, _, stv2, _ = acseg.solve(pvf, prep(img), u)
+        if stv2["status"] != acseg.OK:
+            raise RuntimeError(f"V-cycle schedule did not converge: {stv2}")
+        vcycle = {"levels": args.vcycle_levels, "value": round(args.steps / tv, 3), "unit": "segmentations/s",
+                  "ms_per_segmentation": round(tv / args.steps * 1e3, 4), "batch": 1,
+                  "cycles_per_step_max": stv["cycles_max"], "final_residual": stv2["final_residual"]}
+        log(f"[bench] {args.vcycle_levels}-level V-cycles, one image per call: {args.steps} segmentations in {tv:.4f} s")
+
     # the timed schedule converges: check it once with statistics
     u.copy_(u0)
     _, _, st_run, _ = acseg.solve(prob, prep(img), u)
@@ -509,6 +538,7 @@ def main():
                    "cycles_total": st_run["cycles_total"], "final_residual": st_run["final_residual"]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "vcycle": vcycle,
     }
     # absolute smoothing rate: full-image red-black sweeps of the finest lattice per
     # second (and the node updates they make)
