@@ -77,7 +77,8 @@ typedef int32_t acseg_status;
  * With this flag and stats == NULL, acseg_solve enqueues only kernels and
  * device-to-device copies on its stream (no host reads, no memsets), so the
  * call can be captured in a HIP graph and replayed.  acseg_solve_batched
- * uploads host-built descriptor tables on every call and is not capturable.
+ * uploads host-built descriptor tables on every call; with
+ * ACSEG_FLAG_REUSE_TABLES it does not, and is capturable too.
  */
 #define ACSEG_FLAG_FIXED_CYCLES 2u
 /*
@@ -111,6 +112,17 @@ typedef int32_t acseg_status;
  * support reaches zero.  No effect with one level.
  */
 #define ACSEG_FLAG_SSC 16u
+/*
+ * acseg_solve_batched only: the workspace already holds the descriptor tables
+ * of an earlier acseg_solve_batched call with the same B, problems (flags
+ * aside), images, us, c_outs and workspace, and nothing has written to the
+ * workspace's table region since; the call then builds no tables on the device
+ * side and uploads nothing.  With ACSEG_FLAG_FIXED_CYCLES as well and stats ==
+ * NULL, the call enqueues kernels only and can be captured in a HIP graph.  The
+ * caller is responsible for the precondition: stale tables point the kernels
+ * at the earlier call's arrays.  Ignored by the other entry points.
+ */
+#define ACSEG_FLAG_REUSE_TABLES 32u
 
 /*
  * One segmentation problem.  Parameters follow eq. E and eq. alpha:

@@ -30,6 +30,7 @@ FLAG_FIXED_CYCLES = 2
 FLAG_FIXED_C = 4
 FLAG_NO_HOST_WAIT = 8
 FLAG_SSC = 16
+FLAG_REUSE_TABLES = 32
 
 
 class _Problem(ctypes.Structure):
@@ -355,14 +356,21 @@ def batch_workspace_size(problems) -> int:
 
 
 def solve_batched(problems, images, us, want_stats: bool = True, c_out: bool = True,
-                  c_fixed=None):
+                  c_fixed=None, cs=None, reuse_tables: bool = False):
     """One time loop over independent images; every ``us[b]`` is overwritten.
 
     Returns (us, cs (list of [N][C] or None), stats (list) or None).  With
     ``c_fixed`` (a list of [N][C]) every step of image b uses c_fixed[b].
+    ``cs`` (a list of [N][C]) receives the means instead of new tensors.  With
+    ``reuse_tables`` the workspace keeps the descriptor tables of the previous
+    call, which must have had the same problems, images, us and cs
+    (FLAG_REUSE_TABLES); with a fixed schedule and ``want_stats=False`` the call
+    can then be captured in a CUDA graph.
     """
     if c_fixed is not None:
         problems = [replace(p, flags=p.flags | FLAG_FIXED_C) for p in problems]
+    if reuse_tables:
+        problems = [replace(p, flags=p.flags | FLAG_REUSE_TABLES) for p in problems]
     B = len(problems)
     if not (len(images) == len(us) == B) or B == 0:
         raise ValueError("need one image and one field per problem")
@@ -374,6 +382,10 @@ def solve_batched(problems, images, us, want_stats: bool = True, c_out: bool = T
         cs = list(c_fixed)
         for p, c in zip(problems, cs):
             _need(c, (p.N, p.C), name="c_fixed")
+        c_out = True
+    elif cs is not None:
+        for p, c in zip(problems, cs):
+            _need(c, (p.N, p.C), name="cs")
         c_out = True
     else:
         cs = [torch.empty((p.N, p.C), dtype=torch.float32, device=dev) for p in problems] if c_out else None

@@ -82,7 +82,7 @@ acseg_status validate(const acseg_problem* p, bool need_steps) {
     const int L = p->levels == 0 ? auto_levels(p->W, p->H) : p->levels;
     if (L >= 2 && (p->nu_pre < 1 || p->nu_post < 1)) return ACSEG_ERR_UNSUPPORTED;
     if ((p->flags & ~(ACSEG_FLAG_STORE_CHECKPOINTS | ACSEG_FLAG_FIXED_CYCLES | ACSEG_FLAG_FIXED_C |
-                      ACSEG_FLAG_NO_HOST_WAIT | ACSEG_FLAG_SSC)) != 0u)
+                      ACSEG_FLAG_NO_HOST_WAIT | ACSEG_FLAG_SSC | ACSEG_FLAG_REUSE_TABLES)) != 0u)
         return ACSEG_ERR_INVALID_ARG;
     return ACSEG_OK;
 }
@@ -902,18 +902,29 @@ acseg_status acseg_solve_batched(acseg_ctx* ctx, int32_t B, const acseg_problem*
     hipStream_t s = (hipStream_t)stream;
     char* base = static_cast<char*>(ws);
 
-    // ---- descriptor table, work lists and group lists, built on the host
-    if (ctx->stage_ev) ACSEG_TRY(hipEventSynchronize(ctx->stage_ev));  // the last upload is done
-    if (ctx->stage_bytes < bl.table_bytes) {
-        if (ctx->stage) ACSEG_TRY(hipHostFree(ctx->stage));
-        ctx->stage = nullptr;
-        ctx->stage_bytes = 0;
-        ACSEG_TRY(hipHostMalloc(&ctx->stage, bl.table_bytes, hipHostMallocDefault));
-        ctx->stage_bytes = bl.table_bytes;
+    // ---- descriptor table, work lists and group lists, built on the host.  With
+    // REUSE_TABLES the workspace already holds them (from an earlier call with the
+    // same arguments): they are built into host memory for the launch plan only,
+    // and neither the staging buffer nor the stream is touched.
+    const bool reuse = (ps[0].flags & ACSEG_FLAG_REUSE_TABLES) != 0u;
+    std::vector<char> local;
+    char* hs = nullptr;
+    if (reuse) {
+        local.assign(bl.table_bytes, 0);
+        hs = local.data();
+    } else {
+        if (ctx->stage_ev) ACSEG_TRY(hipEventSynchronize(ctx->stage_ev));  // the last upload is done
+        if (ctx->stage_bytes < bl.table_bytes) {
+            if (ctx->stage) ACSEG_TRY(hipHostFree(ctx->stage));
+            ctx->stage = nullptr;
+            ctx->stage_bytes = 0;
+            ACSEG_TRY(hipHostMalloc(&ctx->stage, bl.table_bytes, hipHostMallocDefault));
+            ctx->stage_bytes = bl.table_bytes;
+        }
+        if (!ctx->stage_ev) ACSEG_TRY(hipEventCreateWithFlags(&ctx->stage_ev, hipEventDisableTiming));
+        hs = static_cast<char*>(ctx->stage);
+        memset(hs, 0, bl.table_bytes);
     }
-    if (!ctx->stage_ev) ACSEG_TRY(hipEventCreateWithFlags(&ctx->stage_ev, hipEventDisableTiming));
-    char* hs = static_cast<char*>(ctx->stage);
-    memset(hs, 0, bl.table_bytes);
     CycleArgs* hdesc = reinterpret_cast<CycleArgs*>(hs + bl.descs);
     int2* hwork = reinterpret_cast<int2*>(hs + bl.work);
     int* himgs = reinterpret_cast<int*>(hs + bl.imgs);
@@ -948,8 +959,10 @@ acseg_status acseg_solve_batched(acseg_ctx* ctx, int32_t B, const acseg_problem*
             groups.push_back(g);
         }
     }
-    ACSEG_TRY(hipMemcpyAsync(base, hs, bl.table_bytes, hipMemcpyHostToDevice, s));
-    ACSEG_TRY(hipEventRecord(ctx->stage_ev, s));
+    if (!reuse) {
+        ACSEG_TRY(hipMemcpyAsync(base, hs, bl.table_bytes, hipMemcpyHostToDevice, s));
+        ACSEG_TRY(hipEventRecord(ctx->stage_ev, s));
+    }
     const CycleArgs* ddesc = reinterpret_cast<const CycleArgs*>(base + bl.descs);
     const int2* dwork = reinterpret_cast<const int2*>(base + bl.work);
     const int* dimgs = reinterpret_cast<const int*>(base + bl.imgs);

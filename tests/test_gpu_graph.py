@@ -50,3 +50,42 @@ def test_fixed_schedule_solve_replays_equal_eager(levels):
         torch.cuda.synchronize()
         assert torch.equal(u, u_ref), k
         assert torch.equal(c, c_ref), k
+
+
+def test_batched_solve_with_reused_tables_replays_equal_eager():
+    """acseg_solve_batched with FLAG_REUSE_TABLES (tables left by an eager call with
+    the same arguments) captured with labels and replayed three times, with eager
+    work between replays: every replay equals the eager batched solve."""
+    ws = [synth.VORONOI1024.scaled(160, 120), synth.VORONOI1024.scaled(96, 130, N=3),
+          synth.VORONOI1024.scaled(200, 64)]
+    probs = [acseg.Problem.from_workload(w, levels=1, steps=5, max_cycles=2, flags=acseg.FLAG_FIXED_CYCLES)
+             for w in ws]
+    made = [w.make(3 + k) for k, w in enumerate(ws)]
+    imgs = [cuda(m[0]) for m in made]
+    u0s = [cuda(m[1]) for m in made]
+    us = [x.clone() for x in u0s]
+    cs = [torch.empty((p.N, p.C), dtype=torch.float32, device="cuda") for p in probs]
+    _, _, st = acseg.solve_batched(probs, imgs, us, cs=cs)
+    assert all(x["status"] == acseg.OK for x in st), st
+    u_ref = [x.clone() for x in us]
+    c_ref = [x.clone() for x in cs]
+    torch.cuda.synchronize()
+
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for b in range(len(us)):
+            us[b].copy_(u0s[b])
+        acseg.solve_batched(probs, imgs, us, want_stats=False, cs=cs, reuse_tables=True)
+        labs = [acseg.labels(p, u, c)[0] for p, u, c in zip(probs, us, cs)]
+    lab_ref = [acseg.labels(p, u, c)[0].clone() for p, u, c in zip(probs, u_ref, c_ref)]
+    for k in range(3):
+        for u, c in zip(us, cs):
+            u.fill_(0.25)  # eager work between replays
+            c.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for b in range(len(us)):
+            assert torch.equal(us[b], u_ref[b]), (k, b)
+            assert torch.equal(cs[b], c_ref[b]), (k, b)
+            assert torch.equal(labs[b], lab_ref[b]), (k, b)
