@@ -531,7 +531,25 @@ def main():
                 "bytes_per_launch": int(bytes_per_launch), "avg_launch_us": round(avg_s * 1e6, 2),
                 "launches": launches,
                 "per_family_ms": {k: round(v[1] / reps, 4) for k, v in t.items()}}
-        log(f"[bench] smoother {avg_s*1e6:.2f} us/launch -> {achieved:.1f} GB/s algorithmic")
+        # the attainable streaming rate for the same bytes: a plain device copy that
+        # reads and writes half of them each
+        ncp = max(1, int(bytes_per_launch) // 8)
+        src_cp = torch.ones(ncp, dtype=torch.float32, device=dev)
+        dst_cp = torch.empty_like(src_cp)
+        dst_cp.copy_(src_cp)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(20):
+            dst_cp.copy_(src_cp)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 8 * ncp / (e0.elapsed_time(e1) / 20 * 1e-3) / 1e9
+        del src_cp, dst_cp
+        roof["copy_same_bytes_GBs"] = round(copy_gbs, 1)
+        roof["frac_of_copy"] = round(achieved / copy_gbs, 4)
+        log(f"[bench] smoother {avg_s*1e6:.2f} us/launch -> {achieved:.1f} GB/s algorithmic "
+            f"(a device copy of the same bytes: {copy_gbs:.1f} GB/s)")
 
     cpu = None
     if not args.no_cpu_baseline:
