@@ -248,11 +248,14 @@ def run_adjoint(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     w = synth.WORKLOADS["voronoi512_n4"]
+    if args.pixel_units:
+        w = synth.pixel_twin(w)
     img_np, u0_np, lab = w.make(0)
     I = torch.from_numpy(img_np).to(dev)
     U0 = torch.from_numpy(u0_np).to(dev)
     y = torch.from_numpy(np.stack([(lab == i) for i in range(w.N)]).astype(np.float32)).to(dev)
-    p = acseg.Problem.from_workload(w, C=3, levels=1, max_cycles=args.max_cycles)
+    p = acseg.Problem.from_workload(w, C=3, levels=args.levels, max_cycles=args.max_cycles,
+                                    flags=acseg.FLAG_SSC if args.ssc else 0)
     st = {}
 
     def forward():
@@ -277,13 +280,16 @@ def run_adjoint(args):
     t_fb = timed(both, k)
     u, ck = forward()
     _, _, _, _, bst = acseg.backward(p, I, ck, 2 * (u - y))
-    out = {"metric": "adjoint: forward+backward time per segmentation (voronoi512_n4)",
+    _, _, fst, _ = acseg.solve(p, I, U0.clone())
+    out = {"metric": f"adjoint: forward+backward time per segmentation ({w.name})",
            "value": round(t_fb * 1e3, 3), "unit": "ms", "n_gpus": 1, "steps": k, "warmup": 1,
            "ms_per_step": round(t_fb * 1e3, 3), "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "forward_ms": round(t_f * 1e3, 3), "backward_ms": round((t_fb - t_f) * 1e3, 3),
            "backward_over_forward": round((t_fb - t_f) / t_f, 2),
            "config": {"workload": w.name, "W": w.W, "H": w.H, "N": w.N, "time_steps": w.steps,
+                      "levels": p.levels, "forward_cycles_total": fst["cycles_total"],
+                      "forward_cycles_max": fst["cycles_max"], "forward_status": fst["status"],
                       "adjoint_sweeps_total": bst["cycles_total"], "adjoint_sweeps_max": bst["cycles_max"],
                       "status": bst["status"]},
            "roofline": None, "cpu_baseline": None}
