@@ -235,6 +235,34 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// This thread's share (t, t + kBlock, ...) of a sum / max over n values, with
+// four independent accumulators combined in a fixed order: deterministic, and
+// four loads in flight per thread instead of one dependent chain.
+__device__ __forceinline__ double strided_sum4(const double* __restrict__ v, int n) {
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    int b = threadIdx.x;
+    for (; b + 3 * kBlock < n; b += 4 * kBlock) {
+        t0 += v[b];
+        t1 += v[b + kBlock];
+        t2 += v[b + 2 * kBlock];
+        t3 += v[b + 3 * kBlock];
+    }
+    for (; b < n; b += kBlock) t0 += v[b];
+    return (t0 + t1) + (t2 + t3);
+}
+__device__ __forceinline__ float strided_max4(const float* __restrict__ v, int n) {
+    float r0 = 0.f, r1 = 0.f, r2 = 0.f, r3 = 0.f;
+    int b = threadIdx.x;
+    for (; b + 3 * kBlock < n; b += 4 * kBlock) {
+        r0 = fmaxf(r0, v[b]);
+        r1 = fmaxf(r1, v[b + kBlock]);
+        r2 = fmaxf(r2, v[b + 2 * kBlock]);
+        r3 = fmaxf(r3, v[b + 3 * kBlock]);
+    }
+    for (; b < n; b += kBlock) r0 = fmaxf(r0, v[b]);
+    return fmaxf(fmaxf(r0, r1), fmaxf(r2, r3));
+}
+
 // Block-wide max over kBlock threads; result valid in thread 0.
 __device__ __forceinline__ float block_max(float v, float* sh /* >= kBlock/kWave */) {
     v = wave_max(v);

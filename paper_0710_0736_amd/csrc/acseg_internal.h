@@ -91,6 +91,7 @@ hipError_t launch_cmeans_finish(int N, int C, int W, int H, const double* partia
 // ---- smoothing cycles and the end of a step (kernels_cycle.hip) -----------
 
 constexpr int kXcd = 8;  // XCDs of an MI355X: workgroup id mod 8 selects the XCD
+constexpr int kStrip = 8;  // tile columns per strip of a single-image cycle launch
 constexpr int kCmeansMaxM = 8 * 4 + 8 + 4 + 2;  // colour-mean sums per set, N <= 8, C <= 4
 constexpr int kNC = 8 * 4;                       // stride of one set of means
 
@@ -111,6 +112,7 @@ struct CycleArgs {
     float tol;
     int W, H;
     int tiles_x, ntiles, tiles_per_xcd;
+    int tiles_y, rows_per_xcd;  // tile rows; tile rows per XCD band (single-image launch order)
 };
 
 // Per launch.

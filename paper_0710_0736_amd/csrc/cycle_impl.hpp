@@ -561,10 +561,33 @@ __device__ __forceinline__ void cycle_tile_any(const CycleArgs& a, const CycleSt
         cycle_tile<N, C, K, FIRST, RESID, false>(a, st, tile);
 }
 
+// Tile of workgroup b in a single-image launch, -1 for none.  XCD x = b mod 8
+// owns a band of whole tile rows.  Inside the band the tiles go down strips of
+// kStrip tile columns, row by row within a strip, so the tile above a tile ran
+// about kStrip tiles earlier on the same XCD and the halo rows they share are
+// still in that XCD's L2.  In plain row-major order a whole tile row runs in
+// between, which on a wide lattice (64 tiles of about 85 KB each at 4096 nodes
+// and N = 8) no longer fits in the 4 MB L2.
+__device__ __forceinline__ int tile_of_block(const CycleArgs& a, int b) {
+    const int x = b % kXcd, j = b / kXcd;
+    const int r0 = x * a.rows_per_xcd;
+    const int rows = min(a.rows_per_xcd, a.tiles_y - r0);
+    if (rows <= 0) return -1;
+    const int per_strip = rows * kStrip;
+    const int g = j / per_strip;
+    const int c0 = g * kStrip;
+    if (c0 >= a.tiles_x) return -1;
+    const int w = min(kStrip, a.tiles_x - c0);  // the last strip may be narrower
+    const int rem = j - g * per_strip;
+    const int r = rem / w, c = rem - r * w;
+    if (r >= rows) return -1;
+    return (r0 + r) * a.tiles_x + c0 + c;
+}
+
 template <int N, int C, int K, bool FIRST, bool RESID>
 __global__ __launch_bounds__(kCycT, cycle_min_waves(N)) void k_cycle(CycleArgs a, CycleStep st) {
-    const int tile = (blockIdx.x % kXcd) * a.tiles_per_xcd + blockIdx.x / kXcd;
-    if (tile >= a.ntiles) return;
+    const int tile = tile_of_block(a, blockIdx.x);
+    if (tile < 0) return;
     cycle_tile_any<N, C, K, FIRST, RESID>(a, st, tile);
 }
 
@@ -604,8 +627,7 @@ __device__ __forceinline__ void step_end(const CycleArgs& a, const CycleStep& st
     if ((int)blockIdx.x < MD) {
         const int q = blockIdx.x;
         const double* row = a.cm_part + ((int64_t)((cycles - 1) & 1) * MD + q) * a.part_stride;
-        double t = 0.0;
-        for (int b = threadIdx.x; b < a.ntiles; b += kBlock) t += row[b];
+        double t = strided_sum4(row, a.ntiles);
         t = wave_sum(t);
         if (threadIdx.x % kWave == 0) shd[threadIdx.x / kWave] = t;
         __syncthreads();
@@ -623,9 +645,7 @@ __device__ __forceinline__ void step_end(const CycleArgs& a, const CycleStep& st
         resid = slot->resid;
     } else {
         const float* last = a.res_part + ((e.max_cycles - 1) & 1) * a.part_stride;
-        float r = 0.f;
-        for (int b = threadIdx.x; b < a.ntiles; b += kBlock) r = fmaxf(r, last[b]);
-        resid = block_max(r, red);
+        resid = block_max(strided_max4(last, a.ntiles), red);
     }
     if (threadIdx.x != 0) return;
     ctl->cur = iterate_buf(ctl->cur, cycles * e.launches_per_cycle);

@@ -17,8 +17,12 @@ void cycle_tiling(int N, int W, int H, CycleArgs* a) {
     a->W = W;
     a->H = H;
     a->tiles_x = (W + kTX - 1) / kTX;
+    a->tiles_y = (H + cycle_ty(N) - 1) / cycle_ty(N);
     a->ntiles = cycle_tiles(N, W, H);
-    a->tiles_per_xcd = (a->ntiles + kXcd - 1) / kXcd;
+    // XCD x takes tile rows [x rows_per_xcd, (x + 1) rows_per_xcd), walked in
+    // strips of kStrip tile columns (workgroups per XCD: strips x kStrip x rows)
+    a->rows_per_xcd = (a->tiles_y + kXcd - 1) / kXcd;
+    a->tiles_per_xcd = ((a->tiles_x + kStrip - 1) / kStrip) * kStrip * a->rows_per_xcd;
 }
 
 // Convergence test after `cycles` cycles of a step (one workgroup): the
@@ -28,9 +32,7 @@ __global__ __launch_bounds__(kBlock) void k_step_check(CycleArgs a, int slot_idx
     StepSlot* slot = &a.ctl->step[slot_idx];
     if (slot->done) return;
     const float* last = a.res_part + ((cycles - 1) & 1) * a.part_stride;
-    float r = 0.f;
-    for (int b = threadIdx.x; b < a.ntiles; b += kBlock) r = fmaxf(r, last[b]);
-    r = block_max(r, red);
+    const float r = block_max(strided_max4(last, a.ntiles), red);
     if (threadIdx.x == 0 && !(r > a.tol)) {
         slot->done = 1;
         slot->cycles = cycles;
