@@ -119,8 +119,11 @@ typedef int32_t acseg_status;
  * workspace's table region since; the call then builds no tables on the device
  * side and uploads nothing.  With ACSEG_FLAG_FIXED_CYCLES as well and stats ==
  * NULL, the call enqueues kernels only and can be captured in a HIP graph.  The
- * caller is responsible for the precondition: stale tables point the kernels
- * at the earlier call's arrays.  Ignored by the other entry points.
+ * call still builds the tables on the host and returns ACSEG_ERR_INVALID_ARG,
+ * enqueueing nothing, unless they equal the last tables this context uploaded
+ * and went to the same workspace address.  That the workspace still holds them
+ * (nothing else wrote there, the memory was not handed to another owner) is
+ * the caller's responsibility.  Ignored by the other entry points.
  */
 #define ACSEG_FLAG_REUSE_TABLES 32u
 

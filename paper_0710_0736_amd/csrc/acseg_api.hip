@@ -40,6 +40,9 @@ struct acseg_ctx {
     void* stage = nullptr;
     size_t stage_bytes = 0;
     hipEvent_t stage_ev = nullptr;
+    // the last uploaded tables and the workspace they went to (REUSE_TABLES check)
+    std::vector<char> last_tables;
+    const void* last_tables_ws = nullptr;
 };
 
 namespace {
@@ -962,6 +965,11 @@ acseg_status acseg_solve_batched(acseg_ctx* ctx, int32_t B, const acseg_problem*
     if (!reuse) {
         ACSEG_TRY(hipMemcpyAsync(base, hs, bl.table_bytes, hipMemcpyHostToDevice, s));
         ACSEG_TRY(hipEventRecord(ctx->stage_ev, s));
+        ctx->last_tables.assign(hs, hs + bl.table_bytes);
+        ctx->last_tables_ws = ws;
+    } else if (ctx->last_tables_ws != ws || ctx->last_tables.size() != bl.table_bytes ||
+               memcmp(ctx->last_tables.data(), hs, bl.table_bytes) != 0) {
+        return ACSEG_ERR_INVALID_ARG;  // not the tables of this context's last upload to ws
     }
     const CycleArgs* ddesc = reinterpret_cast<const CycleArgs*>(base + bl.descs);
     const int2* dwork = reinterpret_cast<const int2*>(base + bl.work);

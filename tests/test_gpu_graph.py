@@ -89,3 +89,27 @@ def test_batched_solve_with_reused_tables_replays_equal_eager():
             assert torch.equal(us[b], u_ref[b]), (k, b)
             assert torch.equal(cs[b], c_ref[b]), (k, b)
             assert torch.equal(labs[b], lab_ref[b]), (k, b)
+
+
+def test_reuse_tables_refuses_other_arguments():
+    """FLAG_REUSE_TABLES with arguments whose tables differ from the last upload is
+    refused on the host, before anything is enqueued."""
+    w = synth.VORONOI1024.scaled(96, 64)
+    probs = [acseg.Problem.from_workload(w, levels=1, steps=2, max_cycles=1, flags=acseg.FLAG_FIXED_CYCLES)] * 2
+    img, u0, _ = w.make(1)
+    imgs = [cuda(img), cuda(img)]
+    us = [cuda(u0), cuda(u0)]
+    acseg.solve_batched(probs, imgs, us, want_stats=False)
+    torch.cuda.synchronize()
+    other = [cuda(u0), cuda(u0)]  # new output arrays: the uploaded tables point elsewhere
+    with pytest.raises(acseg.AcsegError) as e:
+        acseg.solve_batched(probs, imgs, other, want_stats=False, reuse_tables=True)
+    assert e.value.code == acseg.ERR_INVALID_ARG
+    # the same arguments are accepted (and give the same result as an upload)
+    for x in us:
+        x.copy_(cuda(u0))
+    acseg.solve_batched(probs, imgs, us, want_stats=False, reuse_tables=True)
+    ref = [cuda(u0), cuda(u0)]
+    acseg.solve_batched(probs, imgs, ref, want_stats=False)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(us, ref))
