@@ -109,3 +109,32 @@ def test_multigrid_validation_codes():
         assert acseg.lib().acseg_workspace_size(ctypes.byref(p.c()), ctypes.byref(n)) == code, kw
     # the multigrid hierarchy needs its own buffers
     assert acseg.workspace_size(base_problem(levels=3)) > acseg.workspace_size(base_problem(levels=1))
+
+
+def header_defines():
+    text = open(os.path.join(ROOT, "include", "acseg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for name, val in re.findall(r"#define\s+ACSEG_(\w+)\s+\(?(-?\d+)u?\)?", text):
+        out[name] = int(val)
+    return out
+
+
+def test_binding_constants_match_the_header():
+    d = header_defines()
+    flags = {k[len("FLAG_"):]: v for k, v in d.items() if k.startswith("FLAG_")}
+    assert {"STORE_CHECKPOINTS", "FIXED_CYCLES", "FIXED_C", "NO_HOST_WAIT", "SSC", "REUSE_TABLES"} <= set(flags)
+    for name, v in flags.items():
+        assert getattr(acseg, "FLAG_" + name) == v, name
+    assert len(set(flags.values())) == len(flags)  # distinct bits
+    for name in ("OK", "ERR_INVALID_ARG", "ERR_NONFINITE", "ERR_WORKSPACE", "ERR_HIP", "ERR_UNSUPPORTED",
+                 "WARN_NOT_CONVERGED", "WARN_EMPTY_PHASE"):
+        assert getattr(acseg, name) == d[name], name
+
+
+def test_unknown_flag_bits_are_rejected():
+    n = ctypes.c_size_t()
+    for flags, ok in ((acseg.FLAG_SSC, True), (acseg.FLAG_REUSE_TABLES, True), (64, False), (1 << 20, False)):
+        p = base_problem(flags=flags)
+        r = acseg.lib().acseg_workspace_size(ctypes.byref(p.c()), ctypes.byref(n))
+        assert (r == acseg.OK) == ok, (flags, r)
