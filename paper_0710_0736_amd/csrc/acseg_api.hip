@@ -1108,6 +1108,14 @@ acseg_status acseg_backward(acseg_ctx* ctx, const acseg_problem* p, const float*
     a.coef = coefs_of(p).fine;
     const float dA[4] = {4.f, 2.f, 1.f, 1.f};
     for (int k = 0; k < 4; ++k) a.diagA[k] = dA[k];
+    // SOR factor from q = max over node classes of kappa * (sum of edge weights
+    // = stiffness diagonal), the bound of the block-Jacobi radius
+    {
+        double q = 0.0;
+        for (int k = 0; k < 4; ++k) q = std::max(q, (double)a.coef.kappa[k] * dA[k]);
+        q = std::min(q, 0.999);
+        a.omega = (float)std::min(1.95, 2.0 / (1.0 + std::sqrt(1.0 - q * q)));
+    }
     a.h2 = p->h * p->h;
     a.inv_h2 = (float)(1.0 / a.h2);
     a.rtol = (float)std::max(p->tol, 2e-7);

@@ -284,9 +284,10 @@ hipError_t launch_mass_avg(int planes, int W, int H, const float* src, float* ds
 // ---- launchers (kernels_adjoint.hip): gradients through the time steps ------
 
 struct AdjCtl {
-    int done;    // the current adjoint solve converged
-    int sweeps;  // after this many sweeps
-    int pad[2];
+    int done;     // the current adjoint solve converged
+    int sweeps;   // after this many sweeps
+    float omega;  // over-relaxation factor of the current solve, set at sweep kAdjOmegaSweep
+    int pad;
 };
 
 enum AdjOp { kAdjSweep = 0, kAdjAccum, kAdjReduce, kAdjMeans };
@@ -315,6 +316,7 @@ struct AdjArgs {
     LevelCoef coef;       // finest level
     float diagA[4];       // stiffness diagonal per node class
     float inv_h2, rtol;
+    float omega;          // largest over-relaxation factor of the sweeps (from the coupling bound)
     double h2, eps, tau, lambda;
     int W, H, nblocks, nblocks_acc, max_sweeps;
 };

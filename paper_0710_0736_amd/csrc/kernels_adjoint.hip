@@ -9,8 +9,18 @@
 // zero when |I_p| <= 1).  z is found by red-black block Gauss-Seidel on
 //     z_p = T_p (ubar_p / (h^2 D_p) + kappa_p sum_q c_pq z_q)
 // (the nodal minimiser of z.H z / 2 - ubar.z on the range of T_p, in the
-// scaled units of the smoother), stopped when a sweep changes z by at most
-// rtol max|z|.  The chain rule then runs through
+// scaled units of the smoother), over-relaxed: z_p <- z_p + omega (that - z_p),
+// which stays in the range of T_p.  The system is symmetric positive definite
+// and red-black ordered (two-cyclic), so the sweeps converge for 0 < omega < 2
+// and Young's optimum is 2 / (1 + sqrt(1 - rho^2)) with rho the block-Jacobi
+// radius.  The first kAdjOmegaSweep sweeps of a solve are plain Gauss-Seidel
+// (omega = 1); their successive changes shrink by its contraction rho^2, whose
+// estimate, the ratio of the last two changes, then fixes omega for the rest
+// of the solve, capped by
+// the value for the bound rho <= q = max_p kappa_p sum_q c_pq (the T_p only
+// shrink the coupling).  An early estimate errs low (fast transients), which
+// under-relaxes: still faster than Gauss-Seidel.  Stopped when a sweep changes
+// z by at most rtol max|z|.  The chain rule then runs through
 //     b_pi = M_p [(1/tau + 2/eps) un_pi - lambda F_pi],  F_pi = sum_k (I_pk - c_ik)^2,
 //     c_ik = S_ik / S_i,  H = M/tau + eps A,
 // with M_p = h^2 w_p; an empty phase's (kept) mean is a constant.
@@ -63,6 +73,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // of the solve once they meet rtol.  Per node the arithmetic is that of the
 // two half-sweeps it replaces.
 constexpr int kAdjTX = 64, kAdjTY = 8, kAdjR = 2;
+constexpr int kAdjOmegaSweep = 6;  // the sweep that fixes omega from the Gauss-Seidel contraction
 constexpr int kAdjLX = kAdjTX + 2 * kAdjR, kAdjLY = kAdjTY + 2 * kAdjR;
 
 __host__ __device__ inline int adj_tiles(int W, int H) {
@@ -83,6 +94,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs a, int sweep) {
     __shared__ float zl[N][kAdjLY][kAdjLX];
     AdjCtl* ac = a.actl;
     if (ac->done) return;
+    float omega = 1.f;
     if (sweep > 1) {  // sweep 0 compared its black values with unset memory
         const float* prev = a.part_f + ((sweep - 1) & 1) * 2 * kMgBlocks;
         float dz = 0.f, zm = 0.f;
@@ -98,6 +110,18 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs a, int sweep) {
                 ac->sweeps = sweep;
             }
             return;
+        }
+        if (sweep == kAdjOmegaSweep) {
+            // the partials of sweep - 2 are still in this parity's set
+            const float* pp = a.part_f + (sweep & 1) * 2 * kMgBlocks;
+            float dz2 = 0.f;
+            for (int b = threadIdx.x; b < a.nblocks; b += kBlock) dz2 = fmaxf(dz2, pp[b]);
+            dz2 = block_max_f(dz2, sh);
+            const float r = dz2 > 0.f ? fminf(dz / dz2, 0.99f) : 0.f;
+            omega = fminf(a.omega, fmaxf(1.f, 2.f / (1.f + sqrtf(1.f - r))));
+            if (blockIdx.x == 0 && threadIdx.x == 0) ac->omega = omega;  // read by later sweeps
+        } else if (sweep > kAdjOmegaSweep) {
+            omega = ac->omega;
         }
     }
     const int W = a.W, H = a.H;
@@ -158,9 +182,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs a, int sweep) {
                 const bool own = lx >= kAdjR && lx < kAdjR + kAdjTX && ly >= kAdjR && ly < kAdjR + kAdjTY;
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
-                    const float zn = (kf >= 2 && fr[i]) ? yv[i] - mean : 0.f;
+                    const float zo = zl[i][ly][lx];  // this node's value before the sweep (0 at sweep 0)
+                    const float zg = (kf >= 2 && fr[i]) ? yv[i] - mean : 0.f;
+                    const float zn = fmaf(omega, zg - zo, zo);
                     if (colour == 1) {
-                        dzm = fmaxf(dzm, fabsf(zn - zl[i][ly][lx]));
+                        dzm = fmaxf(dzm, fabsf(zn - zo));
                         zmax = fmaxf(zmax, fabsf(zn));
                     } else {
                         zl[i][ly][lx] = zn;  // reds are read only by the black half
