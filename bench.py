@@ -316,6 +316,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true",
                     help="time the batched segmentation eagerly only (default: also as a captured graph, "
                          "which gives `value`)")
+    ap.add_argument("--sor", action="store_true",
+                    help="over-relaxed smoothing sweeps (ACSEG_FLAG_SOR; one image per call)")
     ap.add_argument("--ssc", action="store_true",
                     help="coarse correction = the paper's subspace correction over all basis functions")
     ap.add_argument("--adjoint", action="store_true",
@@ -370,8 +372,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     B = max(1, args.batch)
-    if args.levels != 1 and B > 1:
-        log("[bench] the batched solve runs Gauss-Seidel cycles only: --levels != 1 uses --batch 1")
+    if (args.levels != 1 or args.sor) and B > 1:
+        log("[bench] the batched solve runs plain Gauss-Seidel cycles only: --levels != 1 or --sor uses --batch 1")
         B = 1
     made = [w.make(seed) for seed in range(B)]
     img_np, u0_np, _ = made[0]
@@ -382,7 +384,7 @@ def main():
     us = [torch.empty_like(u0) for u0 in u0s]
     img, u0, u = imgs[0], u0s[0], us[0]
 
-    ssc_flag = acseg.FLAG_SSC if args.ssc else 0
+    ssc_flag = (acseg.FLAG_SSC if args.ssc else 0) | (acseg.FLAG_SOR if args.sor else 0)
     base = acseg.Problem.from_workload(w, C=C, levels=args.levels, nu_pre=args.nu[0],
                                        nu_post=args.nu[1], max_cycles=args.max_cycles, flags=ssc_flag)
 
@@ -591,7 +593,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name + ("_consistent_mass" if args.consistent_mass else "")
-                               + ("_ssc" if args.ssc and prob.levels != 1 else ""), "batch": B,
+                               + ("_ssc" if args.ssc and prob.levels != 1 else "") + ("_sor" if args.sor else ""),
+                   "batch": B,
                    "W": w.W, "H": w.H, "N": w.N, "C": C,
                    "time_steps": w.steps, "lambda": w.lam, "h": w.h, "eps": w.eps, "tau": w.tau,
                    "tol": w.tol, "levels": prob.levels, "sweeps_per_cycle": prob.nu_pre + prob.nu_post,

@@ -31,6 +31,7 @@ FLAG_FIXED_C = 4
 FLAG_NO_HOST_WAIT = 8
 FLAG_SSC = 16
 FLAG_REUSE_TABLES = 32
+FLAG_SOR = 64
 
 
 class _Problem(ctypes.Structure):

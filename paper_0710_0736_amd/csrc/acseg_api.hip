@@ -85,7 +85,8 @@ acseg_status validate(const acseg_problem* p, bool need_steps) {
     const int L = p->levels == 0 ? auto_levels(p->W, p->H) : p->levels;
     if (L >= 2 && (p->nu_pre < 1 || p->nu_post < 1)) return ACSEG_ERR_UNSUPPORTED;
     if ((p->flags & ~(ACSEG_FLAG_STORE_CHECKPOINTS | ACSEG_FLAG_FIXED_CYCLES | ACSEG_FLAG_FIXED_C |
-                      ACSEG_FLAG_NO_HOST_WAIT | ACSEG_FLAG_SSC | ACSEG_FLAG_REUSE_TABLES)) != 0u)
+                      ACSEG_FLAG_NO_HOST_WAIT | ACSEG_FLAG_SSC | ACSEG_FLAG_REUSE_TABLES |
+                      ACSEG_FLAG_SOR)) != 0u)
         return ACSEG_ERR_INVALID_ARG;
     return ACSEG_OK;
 }
@@ -426,6 +427,16 @@ CycleArgs cycle_args_of(const acseg_problem* p, const Coefs& cf, const float* im
     a.coef = cf.fine;
     a.rc = cf.rhs;
     a.tol = (float)p->tol;
+    a.omega = 1.f;
+    if ((p->flags & ACSEG_FLAG_SOR) != 0u) {
+        // Young's factor for the bound rho <= q = max over node classes of
+        // kappa * (sum of edge weights = stiffness diagonal) of the block-Jacobi radius
+        static const double diag[4] = {4.0, 2.0, 1.0, 1.0};
+        double q = 0.0;
+        for (int k = 0; k < 4; ++k) q = std::max(q, (double)cf.fine.kappa[k] * diag[k]);
+        q = std::min(q, 0.999);
+        a.omega = (float)std::min(1.95, 2.0 / (1.0 + std::sqrt(1.0 - q * q)));
+    }
     cycle_tiling(p->N, p->W, p->H, &a);
     return a;
 }
@@ -578,6 +589,7 @@ acseg_status validate_batch(int32_t B, const acseg_problem* ps) {
         if (v != ACSEG_OK) return v;
         if (!same_schedule(ps[0], ps[b])) return ACSEG_ERR_INVALID_ARG;
         if ((ps[b].flags & ACSEG_FLAG_STORE_CHECKPOINTS) != 0u) return ACSEG_ERR_INVALID_ARG;
+        if ((ps[b].flags & ACSEG_FLAG_SOR) != 0u) return ACSEG_ERR_UNSUPPORTED;
         if (plan_of(&ps[b]).L != 1) return ACSEG_ERR_UNSUPPORTED;
     }
     return ACSEG_OK;

@@ -113,6 +113,7 @@ struct CycleArgs {
     int W, H;
     int tiles_x, ntiles, tiles_per_xcd;
     int tiles_y, rows_per_xcd;  // tile rows; tile rows per XCD band (single-image launch order)
+    float omega;                // over-relaxation of the smoothing sweeps (1: Gauss-Seidel; single image)
 };
 
 // Per launch.

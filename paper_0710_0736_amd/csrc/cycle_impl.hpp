@@ -139,7 +139,11 @@ __device__ __forceinline__ float block_max_t(float v, float* sh /* >= T/kWave */
 // one owning tile 0 records it.
 // INT: the staged region lies strictly inside the image, so every staged node
 // is an interior node (class 0, unit edge weights) and no bounds test is needed.
-template <int N, int C, int K, bool FIRST, bool RESID, bool INT>
+// SOR: the writing half-sweeps are over-relaxed, u_p <- Pi(u_p + omega (y_p - u_p))
+// (single-image launches only).  The launch that measures the residual keeps
+// its last black half-sweep plain, so the black residual is zero again and the
+// red residual half-sweep still measures the natural residual.
+template <int N, int C, int K, bool FIRST, bool RESID, bool INT, bool SOR = false>
 __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& st, int tile) {
     constexpr int T = kCycT;
     constexpr int TX = kTX, TY = cycle_ty(N);
@@ -416,6 +420,7 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
 
     // ---- red-black half-sweeps on the shrinking region
     float res = 0.f;
+    const float om = SOR ? uniform_f(a.omega) : 1.f;
     for (int s = 0; s < NHALF; ++s) {
         const int r = R - 1 - s;
         if (RESID && s == NHALF - 1) {
@@ -445,6 +450,14 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
                 lds_ld<N>(yr[m] + 2 * RW * NPD, a3);
 #pragma unroll
                 for (int i = 0; i < N; ++i) v[i] = rr0[m][i] + kh0[m] * (a0[i] + a1[i]) + kv0[m] * (a2[i] + a3[i]);
+                if constexpr (SOR) {
+                    if (!(RESID && s == NHALF - 1)) {
+                        float o[N];
+                        lds_ld<N>(yr[m] + RW * NPD, o);
+#pragma unroll
+                        for (int i = 0; i < N; ++i) v[i] = fmaf(om, v[i] - o[i], o[i]);
+                    }
+                }
                 project_simplex<N, false>(v);
                 if (RESID && s == NHALF - 1) {
                     float o[N];
@@ -466,6 +479,14 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
                 lds_ld<N>(zb[m] + 2 * RW * NPD, a3);
 #pragma unroll
                 for (int i = 0; i < N; ++i) v[i] = rr1[m][i] + kh1[m] * (a0[i] + a1[i]) + kv1[m] * (a2[i] + a3[i]);
+                if constexpr (SOR) {
+                    if (!(RESID && s == NHALF - 2)) {
+                        float o[N];
+                        lds_ld<N>(zb[m] + RW * NPD, o);
+#pragma unroll
+                        for (int i = 0; i < N; ++i) v[i] = fmaf(om, v[i] - o[i], o[i]);
+                    }
+                }
                 project_simplex<N, false>(v);
                 lds_st<N>(zb[m] + RW * NPD, v);
             }
@@ -553,12 +574,12 @@ __device__ __forceinline__ bool tile_interior(const CycleArgs& a, int tile) {
     return x0 >= 1 && y0 >= 1 && x0 + kTX + 2 * R <= a.W - 1 && y0 + cycle_ty(N) + 2 * R <= a.H - 1;
 }
 
-template <int N, int C, int K, bool FIRST, bool RESID>
+template <int N, int C, int K, bool FIRST, bool RESID, bool SOR = false>
 __device__ __forceinline__ void cycle_tile_any(const CycleArgs& a, const CycleStep& st, int tile) {
     if (tile_interior<N, K, RESID>(a, tile))
-        cycle_tile<N, C, K, FIRST, RESID, true>(a, st, tile);
+        cycle_tile<N, C, K, FIRST, RESID, true, SOR>(a, st, tile);
     else
-        cycle_tile<N, C, K, FIRST, RESID, false>(a, st, tile);
+        cycle_tile<N, C, K, FIRST, RESID, false, SOR>(a, st, tile);
 }
 
 // Tile of workgroup b in a single-image launch, -1 for none.  XCD x = b mod 8
@@ -584,11 +605,11 @@ __device__ __forceinline__ int tile_of_block(const CycleArgs& a, int b) {
     return (r0 + r) * a.tiles_x + c0 + c;
 }
 
-template <int N, int C, int K, bool FIRST, bool RESID>
+template <int N, int C, int K, bool FIRST, bool RESID, bool SOR>
 __global__ __launch_bounds__(kCycT, cycle_min_waves(N)) void k_cycle(CycleArgs a, CycleStep st) {
     const int tile = tile_of_block(a, blockIdx.x);
     if (tile < 0) return;
-    cycle_tile_any<N, C, K, FIRST, RESID>(a, st, tile);
+    cycle_tile_any<N, C, K, FIRST, RESID, SOR>(a, st, tile);
 }
 
 // A batch of images with the same N and C: work[] lists (image, tile) of
@@ -683,8 +704,11 @@ hipError_t run_cycle(const CycleArgs& a, const CycleStep& st, const CycleGrid& g
     if (g.descs)
         hipLaunchKernelGGL((k_cycle_batch<N, C, K, FIRST, RESID>), dim3(g.nwork), dim3(kCycT), lds, s,
                            g.descs, g.work, g.nwork, st);
+    else if (a.omega != 1.f)
+        hipLaunchKernelGGL((k_cycle<N, C, K, FIRST, RESID, true>), dim3(a.tiles_per_xcd * kXcd), dim3(kCycT),
+                           lds, s, a, st);
     else
-        hipLaunchKernelGGL((k_cycle<N, C, K, FIRST, RESID>), dim3(a.tiles_per_xcd * kXcd), dim3(kCycT),
+        hipLaunchKernelGGL((k_cycle<N, C, K, FIRST, RESID, false>), dim3(a.tiles_per_xcd * kXcd), dim3(kCycT),
                            lds, s, a, st);
     return hipGetLastError();
 }

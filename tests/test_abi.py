@@ -123,7 +123,8 @@ def header_defines():
 def test_binding_constants_match_the_header():
     d = header_defines()
     flags = {k[len("FLAG_"):]: v for k, v in d.items() if k.startswith("FLAG_")}
-    assert {"STORE_CHECKPOINTS", "FIXED_CYCLES", "FIXED_C", "NO_HOST_WAIT", "SSC", "REUSE_TABLES"} <= set(flags)
+    assert {"STORE_CHECKPOINTS", "FIXED_CYCLES", "FIXED_C", "NO_HOST_WAIT", "SSC", "REUSE_TABLES",
+            "SOR"} <= set(flags)
     for name, v in flags.items():
         assert getattr(acseg, "FLAG_" + name) == v, name
     assert len(set(flags.values())) == len(flags)  # distinct bits
@@ -134,7 +135,8 @@ def test_binding_constants_match_the_header():
 
 def test_unknown_flag_bits_are_rejected():
     n = ctypes.c_size_t()
-    for flags, ok in ((acseg.FLAG_SSC, True), (acseg.FLAG_REUSE_TABLES, True), (64, False), (1 << 20, False)):
+    for flags, ok in ((acseg.FLAG_SSC, True), (acseg.FLAG_REUSE_TABLES, True), (acseg.FLAG_SOR, True), (128, False),
+                      (1 << 20, False)):
         p = base_problem(flags=flags)
         r = acseg.lib().acseg_workspace_size(ctypes.byref(p.c()), ctypes.byref(n))
         assert (r == acseg.OK) == ok, (flags, r)

@@ -1,0 +1,74 @@
+"""GPU parity of the over-relaxed smoother (ACSEG_FLAG_SOR) against the FP64 oracle.
+
+Over-relaxation changes only the path to a time step's unique minimiser, so its
+steps meet the gates of every other step (natural residual <= 1e-6,
+max |u_gpu - u_oracle| <= 1e-4 from the oracle's state, labels), in pixel units
+(omega about 1.67) and at the unit scale (omega about 1).  In pixel units it
+must also need fewer cycles than plain Gauss-Seidel.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+from paper_0710_0736_amd import acseg, synth
+from test_gpu_parity import GATE_U, check_step, cuda, gpu_problem, host, orc_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("W,H,N,levels,seed", [(96, 80, 4, 1, 1), (77, 130, 3, 1, 2), (64, 64, 2, 1, 3),
+                                               (90, 70, 6, 1, 4), (45, 33, 8, 1, 5), (120, 90, 4, 0, 6)])
+def test_sor_step_parity_pixel_units(W, H, N, levels, seed):
+    base = synth.pixel_twin(synth.VORONOI1024).scaled(W, H, N=N)
+    img, u0, _ = base.make(seed)
+    print(f"sor step W={W} H={H} N={N} levels={levels} seed={seed}", flush=True)
+    check_step(base, img, u0, levels=levels, max_cycles=2000, flags=acseg.FLAG_SOR)
+
+
+def test_sor_step_parity_unit_scale():
+    w = synth.VORONOI1024.scaled(200, 150)
+    img, u0, _ = w.make(2)
+    check_step(w, img, u0, levels=1, max_cycles=200, flags=acseg.FLAG_SOR)
+
+
+def test_sor_needs_fewer_cycles_in_pixel_units():
+    w = synth.pixel_twin(synth.VORONOI1024, 256)
+    img, u0, _ = w.make(5)
+    p_gs = gpu_problem(w, levels=1, max_cycles=2000)
+    p_sor = gpu_problem(w, levels=1, max_cycles=2000, flags=acseg.FLAG_SOR)
+    u_gs, _, st_gs = acseg.step(p_gs, cuda(img), cuda(u0))
+    u_sor, _, st_sor = acseg.step(p_sor, cuda(img), cuda(u0))
+    torch.cuda.synchronize()
+    print("cycles: Gauss-Seidel", st_gs["cycles_max"], "over-relaxed", st_sor["cycles_max"], flush=True)
+    assert st_gs["status"] == acseg.OK and st_sor["status"] == acseg.OK, (st_gs, st_sor)
+    assert np.abs(host(u_gs) - host(u_sor)).max() <= GATE_U
+    assert 2 * st_sor["cycles_max"] < st_gs["cycles_max"], (st_sor, st_gs)
+
+
+@pytest.mark.parametrize("fixed", [False, True])
+def test_sor_solve_every_step(fixed):
+    w = synth.pixel_twin(synth.VORONOI1024, 64)
+    img, u0, _ = w.make(8)
+    steps = 4
+    flags = acseg.FLAG_SOR | (acseg.FLAG_FIXED_CYCLES if fixed else 0)
+    p = acseg.Problem.from_workload(w, levels=1, steps=steps, tol=1e-6, max_cycles=400, flags=flags)
+    u, c, st, traj = acseg.solve(p, cuda(img), cuda(u0), checkpoints=True)
+    torch.cuda.synchronize()
+    assert st["status"] == acseg.OK, st
+    tr = host(traj)
+    P = orc_params(w, tol=1e-12, levels=0)
+    c_prev = None
+    for n in range(steps):
+        u_ref, c_ref, _ = orc.step(P, img, tr[n], c_prev)
+        assert np.abs(tr[n + 1] - u_ref).max() <= GATE_U, n
+        c_prev = c_ref
+
+
+def test_batched_solve_rejects_sor():
+    w = synth.VORONOI1024.scaled(64, 48)
+    p = acseg.Problem.from_workload(w, levels=1, steps=2, max_cycles=2, flags=acseg.FLAG_SOR)
+    img, u0, _ = w.make(1)
+    with pytest.raises(acseg.AcsegError) as e:
+        acseg.solve_batched([p], [cuda(img)], [cuda(u0)], want_stats=False)
+    assert e.value.code == acseg.ERR_UNSUPPORTED
