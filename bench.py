@@ -181,7 +181,7 @@ def run_refined(args):
     eps = 0.5            # half a pixel: 2^(r-1) refined nodes
     base = acseg.Problem(H=Hf, W=Wf, C=C, N=N, h=h, eps=eps, lam=100.0, tau=eps * eps, steps=steps,
                          levels=args.levels, tol=1e-6, nu_pre=args.nu[0], nu_post=args.nu[1],
-                         max_cycles=args.max_cycles)
+                         max_cycles=args.max_cycles, flags=acseg.FLAG_SOR if args.sor else 0)
     pix = acseg.Problem(H=Wp, W=Wp, C=C, N=N, h=1.0, eps=eps, lam=100.0, tau=eps * eps, steps=steps)
     If = acseg.refine(Ip, r)
     u.copy_(U0)
@@ -189,7 +189,7 @@ def run_refined(args):
     if st["status"] != acseg.OK:
         raise RuntimeError(f"calibration solve did not converge: {st}")
     cycles = max(1, st["cycles_max"])
-    prob = acseg.Problem(**{**base.__dict__, "max_cycles": cycles, "flags": acseg.FLAG_FIXED_CYCLES})
+    prob = acseg.Problem(**{**base.__dict__, "max_cycles": cycles, "flags": acseg.FLAG_FIXED_CYCLES | base.flags})
     log(f"[bench] refined: {Wp}^2 pixels, r={r} -> {Wf}x{Hf} nodes, levels={prob.levels}, "
         f"cycles/step<={cycles}")
 
@@ -227,7 +227,7 @@ def run_refined(args):
            "value": round(1.0 / t, 3), "unit": "segmentations/s", "n_gpus": 1, "steps": k,
            "warmup": args.warmup, "ms_per_step": round(t * 1e3, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"voronoi{Wp}_n{N}_refined{r}", "pixels": Wp * Wp, "r": r, "W": Wf, "H": Hf,
+           "config": {"workload": f"voronoi{Wp}_n{N}_refined{r}" + ("_sor" if args.sor else ""), "pixels": Wp * Wp, "r": r, "W": Wf, "H": Hf,
                       "N": N, "C": C, "h": h, "eps": eps, "tau": eps * eps, "lambda": 100.0,
                       "time_steps": steps, "levels": prob.levels,
                       "sweeps_per_cycle": prob.nu_pre + prob.nu_post, "cycles_per_step_max": cycles,
@@ -317,7 +317,7 @@ def main():
                     help="time the batched segmentation eagerly only (default: also as a captured graph, "
                          "which gives `value`)")
     ap.add_argument("--sor", action="store_true",
-                    help="over-relaxed smoothing sweeps (ACSEG_FLAG_SOR; one image per call)")
+                    help="over-relaxed smoothing sweeps (ACSEG_FLAG_SOR)")
     ap.add_argument("--ssc", action="store_true",
                     help="coarse correction = the paper's subspace correction over all basis functions")
     ap.add_argument("--adjoint", action="store_true",
@@ -372,8 +372,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     B = max(1, args.batch)
-    if (args.levels != 1 or args.sor) and B > 1:
-        log("[bench] the batched solve runs plain Gauss-Seidel cycles only: --levels != 1 or --sor uses --batch 1")
+    if args.levels != 1 and B > 1:
+        log("[bench] the batched solve runs Gauss-Seidel cycles only: --levels != 1 uses --batch 1")
         B = 1
     made = [w.make(seed) for seed in range(B)]
     img_np, u0_np, _ = made[0]

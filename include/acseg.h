@@ -127,16 +127,15 @@ typedef int32_t acseg_status;
  */
 #define ACSEG_FLAG_REUSE_TABLES 32u
 /*
- * acseg_step / acseg_solve / acseg_backward's forward checkpoints: the
- * smoothing sweeps are over-relaxed, u_p <- Pi_G(u_p + omega (y_p - u_p)) with
+ * The smoothing sweeps are over-relaxed, u_p <- Pi_G(u_p + omega (y_p - u_p)) with
  * y_p the node's Gauss-Seidel value, omega = 2 / (1 + sqrt(1 - q^2)) from the
  * bound q = max_p kappa_p sum_q c_pq of the block-Jacobi radius (Young's
  * factor; about 1.67 in pixel units, 1.00 at the unit scale).  Each update is
  * a projected step of length omega / D_p along the node's own block, which
  * for 0 < omega < 2 never raises the step's objective, so the minimiser is
  * the same.  The launch that measures the residual keeps its last black
- * half-sweep plain, so the residual is the natural one.  acseg_solve_batched
- * returns ACSEG_ERR_UNSUPPORTED for it.
+ * half-sweep plain, so the residual is the natural one.  Also for
+ * acseg_solve_batched (all problems of a batch share their flags).
  */
 #define ACSEG_FLAG_SOR 64u
 

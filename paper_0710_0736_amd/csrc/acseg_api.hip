@@ -471,7 +471,7 @@ acseg_status enqueue_step(acseg_ctx* ctx, const acseg_problem* p, const Coefs& c
                           int tot_sel, int c64_sel, int prev_sel, hipStream_t s) {
     const CycleArgs a = cycle_args_of(p, cf, image, bufs, L, ws);
     const Schedule sc = schedule_of(p);
-    const CycleGrid single{nullptr, nullptr, 0};
+    const CycleGrid single{nullptr, nullptr, 0, 0};
     CycleStep st{};
     st.slot = n & 1;
     st.fixed = sc.fixed ? 1 : 0;
@@ -589,7 +589,6 @@ acseg_status validate_batch(int32_t B, const acseg_problem* ps) {
         if (v != ACSEG_OK) return v;
         if (!same_schedule(ps[0], ps[b])) return ACSEG_ERR_INVALID_ARG;
         if ((ps[b].flags & ACSEG_FLAG_STORE_CHECKPOINTS) != 0u) return ACSEG_ERR_INVALID_ARG;
-        if ((ps[b].flags & ACSEG_FLAG_SOR) != 0u) return ACSEG_ERR_UNSUPPORTED;
         if (plan_of(&ps[b]).L != 1) return ACSEG_ERR_UNSUPPORTED;
     }
     return ACSEG_OK;
@@ -1014,7 +1013,7 @@ acseg_status acseg_solve_batched(acseg_ctx* ctx, int32_t B, const acseg_problem*
         st.fixed_c = fixed_c ? 1 : 0;
         st.prev_sel = fixed_c ? 2 : (n > 0 ? bsel : -1);
         for (const Group& g : groups) {
-            const CycleGrid grid{ddesc, dwork + g.work0, g.nwork};
+            const CycleGrid grid{ddesc, dwork + g.work0, g.nwork, (ps[0].flags & ACSEG_FLAG_SOR) != 0u ? 1 : 0};
             const CycleArgs& any = hdesc[himgs[g.img0]];
             for (int k = 0; k < p0.max_cycles; ++k) {
                 st.cycle = k;

@@ -143,6 +143,7 @@ struct CycleGrid {
     const CycleArgs* descs;
     const int2* work;
     int nwork;
+    int sor;  // batched launch with over-relaxed sweeps (omega from each descriptor)
 };
 
 struct StepEndArgs {

@@ -139,8 +139,7 @@ __device__ __forceinline__ float block_max_t(float v, float* sh /* >= T/kWave */
 // one owning tile 0 records it.
 // INT: the staged region lies strictly inside the image, so every staged node
 // is an interior node (class 0, unit edge weights) and no bounds test is needed.
-// SOR: the writing half-sweeps are over-relaxed, u_p <- Pi(u_p + omega (y_p - u_p))
-// (single-image launches only).  The launch that measures the residual keeps
+// SOR: the writing half-sweeps are over-relaxed, u_p <- Pi(u_p + omega (y_p - u_p)).  The launch that measures the residual keeps
 // its last black half-sweep plain, so the black residual is zero again and the
 // red residual half-sweep still measures the natural residual.
 template <int N, int C, int K, bool FIRST, bool RESID, bool INT, bool SOR = false>
@@ -615,14 +614,14 @@ __global__ __launch_bounds__(kCycT, cycle_min_waves(N)) void k_cycle(CycleArgs a
 // A batch of images with the same N and C: work[] lists (image, tile) of
 // every tile of the batch, already in XCD-aware order (image -1: nothing to
 // do); the per-image constants are read from the descriptor table.
-template <int N, int C, int K, bool FIRST, bool RESID>
+template <int N, int C, int K, bool FIRST, bool RESID, bool SOR>
 __global__ __launch_bounds__(kCycT, cycle_min_waves(N)) void k_cycle_batch(const CycleArgs* __restrict__ descs,
                                                        const int2* __restrict__ work, int nwork,
                                                        CycleStep st) {
     if ((int)blockIdx.x >= nwork) return;
     const int2 wv = work[blockIdx.x];
     if (wv.x < 0) return;
-    cycle_tile_any<N, C, K, FIRST, RESID>(descs[wv.x], st, wv.y);
+    cycle_tile_any<N, C, K, FIRST, RESID, SOR>(descs[wv.x], st, wv.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -701,8 +700,11 @@ template <int N, int C, int K, bool FIRST, bool RESID>
 hipError_t run_cycle(const CycleArgs& a, const CycleStep& st, const CycleGrid& g, hipStream_t s) {
     constexpr int lds = cycle_lds_bytes<N, K, RESID>();
     static_assert(lds <= 65536, "tile does not fit in 64 KiB of LDS");
-    if (g.descs)
-        hipLaunchKernelGGL((k_cycle_batch<N, C, K, FIRST, RESID>), dim3(g.nwork), dim3(kCycT), lds, s,
+    if (g.descs && g.sor)
+        hipLaunchKernelGGL((k_cycle_batch<N, C, K, FIRST, RESID, true>), dim3(g.nwork), dim3(kCycT), lds, s,
+                           g.descs, g.work, g.nwork, st);
+    else if (g.descs)
+        hipLaunchKernelGGL((k_cycle_batch<N, C, K, FIRST, RESID, false>), dim3(g.nwork), dim3(kCycT), lds, s,
                            g.descs, g.work, g.nwork, st);
     else if (a.omega != 1.f)
         hipLaunchKernelGGL((k_cycle<N, C, K, FIRST, RESID, true>), dim3(a.tiles_per_xcd * kXcd), dim3(kCycT),

@@ -65,10 +65,18 @@ def test_sor_solve_every_step(fixed):
         c_prev = c_ref
 
 
-def test_batched_solve_rejects_sor():
-    w = synth.VORONOI1024.scaled(64, 48)
-    p = acseg.Problem.from_workload(w, levels=1, steps=2, max_cycles=2, flags=acseg.FLAG_SOR)
-    img, u0, _ = w.make(1)
-    with pytest.raises(acseg.AcsegError) as e:
-        acseg.solve_batched([p], [cuda(img)], [cuda(u0)], want_stats=False)
-    assert e.value.code == acseg.ERR_UNSUPPORTED
+def test_batched_sor_equals_single_image_solves():
+    """The batched kernel's over-relaxed variant gives each image exactly what a
+    single-image solve gives it."""
+    ws = [synth.pixel_twin(synth.VORONOI1024).scaled(96, 72), synth.pixel_twin(synth.VORONOI1024).scaled(64, 80, N=3)]
+    probs = [acseg.Problem.from_workload(w, levels=1, steps=3, max_cycles=40, tol=1e-6,
+                                         flags=acseg.FLAG_SOR | acseg.FLAG_FIXED_CYCLES) for w in ws]
+    made = [w.make(11 + k) for k, w in enumerate(ws)]
+    us = [cuda(m[1]) for m in made]
+    _, cs, st = acseg.solve_batched(probs, [cuda(m[0]) for m in made], us)
+    assert all(x["status"] == acseg.OK for x in st), st
+    for p, m, u, c in zip(probs, made, us, cs):
+        u1, c1, s1, _ = acseg.solve(p, cuda(m[0]), cuda(m[1]))
+        torch.cuda.synchronize()
+        assert s1["status"] == acseg.OK, s1
+        assert torch.equal(u, u1) and torch.equal(c, c1)
