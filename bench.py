@@ -255,7 +255,7 @@ def run_adjoint(args):
     U0 = torch.from_numpy(u0_np).to(dev)
     y = torch.from_numpy(np.stack([(lab == i) for i in range(w.N)]).astype(np.float32)).to(dev)
     p = acseg.Problem.from_workload(w, C=3, levels=args.levels, max_cycles=args.max_cycles,
-                                    flags=acseg.FLAG_SSC if args.ssc else 0)
+                                    flags=(acseg.FLAG_SSC if args.ssc else 0) | (acseg.FLAG_SOR if args.sor else 0))
     st = {}
 
     def forward():
@@ -281,7 +281,7 @@ def run_adjoint(args):
     u, ck = forward()
     _, _, _, _, bst = acseg.backward(p, I, ck, 2 * (u - y))
     _, _, fst, _ = acseg.solve(p, I, U0.clone())
-    out = {"metric": f"adjoint: forward+backward time per segmentation ({w.name})",
+    out = {"metric": f"adjoint: forward+backward time per segmentation ({w.name}{'_sor' if args.sor else ''})",
            "value": round(t_fb * 1e3, 3), "unit": "ms", "n_gpus": 1, "steps": k, "warmup": 1,
            "ms_per_step": round(t_fb * 1e3, 3), "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
