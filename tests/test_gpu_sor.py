@@ -80,3 +80,48 @@ def test_batched_sor_equals_single_image_solves():
         torch.cuda.synchronize()
         assert s1["status"] == acseg.OK, s1
         assert torch.equal(u, u1) and torch.equal(c, c1)
+
+
+def test_backward_through_an_over_relaxed_forward():
+    """A solve with over-relaxed sweeps reaches the same steps, so its checkpoints
+    give the oracle adjoint's gradients (the oracle runs on those checkpoints)."""
+    from dataclasses import replace
+    from test_gpu_adjoint import rel_err, setup
+    w, p, img, u0, y = setup(True, 40, 32, 3, 3, 3, 1500)
+    p = replace(p, flags=p.flags | acseg.FLAG_SOR)
+    I = cuda(img)
+    u, _, st, ck = acseg.solve(p, I, cuda(u0), checkpoints=True)
+    assert st["status"] == acseg.OK, st
+    gT = 2 * (u - cuda(y))
+    gI, gu0, gp, gc, bst = acseg.backward(p, I, ck, gT)
+    torch.cuda.synchronize()
+    assert bst["status"] == acseg.OK, bst
+    P = orc.Params.from_workload(w, C=3, tol=1e-12, levels=1)
+    Ibar, grads, cbar, ubar0 = orc.backward(P, 3, img, host(ck), host(gT))
+    assert rel_err(host(gI), Ibar) <= 2e-3 and rel_err(host(gu0), ubar0) <= 2e-3
+    g = gp.cpu().numpy()
+    for k in range(3):
+        assert abs(g[k] - grads[k]) <= 2e-3 * abs(grads[k]) + 1e-9, (k, g[k], grads[k])
+
+
+def test_over_relaxed_fixed_schedule_solve_replays_equal_eager():
+    w = synth.pixel_twin(synth.VORONOI1024, 96)
+    p = acseg.Problem.from_workload(w, levels=1, steps=3, max_cycles=12,
+                                    flags=acseg.FLAG_FIXED_CYCLES | acseg.FLAG_SOR)
+    img, u0, _ = w.make(4)
+    I, U0 = cuda(img), cuda(u0)
+    u_ref, c_ref, st, _ = acseg.solve(p, I, U0.clone())
+    assert st["status"] in (acseg.OK, acseg.WARN_NOT_CONVERGED), st
+    u = U0.clone()
+    acseg.solve(p, I, u, want_stats=False)  # warm-up (workspace, code objects)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        u.copy_(U0)
+        _, c, _, _ = acseg.solve(p, I, u, want_stats=False)
+    for k in range(3):
+        u.fill_(0.25)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(u, u_ref) and torch.equal(c, c_ref), k
