@@ -96,7 +96,9 @@ typedef int32_t acseg_status;
  * acseg_solve wait for the stream while they run.  With this flag they instead
  * enqueue all max_cycles cycles of every step at once, which exit on the
  * device after convergence (no host wait; each skipped launch still costs a
- * few microseconds).  acseg_solve_batched always works this way.
+ * few microseconds).  acseg_solve_batched always works this way.  With this
+ * flag and stats == NULL, acseg_solve enqueues only kernels and device copies,
+ * so it can be captured in a HIP graph whose converged cycles exit on the device.
  */
 #define ACSEG_FLAG_NO_HOST_WAIT 8u
 /*

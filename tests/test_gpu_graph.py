@@ -1,10 +1,11 @@
-"""A fixed-schedule solve captured in a HIP graph (through torch.cuda.graph).
+"""Solves captured in a HIP graph (through torch.cuda.graph).
 
-With ACSEG_FLAG_FIXED_CYCLES and no statistics, acseg_solve enqueues kernels
-and device copies only (control blocks are cleared by a kernel, never by a
-memset), so a caller can capture a whole solve and replay it.  Each replay,
-with eager work and synchronisations between replays, must reproduce the
-eager solve bit for bit.
+With ACSEG_FLAG_FIXED_CYCLES, or ACSEG_FLAG_NO_HOST_WAIT (every cycle enqueued,
+converged ones exiting on the device), and no statistics, acseg_solve enqueues
+kernels and device copies only (control blocks are cleared by a kernel, never
+by a memset), so a caller can capture a whole solve and replay it.  Each
+replay, with eager work and synchronisations between replays, must reproduce
+the eager solve bit for bit.
 """
 import numpy as np
 import pytest
@@ -16,14 +17,17 @@ from test_gpu_parity import cuda
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("levels", [1, 0])
-def test_fixed_schedule_solve_replays_equal_eager(levels):
+@pytest.mark.parametrize("levels,early_exit", [(1, False), (0, False), (1, True), (0, True)])
+def test_fixed_schedule_solve_replays_equal_eager(levels, early_exit):
+    # early_exit: an adaptive schedule with every cycle enqueued (NO_HOST_WAIT); the
+    # cycles after a step converges exit on the device, inside the graph too
+    sched = acseg.FLAG_NO_HOST_WAIT if early_exit else acseg.FLAG_FIXED_CYCLES
     if levels == 1:
         w = synth.VORONOI1024.scaled(160, 120)
-        p = acseg.Problem.from_workload(w, levels=1, steps=4, max_cycles=2, flags=acseg.FLAG_FIXED_CYCLES)
+        p = acseg.Problem.from_workload(w, levels=1, steps=4, max_cycles=6 if early_exit else 2, flags=sched)
     else:
         w = synth.pixel_twin(synth.VORONOI1024, 96)
-        p = acseg.Problem.from_workload(w, levels=0, steps=3, max_cycles=20, flags=acseg.FLAG_FIXED_CYCLES)
+        p = acseg.Problem.from_workload(w, levels=0, steps=3, max_cycles=20, flags=sched)
     img, u0, _ = w.make(2)
     I, U0 = cuda(img), cuda(u0)
     u_ref, c_ref, st, _ = acseg.solve(p, I, U0.clone())
