@@ -19,12 +19,15 @@
 // least two finest nodes apart, so no node of one is a 5-point neighbour of a
 // node of the other: the four parity classes of (X, Y) are four launches, and
 // the functions of one launch update in place without touching each other's
-// reads.  One workgroup per function: its threads stride over the support's
-// bounding box, reduce, and every thread applies the same alpha.  On the
-// coarsest levels a class holds few functions with large supports, so there a
-// function's box is cut into chunks of rows: one launch writes each chunk's
-// partial sums, a second one recomputes alpha from all partials of the
-// function (the same order in every workgroup) and updates the chunk.
+// reads.  The lanes serving a function stride over its support's bounding
+// box, reduce, and all apply the same alpha.  By support size:
+//   * small (levels 1-3): a group of 16 or 64 lanes per function, several
+//     functions per workgroup, xor-butterfly reductions inside the group;
+//   * medium (level 4): one workgroup per function;
+//   * large (coarsest levels): a class holds few functions, so a function's
+//     box is cut into chunks of rows: one launch writes each chunk's partial
+//     sums, a second one recomputes alpha from all partials of the function
+//     (the same order in every workgroup) and updates the chunk.
 //
 // Units as the multigrid path: the level is scaled by 1/h^2 of the finest
 // spacing, the residual is D_p (y_p - u_p) with y_p the smoother's nodal map,
