@@ -411,8 +411,12 @@ def main():
     img, u0, u = imgs[0], u0s[0], us[0]
 
     ssc_flag = (acseg.FLAG_SSC if args.ssc else 0) | (acseg.FLAG_SOR if args.sor else 0)
+    # a workload's tolerance below 1e-6 is the FP64 oracle's; the FP32 solve stops at 1e-6,
+    # above its rounding floor of about 1e-7
+    gpu_tol = max(w.tol, 1e-6)
     base = acseg.Problem.from_workload(w, C=C, levels=args.levels, nu_pre=args.nu[0],
-                                       nu_post=args.nu[1], max_cycles=args.max_cycles, flags=ssc_flag)
+                                       nu_post=args.nu[1], max_cycles=args.max_cycles, flags=ssc_flag,
+                                       tol=gpu_tol)
 
     # consistent-mass fitting: the solver runs on M I / m, computed per segmentation
     # into a fixed buffer per image
@@ -431,7 +435,7 @@ def main():
                                 "flags": acseg.FLAG_FIXED_CYCLES | ssc_flag})
     else:
         prob = base
-    log(f"[bench] {w.name}: {w.W}x{w.H} N={w.N} C={C} steps={w.steps} tol={w.tol} "
+    log(f"[bench] {w.name}: {w.W}x{w.H} N={w.N} C={C} steps={w.steps} tol={gpu_tol} "
         f"schedule={args.schedule} cycles/step<={cycles} batch={B}")
 
     def segment():
@@ -623,7 +627,7 @@ def main():
                    "batch": B,
                    "W": w.W, "H": w.H, "N": w.N, "C": C,
                    "time_steps": w.steps, "lambda": w.lam, "h": w.h, "eps": w.eps, "tau": w.tau,
-                   "tol": w.tol, "levels": prob.levels, "sweeps_per_cycle": prob.nu_pre + prob.nu_post,
+                   "tol": gpu_tol, "levels": prob.levels, "sweeps_per_cycle": prob.nu_pre + prob.nu_post,
                    "coarse_correction": ("subspace correction" if args.ssc else "truncated") if prob.levels != 1 else None,
                    "schedule": args.schedule, "cycles_per_step_max": cycles,
                    "cycles_total": st_run["cycles_total"], "final_residual": st_run["final_residual"]},
