@@ -5,8 +5,9 @@ never by the product path.  Plain numpy, no code shared with the HIP kernels.
 
 Parity status: pinned by ``tests/test_oracle_data.py`` (the paper's injection
 rule checked node by node, invariants of the colour transform, continuity at
-its knots, and published values of the sRGB primaries); none is "parity
-unpinned".
+its knots, published values of the sRGB primaries, the consistent and
+by-simplex projections against each other and against steps assembled from
+their definitions); none is "parity unpinned".
 """
 from __future__ import annotations
 
@@ -112,3 +113,31 @@ def mass_average(img: np.ndarray, h: float = 1.0) -> np.ndarray:
     M = mass_matrix(W, H, h)
     m = np.asarray(M.sum(axis=1)).ravel()
     return np.stack([(M @ img[k].ravel()) / m for k in range(C)]).reshape(C, H, W)
+
+
+def simplex_average(img: np.ndarray, h: float = 1.0) -> np.ndarray:
+    """The image as "projection by simplex" sees it (Section "Data Projection").
+
+    The image enters only through its integral over each element, so it is
+    replaced by one value per triangle, I_t = its integral over t divided by |t|:
+    for the P1 interpolant of the nodal data, the mean of the three vertex
+    values.  The load vector is (M I)_p = sum_{t at p} I_t <eta_p, 1>_t =
+    sum_t I_t |t| / 3 (the basis functions sum to one on t), and the nodal value
+    is (M I)_p / m_p with m_p = sum_t |t| / 3 the lumped mass.  Assembled
+    element by element over the lattice cells, each split along its
+    (x, y)-(x+1, y+1) diagonal.
+    """
+    img = np.asarray(img, dtype=np.float64)
+    C, H, W = img.shape
+    load = np.zeros((C, H, W))
+    m = np.zeros((H, W))
+    area = h * h / 2.0
+    for cy in range(H - 1):
+        for cx in range(W - 1):
+            for tri in (((cx, cy), (cx + 1, cy), (cx + 1, cy + 1)),
+                        ((cx, cy), (cx, cy + 1), (cx + 1, cy + 1))):
+                It = sum(img[:, y, x] for x, y in tri) / 3.0
+                for x, y in tri:
+                    load[:, y, x] += area / 3.0 * It
+                    m[y, x] += area / 3.0
+    return load / m

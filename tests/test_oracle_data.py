@@ -145,3 +145,74 @@ def test_consistent_mass_fitting_is_the_lumped_solver_on_the_mass_average():
     u_red, s2 = orc.solve_qp(P, b_red, un)
     assert s1["converged"] and s2["converged"]
     assert np.abs(u_cons - u_red).max() < 1e-9
+
+
+def test_simplex_average_invariants_and_relation_to_the_mass_matrix():
+    """Projection by simplex: constants and (at interior nodes) linear functions
+    are kept, and per triangle (I_p + I_a + I_b) / 9 = (4/3) (2 I_p + I_a + I_b) / 12
+    - I_p / 9, so the by-simplex value is (4/3) (M I) / m - I / 3 with M the
+    consistent mass matrix assembled independently."""
+    W, H, h = 8, 6, 0.7
+    Y, X = np.mgrid[0:H, 0:W].astype(np.float64)
+    img = np.stack([np.full((H, W), -0.4), 0.3 * X + 0.2 * Y - 1.0])
+    sa = od.simplex_average(img, h)
+    assert np.allclose(sa[0], -0.4)
+    assert np.allclose(sa[1][1:-1, 1:-1], img[1][1:-1, 1:-1])
+    rng = np.random.default_rng(11)
+    img = rng.random((3, H, W))
+    sa = od.simplex_average(img, h)
+    ca = od.mass_average(img, h)
+    np.testing.assert_allclose(sa, 4.0 / 3.0 * ca - img / 3.0, atol=1e-14)
+
+
+def test_simplex_projection_fitting_is_the_lumped_solver_on_the_simplex_average():
+    """Fitting with the image replaced by its element values I_t (projection by
+    simplex): the fidelity gradient sum_t (I_t - c_i)^2 |t| / 3 at each node and
+    the means int u_i I / int u_i, built element by element, give the same step
+    as the lumped oracle on the simplex average (the right-hand sides differ by a
+    term common to all phases at each node)."""
+    import oracle as orc
+    from paper_0710_0736_amd import synth
+    W, H, N, C, h = 8, 7, 3, 2, 0.3
+    P = orc.Params(H=H, W=W, C=C, N=N, h=h, eps=2 * h, lam=20.0, tau=(2 * h) ** 2, levels=1, tol=1e-12)
+    rng = np.random.default_rng(7)
+    img = rng.random((C, H, W))
+    un = synth.random_simplex_field(N, H, W, seed=8).astype(np.float64)
+    area = h * h / 2.0
+    tris = []
+    for cy in range(H - 1):
+        for cx in range(W - 1):
+            tris.append(((cx, cy), (cx + 1, cy), (cx + 1, cy + 1)))
+            tris.append(((cx, cy), (cx, cy + 1), (cx + 1, cy + 1)))
+    It = np.array([[sum(img[k, y, x] for x, y in t) / 3.0 for k in range(C)] for t in tris])
+    m = np.zeros((H, W))
+    for t in tris:
+        for x, y in t:
+            m[y, x] += area / 3.0
+    # means: int u_i I = sum_t I_t int_t u_i, int_t u_i = |t| (u_a + u_b + u_c) / 3
+    c_el = np.zeros((N, C))
+    for i in range(N):
+        mass = (m * un[i]).sum()
+        for ti, t in enumerate(tris):
+            ut = sum(un[i, y, x] for x, y in t) / 3.0
+            c_el[i] += It[ti] * area * ut
+        c_el[i] /= mass
+    a = 1.0 / P.tau + 2.0 / P.eps
+    b_el = np.empty((N, H, W))
+    for i in range(N):
+        g = np.zeros((H, W))
+        for ti, t in enumerate(tris):
+            f = ((It[ti] - c_el[i]) ** 2).sum()
+            for x, y in t:
+                g[y, x] += area / 3.0 * f
+        b_el[i] = m * a * un[i] - P.lam * g
+    Is = od.simplex_average(img, h)
+    c_red, _ = orc.colour_means(P, Is, un)
+    assert np.abs(c_red - c_el).max() < 1e-12
+    b_red = orc.rhs(P, Is, un, c_red)
+    d = b_el - b_red
+    assert np.abs(d - d[0:1]).max() < 1e-10 * np.abs(b_el).max()
+    u_el, s1 = orc.solve_qp(P, b_el, un)
+    u_red, s2 = orc.solve_qp(P, b_red, un)
+    assert s1["converged"] and s2["converged"]
+    assert np.abs(u_el - u_red).max() < 1e-9
