@@ -368,6 +368,8 @@ def main():
                     help="only time segmentation on R uniform refinements of a pixel image "
                          "(--refine-pixels square, N = 4, eps half a pixel)")
     ap.add_argument("--refine-pixels", type=int, default=128)
+    ap.add_argument("--simplex-projection", action="store_true",
+                    help="fitting with projection by simplex (the by-simplex view of each image, per segmentation)")
     ap.add_argument("--consistent-mass", action="store_true",
                     help="fitting with the consistent mass matrix (the solver runs on M I / m)")
     args = ap.parse_args()
@@ -421,7 +423,12 @@ def main():
     # consistent-mass fitting: the solver runs on M I / m, computed per segmentation
     # into a fixed buffer per image
     avg = {id(x): torch.empty_like(x) for x in imgs}
-    prep = (lambda x: acseg.mass_average(x, out=avg[id(x)])) if args.consistent_mass else (lambda x: x)
+    if args.consistent_mass:
+        prep = lambda x: acseg.mass_average(x, out=avg[id(x)])  # noqa: E731
+    elif args.simplex_projection:
+        prep = lambda x: acseg.simplex_average(x, out=avg[id(x)])  # noqa: E731
+    else:
+        prep = lambda x: x  # noqa: E731
     # calibration: how many cycles does the slowest time step of any image need?
     cycles = max(1, args.cycles)
     for b in (range(B) if args.cycles == 0 else ()):
@@ -559,7 +566,8 @@ def main():
             w.N, C, n, launches_per_cycle(prob.levels, prob.nu_pre, prob.nu_post),
             cycles if fixed else st_run["cycles_total"] / w.steps, fixed)
         achieved = bytes_per_launch / avg_s / 1e9
-        tkey = (w.name + ("_consistent_mass" if args.consistent_mass else ""), B, cycles, prob.levels,
+        tkey = (w.name + ("_consistent_mass" if args.consistent_mass else "")
+                + ("_simplex_projection" if args.simplex_projection else ""), B, cycles, prob.levels,
                 prob.nu_pre + prob.nu_post)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": (int(TRAFFIC[tkey]) if fixed and tkey in TRAFFIC else None),
@@ -623,6 +631,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name + ("_consistent_mass" if args.consistent_mass else "")
+                               + ("_simplex_projection" if args.simplex_projection else "")
                                + ("_ssc" if args.ssc and prob.levels != 1 else "") + ("_sor" if args.sor else ""),
                    "batch": B,
                    "W": w.W, "H": w.H, "N": w.N, "C": C,

@@ -274,6 +274,23 @@ acseg_status acseg_mass_average(acseg_ctx *ctx, int32_t planes, int32_t W, int32
                                 const float *src, float *dst, void *stream);
 
 /*
+ * The image as "projection by simplex" sees it (Section "Data Projection": the
+ * image enters the fidelity terms only through its integral over each
+ * element).  Each triangle carries one value, the mean of its three vertex
+ * values (the integral of the P1 interpolant over it divided by its area);
+ * the load (M I)_p = sum over the triangles at p of that value times |T|/3,
+ * and dst_p = (M I)_p / m_p, the mean of the values of the triangles at p
+ * (cells split along (x,y)-(x+1,y+1)).  Inside the lattice this is I_p / 3
+ * plus 1/9 of the six neighbours sharing a triangle.  Fitting with the
+ * element values is the lumped solver run on dst: the right-hand sides differ
+ * per node by a term common to all phases and the colour means agree.
+ *   src, dst  float[planes][H][W] (device), not overlapping; W, H >= 2,
+ *   W * H <= 2^30, planes >= 1 (ACSEG_ERR_INVALID_ARG otherwise).
+ */
+acseg_status acseg_simplex_average(acseg_ctx *ctx, int32_t planes, int32_t W, int32_t H,
+                                   const float *src, float *dst, void *stream);
+
+/*
  * Colour-space pre-pass (Section "Two Dimensional Examples", multi-channel
  * data: the model takes any colour space and number of channels, and L*a*b*
  * with the luminosity ignored is suggested in place of RGB).  rgb

@@ -120,6 +120,7 @@ def lib():
                                    vp, vp, vp]
         L.acseg_colour_space.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp]
         L.acseg_mass_average.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+        L.acseg_simplex_average.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
         L.acseg_colour_means.argtypes = [vp, pp, vp, vp, vp, vp, sp, vp, sz, vp]
         L.acseg_step.argtypes = [vp, pp, vp, vp, vp, vp, vp, sp, vp, sz, vp]
         L.acseg_solve.argtypes = [vp, pp, vp, vp, vp, vp, sp, vp, sz, vp]
@@ -262,6 +263,18 @@ def mass_average(img: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch
     _need(dst, (planes, H, W), name="out")
     _check(lib().acseg_mass_average(ctx(img.device.index), planes, W, H, _ptr(img), _ptr(dst), _stream()),
            "acseg_mass_average")
+    return dst
+
+
+def simplex_average(img: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """The by-simplex view of the image (mean of the adjacent triangles' vertex
+    means): run the solver on it for fitting with projection by simplex."""
+    planes, H, W = img.shape
+    _need(img, (planes, H, W), name="img")
+    dst = torch.empty_like(img) if out is None else out
+    _need(dst, (planes, H, W), name="out")
+    _check(lib().acseg_simplex_average(ctx(img.device.index), planes, W, H, _ptr(img), _ptr(dst), _stream()),
+           "acseg_simplex_average")
     return dst
 
 

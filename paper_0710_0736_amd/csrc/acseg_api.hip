@@ -794,7 +794,14 @@ acseg_status acseg_mass_average(acseg_ctx* ctx, int32_t planes, int32_t W, int32
                                 float* dst, void* stream) {
     if (!ctx || planes < 1 || W < 2 || H < 2 || !src || !dst || (int64_t)W * H > ((int64_t)1 << 30))
         return ACSEG_ERR_INVALID_ARG;
-    return hip_status(launch_mass_avg(planes, W, H, src, dst, (hipStream_t)stream));
+    return hip_status(launch_mass_avg(planes, W, H, src, dst, 0, (hipStream_t)stream));
+}
+
+acseg_status acseg_simplex_average(acseg_ctx* ctx, int32_t planes, int32_t W, int32_t H, const float* src,
+                                   float* dst, void* stream) {
+    if (!ctx || planes < 1 || W < 2 || H < 2 || !src || !dst || (int64_t)W * H > ((int64_t)1 << 30))
+        return ACSEG_ERR_INVALID_ARG;
+    return hip_status(launch_mass_avg(planes, W, H, src, dst, 1, (hipStream_t)stream));
 }
 
 acseg_status acseg_colour_space(acseg_ctx* ctx, int32_t kind, int64_t count, const float* rgb, float* dst,

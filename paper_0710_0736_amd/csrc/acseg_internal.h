@@ -281,7 +281,7 @@ hipError_t launch_transfer(int planes, int dir, const float* src, float* dst, in
 hipError_t launch_refine(int planes, int W, int H, int r, const float* src, float* dst, hipStream_t s);
 hipError_t launch_sample(int planes, int W, int H, int r, const float* src, float* dst, hipStream_t s);
 hipError_t launch_lab(int ab_only, int64_t count, const float* rgb, float* dst, hipStream_t s);
-hipError_t launch_mass_avg(int planes, int W, int H, const float* src, float* dst, hipStream_t s);
+hipError_t launch_mass_avg(int planes, int W, int H, const float* src, float* dst, int simplex, hipStream_t s);
 
 // ---- launchers (kernels_adjoint.hip): gradients through the time steps ------
 

@@ -1,5 +1,5 @@
-// kernels_data.hip -- image data on refined lattices, the consistent-mass view
-// of the image, and the colour-space pre-pass.  Each is one pass over the data
+// kernels_data.hip -- image data on refined lattices, the consistent-mass and
+// by-simplex views of the image, and the colour-space pre-pass.  Each is one pass over the data
 // (HBM bound).
 #include <algorithm>
 
@@ -82,7 +82,12 @@ __global__ __launch_bounds__(kBlock) void k_lab(const float* __restrict__ rgb, f
 // p with other vertices a, b adds |T|/12 (2 I_p + I_a + I_b) to (M I)_p and
 // |T|/3 to the lumped mass m_p, so (M I)_p / m_p is the sum over the n_T
 // triangles at p of (2 I_p + I_a + I_b), divided by 4 n_T (6 triangles inside;
-// fewer on the boundary, at least one).  One workgroup per row.
+// fewer on the boundary, at least one).
+// SIMPLEX: projection by simplex instead.  Each triangle carries one value, the
+// mean (I_p + I_a + I_b) / 3 of its vertices (its integral over |T|), and adds
+// |T|/3 of it to node p's load, so the nodal value is the sum over the n_T
+// triangles of (I_p + I_a + I_b), divided by 3 n_T.  One workgroup per row.
+template <bool SIMPLEX>
 __global__ __launch_bounds__(kBlock) void k_mass_avg(const float* __restrict__ src, float* __restrict__ dst,
                                                      int W, int H, int planes) {
     const int64_t n = (int64_t)W * H;
@@ -96,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void k_mass_avg(const float* __restrict__ s
         const float* ru = y < H - 1 ? r0 + W : r0;       // row y + 1
         for (int x = threadIdx.x; x < W; x += kBlock) {
             const bool L = x > 0, R = x < W - 1, D = y > 0, U = y < H - 1;
-            const float ip2 = 2.f * r0[x];
+            const float ip2 = SIMPLEX ? r0[x] : 2.f * r0[x];
             float acc = 0.f;
             int nt = 0;
             if (L && D) {  // cell (x-1, y-1): both triangles have p as their (x+1, y+1) corner
@@ -115,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_mass_avg(const float* __restrict__ s
                 acc += (ip2 + r0[x + 1] + ru[x + 1]) + (ip2 + ru[x] + ru[x + 1]);
                 nt += 2;
             }
-            d[x] = acc / (float)(4 * nt);
+            d[x] = acc / (float)((SIMPLEX ? 3 : 4) * nt);
         }
     }
 }
@@ -138,9 +143,13 @@ hipError_t launch_sample(int planes, int W, int H, int r, const float* src, floa
     return hipGetLastError();
 }
 
-hipError_t launch_mass_avg(int planes, int W, int H, const float* src, float* dst, hipStream_t s) {
-    hipLaunchKernelGGL(k_mass_avg, dim3(row_blocks((int64_t)H * planes)), dim3(kBlock), 0, s, src, dst, W, H,
-                       planes);
+hipError_t launch_mass_avg(int planes, int W, int H, const float* src, float* dst, int simplex, hipStream_t s) {
+    if (simplex)
+        hipLaunchKernelGGL(k_mass_avg<true>, dim3(row_blocks((int64_t)H * planes)), dim3(kBlock), 0, s, src, dst,
+                           W, H, planes);
+    else
+        hipLaunchKernelGGL(k_mass_avg<false>, dim3(row_blocks((int64_t)H * planes)), dim3(kBlock), 0, s, src, dst,
+                           W, H, planes);
     return hipGetLastError();
 }
 

@@ -164,3 +164,66 @@ def test_consistent_mass_step_matches_oracle():
     assert st["final_residual"] <= 1e-6, st
     assert np.abs(host(c_g) - c).max() < 1e-5
     assert np.abs(host(u_g) - u_ref).max() <= 1e-4
+
+
+@pytest.mark.parametrize("W,H,P", [(2, 2, 1), (5, 3, 2), (130, 67, 3), (257, 9, 1)])
+def test_simplex_average_matches_oracle(W, H, P):
+    rng = np.random.default_rng(W * H + P + 1)
+    img = rng.random((P, H, W)).astype(np.float32)
+    got = host(acseg.simplex_average(cuda(img)))
+    ref = od.simplex_average(img.astype(np.float64), 1.0)
+    assert np.abs(got - ref).max() < 1e-6
+
+
+def test_simplex_average_rejects_bad_sizes():
+    L = acseg.lib()
+    x = torch.zeros(16, device=DEV)
+    cx, p = acseg.ctx(0), x.data_ptr()
+    assert L.acseg_simplex_average(cx, 1, 1, 4, p, p, None) == acseg.ERR_INVALID_ARG
+    assert L.acseg_simplex_average(cx, 0, 2, 2, p, p, None) == acseg.ERR_INVALID_ARG
+
+
+def test_simplex_projection_step_matches_oracle():
+    """A GPU step on the by-simplex view against the oracle step assembled element
+    by element (element values I_t, means int u_i I / int u_i, gradient
+    sum_t (I_t - c_i)^2 |t| / 3), solved by the oracle's own QP solver."""
+    W, H, N, C, h = 41, 33, 3, 3, 1.0
+    kw = dict(H=H, W=W, C=C, N=N, h=h, eps=2 * h, lam=40.0, tau=(2 * h) ** 2)
+    P = orc.Params(levels=0, tol=1e-12, **kw)
+    img, _ = synth.voronoi_image(W, H, N, 0.1, seed=10, channels=C)
+    img64 = img.astype(np.float64)
+    un = synth.random_simplex_field(N, H, W, seed=11).astype(np.float32)
+    un64 = un.astype(np.float64)
+    area = h * h / 2.0
+    m = np.zeros((H, W))
+    num = np.zeros((N, C))
+    mass = np.zeros(N)
+    tris = []
+    for cy in range(H - 1):
+        for cx in range(W - 1):
+            for t in (((cx, cy), (cx + 1, cy), (cx + 1, cy + 1)), ((cx, cy), (cx, cy + 1), (cx + 1, cy + 1))):
+                It = sum(img64[:, y, x] for x, y in t) / 3.0
+                tris.append((t, It))
+                for x, y in t:
+                    m[y, x] += area / 3.0
+                for i in range(N):
+                    num[i] += It * area * sum(un64[i, y, x] for x, y in t) / 3.0
+    for i in range(N):
+        mass[i] = (m * un64[i]).sum()
+    c = num / mass[:, None]
+    a = 1.0 / P.tau + 2.0 / P.eps
+    b = np.stack([m * a * un64[i] for i in range(N)])
+    for t, It in tris:
+        for i in range(N):
+            f = ((It - c[i]) ** 2).sum()
+            for x, y in t:
+                b[i, y, x] -= P.lam * area / 3.0 * f
+    u_ref, st_ref = orc.solve_qp(P, b, un64)
+    assert st_ref["converged"]
+    p = acseg.Problem(steps=1, levels=1, tol=1e-6, max_cycles=400, **kw)
+    Is = acseg.simplex_average(cuda(img))
+    u_g, c_g, st = acseg.step(p, Is, cuda(un))
+    torch.cuda.synchronize()
+    assert st["final_residual"] <= 1e-6, st
+    assert np.abs(host(c_g) - c).max() < 1e-5
+    assert np.abs(host(u_g) - u_ref).max() <= 1e-4
