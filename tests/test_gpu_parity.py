@@ -303,3 +303,26 @@ def test_adaptive_chunks_equal_device_only_schedule(levels):
     torch.cuda.synchronize()
     assert st_a["status"] == acseg.OK and st_a == st_b, (st_a, st_b)
     assert torch.equal(u_a, u_b) and torch.equal(c_a, c_b)
+
+
+def test_workspace_too_small_or_misaligned_is_refused():
+    """acseg_solve checks the caller's workspace on the host and enqueues nothing
+    when it is too small or not aligned (ACSEG_ERR_WORKSPACE)."""
+    import ctypes
+    w = synth.VORONOI1024.scaled(64, 48)
+    p = gpu_problem(w, steps=2, max_cycles=2)
+    img, u0, _ = w.make(0)
+    I, U = cuda(img), cuda(u0)
+    c = torch.empty((p.N, p.C), dtype=torch.float32, device="cuda")
+    n = acseg.workspace_size(p)
+    ws = torch.empty(n + 512, dtype=torch.uint8, device="cuda")
+    L, cx, pc = acseg.lib(), acseg.ctx(0), ctypes.byref(p.c())
+    base = ws.data_ptr()
+    call = lambda ptr, size: L.acseg_solve(cx, pc, I.data_ptr(), U.data_ptr(), c.data_ptr(), None, None,  # noqa: E731
+                                           ptr, size, None)
+    assert call(base, n - 1) == acseg.ERR_WORKSPACE
+    assert call(base + 4, n) == acseg.ERR_WORKSPACE
+    assert call(None, n) == acseg.ERR_WORKSPACE
+    assert torch.equal(U, cuda(u0))  # nothing ran
+    assert call(base, n) == acseg.OK
+    torch.cuda.synchronize()
