@@ -326,3 +326,43 @@ def test_workspace_too_small_or_misaligned_is_refused():
     assert torch.equal(U, cuda(u0))  # nothing ran
     assert call(base, n) == acseg.OK
     torch.cuda.synchronize()
+
+
+def _red_black_sweeps(P, b, u, sweeps):
+    """Global red-black projected block Gauss-Seidel written plainly (FP64): every
+    node of one colour ((x + y) even first) takes Pi_G(u_p + (b_p - (H u)_p) / D_p)
+    from the current neighbours, then every node of the other colour."""
+    from test_oracle_projection import proj_sort
+    m, s = orc.assemble(P.W, P.H, P.h)
+    D = m / P.tau + P.eps * s[:, :, 1, 1]
+    Y, X = np.mgrid[0:P.H, 0:P.W]
+    u = u.copy()
+    for _ in range(sweeps):
+        for colour in (0, 1):
+            Hu = orc.apply_H(P, u)
+            y = u + (b - Hu) / D[None]
+            for yy, xx in zip(*np.nonzero((X + Y) % 2 == colour)):
+                u[:, yy, xx] = proj_sort(y[:, yy, xx])
+    return u
+
+
+@pytest.mark.parametrize("w,N", [(synth.VORONOI1024.scaled(150, 70), 4), (synth.VORONOI1024.scaled(131, 75), 3),
+                                 (synth.pixel_twin(synth.VORONOI1024).scaled(150, 70), 4)],
+                         ids=["unit-N4", "unit-N3", "pixel-N4"])
+def test_one_cycle_is_two_global_red_black_sweeps(w, N):
+    """The fused step kernel's temporal blocking (two sweeps per launch on tiles
+    with a recomputed halo) reproduces two global red-black sweeps exactly, up
+    to FP32 rounding: one fixed cycle of a step against the plain sweeps from
+    the same right-hand side."""
+    w = w.scaled(w.W, w.H, N=N)
+    img, u0, _ = w.make(3)
+    u0 = np.asarray(u0, np.float32)
+    P = orc_params(w, levels=1)
+    c, _ = orc.colour_means(P, img, u0)
+    b = orc.rhs(P, img, u0, c)
+    ref = _red_black_sweeps(P, b, u0.astype(np.float64), 2)
+    p = gpu_problem(w, levels=1, max_cycles=1, nu_pre=1, nu_post=1, flags=acseg.FLAG_FIXED_CYCLES)
+    u_g, _, st = acseg.step(p, cuda(img), cuda(u0))
+    torch.cuda.synchronize()
+    assert st["cycles_max"] == 1, st
+    assert np.abs(host(u_g) - ref).max() < 2e-5
