@@ -100,3 +100,28 @@ def test_multigrid_two_levels_and_odd_sizes():
     img, u0, _ = w.make(9)
     for levels in (2, 3):
         check_step(w, img, u0, levels=levels, max_cycles=400)
+
+
+@pytest.mark.parametrize("flags", [0, acseg.FLAG_SSC, acseg.FLAG_SOR], ids=["truncated", "ssc", "sor"])
+def test_cycles_never_raise_the_step_objective(flags):
+    """Every cycle (smoothing sweeps and the coarse correction) is a descent step
+    of the step's strictly convex objective J: J after k + 1 fixed cycles is at
+    most J after k (evaluated by the oracle in FP64 on the GPU's iterates, with
+    a slack for their FP32 rounding), and it decreases overall."""
+    w = synth.pixel_twin(synth.VORONOI1024).scaled(96, 80, N=4)
+    img, u0, _ = w.make(12)
+    u0 = np.asarray(u0, np.float32)
+    P = orc_params(w, levels=0)
+    c, _ = orc.colour_means(P, img, u0)
+    b = orc.rhs(P, img, u0, c)
+    Js = []
+    for k in range(1, 9):
+        p = gpu_problem(w, levels=0, max_cycles=k, flags=acseg.FLAG_FIXED_CYCLES | flags)
+        u_g, _, st = acseg.step(p, cuda(img), cuda(u0))
+        torch.cuda.synchronize()
+        ug = host(u_g).astype(np.float64)
+        ug /= ug.sum(0, keepdims=True)  # onto the simplices in FP64 (FP32 sums miss 1 by rounding)
+        Js.append(orc.objective(P, b, ug))
+    slack = 1e-6 * abs(Js[0])
+    assert all(Js[k + 1] <= Js[k] + slack for k in range(len(Js) - 1)), Js
+    assert Js[-1] < Js[0]
