@@ -166,3 +166,44 @@ def test_fixed_means_backward_matches_finite_differences(pixel):
     Vu = rng.standard_normal(u0.shape)
     fd = (L(u=u0 + d * Vu) - L(u=u0 - d * Vu)) / (2 * d)
     assert abs(fd - (ubar0 * Vu).sum()) <= 1e-4 * max(abs(fd), 1e-6)
+
+
+def test_differentiation_workload_finite_differences():
+    """The differentiation workload at its own size (512^2 RGB, 4 Voronoi
+    regions, sigma 0.1, N = 4, 20 steps, unit scale) with its finite-difference
+    protocol: central differences of the FP64 forward with step 1e-3, absolute
+    for lambda and for the image along a seeded Rademacher direction (every
+    pixel-channel moves by 1e-3), relative for eps and tau.  The free sets of
+    the +step and -step trajectories are compared component by component
+    over all steps; a flip puts a kink between them, so the count is reported
+    and the agreement is required where there is none."""
+    w = synth.VORONOI512
+    img, u0, lab = w.make(0)
+    img, u0 = img.astype(np.float64), u0.astype(np.float64)
+    P = orc.Params.from_workload(w, C=3, tol=1e-13, levels=1, max_cycles=200000)
+    y = np.stack([(lab == i).astype(np.float64) for i in range(P.N)])
+    uT, traj, _, _ = orc.solve(P, w.steps, img, u0)
+    Ibar, grads, _, _ = orc.backward(P, w.steps, img, traj, 2 * (uT - y))
+
+    def run(Pp=P, I=img):
+        u, tr, _, _ = orc.solve(Pp, w.steps, I, u0)
+        return ((u - y) ** 2).sum(), tr[1:] > 0
+
+    def central(plus, minus, d):
+        (Lp, fp), (Lm, fm) = plus, minus
+        return (Lp - Lm) / (2 * d), int((fp != fm).sum())
+
+    report = {}
+    for k, (name, rel) in enumerate([("lam", False), ("eps", True), ("tau", True)]):
+        v = getattr(P, name)
+        d = 1e-3 * (v if rel else 1.0)
+        fd, flips = central(run(Pp=with_(P, **{name: v + d})), run(Pp=with_(P, **{name: v - d})), d)
+        report[name] = (fd, grads[k], flips)
+    V = synth.rademacher(img.shape, seed=0).astype(np.float64)
+    fd, flips = central(run(I=img + 1e-3 * V), run(I=img - 1e-3 * V), 1e-3)
+    report["image"] = (fd, (Ibar * V).sum(), flips)
+    print("finite differences (fd, adjoint, active-set flips):", report)
+    for name, (fd, an, flips) in report.items():
+        if flips == 0:
+            assert abs(fd - an) <= 1e-3 * abs(fd), (name, fd, an)
+    assert sum(r[2] for r in report.values()) == 0, report
