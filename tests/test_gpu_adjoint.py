@@ -109,3 +109,35 @@ def test_fixed_means_batched_equals_single():
     torch.cuda.synchronize()
     assert torch.equal(us[0], u_s) and torch.equal(us[1], u_s)
     assert sts[0] == st_s
+
+
+def test_differentiation_workload_at_full_size():
+    """The differentiation workload itself (512^2 RGB, 4 Voronoi regions, N = 4,
+    20 steps with every state checkpointed, loss = squared distance of u^20 to
+    the one-hot ground truth): the forward against the oracle's trajectory, and
+    the GPU gradients with respect to the image, u^0, lambda, eps, tau and every
+    step's colour means against the FP64 oracle adjoint run on the GPU's
+    checkpoints.  The oracle adjoint at this size is pinned by central
+    differences in test_oracle_adjoint."""
+    w = synth.VORONOI512
+    img, u0, lab = w.make(0)
+    y = np.stack([(lab == i) for i in range(w.N)]).astype(np.float32)
+    p = acseg.Problem.from_workload(w, C=3, levels=1, tol=1e-6, max_cycles=50)
+    I = cuda(img)
+    u, _, st, ck = acseg.solve(p, I, cuda(u0), checkpoints=True)
+    assert st["status"] == acseg.OK and st["steps_done"] == w.steps, st
+    gT = 2 * (u - cuda(y))
+    gI, gu0, gp, gc, bst = acseg.backward(p, I, ck, gT)
+    torch.cuda.synchronize()
+    assert bst["status"] == acseg.OK and bst["steps_done"] == w.steps, bst
+    assert gc.shape == (w.steps, w.N, 3)
+    P = orc.Params.from_workload(w, C=3, tol=1e-12, levels=1)
+    uT_ref, _, _, _ = orc.solve(P, w.steps, img, u0, keep_trajectory=False)
+    assert np.abs(host(u) - uT_ref).max() <= GATE_U
+    Ibar, grads, cbar, ubar0 = orc.backward(P, w.steps, img, host(ck), host(gT))
+    assert rel_err(host(gI), Ibar) <= 2e-3
+    assert rel_err(host(gu0), ubar0) <= 2e-3
+    assert rel_err(host(gc), cbar) <= 2e-3
+    g = gp.cpu().numpy()
+    for k in range(3):
+        assert abs(g[k] - grads[k]) <= 2e-3 * abs(grads[k]) + 1e-9, (k, g[k], grads[k])

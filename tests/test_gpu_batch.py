@@ -5,6 +5,8 @@ convergence control, and every reduction has a fixed order, so each result
 must be bit-identical to the one-image solve of the same problem.  The
 one-image solve itself is held to the oracle by test_gpu_parity.
 """
+from dataclasses import replace
+
 import numpy as np
 import pytest
 import torch
@@ -99,3 +101,56 @@ def test_segment_and_segment_batch_agree():
         torch.cuda.synchronize()
         assert st["status"] == acseg.OK and res[b][3]["status"] == acseg.OK
         assert torch.equal(res[b][0], u) and torch.equal(res[b][2], lab)
+
+
+def config5_sample(count=10, seed=11):
+    """A sample of the heterogeneous-batch workload at reduced sides: independent
+    sides in [64, 200], noise sigma in [0.02, 0.15], Voronoi regions = N, every
+    phase count 2..6 twice (N = 5 and 6 have kernels of their own), RGB, unit
+    scale, 30 time steps."""
+    ws = synth.batch_workloads(count, seed=seed, min_side=64, max_side=200)
+    return [replace(w, N=2 + b % 5) for b, w in enumerate(ws)]
+
+
+def test_batched_against_oracle_config5_sample():
+    """Each image of a batched solve against the oracle: the final field of 30
+    steps against the oracle's trajectory (max |du| <= 1e-4 and the label
+    gate), and single steps taken by batched solves from the oracle's own
+    states (rounded to float32) at the start, middle and end."""
+    from test_gpu_parity import GATE_U, host, label_gate
+    import oracle as orc
+    ws = config5_sample()
+    assert sorted({w.N for w in ws}) == [2, 3, 4, 5, 6]
+    made = [w.make(b) for b, w in enumerate(ws)]
+    refs = []
+    for w, (img, u0, _) in zip(ws, made):
+        P = orc.Params.from_workload(w, C=3, tol=1e-11, levels=1)
+        _, traj, ct, sts = orc.solve(P, w.steps, img, u0)
+        assert all(s["converged"] for s in sts)
+        refs.append((P, traj, ct))
+    probs = [acseg.Problem.from_workload(w, C=3, levels=1, tol=1e-6, max_cycles=60) for w in ws]
+    us, cs, sts = acseg.solve_batched(probs, [cuda(m[0]) for m in made], [cuda(m[1]) for m in made])
+    torch.cuda.synchronize()
+    for b, (w, (P, traj, ct)) in enumerate(zip(ws, refs)):
+        assert sts[b]["status"] == acseg.OK and sts[b]["steps_done"] == w.steps, (b, sts[b])
+        ug = host(us[b])
+        err = np.abs(ug - traj[-1]).max()
+        assert err <= GATE_U, (b, w.N, w.W, w.H, err)
+        bad, total, raw = label_gate(ug, traj[-1])
+        assert bad <= 1e-3 * total, (b, bad, raw)
+    # per step, from the oracle's states: one batched call per step index
+    one = [acseg.Problem(**{**p.__dict__, "steps": 1}) for p in probs]
+    for n in (0, 15, 29):
+        starts = [np.asarray(traj[n], np.float32) for (_, traj, _) in refs]
+        us, cs, sts = acseg.solve_batched(one, [cuda(m[0]) for m in made], [cuda(s) for s in starts])
+        torch.cuda.synchronize()
+        for b, (w, (P, traj, ct)) in enumerate(zip(ws, refs)):
+            u_ref, c_ref, st_ref = orc.step(P, made[b][0], starts[b], ct[n - 1] if n > 0 else None)
+            assert st_ref["converged"]
+            assert np.abs(host(cs[b]) - orc.colour_means(P, made[b][0], u_ref, c_ref)[0]).max() < 1e-5
+            ug = host(us[b])
+            assert sts[b]["status"] == acseg.OK and sts[b]["final_residual"] <= 1e-6, (n, b, sts[b])
+            err = np.abs(ug - u_ref).max()
+            assert err <= GATE_U, (n, b, w.N, err)
+            bad, total, raw = label_gate(ug, u_ref)
+            assert bad <= 1e-3 * total, (n, b, bad, raw)
