@@ -395,9 +395,13 @@ acseg_status acseg_energy(acseg_ctx *ctx, const acseg_problem *p, const float *i
  * grad_c is float[N][C] = dL/dc_fixed; otherwise c_fixed is ignored.  Each step's
  * derivative holds the free sets {i : u^{n+1}_pi > 0} fixed (components at 0
  * count as active) and treats the kept mean of an empty phase as a constant.
- * The per-step linear solves are red-black sweeps to a relative change of
- * max(tol, 2e-7), at most max(4, 2 max_cycles) sweeps (stats count steps that
- * hit the cap as not converged, and the sweeps as cycles).  The sweeps are
+ * The per-step linear solves are over-relaxed red-black sweeps, stopped when
+ * the change dz of a sweep, with r the observed contraction per sweep (the
+ * ratio of the last two changes, at least omega - 1, at most 0.999),
+ * satisfies dz <= max(tol, 2e-7) max|z| (1 - r), so that the distance to the
+ * solution, at most dz r / (1 - r), is below that relative tolerance; at most
+ * max(4, 2 max_cycles) sweeps (stats count steps that hit the cap as not
+ * converged, and the sweeps as cycles).  The sweeps are
  * enqueued in chunks of 4, 8, ... 64; between chunks the call waits for the
  * stream to read the convergence flag, so it returns with the work done.
  * Workspace from acseg_backward_workspace_size.

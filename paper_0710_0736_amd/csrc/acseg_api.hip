@@ -673,7 +673,7 @@ BackLayout back_layout_of(const acseg_problem* p) {
     L.tot = take(sizeof(double) * S * kCmeansMaxM);
     L.part_cm = take(sizeof(double) * (size_t)kCmeansBlocks * kCmeansMaxM);
     L.part_adj = take(sizeof(double) * (size_t)kMgBlocks * (3 + kNC));
-    L.part_f = take(sizeof(float) * 4 * kMgBlocks);
+    L.part_f = take(sizeof(float) * 6 * kMgBlocks);
     L.cbar = take(sizeof(double) * kNC);
     L.z = take(sizeof(float) * p->N * n);
     L.z2 = take(sizeof(float) * p->N * n);

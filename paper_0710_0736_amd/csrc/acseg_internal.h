@@ -313,7 +313,7 @@ struct AdjArgs {
     double* cbar64;       // [N][C]
     float* cbar_out;      // [N][C] or NULL
     int cbar_accumulate;  // add cbar to cbar_out (fixed means) instead of storing it
-    float* part_f;        // [2 sweep parities][2][kMgBlocks]: max |dz|, max |z| per workgroup
+    float* part_f;        // [3 (sweep mod 3)][2][kMgBlocks]: max |dz|, max |z| per workgroup
     double* part_d;       // [kMgBlocks][3 + N C]
     LevelCoef coef;       // finest level
     float diagA[4];       // stiffness diagonal per node class

@@ -19,8 +19,12 @@
 // of the solve, capped by
 // the value for the bound rho <= q = max_p kappa_p sum_q c_pq (the T_p only
 // shrink the coupling).  An early estimate errs low (fast transients), which
-// under-relaxes: still faster than Gauss-Seidel.  Stopped when a sweep changes
-// z by at most rtol max|z|.  The chain rule then runs through
+// under-relaxes: still faster than Gauss-Seidel.  For a contraction by r per
+// sweep, the distance to the solution after a sweep that changed z by dz is
+// at most dz r / (1 - r); so the solve stops when dz <= rtol max|z| (1 - r),
+// with r the larger of the ratio of the last two changes and omega - 1 (the
+// contraction of over-relaxed sweeps cannot be smaller), at most 0.999.  The
+// chain rule then runs through
 //     b_pi = M_p [(1/tau + 2/eps) un_pi - lambda F_pi],  F_pi = sum_k (I_pk - c_ik)^2,
 //     c_ik = S_ik / S_i,  H = M/tau + eps A,
 // with M_p = h^2 w_p; an empty phase's (kept) mean is a constant.
@@ -68,10 +72,11 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // the tile's black nodes from those reds, so the tile ends as one global
 // red-black sweep leaves it.  Sweep s reads z from buffer s & 1 (a.z, a.z2)
 // and writes the other, so tiles never see each other's new values.  Every
-// sweep after the second first checks the previous sweep's partials (max |dz|
-// over its black nodes, max |z|; two sets, by sweep parity) and skips the rest
-// of the solve once they meet rtol.  Per node the arithmetic is that of the
-// two half-sweeps it replaces.
+// sweep after the second first checks the partials of the two sweeps before
+// it (max |dz| over its black nodes, max |z|; three sets, by sweep mod 3, so
+// that no workgroup of a launch overwrites a set another one may still read)
+// and skips the rest of the solve once the stopping rule holds.  Per node the
+// arithmetic is that of the two half-sweeps it replaces.
 constexpr int kAdjTX = 64, kAdjTY = 8, kAdjR = 2;
 constexpr int kAdjOmegaSweep = 6;  // the sweep that fixes omega from the Gauss-Seidel contraction
 constexpr int kAdjLX = kAdjTX + 2 * kAdjR, kAdjLY = kAdjTY + 2 * kAdjR;
@@ -96,15 +101,23 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs a, int sweep) {
     if (ac->done) return;
     float omega = 1.f;
     if (sweep > 1) {  // sweep 0 compared its black values with unset memory
-        const float* prev = a.part_f + ((sweep - 1) & 1) * 2 * kMgBlocks;
-        float dz = 0.f, zm = 0.f;
+        const float* prev = a.part_f + ((sweep - 1) % 3) * 2 * kMgBlocks;
+        const float* pp = a.part_f + ((sweep - 2) % 3) * 2 * kMgBlocks;
+        float dz = 0.f, zm = 0.f, dz2 = 0.f;
         for (int b = threadIdx.x; b < a.nblocks; b += kBlock) {
             dz = fmaxf(dz, prev[b]);
             zm = fmaxf(zm, prev[kMgBlocks + b]);
+            dz2 = fmaxf(dz2, pp[b]);
         }
         dz = block_max_f(dz, sh);
         zm = block_max_f(zm, sh);
-        if (!(dz > a.rtol * zm)) {
+        dz2 = block_max_f(dz2, sh);
+        // contraction per sweep: the ratio of the last two changes (sweep - 2
+        // >= 1 compared real values), never below omega - 1 of the last sweep
+        const float ratio = sweep > 2 ? (dz2 > 0.f ? dz / dz2 : 0.f) : 1.f;
+        const float om_prev = sweep - 1 >= kAdjOmegaSweep ? ac->omega : 1.f;
+        const float r = fminf(fmaxf(ratio, om_prev - 1.f), 0.999f);
+        if (!(dz > a.rtol * zm * (1.f - r))) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 ac->done = 1;
                 ac->sweeps = sweep;
@@ -112,13 +125,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs a, int sweep) {
             return;
         }
         if (sweep == kAdjOmegaSweep) {
-            // the partials of sweep - 2 are still in this parity's set
-            const float* pp = a.part_f + (sweep & 1) * 2 * kMgBlocks;
-            float dz2 = 0.f;
-            for (int b = threadIdx.x; b < a.nblocks; b += kBlock) dz2 = fmaxf(dz2, pp[b]);
-            dz2 = block_max_f(dz2, sh);
-            const float r = dz2 > 0.f ? fminf(dz / dz2, 0.99f) : 0.f;
-            omega = fminf(a.omega, fmaxf(1.f, 2.f / (1.f + sqrtf(1.f - r))));
+            // Gauss-Seidel so far: the ratio estimates rho^2
+            const float rho2 = fminf(ratio, 0.99f);
+            omega = fminf(a.omega, fmaxf(1.f, 2.f / (1.f + sqrtf(1.f - rho2))));
             if (blockIdx.x == 0 && threadIdx.x == 0) ac->omega = omega;  // read by later sweeps
         } else if (sweep > kAdjOmegaSweep) {
             omega = ac->omega;
@@ -200,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(AdjArgs a, int sweep) {
     const float d = block_max_f(dzm, sh);
     const float m = block_max_f(zmax, sh);
     if (threadIdx.x == 0) {
-        float* cur = a.part_f + (sweep & 1) * 2 * kMgBlocks;
+        float* cur = a.part_f + (sweep % 3) * 2 * kMgBlocks;
         cur[blockIdx.x] = d;
         cur[kMgBlocks + blockIdx.x] = m;
     }
