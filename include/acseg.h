@@ -59,6 +59,7 @@ typedef int32_t acseg_status;
 #define ACSEG_ERR_WORKSPACE (-3)    /* ws is NULL, misaligned or smaller than required */
 #define ACSEG_ERR_HIP (-4)          /* a HIP runtime call failed */
 #define ACSEG_ERR_UNSUPPORTED (-5)  /* N or C outside the compiled range */
+#define ACSEG_ERR_TOO_LARGE (-6)    /* acseg_solve_no_alloc: the problem needs more than its scratch */
 #define ACSEG_WARN_NOT_CONVERGED 1  /* some step hit max_cycles with residual > tol */
 #define ACSEG_WARN_EMPTY_PHASE 2    /* some phase had no mass; its colour mean was kept */
 
@@ -340,6 +341,28 @@ acseg_status acseg_step(acseg_ctx *ctx, const acseg_problem *p, const float *ima
 acseg_status acseg_solve(acseg_ctx *ctx, const acseg_problem *p, const float *image, float *u,
                          float *c_out, float *checkpoints, acseg_stats *stats, void *ws,
                          size_t ws_bytes, void *stream);
+
+/*
+ * acseg_solve without a workspace argument, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation.  The call runs the kernels of acseg_solve with the
+ * same arguments and results, on a scratch array that the library holds in
+ * static device memory: ACSEG_NO_ALLOC_SCRATCH_BYTES (80 MiB) on every device
+ * the library runs on, reserved when the library's code is loaded there and
+ * held until the process ends.  It calls no device or host allocator.
+ * Problems whose workspace (acseg_workspace_size) exceeds the scratch are
+ * refused with ACSEG_ERR_TOO_LARGE before anything is enqueued; 1024 x 1024 at
+ * N = 4 fits with its full multigrid hierarchy.  Every call on one device
+ * uses that device's one scratch array and leaves its contents behind (each
+ * call initialises what it reads): calls that can overlap on one device --
+ * other streams, other threads, other contexts -- race and must be
+ * serialised by the caller.  Kernel timing (acseg_timing_enable) does not
+ * record these calls.
+ */
+#define ACSEG_NO_ALLOC_SCRATCH_BYTES 83886080u
+acseg_status acseg_solve_no_alloc(acseg_ctx *ctx, const acseg_problem *p, const float *image,
+                                  float *u, float *c_out, float *checkpoints, acseg_stats *stats,
+                                  void *stream);
 
 /*
  * B independent segmentations in one time loop: the solve of acseg_solve

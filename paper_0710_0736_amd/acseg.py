@@ -23,6 +23,7 @@ ERR_NONFINITE = -2
 ERR_WORKSPACE = -3
 ERR_HIP = -4
 ERR_UNSUPPORTED = -5
+ERR_TOO_LARGE = -6
 WARN_NOT_CONVERGED = 1
 WARN_EMPTY_PHASE = 2
 FLAG_STORE_CHECKPOINTS = 1
@@ -124,6 +125,7 @@ def lib():
         L.acseg_colour_means.argtypes = [vp, pp, vp, vp, vp, vp, sp, vp, sz, vp]
         L.acseg_step.argtypes = [vp, pp, vp, vp, vp, vp, vp, sp, vp, sz, vp]
         L.acseg_solve.argtypes = [vp, pp, vp, vp, vp, vp, sp, vp, sz, vp]
+        L.acseg_solve_no_alloc.argtypes = [vp, pp, vp, vp, vp, vp, sp, vp]
         L.acseg_labels.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp]
         L.acseg_backward_workspace_size.argtypes = [pp, ctypes.POINTER(sz)]
         L.acseg_backward.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp, vp, vp, sp, vp, sz, vp]
@@ -355,6 +357,26 @@ def solve(p: Problem, image: torch.Tensor, u: torch.Tensor, checkpoints: bool = 
                              _ptr(c), _ptr(ck), ctypes.byref(st) if want_stats else None,
                              _ptr(ws), ws.numel(), _stream()), "acseg_solve")
     return u, c, (_stats_dict(st) if want_stats else None), ck
+
+
+def solve_no_alloc(p: Problem, image: torch.Tensor, u: torch.Tensor, c: Optional[torch.Tensor] = None,
+                   checkpoints: Optional[torch.Tensor] = None, want_stats: bool = True):
+    """``acseg_solve_no_alloc``: ``solve`` on the library's static scratch, with
+    caller-owned outputs only (``u`` in/out, ``c`` [N][C] and ``checkpoints``
+    [steps+1][N][H][W] when given), so the call itself allocates nothing.
+    Returns the stats dict (or None)."""
+    _need(image, (p.C, p.H, p.W), name="image")
+    _need(u, (p.N, p.H, p.W), name="u")
+    if c is not None:
+        _need(c, (p.N, p.C), name="c")
+    if checkpoints is not None:
+        _need(checkpoints, (p.steps + 1, p.N, p.H, p.W), name="checkpoints")
+        p = replace(p, flags=p.flags | FLAG_STORE_CHECKPOINTS)
+    st = _Stats()
+    _check(lib().acseg_solve_no_alloc(ctx(u.device.index), ctypes.byref(p.c()), _ptr(image), _ptr(u),
+                                      _ptr(c), _ptr(checkpoints), ctypes.byref(st) if want_stats else None,
+                                      _stream()), "acseg_solve_no_alloc")
+    return _stats_dict(st) if want_stats else None
 
 
 def _batch_arrays(problems):

@@ -43,7 +43,17 @@ struct acseg_ctx {
     // the last uploaded tables and the workspace they went to (REUSE_TABLES check)
     std::vector<char> last_tables;
     const void* last_tables_ws = nullptr;
+    // device address of this device's copy of the static scratch array
+    // (acseg_solve_no_alloc), looked up once at creation with the device current
+    void* scratch = nullptr;
 };
+
+// Scratch of acseg_solve_no_alloc: a file-scope device array, one copy per
+// device the library runs on, held until the process ends.  Host code never
+// uses its name as an address (on the host it is only a stand-in for the
+// symbol): acseg_create looks up the device address with hipGetSymbolAddress
+// and every use goes through acseg_ctx::scratch.
+static __device__ __align__(256) unsigned char scratch[ACSEG_NO_ALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -683,6 +693,11 @@ BackLayout back_layout_of(const acseg_problem* p) {
     return L;
 }
 
+// acseg_solve on a given workspace (arguments validated by the caller).
+acseg_status solve_impl(acseg_ctx* ctx, const acseg_problem* p, const float* image, float* u,
+                        float* c_out, float* checkpoints, acseg_stats* stats, void* ws, size_t ws_bytes,
+                        void* stream);
+
 }  // namespace
 
 extern "C" {
@@ -697,6 +712,7 @@ const char* acseg_status_string(acseg_status s) {
         case ACSEG_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
         case ACSEG_ERR_HIP: return "HIP runtime error";
         case ACSEG_ERR_UNSUPPORTED: return "unsupported size or option";
+        case ACSEG_ERR_TOO_LARGE: return "problem needs more than the library's static scratch";
         case ACSEG_WARN_NOT_CONVERGED: return "a step did not reach the tolerance";
         case ACSEG_WARN_EMPTY_PHASE: return "a phase had no mass";
         default: return "unknown status";
@@ -713,6 +729,7 @@ acseg_status acseg_create(int device, acseg_ctx** out) {
     acseg_ctx* c = new acseg_ctx();
     c->device = device;
     if (hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        hipGetSymbolAddress(&c->scratch, HIP_SYMBOL(scratch)) != hipSuccess || !c->scratch ||
         hipHostMalloc((void**)&c->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->host_actl, sizeof(AdjCtl), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->host_slot, sizeof(StepSlot), hipHostMallocDefault) != hipSuccess) {
@@ -866,6 +883,32 @@ acseg_status acseg_solve(acseg_ctx* ctx, const acseg_problem* p, const float* im
                          size_t ws_bytes, void* stream) {
     acseg_status v = validate(p, true);
     if (v != ACSEG_OK) return v;
+    return solve_impl(ctx, p, image, u, c_out, checkpoints, stats, ws, ws_bytes, stream);
+}
+
+acseg_status acseg_solve_no_alloc(acseg_ctx* ctx, const acseg_problem* p, const float* image, float* u,
+                                  float* c_out, float* checkpoints, acseg_stats* stats, void* stream) {
+    const acseg_status v = validate(p, true);
+    if (v != ACSEG_OK) return v;
+    if (!ctx || !ctx->scratch) return ACSEG_ERR_INVALID_ARG;
+    if (layout_of(p).total > ACSEG_NO_ALLOC_SCRATCH_BYTES) return ACSEG_ERR_TOO_LARGE;
+    // kernel timing would create HIP events: off for this call
+    const bool timing = ctx->timing;
+    ctx->timing = false;
+    const acseg_status r = solve_impl(ctx, p, image, u, c_out, checkpoints, stats, ctx->scratch,
+                                      ACSEG_NO_ALLOC_SCRATCH_BYTES, stream);
+    ctx->timing = timing;
+    return r;
+}
+
+}  // extern "C"
+
+namespace {
+
+acseg_status solve_impl(acseg_ctx* ctx, const acseg_problem* p, const float* image, float* u,
+                        float* c_out, float* checkpoints, acseg_stats* stats, void* ws, size_t ws_bytes,
+                        void* stream) {
+    acseg_status v;
     const bool ckpt = (p->flags & ACSEG_FLAG_STORE_CHECKPOINTS) != 0u;
     const bool fixed_c = (p->flags & ACSEG_FLAG_FIXED_C) != 0u;
     if (!ctx || !image || !u || (ckpt && !checkpoints) || (fixed_c && !c_out))
@@ -899,6 +942,10 @@ acseg_status acseg_solve(acseg_ctx* ctx, const acseg_problem* p, const float* im
     }
     return read_stats(ctx, L, ws, s, stats);
 }
+
+}  // namespace
+
+extern "C" {
 
 acseg_status acseg_batch_workspace_size(int32_t B, const acseg_problem* ps, size_t* bytes) {
     if (!bytes) return ACSEG_ERR_INVALID_ARG;

@@ -64,7 +64,7 @@ def test_workspace_size_grows_with_problem():
 
 def test_status_strings():
     L = acseg.lib()
-    for code in (0, -1, -2, -3, -4, -5, 1, 2):
+    for code in (0, -1, -2, -3, -4, -5, -6, 1, 2):
         assert L.acseg_status_string(code).decode() not in ("", "unknown status")
 
 
@@ -129,7 +129,7 @@ def test_binding_constants_match_the_header():
         assert getattr(acseg, "FLAG_" + name) == v, name
     assert len(set(flags.values())) == len(flags)  # distinct bits
     for name in ("OK", "ERR_INVALID_ARG", "ERR_NONFINITE", "ERR_WORKSPACE", "ERR_HIP", "ERR_UNSUPPORTED",
-                 "WARN_NOT_CONVERGED", "WARN_EMPTY_PHASE"):
+                 "ERR_TOO_LARGE", "WARN_NOT_CONVERGED", "WARN_EMPTY_PHASE"):
         assert getattr(acseg, name) == d[name], name
 
 
