@@ -102,12 +102,13 @@ acseg_status validate(const acseg_problem* p, bool need_steps) {
 }
 
 // Multigrid hierarchy of a problem: level l has side ceil(side_{l-1} / 2) and
-// spacing 2^l h.  Levels tail..L-1 (both sides <= kTailSide) run in the LDS
-// tail kernel; tail == L when none does.
+// spacing 2^l h.  Levels tail..L-1 (the first level whose sides are both <=
+// kTailSide and whose tail fits in kTailLds bytes of LDS, and every coarser
+// one) run in the LDS tail kernel; tail == L when none does.
 struct MgPlan {
     int L = 1, tail = 1;
-    int W[32], H[32];
-    LevelCoef coef[32];
+    int W[kMaxLevels], H[kMaxLevels];
+    LevelCoef coef[kMaxLevels];
 };
 
 LevelCoef level_coef(const acseg_problem* p, int l) {
@@ -127,19 +128,9 @@ LevelCoef level_coef(const acseg_problem* p, int l) {
     return c;
 }
 
-size_t tail_lds_bytes(const MgPlan& m, int t0) {
-    size_t f = 0, big = 0;
-    for (int l = t0; l < m.L; ++l) {
-        const size_t n = (size_t)m.W[l] * m.H[l];
-        f += 2 * n;
-        big = std::max(big, n);
-    }
-    return (f + big) * sizeof(float);
-}
-
 MgPlan plan_of(const acseg_problem* p) {
     MgPlan m;
-    m.L = p->levels == 0 ? auto_levels(p->W, p->H) : p->levels;
+    m.L = std::min(p->levels == 0 ? auto_levels(p->W, p->H) : p->levels, kMaxLevels);
     m.W[0] = p->W;
     m.H[0] = p->H;
     for (int l = 0; l < m.L; ++l) {
@@ -151,8 +142,7 @@ MgPlan plan_of(const acseg_problem* p) {
     }
     m.tail = m.L;
     for (int l = 1; l < m.L; ++l)
-        if (m.W[l] <= kTailSide && m.H[l] <= kTailSide && m.L - l <= kMaxTail &&
-            tail_lds_bytes(m, l) <= 65536) {
+        if (m.W[l] <= kTailSide && m.H[l] <= kTailSide && mg_tail_lds(m.W, m.H, l, m.L) <= (size_t)kTailLds) {
             m.tail = l;
             break;
         }
@@ -163,10 +153,14 @@ MgPlan plan_of(const acseg_problem* p) {
 struct Layout {
     size_t ubuf = 0, rhs = 0, part_f = 0, part_cm = 0, part_d = 0, c64 = 0, tot = 0, ctl = 0;
     size_t mg_gt = 0, mg_part = 0;
-    size_t mg_v[32] = {}, mg_r[32] = {}, mg_res[32] = {};  // coarse levels 1..L-1
+    size_t mg_v[kMaxLevels] = {}, mg_r[kMaxLevels] = {}, mg_v2[kMaxLevels] = {};  // coarse levels 1..L-1
     size_t total = 0;
     int part_stride = 0;
 };
+
+int dir_blocks(int W, int H) {
+    return std::min(((W + kDirTX - 1) / kDirTX) * ((H + kDirTY - 1) / kDirTY), kDirBlocks);
+}
 
 Layout layout_of(const acseg_problem* p) {
     Layout L;
@@ -189,12 +183,12 @@ Layout layout_of(const acseg_problem* p) {
     const MgPlan m = plan_of(p);
     if (m.L >= 2) {
         L.mg_gt = take(sizeof(float) * p->N * n);
-        L.mg_part = take(sizeof(double) * 2 * kMgBlocks);
+        L.mg_part = take(sizeof(double) * 2 * (size_t)dir_blocks(p->W, p->H));
         for (int l = 1; l < m.L; ++l) {
             const size_t nl = (size_t)p->N * m.W[l] * m.H[l];
             L.mg_v[l] = take(sizeof(float) * nl);
             L.mg_r[l] = take(sizeof(float) * nl);
-            L.mg_res[l] = take(sizeof(float) * nl);
+            L.mg_v2[l] = take(sizeof(float) * nl);
         }
     }
     L.total = off;
@@ -270,110 +264,77 @@ hipError_t timed(acseg_ctx* ctx, int fam, hipStream_t s, F&& launch) {
     return e;
 }
 
+// One image's multigrid descriptor (constant over a solve).
+MgImage mg_image_of(const acseg_problem* p, const MgPlan& m, const Layout& L, void* ws, Bufs bufs) {
+    MgImage d;
+    memset(&d, 0, sizeof(d));
+    d.bufs = bufs;
+    d.ctl = at<Ctl>(ws, L.ctl);
+    d.rhs = at<float>(ws, L.rhs);
+    d.gt = at<float>(ws, L.mg_gt);
+    d.part = at<double>(ws, L.mg_part);
+    d.N = p->N;
+    d.W = p->W;
+    d.H = p->H;
+    d.L = m.L;
+    d.tail = m.tail;
+    d.dir_blocks = dir_blocks(p->W, p->H);
+    d.fine = m.coef[0];
+    for (int l = 1; l < m.L; ++l) {
+        MgLevel& v = d.lv[l];
+        v.r = at<float>(ws, L.mg_r[l]);
+        v.v = at<float>(ws, L.mg_v[l]);
+        v.v2 = at<float>(ws, L.mg_v2[l]);
+        v.coef = m.coef[l];
+        v.W = m.W[l];
+        v.H = m.H[l];
+    }
+    return d;
+}
+
+// The passes of one truncated multigrid correction, in order: (pass, level,
+// sweeps, zero).  Levels 1..tail-1 go down (sweeps from zero, restriction)
+// and up (prolongation, sweeps) in tiled passes, the LDS tail solves levels
+// tail..L-1; without a tail the coarsest level is an up pass from zero.
+struct MgPassRec {
+    int op, level, sweeps, zero;
+};
+
+std::vector<MgPassRec> mg_passes(const MgPlan& m, int nu_pre, int nu_post) {
+    std::vector<MgPassRec> v;
+    v.push_back({kMgDefectRestrict, 0, 0, 0});
+    const int down_end = m.tail < m.L ? m.tail : m.L - 1;  // levels 1 .. down_end-1 go down
+    for (int l = 1; l < down_end; ++l) v.push_back({kMgDown, l, nu_pre, 0});
+    if (m.tail < m.L)
+        v.push_back({kMgTail, m.tail, 0, 0});
+    else
+        v.push_back({kMgUp, m.L - 1, kCoarseSweeps, 1});
+    for (int l = down_end - 1; l >= 1; --l) v.push_back({kMgUp, l, nu_post, 0});
+    v.push_back({kMgDir, 0, 0, 0});
+    v.push_back({kMgUpdate, 0, 0, 0});
+    return v;
+}
+
 // The truncated multigrid correction of the iterate left by `launch`
 // smoothing launches of the current step (in place).
 acseg_status enqueue_correction(acseg_ctx* ctx, const acseg_problem* p, const MgPlan& m,
                                 const Layout& L, void* ws, Bufs bufs, int slot, bool fixed,
                                 int launch, hipStream_t s) {
-    const int N = p->N;
-    Ctl* ctl = at<Ctl>(ws, L.ctl);
-    MgArgs f{};
-    f.bufs = bufs;
-    f.ctl = ctl;
-    f.rhs = at<float>(ws, L.rhs);
-    f.gt = at<float>(ws, L.mg_gt);
-    f.r1 = at<float>(ws, L.mg_r[1]);
-    f.v1 = at<float>(ws, L.mg_v[1]);
-    f.part = at<double>(ws, L.mg_part);
-    f.coef = m.coef[0];
-    f.W = m.W[0];
-    f.H = m.H[0];
-    f.Wc = m.W[1];
-    f.Hc = m.H[1];
-    f.slot = slot;
-    f.fixed = fixed ? 1 : 0;
-    f.launch = launch;
-    f.nblocks = mg_blocks(f.W, f.H);
-    auto coarse = [&](int op, int l, const float* src, float* dst, const float* aux, float* res,
-                      int colour, int zero) {
-        CoarseArgs a{};
-        a.ctl = ctl;
-        a.src = src;
-        a.dst = dst;
-        a.aux = aux;
-        a.res = res;
-        a.coef = op == kCoarseResidRestrict ? m.coef[l - 1] : m.coef[l];
-        a.W = m.W[l];
-        a.H = m.H[l];
-        a.Wf = m.W[l - 1];
-        a.Hf = m.H[l - 1];
-        a.colour = colour;
-        a.zero = zero;
-        a.slot = slot;
-        a.fixed = f.fixed;
-        return timed(ctx, kFamMg, s, [&] { return launch_mg_coarse(N, op, a, s); });
-    };
-    // count sweeps on level l: from v = 0 (zero), or after adding the prolonged
-    // correction vc of level l + 1 (folded into the first red half-sweep)
-    auto sweeps = [&](int l, int count, bool zero, const float* vc) -> hipError_t {
-        float* v = at<float>(ws, L.mg_v[l]);
-        const float* r = at<float>(ws, L.mg_r[l]);
-        for (int k = 0; k < count; ++k) {
-            hipError_t e = coarse(kCoarseHalf, l, r, v, k == 0 ? vc : nullptr, nullptr, 0, zero && k == 0);
-            if (e == hipSuccess) e = coarse(kCoarseHalf, l, r, v, nullptr, nullptr, 1, 0);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
-    };
-    auto fine = [&](int op) { return timed(ctx, kFamMg, s, [&] { return launch_mg_fine(N, op, f, s); }); };
-
-    // truncated defect, restricted to level 1
-    ACSEG_TRY(fine(kMgDefectRestrict));
-    // down: levels 1 .. tail-1 in global memory
-    const int last_global = std::min(m.tail, m.L) - 1;  // deepest level solved by global kernels
-    for (int l = 1; l <= last_global; ++l) {
-        const bool coarsest = l == m.L - 1;
-        ACSEG_TRY(sweeps(l, coarsest ? kCoarseSweeps : p->nu_pre, true, nullptr));
-        if (coarsest) break;
-        ACSEG_TRY(coarse(kCoarseResidRestrict, l + 1, at<float>(ws, L.mg_r[l]), at<float>(ws, L.mg_r[l + 1]),
-                         at<float>(ws, L.mg_v[l]), nullptr, 0, 0));
+    const MgImage d = mg_image_of(p, m, L, ws, bufs);
+    const MgGrid single{nullptr, nullptr, 0};
+    MgStep st{};
+    st.slot = slot;
+    st.fixed = fixed ? 1 : 0;
+    st.launch = launch;
+    st.nu_pre = p->nu_pre;
+    st.nu_post = p->nu_post;
+    for (const MgPassRec& r : mg_passes(m, p->nu_pre, p->nu_post)) {
+        st.level = r.level;
+        st.sweeps = r.sweeps;
+        st.zero = r.zero;
+        const size_t lds = mg_pass_lds(r.op, d, r.sweeps);
+        ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_mg(r.op, p->N, p->N, d, single, st, lds, s); }));
     }
-    if (m.tail < m.L) {
-        TailArgs t{};
-        t.ctl = ctl;
-        t.r_in = at<float>(ws, L.mg_r[m.tail]);
-        t.v_out = at<float>(ws, L.mg_v[m.tail]);
-        t.nl = m.L - m.tail;
-        int off = 0;
-        int big = 0;
-        for (int l = 0; l < t.nl; ++l) {
-            const int g = m.tail + l;
-            t.lv[l].W = m.W[g];
-            t.lv[l].H = m.H[g];
-            t.lv[l].off_v = off;
-            off += m.W[g] * m.H[g];
-            t.lv[l].off_r = off;
-            off += m.W[g] * m.H[g];
-            big = std::max(big, m.W[g] * m.H[g]);
-            t.coef[l] = m.coef[g];
-        }
-        t.off_res = off;
-        t.nu_pre = p->nu_pre;
-        t.nu_post = p->nu_post;
-        t.coarse_sweeps = kCoarseSweeps;
-        t.slot = slot;
-        t.fixed = f.fixed;
-        const size_t bytes = (size_t)(off + big) * sizeof(float);
-        ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_coarse_tail(N, t, bytes, s); }));
-    }
-    // up: prolongate and post-smooth levels tail-1 .. 1
-    for (int l = std::min(m.tail, m.L - 1) - 1; l >= 1; --l)
-        ACSEG_TRY(sweeps(l, p->nu_post, false, at<float>(ws, L.mg_v[l + 1])));
-    // direction, line search, update
-    ACSEG_TRY(fine(kMgDir));
-    ACSEG_TRY(fine(kMgWhw));
-    ACSEG_TRY(fine(kMgAlpha));
-    ACSEG_TRY(fine(kMgUpdate));
     return ACSEG_OK;
 }
 

@@ -185,67 +185,84 @@ hipError_t launch_means_from_tot(int N, int C, const double* tot, const double* 
 
 // ---- launchers (kernels_mg.hip): the truncated multigrid correction -------
 
-constexpr int kMgBlocks = 1024;   // most workgroups of a fine-level pass (partials per dot)
-constexpr int kTailSide = 64;     // levels with both sides <= this run in the LDS tail
-constexpr int kMaxTail = 8;       // levels in the LDS tail
-constexpr int kCoarseSweeps = 8;  // red-black sweeps on the coarsest level
+constexpr int kMgBlocks = 1024;    // most workgroups of a pass with per-workgroup partials
+constexpr int kTailSide = 64;      // levels with both sides <= this may run in the LDS tail
+constexpr int kTailLds = 64 * 1024;   // LDS bytes the tail may use
+constexpr int kCoarseSweeps = 8;   // red-black sweeps on the coarsest level
+constexpr int kMaxLevels = 16;     // lattice levels of a hierarchy (sides up to 2^15)
 
-enum MgOp { kMgDefectRestrict = 0, kMgDir, kMgWhw, kMgAlpha, kMgUpdate };
+// Tiles of the multigrid passes.
+constexpr int kDrTX = 32, kDrTY = 8;    // defect + restriction: level-1 nodes per workgroup
+constexpr int kDnTX = 32, kDnTY = 16;   // down-leg of level l: level-(l+1) nodes per workgroup
+constexpr int kUpTX = 64, kUpTY = 16;   // up-leg of level l: level-l nodes per workgroup
+constexpr int kDirTX = 64, kDirTY = 8;  // direction and line-search partials: fine nodes
+constexpr int kDirBlocks = 2048;        // most workgroups of one image's direction pass
+constexpr int kUpdTX = 64, kUpdTY = 8;  // update: fine nodes per workgroup
 
-// Fine-level passes.  The iterate is bufs[iterate_buf(ctl->cur, launch)] and
-// is updated in place; gt holds the direction w.
-struct MgArgs {
+// One coarse level l >= 1 of one image.  The level's correction problem is
+// H_l v = r (componentwise, H_l rediscretised at spacing 2^l h); v holds the
+// correction after the down-leg (pre-smoothing from zero), v2 after the
+// up-leg (prolongation of the next coarser level and post-smoothing), or the
+// result of the LDS tail or of the coarsest level's sweeps.
+struct MgLevel {
+    float* r;     // [N][H][W]
+    float* v;     // [N][H][W]
+    float* v2;    // [N][H][W]
+    LevelCoef coef;
+    int W, H;
+    int pad[2];
+};
+
+// One image's truncated multigrid correction, constant over a solve.  The
+// iterate is bufs[iterate_buf(ctl->cur, launch)], updated in place.  Levels
+// 1..tail-1 are processed by tiled global-memory passes, levels tail..L-1 by
+// the LDS tail (tail == L: none; the coarsest level is then a global pass).
+struct MgImage {
     Bufs bufs;
     Ctl* ctl;
     const float* rhs;   // stored right-hand side [N][H][W]
-    float* gt;          // [N][H][W]
-    float* r1;          // restricted truncated defect on level 1 [N][Hc][Wc]
-    const float* v1;    // correction on level 1 [N][Hc][Wc]
-    double* part;       // [2][kMgBlocks]: <g~,w> and <w,Hw> partials
-    LevelCoef coef;     // finest level
-    int W, H, Wc, Hc;
-    int slot, fixed, launch, nblocks;
+    float* gt;          // direction w [N][H][W]
+    double* part;       // line-search partials [dir_blocks][2]
+    int N, W, H;        // finest level
+    int L, tail;
+    int dir_blocks;     // workgroups of the direction pass (partials to reduce)
+    LevelCoef fine;
+    MgLevel lv[kMaxLevels];  // lv[1..L-1]
 };
 
-enum CoarseOp { kCoarseRestrict = 0, kCoarseProlongAdd, kCoarseHalf, kCoarseResid, kCoarseResidRestrict };
-
-// One coarse-level pass on level (W, H); (Wf, Hf) is the next finer level.
-//   restrict:       dst[W x H] = P^T src[Wf x Hf]
-//   prolong_add:    dst[Wf x Hf] += P src[W x H]
-//   half:           red (colour 0) / black half-sweep of H v = src on dst = v;
-//                   with aux (the next coarser level's v), the neighbours are
-//                   read as v + P aux (a red half-sweep after prolongation)
-//   resid:          res = src - H aux
-//   resid_restrict: dst[W x H] = P^T (src - H_f aux) on the finer level (Wf, Hf),
-//                   coef of the finer level
-struct CoarseArgs {
-    const Ctl* ctl;
-    const float* src;
-    float* dst;
-    const float* aux;
-    float* res;
-    LevelCoef coef;
-    int W, H, Wf, Hf;
-    int colour, zero;
-    int slot, fixed;
+// Per launch.
+struct MgStep {
+    int slot, fixed, launch;
+    int level;    // the level a coarse pass works on
+    int sweeps;   // red-black sweeps of a coarse pass
+    int zero;     // up-leg pass starts from v = 0 without a prolongation (coarsest global level)
+    int nu_pre, nu_post;
 };
 
-struct TailLevel {
-    int W, H;
-    int off_v, off_r;  // float offsets in LDS
+// Where a multigrid launch's workgroups come from: one image (descs == NULL:
+// workgroup x is tile x of `single`) or a batch (work[x] = (image, tile), image
+// -1 for none).  blockIdx.y selects the component of componentwise passes.
+struct MgGrid {
+    const MgImage* descs;
+    const int2* work;
+    int nwork;
 };
 
-// V-cycle over the LDS-resident coarsest levels, one workgroup per component.
-struct TailArgs {
-    const Ctl* ctl;
-    const float* r_in;  // [N][lv[0].H][lv[0].W]
-    float* v_out;
-    TailLevel lv[kMaxTail];
-    LevelCoef coef[kMaxTail];
-    int nl, off_res;
-    int nu_pre, nu_post, coarse_sweeps;
-    int slot, fixed;
-};
+enum MgPass { kMgDefectRestrict = 0, kMgDown, kMgTail, kMgUp, kMgDir, kMgUpdate };
+
+// Workgroups of pass `op` on level st.level of one image (single-image grid).
+int mg_pass_tiles(int op, const MgImage& m, int level);
+// Dynamic LDS bytes of pass `op` (down / up: `sweeps` red-black sweeps; tail:
+// the hierarchy from m.tail).
+size_t mg_pass_lds(int op, const MgImage& m, int sweeps);
+// LDS bytes of the tail from level t of an image with level sides W[], H[].
+size_t mg_tail_lds(const int* W, const int* H, int t, int L);
+
+// Enqueue one multigrid pass.  Fine-level passes (defect + restriction,
+// direction, update) are instantiated per N and need one N per launch (`N`);
+// coarse passes are componentwise (grid.y = largest N of the launch).
+hipError_t launch_mg(int op, int N, int ncomp, const MgImage& single, const MgGrid& g, const MgStep& st,
+                     size_t lds, hipStream_t s);
 
 // One launch of the subspace correction over the basis functions of one coarse
 // level: level lattice Wc x Hc, spacing 2^sh finest nodes, the functions whose
@@ -266,10 +283,6 @@ struct SscArgs {
 
 hipError_t launch_ssc(int N, const SscArgs& a, hipStream_t s);
 
-int mg_blocks(int W, int H);
-hipError_t launch_mg_fine(int N, int op, const MgArgs& a, hipStream_t s);
-hipError_t launch_mg_coarse(int N, int op, const CoarseArgs& a, hipStream_t s);
-hipError_t launch_coarse_tail(int N, const TailArgs& a, size_t lds_bytes, hipStream_t s);
 
 // Prolongation (dir 0: dst[planes][Hf][Wf] = P src) or restriction (dir 1:
 // dst[planes][Hc][Wc] = P^T src) between a Wf x Hf lattice and its coarse

@@ -10,11 +10,16 @@
 //   2. r_1 = P^T g~ (transpose of the P1 prolongation of the nested lattices);
 //   3. coarse levels: an approximate solve of the componentwise linear
 //      problems H_l v = r_l (H_l rediscretised at spacing 2^l h) by a V-cycle
-//      of red-black Gauss-Seidel sweeps; the levels whose longer side is at
-//      most kTailSide run in one workgroup per component, entirely in LDS;
+//      of red-black Gauss-Seidel sweeps.  Each large level is one tiled pass
+//      down (sweeps from zero, residual, restriction) and one up
+//      (prolongation, sweeps), every tile staged in LDS with the halo its
+//      sweeps need; the small levels (sides <= kTailSide) run as one V-cycle
+//      in one workgroup per component;
 //   4. direction w_p = Pi(u_p + T_I (P v_1)_p) - u_p (feasible, since the
 //      simplex is convex), and the exact line search on the step's quadratic
-//      along w: alpha = clamp(<g~, w> / <w, H w>, 0, 1), u += alpha w.
+//      along w: alpha = clamp(<g~, w> / <w, H w>, 0, 1), u += alpha w.  The
+//      direction pass also forms the two dot products (the last workgroup
+//      to finish reduces them to alpha), and the update is a pass of its own.
 //      w vanishes on the active components and sums to zero over the free
 //      ones at every node, so <g, w> = <g~, w>; the truncated form keeps the
 //      per-node multiplier of the sum constraint out of the dot product.
@@ -81,55 +86,14 @@ __device__ __forceinline__ float restrict_at(const float* __restrict__ rf, int W
     return s;
 }
 
-// Sum of the lattice neighbours of node (x, y) weighted by the edge weights
-// c_pq (1/2 along the boundary), 0 for neighbours outside the lattice.
-__device__ __forceinline__ float nb_sum(const float* __restrict__ v, int W, int H, int x, int y, int64_t p) {
-    const float h = (x > 0 ? v[p - 1] : 0.f) + (x < W - 1 ? v[p + 1] : 0.f);
-    const float vv = (y > 0 ? v[p - W] : 0.f) + (y < H - 1 ? v[p + W] : 0.f);
-    return edge_w_h(y, H) * h + edge_w_v(x, W) * vv;
-}
+// ---------------------------------------------------------------------------
+// Helpers
+// ---------------------------------------------------------------------------
 
-// nb_sum of v + P vc (vc on the coarse lattice Wc x Hc of this one).
-__device__ __forceinline__ float nb_sum_prolonged(const float* __restrict__ v, const float* __restrict__ vc,
-                                                  int W, int H, int Wc, int Hc, int x, int y, int64_t p) {
-    const float l = x > 0 ? v[p - 1] + prolong_at(vc, Wc, Hc, x - 1, y) : 0.f;
-    const float r = x < W - 1 ? v[p + 1] + prolong_at(vc, Wc, Hc, x + 1, y) : 0.f;
-    const float d = y > 0 ? v[p - W] + prolong_at(vc, Wc, Hc, x, y - 1) : 0.f;
-    const float u = y < H - 1 ? v[p + W] + prolong_at(vc, Wc, Hc, x, y + 1) : 0.f;
-    return edge_w_h(y, H) * (l + r) + edge_w_v(x, W) * (d + u);
-}
-
-// The truncated defect g~_p = T_I (D (y_p(u) - u_p)) of node (x, y), N values.
-template <int N>
-__device__ __forceinline__ void trunc_defect(const MgArgs& a, const float* __restrict__ u, int x, int y,
-                                             float (&g)[N]) {
-    const int W = a.W, H = a.H;
-    const int64_t n = (int64_t)W * H, p = (int64_t)y * W + x;
-    const int cls = node_class(x, y, W, H);
-    const float kap = sel4(a.coef.kappa, cls), D = sel4(a.coef.d, cls);
-    bool fr[N];
-    float s = 0.f;
-    int k = 0;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        const float* ui = u + i * n;
-        const float uc = ui[p];
-        const float yv = a.rhs[i * n + p] + kap * nb_sum(ui, W, H, x, y, p);
-        g[i] = D * (yv - uc);
-        fr[i] = uc > 0.f;
-        if (fr[i]) {
-            s += g[i];
-            ++k;
-        }
-    }
-    const float mean = k > 0 ? s / (float)k : 0.f;
-#pragma unroll
-    for (int i = 0; i < N; ++i) g[i] = (k >= 2 && fr[i]) ? g[i] - mean : 0.f;
-}
-
-__device__ __forceinline__ bool step_done(const MgArgs& a) {
-    return !a.fixed && a.ctl->step[a.slot].done;
-}
+// floor(q / d) for 0 <= q < 2^20 and 1 <= d < 2^20, with inv = 1.0f / d: the
+// quotient of q + 1/2 lies at least 1/(2d) from an integer, further than the
+// rounding error of the product (below 2^-3 / d for q < 2^20).
+__device__ __forceinline__ int fdiv(int q, float inv) { return (int)(((float)q + 0.5f) * inv); }
 
 __device__ __forceinline__ double block_sum_d(double v, double* sh /* kBlock/kWave */) {
     v = wave_sum(v);
@@ -137,313 +101,637 @@ __device__ __forceinline__ double block_sum_d(double v, double* sh /* kBlock/kWa
     if (lane == 0) sh[wid] = v;
     __syncthreads();
     double r = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < kBlock / kWave; ++w) r += sh[w];
+    for (int w = 0; w < kBlock / kWave; ++w) r += sh[w];
+    __syncthreads();
     return r;
 }
 
-// ---------------------------------------------------------------------------
-// Finest level
-// ---------------------------------------------------------------------------
+// The step's state for a pass, loaded in one round: whether the step has
+// converged (the pass then does nothing) and the buffer holding the iterate.
+struct MgState {
+    bool skip;
+    float* u;  // bufs[iterate_buf(ctl->cur, launch)]
+};
 
-// 1-2. r_1 = P^T g~, coarse node by coarse node (the defect of a fine node is
-// recomputed for each coarse node it reaches).
-template <int N>
-__global__ __launch_bounds__(kBlock) void k_mg_defect_restrict(MgArgs a) {
-    if (step_done(a)) return;
-    const float* __restrict__ u = a.bufs.b[__builtin_amdgcn_readfirstlane(iterate_buf(a.ctl->cur, a.launch))];
-    const int Wc = a.Wc, Hc = a.Hc;
-    const int64_t nc = (int64_t)Wc * Hc;
-    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < nc; p += (int64_t)gridDim.x * kBlock) {
-        const int Y = (int)(p / Wc), X = (int)(p - (int64_t)Y * Wc);
-        float r[N];
-#pragma unroll
-        for (int i = 0; i < N; ++i) r[i] = 0.f;
-        for_restrict(a.W, a.H, Wc, Hc, X, Y, [&](int x, int y, float wt) {
-            float g[N];
-            trunc_defect<N>(a, u, x, y, g);
-#pragma unroll
-            for (int i = 0; i < N; ++i) r[i] += wt * g[i];
-        });
-#pragma unroll
-        for (int i = 0; i < N; ++i) a.r1[i * nc + p] = r[i];
+__device__ __forceinline__ MgState mg_state(const MgImage& d, const MgStep& st) {
+    const Ctl* ctl = d.ctl;
+    const int done = ctl->step[st.slot].done;
+    const int cur = ctl->cur;
+    MgState m;
+    m.skip = !st.fixed && __builtin_amdgcn_readfirstlane(done) != 0;
+    m.u = const_cast<float*>(d.bufs.b[__builtin_amdgcn_readfirstlane(iterate_buf(cur, st.launch))]);
+    return m;
+}
+
+__device__ __forceinline__ bool mg_skip(const MgImage& d, const MgStep& st) { return mg_state(d, st).skip; }
+
+// Red-black half-sweep of linear Gauss-Seidel for H v = r on a block of a
+// level held in LDS (row pitch SX, origin (sx0, sy0) in level coordinates):
+// the nodes of `colour` ((x + y) & 1) strictly inside the block and inside the
+// W x H lattice get v = r / D + kappa sum_q c_pq v_q.  Nodes outside the
+// lattice hold 0 and are never updated, which makes the sum over the lattice
+// neighbours only.  INT: the whole block lies inside the lattice's interior
+// (one node class, unit edge weights, no bounds).  T threads.
+template <int T, bool INT>
+__device__ __forceinline__ void block_half(float* __restrict__ v, const float* __restrict__ r, int SX, int SY,
+                                           int sx0, int sy0, int W, int H, const LevelCoef& c, int colour) {
+    const int hw = (SX - 1) / 2;  // nodes of one colour per block row, at most
+    const float inv = 1.0f / (float)hw;
+    const int total = hw * (SY - 2);
+    const float k0 = uniform_f(c.kappa[0]), i0 = uniform_f(c.inv_d[0]);
+    for (int q = threadIdx.x; q < total; q += T) {
+        const int row = fdiv(q, inv), j = q - row * hw;
+        const int ly = row + 1, gy = sy0 + ly;
+        const int lx0 = 1 + ((sx0 + 1 + gy + colour) & 1);  // first node of the colour in the row
+        const int lx = lx0 + 2 * j, gx = sx0 + lx;
+        if (lx > SX - 2) continue;
+        const int p = ly * SX + lx;
+        if (INT) {
+            v[p] = fmaf(k0, (v[p - 1] + v[p + 1]) + (v[p - SX] + v[p + SX]), r[p] * i0);
+        } else {
+            if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;
+            const int cls = node_class(gx, gy, W, H);
+            const float nb = edge_w_h(gy, H) * (v[p - 1] + v[p + 1]) + edge_w_v(gx, W) * (v[p - SX] + v[p + SX]);
+            v[p] = fmaf(sel4(c.kappa, cls), nb, r[p] * sel4(c.inv_d, cls));
+        }
     }
 }
 
-// 4a. w = Pi(u + T_I P v_1) - u into a.gt, block partials of <g~, w> (g~ recomputed).
+// Whether a block of SX x SY level nodes at (sx0, sy0) lies strictly inside the lattice.
+__device__ __forceinline__ bool block_interior(int sx0, int sy0, int SX, int SY, int W, int H) {
+    return sx0 >= 1 && sy0 >= 1 && sx0 + SX <= W - 1 && sy0 + SY <= H - 1;
+}
+
+// (r - H v) at level node (gx, gy), block position p (lattice neighbours in the block).
+__device__ __forceinline__ float block_resid(const float* __restrict__ v, const float* __restrict__ r, int SX,
+                                             int p, int gx, int gy, int W, int H, const LevelCoef& c) {
+    const float nb = edge_w_h(gy, H) * (v[p - 1] + v[p + 1]) + edge_w_v(gx, W) * (v[p - SX] + v[p + SX]);
+    return r[p] - (sel4(c.d, node_class(gx, gy, W, H)) * v[p] - c.e2 * nb);
+}
+
+// Stage N planes of a field on an SX x SY block at (sx0, sy0) into LDS
+// dst[N][SY][SX] (0 outside the lattice): every load of a thread issued before
+// any store, so their latencies overlap.
+template <int N, int SX, int SY>
+__device__ __forceinline__ void stage_planes(float* __restrict__ dst, const float* __restrict__ src, uint32_t n,
+                                             int sx0, int sy0, int W, int H) {
+    constexpr int Q = (SX * SY + kBlock - 1) / kBlock;
+    float t[Q][N];
+    bool ok[Q];
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+        const int q = threadIdx.x + c * kBlock;
+        const int ly = q / SX, lx = q - ly * SX;
+        const int gx = sx0 + lx, gy = sy0 + ly;
+        ok[c] = q < SX * SY && gx >= 0 && gx < W && gy >= 0 && gy < H;
+        const uint32_t g = ok[c] ? (uint32_t)(gy * W + gx) : 0u;
+#pragma unroll
+        for (int i = 0; i < N; ++i) t[c][i] = gload(src + i * n, g);
+    }
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+        const int q = threadIdx.x + c * kBlock;
+        if (q < SX * SY) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) dst[i * SX * SY + q] = ok[c] ? t[c][i] : 0.f;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 1-2. Truncated defect of the finest level, restricted to level 1: one
+// workgroup per kDrTX x kDrTY level-1 nodes.  The fine nodes those reach
+// (2X0-1 .. 2X0+2 kDrTX-1) get their truncated defect once, from u staged
+// with a halo of one.
+// ---------------------------------------------------------------------------
+
 template <int N>
-__global__ __launch_bounds__(kBlock) void k_mg_dir(MgArgs a) {
-    __shared__ double sh[kBlock / kWave];
-    if (step_done(a)) return;
-    const float* __restrict__ u = a.bufs.b[__builtin_amdgcn_readfirstlane(iterate_buf(a.ctl->cur, a.launch))];
-    const int W = a.W, H = a.H, Wc = a.Wc, Hc = a.Hc;
-    const int64_t n = (int64_t)W * H, nc = (int64_t)Wc * Hc;
-    double gw = 0.0;
-    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += (int64_t)gridDim.x * kBlock) {
-        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
-        float uc[N], v[N];
+__device__ __forceinline__ void mg_defect_restrict(const MgImage& d, int tile, const MgStep& st) {
+    constexpr int SX = 2 * kDrTX + 3, SY = 2 * kDrTY + 3;
+    constexpr int FX = 2 * kDrTX + 1, FY = 2 * kDrTY + 1;
+    static_assert(kDrTX * kDrTY == kBlock, "one level-1 node per thread");
+    __shared__ float us[N][SY][SX];
+    __shared__ float gs[N][FY][FX];
+    const MgLevel c = d.lv[1];
+    const int W = d.W, H = d.H, Wc = c.W, Hc = c.H;
+    const MgState ms = mg_state(d, st);
+    if (ms.skip) return;
+    const int tx = (Wc + kDrTX - 1) / kDrTX;
+    const int X0 = (tile % tx) * kDrTX, Y0 = (tile / tx) * kDrTY;
+    const int sx0 = 2 * X0 - 2, sy0 = 2 * Y0 - 2;
+    const uint32_t n = (uint32_t)W * H, nc = (uint32_t)Wc * Hc;
+    const float* u = ms.u;
+    stage_planes<N, SX, SY>(&us[0][0][0], u, n, sx0, sy0, W, H);
+    __syncthreads();
+    for (int q = threadIdx.x; q < FX * FY; q += kBlock) {
+        const int fy = q / FX, fx = q - fy * FX;
+        const int gx = sx0 + 1 + fx, gy = sy0 + 1 + fy;
+        if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;  // never restricted
+        const int lx = fx + 1, ly = fy + 1;
+        const int cls = node_class(gx, gy, W, H);
+        const float kap = sel4(d.fine.kappa, cls), D = sel4(d.fine.d, cls);
+        const float ewh = edge_w_h(gy, H), ewv = edge_w_v(gx, W);
+        const uint32_t p = (uint32_t)(gy * W + gx);
+        float g[N];
+        bool fr[N];
+        float sum = 0.f;
         int k = 0;
-        float s = 0.f;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            uc[i] = u[i * n + p];
-            v[i] = prolong_at(a.v1 + i * nc, Wc, Hc, x, y);
-            if (uc[i] > 0.f) {
-                s += v[i];
+            const float uc = us[i][ly][lx];
+            const float nb = ewh * (us[i][ly][lx - 1] + us[i][ly][lx + 1]) + ewv * (us[i][ly - 1][lx] + us[i][ly + 1][lx]);
+            const float yv = gload(d.rhs + i * n, p) + kap * nb;
+            g[i] = D * (yv - uc);
+            fr[i] = uc > 0.f;
+            if (fr[i]) {
+                sum += g[i];
                 ++k;
             }
         }
-        float g[N];
-        trunc_defect<N>(a, u, x, y, g);
-        float w[N];
-        if (k >= 2) {
-            const float mean = s / (float)k;
-            float xv[N];
+        const float mean = k > 0 ? sum / (float)k : 0.f;
 #pragma unroll
-            for (int i = 0; i < N; ++i) xv[i] = uc[i] + (uc[i] > 0.f ? v[i] - mean : 0.f);
-            project_simplex<N>(xv);
-#pragma unroll
-            for (int i = 0; i < N; ++i) w[i] = xv[i] - uc[i];
-        } else {
-#pragma unroll
-            for (int i = 0; i < N; ++i) w[i] = 0.f;
-        }
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            gw += (double)g[i] * (double)w[i];
-            a.gt[i * n + p] = w[i];
-        }
+        for (int i = 0; i < N; ++i) gs[i][fy][fx] = (k >= 2 && fr[i]) ? g[i] - mean : 0.f;
     }
-    const double t = block_sum_d(gw, sh);
-    if (threadIdx.x == 0) a.part[blockIdx.x] = t;
-}
-
-// 4b. block partials of <w, H w>.
-template <int N>
-__global__ __launch_bounds__(kBlock) void k_mg_whw(MgArgs a) {
-    __shared__ double sh[kBlock / kWave];
-    if (step_done(a)) return;
-    const int W = a.W, H = a.H;
-    const int64_t n = (int64_t)W * H;
-    double acc = 0.0;
-    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += (int64_t)gridDim.x * kBlock) {
-        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
-        const float D = sel4(a.coef.d, node_class(x, y, W, H));
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const float* wi = a.gt + i * n;
-            const float wc = wi[p];
-            const float hw = D * wc - a.coef.e2 * nb_sum(wi, W, H, x, y, p);
-            acc += (double)wc * (double)hw;
-        }
-    }
-    const double t = block_sum_d(acc, sh);
-    if (threadIdx.x == 0) a.part[kMgBlocks + blockIdx.x] = t;
-}
-
-// 4c. alpha from the partials (one workgroup, fixed order).
-__global__ __launch_bounds__(kBlock) void k_mg_alpha(MgArgs a) {
-    __shared__ double sh[kBlock / kWave];
-    if (step_done(a)) return;
-    double g = 0.0, q = 0.0;
-    for (int b = threadIdx.x; b < a.nblocks; b += kBlock) {
-        g += a.part[b];
-        q += a.part[kMgBlocks + b];
-    }
-    const double gt = block_sum_d(g, sh);
     __syncthreads();
-    const double qt = block_sum_d(q, sh);
-    if (threadIdx.x == 0) a.ctl->alpha = (qt > 0.0 && gt > 0.0) ? fmin(gt / qt, 1.0) : 0.0;
-}
-
-// 4d. u += alpha w (in place: the iterate buffer of the cycle).
-template <int N>
-__global__ __launch_bounds__(kBlock) void k_mg_update(MgArgs a) {
-    if (step_done(a)) return;
-    const float alpha = (float)a.ctl->alpha;
-    if (alpha == 0.f) return;
-    float* __restrict__ u = const_cast<float*>(a.bufs.b[__builtin_amdgcn_readfirstlane(iterate_buf(a.ctl->cur, a.launch))]);
-    const int64_t total = (int64_t)N * a.W * a.H;
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total; t += (int64_t)gridDim.x * kBlock)
-        u[t] = fmaxf(u[t] + alpha * a.gt[t], 0.f);
+    const int X = X0 + threadIdx.x % kDrTX, Y = Y0 + threadIdx.x / kDrTX;
+    if (X >= Wc || Y >= Hc) return;
+    float r[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) r[i] = 0.f;
+    for_restrict(W, H, Wc, Hc, X, Y, [&](int x, int y, float wt) {
+        const int fx = x - (sx0 + 1), fy = y - (sy0 + 1);
+#pragma unroll
+        for (int i = 0; i < N; ++i) r[i] += wt * gs[i][fy][fx];
+    });
+#pragma unroll
+    for (int i = 0; i < N; ++i) gstore(c.r + i * nc, (uint32_t)(Y * Wc + X), r[i]);
 }
 
 // ---------------------------------------------------------------------------
-// Coarse levels in global memory (levels too large for the LDS tail)
+// 3a. Down-leg of level l (1 <= l < tail): nu red-black sweeps of H_l v = r_l
+// from v = 0, then r_{l+1} = P^T (r_l - H_l v).  One workgroup per kDnTX x
+// kDnTY level-(l+1) nodes and component.  The level-l nodes that restriction
+// reaches (2X0-1 .. 2X0+2 kDnTX-1) need v with a halo of one; v after the
+// sweeps is exact on the block less 2 nu nodes at its rim (the first
+// half-sweep from zero reads no neighbour, every later one loses a ring, and
+// the rim itself is never updated), so the block is that region plus
+// 2 nu + 1.  The workgroup writes v of the level-l nodes 2X0 .. 2X0+2 kDnTX-1.
 // ---------------------------------------------------------------------------
 
-// dst (coarse) = P^T src (fine), N planes.
-template <int N>
-__global__ __launch_bounds__(kBlock) void k_restrict(CoarseArgs a) {
-    if (!a.fixed && a.ctl->step[a.slot].done) return;
-    const int64_t nf = (int64_t)a.Wf * a.Hf, nc = (int64_t)a.W * a.H;
-    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < nc; p += (int64_t)gridDim.x * kBlock) {
-        const int Y = (int)(p / a.W), X = (int)(p - (int64_t)Y * a.W);
-#pragma unroll
-        for (int i = 0; i < N; ++i) a.dst[i * nc + p] = restrict_at(a.src + i * nf, a.Wf, a.Hf, a.W, a.H, X, Y);
-    }
-}
+__host__ __device__ inline int down_halo(int nu) { return 2 * nu + 1; }
+__host__ __device__ inline int down_sx(int nu) { return 2 * kDnTX + 1 + 2 * down_halo(nu); }
+__host__ __device__ inline int down_sy(int nu) { return 2 * kDnTY + 1 + 2 * down_halo(nu); }
 
-// v (fine level of the pair) += P vc, N planes.
-template <int N>
-__global__ __launch_bounds__(kBlock) void k_prolong_add(CoarseArgs a) {
-    if (!a.fixed && a.ctl->step[a.slot].done) return;
-    const int64_t nf = (int64_t)a.Wf * a.Hf, nc = (int64_t)a.W * a.H;
-    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < nf; p += (int64_t)gridDim.x * kBlock) {
-        const int y = (int)(p / a.Wf), x = (int)(p - (int64_t)y * a.Wf);
+__device__ __forceinline__ void mg_down(const MgImage& d, int tile, const MgStep& st, int comp) {
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    const int l = st.level, nu = st.sweeps;
+    const MgLevel f = d.lv[l];
+    const MgLevel c = d.lv[l + 1];
+    if (comp >= d.N || mg_skip(d, st)) return;
+    const int W = f.W, H = f.H, Wc = c.W, Hc = c.H;
+    const int tx = (Wc + kDnTX - 1) / kDnTX;
+    const int X0 = (tile % tx) * kDnTX, Y0 = (tile / tx) * kDnTY;
+    const int hal = down_halo(nu), SX = down_sx(nu), SY = down_sy(nu);
+    const int sx0 = 2 * X0 - 1 - hal, sy0 = 2 * Y0 - 1 - hal;
+    const uint32_t n = (uint32_t)W * H, nc = (uint32_t)Wc * Hc;
+    float* rs = lds;
+    float* vs = lds + SX * SY;
+    const float* r = f.r + comp * n;
+    const float inv = 1.0f / (float)SX;
+    constexpr int CH = 8;  // loads in flight per thread
+    for (int base = 0; base < SX * SY; base += CH * kBlock) {
+        float t[CH];
+        bool ok[CH];
 #pragma unroll
-        for (int i = 0; i < N; ++i) a.dst[i * nf + p] += prolong_at(a.src + i * nc, a.W, a.H, x, y);
-    }
-}
-
-// One red (colour 0) or black (colour 1) half-sweep of linear Gauss-Seidel on
-// H_l v = r: v_p = r_p / D_p + kappa_p sum_q c_pq v_q.  With `zero` the other
-// colour is taken as 0 (the first half-sweep from v = 0).
-template <int N>
-__global__ __launch_bounds__(kBlock) void k_lin_half(CoarseArgs a) {
-    if (!a.fixed && a.ctl->step[a.slot].done) return;
-    const int W = a.W, H = a.H, hw = (W + 1) / 2;
-    const int64_t n = (int64_t)W * H, nh = (int64_t)hw * H;
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < nh; t += (int64_t)gridDim.x * kBlock) {
-        const int y = (int)(t / hw), j = (int)(t - (int64_t)y * hw);
-        const int x = 2 * j + ((y + a.colour) & 1);
-        if (x >= W) continue;
-        const int64_t p = (int64_t)y * W + x;
-        const int cls = node_class(x, y, W, H);
-        const float kap = sel4(a.coef.kappa, cls), invd = sel4(a.coef.inv_d, cls);
-        const int Wc = (W + 1) / 2, Hc = (H + 1) / 2;
-        const int64_t nc = (int64_t)Wc * Hc;
+        for (int k = 0; k < CH; ++k) {
+            const int q = base + k * kBlock + threadIdx.x;
+            const int ly = fdiv(q, inv), lx = q - ly * SX;
+            const int gx = sx0 + lx, gy = sy0 + ly;
+            ok[k] = q < SX * SY && gx >= 0 && gx < W && gy >= 0 && gy < H;
+            t[k] = gload(r, ok[k] ? (uint32_t)(gy * W + gx) : 0u);
+        }
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            float s = a.src[i * n + p] * invd;
-            if (a.aux)  // the neighbours' values plus the prolonged coarse correction
-                s += kap * nb_sum_prolonged(a.dst + i * n, a.aux + i * nc, W, H, Wc, Hc, x, y, p);
-            else if (!a.zero)
-                s += kap * nb_sum(a.dst + i * n, W, H, x, y, p);
-            a.dst[i * n + p] = s;
+        for (int k = 0; k < CH; ++k) {
+            const int q = base + k * kBlock + threadIdx.x;
+            if (q < SX * SY) {
+                rs[q] = ok[k] ? t[k] : 0.f;
+                vs[q] = 0.f;
+            }
         }
     }
-}
-
-// res = r - H_l v.
-template <int N>
-__global__ __launch_bounds__(kBlock) void k_lin_resid(CoarseArgs a) {
-    if (!a.fixed && a.ctl->step[a.slot].done) return;
-    const int W = a.W, H = a.H;
-    const int64_t n = (int64_t)W * H;
-    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += (int64_t)gridDim.x * kBlock) {
-        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
-        const float D = sel4(a.coef.d, node_class(x, y, W, H));
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const float* v = a.aux + i * n;
-            a.res[i * n + p] = a.src[i * n + p] - (D * v[p] - a.coef.e2 * nb_sum(v, W, H, x, y, p));
-        }
+    const bool in = block_interior(sx0, sy0, SX, SY, W, H);
+    for (int h = 0; h < 2 * nu; ++h) {
+        __syncthreads();
+        if (in)
+            block_half<kBlock, true>(vs, rs, SX, SY, sx0, sy0, W, H, f.coef, h & 1);
+        else
+            block_half<kBlock, false>(vs, rs, SX, SY, sx0, sy0, W, H, f.coef, h & 1);
     }
-}
-
-// dst (level of (W, H)) = P^T (r - H v) of the finer level (Wf, Hf): src = r,
-// aux = v of the finer level, coef of the finer level in a.coef.
-template <int N>
-__global__ __launch_bounds__(kBlock) void k_resid_restrict(CoarseArgs a) {
-    if (!a.fixed && a.ctl->step[a.slot].done) return;
-    const int Wf = a.Wf, Hf = a.Hf;
-    const int64_t nf = (int64_t)Wf * Hf, nc = (int64_t)a.W * a.H;
-    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < nc; p += (int64_t)gridDim.x * kBlock) {
-        const int Y = (int)(p / a.W), X = (int)(p - (int64_t)Y * a.W);
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const float* v = a.aux + i * nf;
-            const float* r = a.src + i * nf;
-            float s = 0.f;
-            for_restrict(Wf, Hf, a.W, a.H, X, Y, [&](int x, int y, float wt) {
-                const int64_t q = (int64_t)y * Wf + x;
-                const float D = sel4(a.coef.d, node_class(x, y, Wf, Hf));
-                s += wt * (r[q] - (D * v[q] - a.coef.e2 * nb_sum(v, Wf, Hf, x, y, q)));
-            });
-            a.dst[i * nc + p] = s;
-        }
+    __syncthreads();
+    // r_{l+1} = P^T (r - H v) on this workgroup's level-(l+1) nodes
+    for (int q = threadIdx.x; q < kDnTX * kDnTY; q += kBlock) {
+        const int X = X0 + q % kDnTX, Y = Y0 + q / kDnTX;
+        if (X >= Wc || Y >= Hc) continue;
+        float sum = 0.f;
+        for_restrict(W, H, Wc, Hc, X, Y, [&](int x, int y, float wt) {
+            sum += wt * block_resid(vs, rs, SX, (y - sy0) * SX + (x - sx0), x, y, W, H, f.coef);
+        });
+        gstore(c.r + comp * nc, (uint32_t)(Y * Wc + X), sum);
+    }
+    // v of the owned level-l nodes
+    float* v = f.v + comp * n;
+    for (int q = threadIdx.x; q < 4 * kDnTX * kDnTY; q += kBlock) {
+        const int ox = q % (2 * kDnTX), oy = q / (2 * kDnTX);
+        const int gx = 2 * X0 + ox, gy = 2 * Y0 + oy;
+        if (gx >= W || gy >= H) continue;
+        gstore(v, (uint32_t)(gy * W + gx), vs[(gy - sy0) * SX + (gx - sx0)]);
     }
 }
 
 // ---------------------------------------------------------------------------
-// LDS tail: the V-cycle over levels t0..L-1 (longer side <= kTailSide), one
-// workgroup per component.  r_{t0} is read from and v_{t0} written to global
-// memory; every other array lives in LDS.
+// 3c. Up-leg of level l: v = v_down + P v2_{l+1} (or v = 0 on the coarsest
+// level when no LDS tail solves it), then nu red-black sweeps of H_l v = r_l;
+// the result goes to v2.  One workgroup per kUpTX x kUpTY level-l nodes and
+// component, staged with a halo of 2 nu: each half-sweep, which updates the
+// block less its rim, loses one ring of exact values.
 // ---------------------------------------------------------------------------
 
-__device__ void tail_half(float* v, const float* r, int W, int H, const LevelCoef& c, int colour, bool zero) {
-    const int hw = (W + 1) / 2, nh = hw * H;
-    for (int t = threadIdx.x; t < nh; t += kTailThreads) {
-        const int y = t / hw, j = t - y * hw;
+__host__ __device__ inline int up_sx(int nu) { return kUpTX + 4 * nu; }
+__host__ __device__ inline int up_sy(int nu) { return kUpTY + 4 * nu; }
+
+__device__ __forceinline__ void mg_up(const MgImage& d, int tile, const MgStep& st, int comp) {
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    const int l = st.level, nu = st.sweeps;
+    const MgLevel f = d.lv[l];
+    const bool zero = st.zero != 0;
+    const MgLevel c = d.lv[zero ? l : l + 1];
+    if (comp >= d.N || mg_skip(d, st)) return;
+    const int W = f.W, H = f.H;
+    const int tx = (W + kUpTX - 1) / kUpTX;
+    const int x0 = (tile % tx) * kUpTX, y0 = (tile / tx) * kUpTY;
+    const int SX = up_sx(nu), SY = up_sy(nu);
+    const int sx0 = x0 - 2 * nu, sy0 = y0 - 2 * nu;
+    const uint32_t n = (uint32_t)W * H;
+    float* rs = lds;
+    float* vs = lds + SX * SY;
+    const float* r = f.r + comp * n;
+    const float* vd = f.v + comp * n;
+    const float* vc = c.v2 + (size_t)comp * c.W * c.H;
+    const float inv = 1.0f / (float)SX;
+    constexpr int CH = 4;  // staged nodes in flight per thread
+    for (int base = 0; base < SX * SY; base += CH * kBlock) {
+        float t[CH], v[CH];
+        bool ok[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int q = base + k * kBlock + threadIdx.x;
+            const int ly = fdiv(q, inv), lx = q - ly * SX;
+            const int gx = sx0 + lx, gy = sy0 + ly;
+            ok[k] = q < SX * SY && gx >= 0 && gx < W && gy >= 0 && gy < H;
+            const uint32_t g = ok[k] ? (uint32_t)(gy * W + gx) : 0u;
+            t[k] = gload(r, g);
+            v[k] = (ok[k] && !zero) ? gload(vd, g) + prolong_at(vc, c.W, c.H, gx, gy) : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int q = base + k * kBlock + threadIdx.x;
+            if (q < SX * SY) {
+                rs[q] = ok[k] ? t[k] : 0.f;
+                vs[q] = v[k];
+            }
+        }
+    }
+    const bool in = block_interior(sx0, sy0, SX, SY, W, H);
+    for (int h = 0; h < 2 * nu; ++h) {
+        __syncthreads();
+        if (in)
+            block_half<kBlock, true>(vs, rs, SX, SY, sx0, sy0, W, H, f.coef, h & 1);
+        else
+            block_half<kBlock, false>(vs, rs, SX, SY, sx0, sy0, W, H, f.coef, h & 1);
+    }
+    __syncthreads();
+    float* v2 = f.v2 + comp * n;
+    for (int q = threadIdx.x; q < kUpTX * kUpTY; q += kBlock) {
+        const int gx = x0 + q % kUpTX, gy = y0 + q / kUpTX;
+        if (gx >= W || gy >= H) continue;
+        gstore(v2, (uint32_t)(gy * W + gx), vs[(gy - sy0) * SX + (gx - sx0)]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3b. LDS tail: the V-cycle over levels t = tail .. L-1 (sides <= kTailSide)
+// of one component in one workgroup of kTailThreads, v and r of every level
+// in LDS.  Residuals are restricted as they are computed.  The levels' sizes,
+// coefficients and LDS offsets are copied to LDS once, so the dozens of
+// steps that follow read them there instead of waiting on scalar loads of the
+// descriptor.  The result v_t goes to v2 of level t.
+// ---------------------------------------------------------------------------
+
+struct TailLevel {
+    LevelCoef coef;
+    int W, H, off;  // off: float offset of v in the LDS field area (r follows v)
+    int pad;
+};
+
+__device__ __forceinline__ float lattice_nb(const float* __restrict__ v, int W, int H, int x, int y, int p) {
+    return edge_w_h(y, H) * ((x > 0 ? v[p - 1] : 0.f) + (x < W - 1 ? v[p + 1] : 0.f)) +
+           edge_w_v(x, W) * ((y > 0 ? v[p - W] : 0.f) + (y < H - 1 ? v[p + W] : 0.f));
+}
+
+__device__ __forceinline__ void tail_half(float* __restrict__ v, const float* __restrict__ r, int W, int H,
+                                          const LevelCoef c, int colour, bool zero) {
+    const int hw = (W + 1) / 2;
+    const float inv = 1.0f / (float)hw;
+    const float k0 = uniform_f(c.kappa[0]), i0 = uniform_f(c.inv_d[0]);
+    for (int q = threadIdx.x; q < hw * H; q += kTailThreads) {
+        const int y = fdiv(q, inv), j = q - y * hw;
         const int x = 2 * j + ((y + colour) & 1);
         if (x >= W) continue;
         const int p = y * W + x;
-        const int cls = node_class(x, y, W, H);
-        float s = r[p] * sel4(c.inv_d, cls);
-        if (!zero) s += sel4(c.kappa, cls) * nb_sum(v, W, H, x, y, p);
-        v[p] = s;
+        if (zero) {
+            v[p] = r[p] * sel4(c.inv_d, node_class(x, y, W, H));
+        } else if (y > 0 && y < H - 1 && x > 0 && x < W - 1) {
+            v[p] = fmaf(k0, (v[p - 1] + v[p + 1]) + (v[p - W] + v[p + W]), r[p] * i0);
+        } else {
+            const int cls = node_class(x, y, W, H);
+            v[p] = fmaf(sel4(c.kappa, cls), lattice_nb(v, W, H, x, y, p), r[p] * sel4(c.inv_d, cls));
+        }
     }
     __syncthreads();
 }
 
-__device__ void tail_sweeps(float* v, const float* r, int W, int H, const LevelCoef& c, int sweeps, bool zero) {
+__device__ __forceinline__ void tail_sweeps(float* v, const float* r, int W, int H, const LevelCoef c, int sweeps,
+                                            bool zero) {
     for (int s = 0; s < sweeps; ++s) {
         tail_half(v, r, W, H, c, 0, zero && s == 0);
         tail_half(v, r, W, H, c, 1, false);
     }
 }
 
-__global__ __launch_bounds__(kTailThreads) void k_coarse_tail(TailArgs a) {
-    if (!a.fixed && a.ctl->step[a.slot].done) return;
-    extern __shared__ __attribute__((aligned(16))) float lds[];
-    const int i = blockIdx.x;  // component
-    const TailLevel* lv = a.lv;
-    float* res = lds + a.off_res;
-    {
-        const int n0 = lv[0].W * lv[0].H;
-        const float* src = a.r_in + (int64_t)i * n0;
-        for (int t = threadIdx.x; t < n0; t += kTailThreads) lds[lv[0].off_r + t] = src[t];
-        __syncthreads();
+// rc = P^T (r - H v) from level (W, H) to (Wc, Hc).
+__device__ __forceinline__ void tail_resid_restrict(const float* __restrict__ v, const float* __restrict__ r,
+                                                    int W, int H, const LevelCoef c, float* __restrict__ rc,
+                                                    int Wc, int Hc) {
+    const float inv = 1.0f / (float)Wc;
+    for (int q = threadIdx.x; q < Wc * Hc; q += kTailThreads) {
+        const int Y = fdiv(q, inv), X = q - Y * Wc;
+        float sum = 0.f;
+        for_restrict(W, H, Wc, Hc, X, Y, [&](int x, int y, float wt) {
+            const int p = y * W + x;
+            sum += wt * (r[p] - (sel4(c.d, node_class(x, y, W, H)) * v[p] - c.e2 * lattice_nb(v, W, H, x, y, p)));
+        });
+        rc[q] = sum;
     }
-    for (int l = 0; l + 1 < a.nl; ++l) {  // down
-        const int W = lv[l].W, H = lv[l].H;
-        float* v = lds + lv[l].off_v;
-        const float* r = lds + lv[l].off_r;
-        tail_sweeps(v, r, W, H, a.coef[l], a.nu_pre, true);
-        for (int p = threadIdx.x; p < W * H; p += kTailThreads) {
-            const int y = p / W, x = p - y * W;
-            const float D = sel4(a.coef[l].d, node_class(x, y, W, H));
-            res[p] = r[p] - (D * v[p] - a.coef[l].e2 * nb_sum(v, W, H, x, y, p));
-        }
-        __syncthreads();
-        const int Wc = lv[l + 1].W, Hc = lv[l + 1].H;
-        float* rc = lds + lv[l + 1].off_r;
-        for (int p = threadIdx.x; p < Wc * Hc; p += kTailThreads) {
-            const int Y = p / Wc, X = p - Y * Wc;
-            rc[p] = restrict_at(res, W, H, Wc, Hc, X, Y);
-        }
-        __syncthreads();
-    }
-    {
-        const int l = a.nl - 1;
-        tail_sweeps(lds + lv[l].off_v, lds + lv[l].off_r, lv[l].W, lv[l].H, a.coef[l], a.coarse_sweeps, true);
-    }
-    for (int l = a.nl - 2; l >= 0; --l) {  // up
-        const int W = lv[l].W, H = lv[l].H, Wc = lv[l + 1].W, Hc = lv[l + 1].H;
-        float* v = lds + lv[l].off_v;
-        const float* vc = lds + lv[l + 1].off_v;
-        for (int p = threadIdx.x; p < W * H; p += kTailThreads) {
-            const int y = p / W, x = p - y * W;
-            v[p] += prolong_at(vc, Wc, Hc, x, y);
-        }
-        __syncthreads();
-        tail_sweeps(v, lds + lv[l].off_r, W, H, a.coef[l], a.nu_post, false);
-    }
-    const int n0 = lv[0].W * lv[0].H;
-    float* dst = a.v_out + (int64_t)i * n0;
-    for (int t = threadIdx.x; t < n0; t += kTailThreads) dst[t] = lds[lv[0].off_v + t];
+    __syncthreads();
 }
+
+__device__ __forceinline__ void tail_prolong_add(float* __restrict__ v, int W, int H, const float* __restrict__ vc,
+                                                 int Wc, int Hc) {
+    const float inv = 1.0f / (float)W;
+    for (int q = threadIdx.x; q < W * H; q += kTailThreads) {
+        const int y = fdiv(q, inv), x = q - y * W;
+        v[q] += prolong_at(vc, Wc, Hc, x, y);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void mg_tail(const MgImage& d, const MgStep& st, int comp) {
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    __shared__ TailLevel tl[kMaxLevels];
+    if (comp >= d.N || mg_skip(d, st)) return;
+    const int t = d.tail, L = d.L;
+    if (threadIdx.x == 0) {
+        int off = 0;
+        for (int l = t; l < L; ++l) {
+            tl[l].coef = d.lv[l].coef;
+            tl[l].W = d.lv[l].W;
+            tl[l].H = d.lv[l].H;
+            tl[l].off = off;
+            off += 2 * d.lv[l].W * d.lv[l].H;
+        }
+    }
+    const int Wt = d.lv[t].W, Ht = d.lv[t].H;
+    const uint32_t nt = (uint32_t)Wt * Ht;
+    {
+        const float* rt = d.lv[t].r + comp * nt;
+        float* r0 = lds + nt;  // level t's v starts at offset 0
+        for (int q = threadIdx.x; q < (int)nt; q += kTailThreads) r0[q] = gload(rt, (uint32_t)q);
+        __syncthreads();
+    }
+    for (int l = t; l < L; ++l) {  // down
+        const TailLevel& g = tl[l];
+        float* v = lds + g.off;
+        float* r = v + g.W * g.H;
+        if (l == L - 1) {
+            tail_sweeps(v, r, g.W, g.H, g.coef, kCoarseSweeps, true);
+        } else {
+            tail_sweeps(v, r, g.W, g.H, g.coef, st.nu_pre, true);
+            const TailLevel& c = tl[l + 1];
+            tail_resid_restrict(v, r, g.W, g.H, g.coef, lds + c.off + c.W * c.H, c.W, c.H);
+        }
+    }
+    for (int l = L - 2; l >= t; --l) {  // up
+        const TailLevel& g = tl[l];
+        const TailLevel& c = tl[l + 1];
+        float* v = lds + g.off;
+        tail_prolong_add(v, g.W, g.H, lds + c.off, c.W, c.H);
+        tail_sweeps(v, v + g.W * g.H, g.W, g.H, g.coef, st.nu_post, false);
+    }
+    float* out = d.lv[t].v2 + comp * nt;
+    for (int q = threadIdx.x; q < (int)nt; q += kTailThreads) gstore(out, (uint32_t)q, lds[q]);
+}
+
+// ---------------------------------------------------------------------------
+// 4a. Direction w = Pi(u + T_I P v2_1) - u and the line-search partials
+// <g~, w>, <w, H w>: workgroup b of an image takes the kDirTX x kDirTY fine
+// tiles b, b + dir_blocks, ...; per tile w on the tile and a ring of one (for
+// H w) from u staged with that ring, g~ on the tile.  Each workgroup leaves
+// its two sums; the update pass reduces them.
+// ---------------------------------------------------------------------------
+
+template <int N>
+__device__ __forceinline__ void mg_dir(const MgImage& d, int blk, const MgStep& st) {
+    constexpr int SX = kDirTX + 2, SY = kDirTY + 2;
+    __shared__ float us[N][SY][SX];
+    __shared__ float ws[N][SY][SX];
+    __shared__ double sh[kBlock / kWave];
+    const int W = d.W, H = d.H;
+    const MgLevel c = d.lv[1];
+    const MgState ms = mg_state(d, st);
+    if (ms.skip) return;
+    const int tx = (W + kDirTX - 1) / kDirTX;
+    const int ntiles = tx * ((H + kDirTY - 1) / kDirTY);
+    const uint32_t n = (uint32_t)W * H, nc = (uint32_t)c.W * c.H;
+    const float* u = ms.u;
+    double gw = 0.0, whw = 0.0;
+    for (int tile = blk; tile < ntiles; tile += d.dir_blocks) {
+        const int x0 = (tile % tx) * kDirTX, y0 = (tile / tx) * kDirTY;
+        const int sx0 = x0 - 1, sy0 = y0 - 1;
+        __syncthreads();  // the previous tile's reads of us / ws are done
+        stage_planes<N, SX, SY>(&us[0][0][0], u, n, sx0, sy0, W, H);
+        __syncthreads();
+#pragma unroll
+        for (int q = threadIdx.x; q < SX * SY; q += kBlock) {
+            const int ly = q / SX, lx = q - ly * SX;
+            const int gx = sx0 + lx, gy = sy0 + ly;
+            float w[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) w[i] = 0.f;
+            if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
+                float uc[N], v[N];
+                int k = 0;
+                float s = 0.f;
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    uc[i] = us[i][ly][lx];
+                    v[i] = prolong_at(c.v2 + i * nc, c.W, c.H, gx, gy);
+                    if (uc[i] > 0.f) {
+                        s += v[i];
+                        ++k;
+                    }
+                }
+                if (k >= 2) {
+                    const float mean = s / (float)k;
+                    float xv[N];
+#pragma unroll
+                    for (int i = 0; i < N; ++i) xv[i] = uc[i] + (uc[i] > 0.f ? v[i] - mean : 0.f);
+                    project_simplex<N>(xv);
+#pragma unroll
+                    for (int i = 0; i < N; ++i) w[i] = xv[i] - uc[i];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < N; ++i) ws[i][ly][lx] = w[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = threadIdx.x; q < kDirTX * kDirTY; q += kBlock) {
+            const int ox = q % kDirTX, oy = q / kDirTX;
+            const int gx = x0 + ox, gy = y0 + oy;
+            if (gx >= W || gy >= H) continue;
+            const int lx = ox + 1, ly = oy + 1;
+            const int cls = node_class(gx, gy, W, H);
+            const float kap = sel4(d.fine.kappa, cls), D = sel4(d.fine.d, cls);
+            const float ewh = edge_w_h(gy, H), ewv = edge_w_v(gx, W);
+            const uint32_t p = (uint32_t)(gy * W + gx);
+            float g[N];
+            bool fr[N];
+            float sum = 0.f;
+            int k = 0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const float uc = us[i][ly][lx];
+                const float nb = ewh * (us[i][ly][lx - 1] + us[i][ly][lx + 1]) + ewv * (us[i][ly - 1][lx] + us[i][ly + 1][lx]);
+                g[i] = D * (gload(d.rhs + i * n, p) + kap * nb - uc);
+                fr[i] = uc > 0.f;
+                if (fr[i]) {
+                    sum += g[i];
+                    ++k;
+                }
+            }
+            const float mean = k > 0 ? sum / (float)k : 0.f;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const float gt = (k >= 2 && fr[i]) ? g[i] - mean : 0.f;
+                const float wc = ws[i][ly][lx];
+                const float nbw = ewh * (ws[i][ly][lx - 1] + ws[i][ly][lx + 1]) + ewv * (ws[i][ly - 1][lx] + ws[i][ly + 1][lx]);
+                const float hw = D * wc - d.fine.e2 * nbw;
+                gw += (double)gt * (double)wc;
+                whw += (double)wc * (double)hw;
+                gstore(d.gt + i * n, p, wc);
+            }
+        }
+    }
+    const double tg = block_sum_d(gw, sh);
+    const double tq = block_sum_d(whw, sh);
+    if (threadIdx.x == 0) {
+        d.part[2 * blk] = tg;
+        d.part[2 * blk + 1] = tq;
+    }
+}
+
+// 4b. alpha = clamp(<g~,w> / <w,Hw>, 0, 1) from the direction pass's partials
+// (every workgroup reduces them in the same fixed order), then
+// u = max(u + alpha w, 0) on one kUpdTX x kUpdTY fine tile (in place).
+template <int N>
+__device__ __forceinline__ void mg_update(const MgImage& d, int tile, const MgStep& st) {
+    __shared__ double sh[kBlock / kWave];
+    const MgState ms = mg_state(d, st);
+    if (ms.skip) return;
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < d.dir_blocks; k += kBlock) {
+        a += d.part[2 * k];
+        b += d.part[2 * k + 1];
+    }
+    const double ga = block_sum_d(a, sh);
+    const double qa = block_sum_d(b, sh);
+    const float alpha = (qa > 0.0 && ga > 0.0) ? (float)fmin(ga / qa, 1.0) : 0.f;
+    if (tile == 0 && threadIdx.x == 0) d.ctl->alpha = alpha;  // for inspection
+    if (alpha == 0.f) return;
+    const int W = d.W, H = d.H;
+    const int tx = (W + kUpdTX - 1) / kUpdTX;
+    const int x0 = (tile % tx) * kUpdTX, y0 = (tile / tx) * kUpdTY;
+    const uint32_t n = (uint32_t)W * H;
+    float* u = ms.u;
+    constexpr int Q = kUpdTX * kUpdTY / kBlock;
+    float uv[Q][N], w[Q][N];
+    uint32_t pp[Q];
+    bool ok[Q];
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+        const int q = threadIdx.x + c * kBlock;
+        const int gx = x0 + q % kUpdTX, gy = y0 + q / kUpdTX;
+        ok[c] = gx < W && gy < H;
+        pp[c] = ok[c] ? (uint32_t)(gy * W + gx) : 0u;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            uv[c][i] = gload(u + i * n, pp[c]);
+            w[c][i] = gload(d.gt + i * n, pp[c]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+        if (!ok[c]) continue;
+#pragma unroll
+        for (int i = 0; i < N; ++i) gstore(u + i * n, pp[c], fmaxf(fmaf(alpha, w[c][i], uv[c][i]), 0.f));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernels: one image (its descriptor by value, workgroup x = tile x) or a
+// batch (descriptor table and work list).
+// ---------------------------------------------------------------------------
+
+// Each pass has two kernels.  One image: its descriptor is the kernel
+// argument (constant offsets into the argument segment, loaded together) and
+// workgroup x is tile x.  A batch: descriptor table and work list.
+#define ACSEG_MG_KERNELS(TPL, NAME, BOUND, BODY)                                             \
+    TPL __global__ __launch_bounds__(BOUND) void NAME(MgImage d, MgStep st) {                \
+        const int tile = blockIdx.x;                                                         \
+        BODY;                                                                                \
+    }                                                                                        \
+    TPL __global__ __launch_bounds__(BOUND) void NAME##_b(const MgImage* __restrict__ descs, \
+                                                          const int2* __restrict__ work,     \
+                                                          int nwork, MgStep st) {            \
+        if ((int)blockIdx.x >= nwork) return;                                                \
+        const int2 wv = work[blockIdx.x];                                                    \
+        if (wv.x < 0) return;                                                                \
+        const MgImage& d = descs[wv.x];                                                      \
+        const int tile = wv.y;                                                               \
+        BODY;                                                                                \
+    }
+
+#define ACSEG_TPL_N template <int N>
+#define ACSEG_TPL_NONE
+ACSEG_MG_KERNELS(ACSEG_TPL_N, k_mg_defect_restrict, kBlock, mg_defect_restrict<N>(d, tile, st))
+ACSEG_MG_KERNELS(ACSEG_TPL_NONE, k_mg_down, kBlock, mg_down(d, tile, st, blockIdx.y))
+ACSEG_MG_KERNELS(ACSEG_TPL_NONE, k_mg_up, kBlock, mg_up(d, tile, st, blockIdx.y))
+ACSEG_MG_KERNELS(ACSEG_TPL_NONE, k_mg_tail, kTailThreads, (void)tile; mg_tail(d, st, blockIdx.y))
+ACSEG_MG_KERNELS(ACSEG_TPL_N, k_mg_dir, kBlock, mg_dir<N>(d, tile, st))
+ACSEG_MG_KERNELS(ACSEG_TPL_N, k_mg_update, kBlock, mg_update<N>(d, tile, st))
+#undef ACSEG_TPL_N
+#undef ACSEG_TPL_NONE
+#undef ACSEG_MG_KERNELS
 
 // ---------------------------------------------------------------------------
 // Launchers
@@ -456,78 +744,88 @@ int grid_for(int64_t work) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(b, kMgBlocks));
 }
 
-template <int N>
-hipError_t mg_fine(int op, const MgArgs& a, hipStream_t s) {
-    const int g = a.nblocks;
-    switch (op) {
-        case kMgDefectRestrict:
-            hipLaunchKernelGGL((k_mg_defect_restrict<N>), dim3(grid_for((int64_t)a.Wc * a.Hc)), dim3(kBlock), 0, s, a);
-            break;
-        case kMgDir: hipLaunchKernelGGL((k_mg_dir<N>), dim3(g), dim3(kBlock), 0, s, a); break;
-        case kMgWhw: hipLaunchKernelGGL((k_mg_whw<N>), dim3(g), dim3(kBlock), 0, s, a); break;
-        case kMgAlpha: hipLaunchKernelGGL(k_mg_alpha, dim3(1), dim3(kBlock), 0, s, a); break;
-        case kMgUpdate: hipLaunchKernelGGL((k_mg_update<N>), dim3(grid_for((int64_t)N * a.W * a.H)), dim3(kBlock), 0, s, a); break;
-        default: return hipErrorInvalidValue;
-    }
+int tiles_of(int W, int H, int TX, int TY) { return ((W + TX - 1) / TX) * ((H + TY - 1) / TY); }
+
+// One launch of a pass: the single-image kernel K1 or the batch kernel KB.
+template <class K1, class KB>
+hipError_t mg_launch(K1 k1, KB kb, dim3 grid, int threads, size_t lds, const MgImage& m, const MgGrid& g,
+                     const MgStep& st, hipStream_t s) {
+    if (g.descs)
+        hipLaunchKernelGGL(kb, grid, dim3(threads), lds, s, g.descs, g.work, g.nwork, st);
+    else
+        hipLaunchKernelGGL(k1, grid, dim3(threads), lds, s, m, st);
     return hipGetLastError();
 }
 
 template <int N>
-hipError_t mg_coarse(int op, const CoarseArgs& a, hipStream_t s) {
+hipError_t mg_fine(int op, const MgImage& m, const MgGrid& g, const MgStep& st, dim3 grid, hipStream_t s) {
     switch (op) {
-        case kCoarseRestrict:
-            hipLaunchKernelGGL((k_restrict<N>), dim3(grid_for((int64_t)a.W * a.H)), dim3(kBlock), 0, s, a);
-            break;
-        case kCoarseProlongAdd:
-            hipLaunchKernelGGL((k_prolong_add<N>), dim3(grid_for((int64_t)a.Wf * a.Hf)), dim3(kBlock), 0, s, a);
-            break;
-        case kCoarseHalf:
-            hipLaunchKernelGGL((k_lin_half<N>), dim3(grid_for((int64_t)(a.W + 1) / 2 * a.H)), dim3(kBlock), 0, s, a);
-            break;
-        case kCoarseResid:
-            hipLaunchKernelGGL((k_lin_resid<N>), dim3(grid_for((int64_t)a.W * a.H)), dim3(kBlock), 0, s, a);
-            break;
-        case kCoarseResidRestrict:
-            hipLaunchKernelGGL((k_resid_restrict<N>), dim3(grid_for((int64_t)a.W * a.H)), dim3(kBlock), 0, s, a);
-            break;
+        case kMgDefectRestrict:
+            return mg_launch(k_mg_defect_restrict<N>, k_mg_defect_restrict_b<N>, grid, kBlock, 0, m, g, st, s);
+        case kMgDir: return mg_launch(k_mg_dir<N>, k_mg_dir_b<N>, grid, kBlock, 0, m, g, st, s);
+        case kMgUpdate: return mg_launch(k_mg_update<N>, k_mg_update_b<N>, grid, kBlock, 0, m, g, st, s);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace
 
-int mg_blocks(int W, int H) { return grid_for((int64_t)W * H); }
-
-hipError_t launch_mg_fine(int N, int op, const MgArgs& a, hipStream_t s) {
-    switch (N) {
-        case 2: return mg_fine<2>(op, a, s);
-        case 3: return mg_fine<3>(op, a, s);
-        case 4: return mg_fine<4>(op, a, s);
-        case 5: return mg_fine<5>(op, a, s);
-        case 6: return mg_fine<6>(op, a, s);
-        case 7: return mg_fine<7>(op, a, s);
-        case 8: return mg_fine<8>(op, a, s);
-        default: return hipErrorInvalidValue;
+int mg_pass_tiles(int op, const MgImage& m, int level) {
+    switch (op) {
+        case kMgDefectRestrict: return tiles_of(m.lv[1].W, m.lv[1].H, kDrTX, kDrTY);
+        case kMgDown: return tiles_of(m.lv[level + 1].W, m.lv[level + 1].H, kDnTX, kDnTY);
+        case kMgUp: return tiles_of(m.lv[level].W, m.lv[level].H, kUpTX, kUpTY);
+        case kMgTail: return 1;
+        case kMgDir: return m.dir_blocks;
+        case kMgUpdate: return tiles_of(m.W, m.H, kUpdTX, kUpdTY);
+        default: return 0;
     }
 }
 
-hipError_t launch_mg_coarse(int N, int op, const CoarseArgs& a, hipStream_t s) {
-    switch (N) {
-        case 2: return mg_coarse<2>(op, a, s);
-        case 3: return mg_coarse<3>(op, a, s);
-        case 4: return mg_coarse<4>(op, a, s);
-        case 5: return mg_coarse<5>(op, a, s);
-        case 6: return mg_coarse<6>(op, a, s);
-        case 7: return mg_coarse<7>(op, a, s);
-        case 8: return mg_coarse<8>(op, a, s);
-        default: return hipErrorInvalidValue;
+size_t mg_tail_lds(const int* W, const int* H, int t, int L) {
+    size_t f = 0;
+    for (int l = t; l < L; ++l) f += (size_t)W[l] * H[l] * 2;
+    return f * sizeof(float);
+}
+
+size_t mg_pass_lds(int op, const MgImage& m, int sweeps) {
+    switch (op) {
+        case kMgDown: return (size_t)2 * down_sx(sweeps) * down_sy(sweeps) * sizeof(float);
+        case kMgUp: return (size_t)2 * up_sx(sweeps) * up_sy(sweeps) * sizeof(float);
+        case kMgTail: {
+            int W[kMaxLevels], H[kMaxLevels];
+            for (int l = 1; l < m.L; ++l) {
+                W[l] = m.lv[l].W;
+                H[l] = m.lv[l].H;
+            }
+            return mg_tail_lds(W, H, m.tail, m.L);
+        }
+        default: return 0;
     }
 }
 
-hipError_t launch_coarse_tail(int N, const TailArgs& a, size_t lds_bytes, hipStream_t s) {
-    hipLaunchKernelGGL(k_coarse_tail, dim3(N), dim3(kTailThreads), lds_bytes, s, a);
-    return hipGetLastError();
+hipError_t launch_mg(int op, int N, int ncomp, const MgImage& single, const MgGrid& g, const MgStep& st,
+                     size_t lds, hipStream_t s) {
+    const int items = g.descs ? g.nwork : mg_pass_tiles(op, single, st.level);
+    if (items <= 0) return hipSuccess;
+    switch (op) {
+        case kMgDown: return mg_launch(k_mg_down, k_mg_down_b, dim3(items, ncomp), kBlock, lds, single, g, st, s);
+        case kMgUp: return mg_launch(k_mg_up, k_mg_up_b, dim3(items, ncomp), kBlock, lds, single, g, st, s);
+        case kMgTail:
+            return mg_launch(k_mg_tail, k_mg_tail_b, dim3(items, ncomp), kTailThreads, lds, single, g, st, s);
+        default: break;
+    }
+    const dim3 grid(items);
+    switch (N) {
+        case 2: return mg_fine<2>(op, single, g, st, grid, s);
+        case 3: return mg_fine<3>(op, single, g, st, grid, s);
+        case 4: return mg_fine<4>(op, single, g, st, grid, s);
+        case 5: return mg_fine<5>(op, single, g, st, grid, s);
+        case 6: return mg_fine<6>(op, single, g, st, grid, s);
+        case 7: return mg_fine<7>(op, single, g, st, grid, s);
+        case 8: return mg_fine<8>(op, single, g, st, grid, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // Transfer operators on their own (no control block), `planes` plane sets.
