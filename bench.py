@@ -111,7 +111,7 @@ def run_hetero(args):
     u0s = [torch.from_numpy(m[1]).to(dev) for m in made]
     us = [torch.empty_like(u) for u in u0s]
     nodes = sum(w.W * w.H for w in ws)
-    probs = [acseg.Problem.from_workload(w, C=3, levels=1, max_cycles=args.max_cycles) for w in ws]
+    probs = [acseg.Problem.from_workload(w, C=3, levels=args.levels, max_cycles=args.max_cycles) for w in ws]
     cycles = 1
     for b in range(len(ws)):  # the slowest time step of any image fixes the schedule
         us[b].copy_(u0s[b])
@@ -400,9 +400,6 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     B = max(1, args.batch)
-    if args.levels != 1 and B > 1:
-        log("[bench] the batched solve runs Gauss-Seidel cycles only: --levels != 1 uses --batch 1")
-        B = 1
     made = [w.make(seed) for seed in range(B)]
     img_np, u0_np, _ = made[0]
     C = img_np.shape[0]

@@ -371,12 +371,17 @@ acseg_status acseg_solve_no_alloc(acseg_ctx *ctx, const acseg_problem *p, const 
  * c_outs[b] are non-NULL, the colour means of the result in c_outs[b].  The
  * images may differ in size, N, C and every model parameter; they must agree
  * on steps, nu_pre, nu_post, max_cycles and flags (ACSEG_ERR_INVALID_ARG
- * otherwise), use Gauss-Seidel cycles only (levels == 1, or 0 resolving to 1;
- * ACSEG_ERR_UNSUPPORTED otherwise) and not ask for checkpoints.  Each cycle
- * is one launch over the tiles of all images with the same N and C, and each
- * image keeps its own convergence control, so the result for every image is
- * identical to acseg_solve's.  images, us, c_outs and stats are HOST arrays
- * of B entries (device pointers / statistics); stats may be NULL.
+ * otherwise) and not ask for checkpoints; the subspace correction
+ * (ACSEG_FLAG_SSC with two or more levels) is refused with
+ * ACSEG_ERR_UNSUPPORTED.  The images are grouped by N, C and cycle kind
+ * (Gauss-Seidel or multigrid).  Each smoothing launch covers the tiles of all
+ * images of a group; each pass of a multigrid correction (defect and
+ * restriction, one down and one up pass per large level, the LDS tail,
+ * direction, update) is one launch over the images of the group that have
+ * that level, whatever their sizes.  Each image keeps its own convergence
+ * control, so the result for every image is identical to acseg_solve's.
+ * images, us, c_outs and stats are HOST arrays of B entries (device pointers
+ * / statistics); stats may be NULL.
  * 1 <= B <= 4096.  The workspace size comes from acseg_batch_workspace_size.
  */
 acseg_status acseg_batch_workspace_size(int32_t B, const acseg_problem *ps, size_t *bytes);

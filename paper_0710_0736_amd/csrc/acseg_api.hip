@@ -560,66 +560,159 @@ acseg_status validate_batch(int32_t B, const acseg_problem* ps) {
         if (v != ACSEG_OK) return v;
         if (!same_schedule(ps[0], ps[b])) return ACSEG_ERR_INVALID_ARG;
         if ((ps[b].flags & ACSEG_FLAG_STORE_CHECKPOINTS) != 0u) return ACSEG_ERR_INVALID_ARG;
-        if (plan_of(&ps[b]).L != 1) return ACSEG_ERR_UNSUPPORTED;
+        // the subspace correction runs per image only
+        if ((ps[b].flags & ACSEG_FLAG_SSC) != 0u && plan_of(&ps[b]).L >= 2) return ACSEG_ERR_UNSUPPORTED;
     }
     return ACSEG_OK;
 }
 
-// Batch workspace: descriptor table, work lists, group image lists, then one
-// single-image region per image.
-struct BatchLayout {
-    size_t descs = 0, work = 0, imgs = 0;
+int tiles_of(int W, int H, int TX, int TY) { return ((W + TX - 1) / TX) * ((H + TY - 1) / TY); }
+
+// One multigrid launch of a batch group: pass, its work items, sweeps, LDS.
+struct MgLaunchRec {
+    int op, work0, nwork, sweeps;
+    size_t lds;
+};
+
+// Images of one batch with the same N, C and cycle kind (Gauss-Seidel cycles
+// or multigrid cycles): their cycles share launches.
+struct BatchGroup {
+    int N = 0, C = 0;
+    bool mg = false;
+    std::vector<int> members;
+    int work0 = 0, nwork = 0;  // smoothing tiles (int2 work list)
+    int img0 = 0;              // step-end image list
+    std::vector<MgLaunchRec> mgl;  // the passes of one multigrid correction, in order
+};
+
+// Everything about a batch that does not depend on the workspace address:
+// groups, work lists, and the workspace carve-up.
+struct BatchPlan {
+    std::vector<BatchGroup> groups;
+    std::vector<int2> work;    // smoothing tiles, every group
+    std::vector<int> imgs;     // step-end image lists, every group
+    std::vector<int4> mgwork;  // multigrid work items, every group
+    std::vector<MgPlan> mp;
+    size_t descs = 0, mgdescs = 0, work_off = 0, imgs_off = 0, mgwork_off = 0;
+    size_t table_bytes = 0;    // descs .. mgwork, uploaded in one copy
     std::vector<size_t> region;
     std::vector<Layout> L;
     size_t total = 0;
-    size_t table_bytes = 0;  // descs .. imgs, uploaded in one copy
-    int nwork = 0;
 };
 
-int batch_work_slots(int N, const acseg_problem* ps, int B, const std::vector<int>& members) {
-    (void)N;
-    int64_t T = 0;
-    for (int b : members) T += cycle_tiles(ps[b].N, ps[b].W, ps[b].H);
-    (void)B;
-    return (int)(((T + kXcd - 1) / kXcd) * kXcd);
-}
-
-// Images grouped by (N, C), in order of first appearance.
-std::vector<std::vector<int>> batch_groups(int32_t B, const acseg_problem* ps) {
-    std::vector<std::vector<int>> g;
-    for (int b = 0; b < B; ++b) {
-        bool placed = false;
-        for (auto& m : g)
-            if (ps[m[0]].N == ps[b].N && ps[m[0]].C == ps[b].C) {
-                m.push_back(b);
-                placed = true;
-                break;
-            }
-        if (!placed) g.push_back({b});
+// The multigrid passes of a group: defect + restriction, down passes level by
+// level, LDS tails, up passes level by level (with the coarsest-level solve of
+// images without a tail), direction, update.  An image takes part in the
+// passes its hierarchy has.
+void plan_group_mg(const acseg_problem* ps, BatchPlan& bp, BatchGroup& g) {
+    const int nu_pre = ps[g.members[0]].nu_pre, nu_post = ps[g.members[0]].nu_post;
+    auto add = [&](int op, int sweeps, size_t lds, const std::vector<int4>& items) {
+        if (items.empty()) return;
+        g.mgl.push_back({op, (int)bp.mgwork.size(), (int)items.size(), sweeps, lds});
+        bp.mgwork.insert(bp.mgwork.end(), items.begin(), items.end());
+    };
+    auto down_end = [&](int b) { const MgPlan& m = bp.mp[b]; return m.tail < m.L ? m.tail : m.L - 1; };
+    std::vector<int4> it;
+    for (int b : g.members) {
+        const MgPlan& m = bp.mp[b];
+        for (int t = 0; t < tiles_of(m.W[1], m.H[1], kDrTX, kDrTY); ++t) it.push_back(make_int4(b, t, 1, 0));
     }
-    return g;
+    add(kMgDefectRestrict, 0, 0, it);
+    int maxL = 0;
+    for (int b : g.members) maxL = std::max(maxL, bp.mp[b].L);
+    for (int l = 1; l < maxL; ++l) {
+        it.clear();
+        for (int b : g.members) {
+            const MgPlan& m = bp.mp[b];
+            if (l >= down_end(b)) continue;
+            for (int t = 0; t < tiles_of(m.W[l + 1], m.H[l + 1], kDnTX, kDnTY); ++t) it.push_back(make_int4(b, t, l, 0));
+        }
+        add(kMgDown, nu_pre, mg_lds_down(nu_pre), it);
+    }
+    it.clear();
+    size_t tail_lds = 0;
+    for (int b : g.members) {
+        const MgPlan& m = bp.mp[b];
+        if (m.tail >= m.L) continue;
+        it.push_back(make_int4(b, 0, m.tail, 0));
+        tail_lds = std::max(tail_lds, mg_tail_lds(m.W, m.H, m.tail, m.L));
+    }
+    add(kMgTail, 0, tail_lds, it);
+    for (int l = maxL - 1; l >= 1; --l) {
+        it.clear();
+        bool zero_any = false;
+        for (int b : g.members) {
+            const MgPlan& m = bp.mp[b];
+            const bool zero = m.tail >= m.L && l == m.L - 1;  // the coarsest level without a tail
+            if (!zero && l >= down_end(b)) continue;
+            zero_any = zero_any || zero;
+            for (int t = 0; t < tiles_of(m.W[l], m.H[l], kUpTX, kUpTY); ++t)
+                it.push_back(make_int4(b, t, l, zero ? 1 : 0));
+        }
+        add(kMgUp, nu_post, std::max(mg_lds_up(nu_post), zero_any ? mg_lds_up(kCoarseSweeps) : 0), it);
+    }
+    it.clear();
+    for (int b : g.members)
+        for (int k = 0; k < dir_blocks(ps[b].W, ps[b].H); ++k) it.push_back(make_int4(b, k, 0, 0));
+    add(kMgDir, 0, 0, it);
+    it.clear();
+    for (int b : g.members)
+        for (int t = 0; t < tiles_of(ps[b].W, ps[b].H, kUpdTX, kUpdTY); ++t) it.push_back(make_int4(b, t, 0, 0));
+    add(kMgUpdate, 0, 0, it);
 }
 
-BatchLayout batch_layout_of(int32_t B, const acseg_problem* ps) {
-    BatchLayout bl;
-    const auto groups = batch_groups(B, ps);
-    for (const auto& m : groups) bl.nwork += batch_work_slots(ps[m[0]].N, ps, B, m);
+BatchPlan plan_batch(int32_t B, const acseg_problem* ps) {
+    BatchPlan bp;
+    for (int b = 0; b < B; ++b) bp.mp.push_back(plan_of(&ps[b]));
+    // groups by (N, C, cycle kind), in order of first appearance
+    for (int b = 0; b < B; ++b) {
+        const bool mg = bp.mp[b].L >= 2;
+        BatchGroup* g = nullptr;
+        for (auto& x : bp.groups)
+            if (x.N == ps[b].N && x.C == ps[b].C && x.mg == mg) g = &x;
+        if (!g) {
+            bp.groups.push_back(BatchGroup{});
+            g = &bp.groups.back();
+            g->N = ps[b].N;
+            g->C = ps[b].C;
+            g->mg = mg;
+        }
+        g->members.push_back(b);
+    }
+    for (BatchGroup& g : bp.groups) {
+        // concatenated smoothing tiles of the group, dealt to the XCDs in contiguous bands
+        std::vector<int2> tiles;
+        for (int b : g.members)
+            for (int t = 0; t < cycle_tiles(ps[b].N, ps[b].W, ps[b].H); ++t) tiles.push_back(make_int2(b, t));
+        g.nwork = (int)((tiles.size() + kXcd - 1) / kXcd * kXcd);
+        g.work0 = (int)bp.work.size();
+        const int tpx = g.nwork / kXcd;
+        for (int k = 0; k < g.nwork; ++k) {
+            const int gt = (k % kXcd) * tpx + k / kXcd;
+            bp.work.push_back(gt < (int)tiles.size() ? tiles[gt] : make_int2(-1, 0));
+        }
+        g.img0 = (int)bp.imgs.size();
+        bp.imgs.insert(bp.imgs.end(), g.members.begin(), g.members.end());
+        if (g.mg) plan_group_mg(ps, bp, g);
+    }
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
         off = align_up(off + bytes);
         return o;
     };
-    bl.descs = take(sizeof(CycleArgs) * B);
-    bl.work = take(sizeof(int2) * (size_t)bl.nwork);
-    bl.imgs = take(sizeof(int) * B);
-    bl.table_bytes = off;
+    bp.descs = take(sizeof(CycleArgs) * B);
+    bp.mgdescs = take(sizeof(MgImage) * B);
+    bp.work_off = take(sizeof(int2) * bp.work.size());
+    bp.imgs_off = take(sizeof(int) * bp.imgs.size());
+    bp.mgwork_off = take(sizeof(int4) * bp.mgwork.size());
+    bp.table_bytes = off;
     for (int b = 0; b < B; ++b) {
-        bl.L.push_back(layout_of(&ps[b]));
-        bl.region.push_back(take(bl.L.back().total));
+        bp.L.push_back(layout_of(&ps[b]));
+        bp.region.push_back(take(bp.L.back().total));
     }
-    bl.total = off;
-    return bl;
+    bp.total = off;
+    return bp;
 }
 
 // ---- backward ---------------------------------------------------------------
@@ -912,7 +1005,7 @@ acseg_status acseg_batch_workspace_size(int32_t B, const acseg_problem* ps, size
     if (!bytes) return ACSEG_ERR_INVALID_ARG;
     const acseg_status v = validate_batch(B, ps);
     if (v != ACSEG_OK) return v;
-    *bytes = batch_layout_of(B, ps).total;
+    *bytes = plan_batch(B, ps).total;
     return ACSEG_OK;
 }
 
@@ -926,85 +1019,66 @@ acseg_status acseg_solve_batched(acseg_ctx* ctx, int32_t B, const acseg_problem*
     if (!ctx || !images || !us || (fixed_c && !c_outs)) return ACSEG_ERR_INVALID_ARG;
     for (int b = 0; b < B; ++b)
         if (!images[b] || !us[b] || (fixed_c && !c_outs[b])) return ACSEG_ERR_INVALID_ARG;
-    const BatchLayout bl = batch_layout_of(B, ps);
-    if (!ws || ((uintptr_t)ws % kAlign) != 0 || ws_bytes < bl.total) return ACSEG_ERR_WORKSPACE;
+    const BatchPlan bp = plan_batch(B, ps);
+    if (!ws || ((uintptr_t)ws % kAlign) != 0 || ws_bytes < bp.total) return ACSEG_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     char* base = static_cast<char*>(ws);
 
-    // ---- descriptor table, work lists and group lists, built on the host.  With
+    // ---- descriptor tables and work lists, built on the host.  With
     // REUSE_TABLES the workspace already holds them (from an earlier call with the
-    // same arguments): they are built into host memory for the launch plan only,
-    // and neither the staging buffer nor the stream is touched.
+    // same arguments): they are built into host memory for the check only, and
+    // neither the staging buffer nor the stream is touched.
     const bool reuse = (ps[0].flags & ACSEG_FLAG_REUSE_TABLES) != 0u;
     std::vector<char> local;
     char* hs = nullptr;
     if (reuse) {
-        local.assign(bl.table_bytes, 0);
+        local.assign(bp.table_bytes, 0);
         hs = local.data();
     } else {
         if (ctx->stage_ev) ACSEG_TRY(hipEventSynchronize(ctx->stage_ev));  // the last upload is done
-        if (ctx->stage_bytes < bl.table_bytes) {
+        if (ctx->stage_bytes < bp.table_bytes) {
             if (ctx->stage) ACSEG_TRY(hipHostFree(ctx->stage));
             ctx->stage = nullptr;
             ctx->stage_bytes = 0;
-            ACSEG_TRY(hipHostMalloc(&ctx->stage, bl.table_bytes, hipHostMallocDefault));
-            ctx->stage_bytes = bl.table_bytes;
+            ACSEG_TRY(hipHostMalloc(&ctx->stage, bp.table_bytes, hipHostMallocDefault));
+            ctx->stage_bytes = bp.table_bytes;
         }
         if (!ctx->stage_ev) ACSEG_TRY(hipEventCreateWithFlags(&ctx->stage_ev, hipEventDisableTiming));
         hs = static_cast<char*>(ctx->stage);
-        memset(hs, 0, bl.table_bytes);
+        memset(hs, 0, bp.table_bytes);
     }
-    CycleArgs* hdesc = reinterpret_cast<CycleArgs*>(hs + bl.descs);
-    int2* hwork = reinterpret_cast<int2*>(hs + bl.work);
-    int* himgs = reinterpret_cast<int*>(hs + bl.imgs);
-    std::vector<Coefs> cfs(B);
+    CycleArgs* hdesc = reinterpret_cast<CycleArgs*>(hs + bp.descs);
+    MgImage* hmg = reinterpret_cast<MgImage*>(hs + bp.mgdescs);
     std::vector<Bufs> bufs(B);
     for (int b = 0; b < B; ++b) {
-        void* wsb = base + bl.region[b];
-        cfs[b] = coefs_of(&ps[b]);
-        bufs[b] = Bufs{{us[b], at<float>(wsb, bl.L[b].ubuf), us[b]}};
-        hdesc[b] = cycle_args_of(&ps[b], cfs[b], images[b], bufs[b], bl.L[b], wsb);
+        void* wsb = base + bp.region[b];
+        const Coefs cf = coefs_of(&ps[b]);
+        bufs[b] = Bufs{{us[b], at<float>(wsb, bp.L[b].ubuf), us[b]}};
+        hdesc[b] = cycle_args_of(&ps[b], cf, images[b], bufs[b], bp.L[b], wsb);
+        if (bp.mp[b].L >= 2) hmg[b] = mg_image_of(&ps[b], bp.mp[b], bp.L[b], wsb, bufs[b]);
     }
-    struct Group {
-        int N, C, work0, nwork, img0, nimg;
-    };
-    std::vector<Group> groups;
-    {
-        int w0 = 0, i0 = 0;
-        for (const auto& m : batch_groups(B, ps)) {
-            Group g{ps[m[0]].N, ps[m[0]].C, w0, batch_work_slots(ps[m[0]].N, ps, B, m), i0, (int)m.size()};
-            // concatenated tiles of the group, dealt to the XCDs in contiguous bands
-            std::vector<int2> tiles;
-            for (int b : m)
-                for (int t = 0; t < hdesc[b].ntiles; ++t) tiles.push_back(make_int2(b, t));
-            const int tpx = g.nwork / kXcd;
-            for (int k = 0; k < g.nwork; ++k) {
-                const int gt = (k % kXcd) * tpx + k / kXcd;
-                hwork[w0 + k] = gt < (int)tiles.size() ? tiles[gt] : make_int2(-1, 0);
-            }
-            for (int j = 0; j < g.nimg; ++j) himgs[i0 + j] = m[j];
-            w0 += g.nwork;
-            i0 += g.nimg;
-            groups.push_back(g);
-        }
-    }
+    if (!bp.work.empty()) memcpy(hs + bp.work_off, bp.work.data(), sizeof(int2) * bp.work.size());
+    memcpy(hs + bp.imgs_off, bp.imgs.data(), sizeof(int) * bp.imgs.size());
+    if (!bp.mgwork.empty()) memcpy(hs + bp.mgwork_off, bp.mgwork.data(), sizeof(int4) * bp.mgwork.size());
     if (!reuse) {
-        ACSEG_TRY(hipMemcpyAsync(base, hs, bl.table_bytes, hipMemcpyHostToDevice, s));
+        ACSEG_TRY(hipMemcpyAsync(base, hs, bp.table_bytes, hipMemcpyHostToDevice, s));
         ACSEG_TRY(hipEventRecord(ctx->stage_ev, s));
-        ctx->last_tables.assign(hs, hs + bl.table_bytes);
+        ctx->last_tables.assign(hs, hs + bp.table_bytes);
         ctx->last_tables_ws = ws;
-    } else if (ctx->last_tables_ws != ws || ctx->last_tables.size() != bl.table_bytes ||
-               memcmp(ctx->last_tables.data(), hs, bl.table_bytes) != 0) {
+    } else if (ctx->last_tables_ws != ws || ctx->last_tables.size() != bp.table_bytes ||
+               memcmp(ctx->last_tables.data(), hs, bp.table_bytes) != 0) {
         return ACSEG_ERR_INVALID_ARG;  // not the tables of this context's last upload to ws
     }
-    const CycleArgs* ddesc = reinterpret_cast<const CycleArgs*>(base + bl.descs);
-    const int2* dwork = reinterpret_cast<const int2*>(base + bl.work);
-    const int* dimgs = reinterpret_cast<const int*>(base + bl.imgs);
+    const CycleArgs* ddesc = reinterpret_cast<const CycleArgs*>(base + bp.descs);
+    const MgImage* dmg = reinterpret_cast<const MgImage*>(base + bp.mgdescs);
+    const int2* dwork = reinterpret_cast<const int2*>(base + bp.work_off);
+    const int* dimgs = reinterpret_cast<const int*>(base + bp.imgs_off);
+    const int4* dmgwork = reinterpret_cast<const int4*>(base + bp.mgwork_off);
 
     // ---- colour means of every u^0
     for (int b = 0; b < B; ++b) {
-        void* wsb = base + bl.region[b];
-        const Layout& L = bl.L[b];
+        void* wsb = base + bp.region[b];
+        const Layout& L = bp.L[b];
         ACSEG_TRY(launch_ctl_init(at<Ctl>(wsb, L.ctl), 0, s));
         if (fixed_c) ACSEG_TRY(launch_widen(c_outs[b], at<double>(wsb, L.c64) + 2 * kNC, ps[b].N * ps[b].C, s));
         v = enqueue_means(&ps[b], images[b], us[b], L, wsb, nullptr, at<double>(wsb, L.c64) + kNC,
@@ -1013,43 +1087,73 @@ acseg_status acseg_solve_batched(acseg_ctx* ctx, int32_t B, const acseg_problem*
         if (v != ACSEG_OK) return v;
     }
 
-    // ---- the time loop, one launch per cycle and group
+    // ---- the time loop: per group, its cycles' launches over the tiles of all
+    // its images (a multigrid cycle: pre-smoothing, the correction's passes,
+    // post-smoothing), then the group's step end
     const acseg_problem& p0 = ps[0];
-    const Schedule sc = schedule_of(&p0);
-    const int sweeps = p0.nu_pre + p0.nu_post;
+    const int sor = (p0.flags & ACSEG_FLAG_SOR) != 0u ? 1 : 0;
+    MgImage none;
+    memset(&none, 0, sizeof(none));
     for (int n = 0; n < p0.steps; ++n) {
         const int a = n & 1, bsel = a ^ 1;
-        CycleStep st{};
-        st.slot = a;
-        st.fixed = sc.fixed ? 1 : 0;
-        st.store_rhs = sc.store_rhs ? 1 : 0;
-        st.tot_sel = a;
-        st.c64_sel = a;
-        st.fixed_c = fixed_c ? 1 : 0;
-        st.prev_sel = fixed_c ? 2 : (n > 0 ? bsel : -1);
-        for (const Group& g : groups) {
-            const CycleGrid grid{ddesc, dwork + g.work0, g.nwork, (ps[0].flags & ACSEG_FLAG_SOR) != 0u ? 1 : 0};
-            const CycleArgs& any = hdesc[himgs[g.img0]];
+        for (const BatchGroup& g : bp.groups) {
+            const acseg_problem& pg = ps[g.members[0]];
+            const Schedule sc = schedule_of(&pg);
+            CycleStep st{};
+            st.slot = a;
+            st.fixed = sc.fixed ? 1 : 0;
+            st.store_rhs = sc.store_rhs ? 1 : 0;
+            st.tot_sel = a;
+            st.c64_sel = a;
+            st.fixed_c = fixed_c ? 1 : 0;
+            st.prev_sel = fixed_c ? 2 : (n > 0 ? bsel : -1);
+            const CycleGrid grid{ddesc, dwork + g.work0, g.nwork, sor};
+            const CycleArgs& any = hdesc[g.members[0]];
             for (int k = 0; k < p0.max_cycles; ++k) {
                 st.cycle = k;
                 st.cm = (!sc.fixed || k == p0.max_cycles - 1) ? 1 : 0;
                 st.launch = k * sc.lpc;
-                const CycleRole role{k == 0, true, true};
+                if (!g.mg) {
+                    const CycleRole role{k == 0, true, true};
+                    ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] {
+                        return launch_cycle(g.N, g.C, pg.nu_pre + pg.nu_post, any, st, grid, role, s);
+                    }));
+                    continue;
+                }
+                const CycleRole pre{k == 0, true, false};
                 ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] {
-                    return launch_cycle(g.N, g.C, sweeps, any, st, grid, role, s);
+                    return launch_cycle(g.N, g.C, pg.nu_pre, any, st, grid, pre, s);
+                }));
+                MgStep ms{};
+                ms.slot = a;
+                ms.fixed = st.fixed;
+                ms.launch = k * sc.lpc + sc.lpre;
+                ms.nu_pre = pg.nu_pre;
+                ms.nu_post = pg.nu_post;
+                for (const MgLaunchRec& r : g.mgl) {
+                    ms.sweeps = r.sweeps;
+                    const MgGrid mgrid{dmg, dmgwork + r.work0, r.nwork};
+                    ACSEG_TRY(timed(ctx, kFamMg, s, [&] {
+                        return launch_mg(r.op, g.N, g.N, none, mgrid, ms, r.lds, s);
+                    }));
+                }
+                st.launch = k * sc.lpc + sc.lpre;
+                const CycleRole post{false, false, true};
+                ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] {
+                    return launch_cycle(g.N, g.C, pg.nu_post, any, st, grid, post, s);
                 }));
             }
             const StepEndArgs e{p0.max_cycles, sc.lpc};
             ACSEG_TRY(timed(ctx, kFamOther, s, [&] {
-                return launch_step_end(g.N, g.C, any, st, e, ddesc, dimgs + g.img0, g.nimg, s);
+                return launch_step_end(g.N, g.C, any, st, e, ddesc, dimgs + g.img0, (int)g.members.size(), s);
             }));
         }
     }
 
     // ---- results
     for (int b = 0; b < B; ++b) {
-        void* wsb = base + bl.region[b];
-        const Layout& L = bl.L[b];
+        void* wsb = base + bp.region[b];
+        const Layout& L = bp.L[b];
         Ctl* ctl = at<Ctl>(wsb, L.ctl);
         const int64_t nu = (int64_t)ps[b].N * ps[b].W * ps[b].H;
         ACSEG_TRY(launch_copy_current(bufs[b], ctl, us[b], nu, s));
@@ -1062,7 +1166,7 @@ acseg_status acseg_solve_batched(acseg_ctx* ctx, int32_t B, const acseg_problem*
     }
     if (stats)
         for (int b = 0; b < B; ++b) {
-            v = read_stats(ctx, bl.L[b], base + bl.region[b], s, &stats[b]);
+            v = read_stats(ctx, bp.L[b], base + bp.region[b], s, &stats[b]);
             if (v != ACSEG_OK) return v;
         }
     return ACSEG_OK;

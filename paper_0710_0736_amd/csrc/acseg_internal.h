@@ -240,11 +240,13 @@ struct MgStep {
 };
 
 // Where a multigrid launch's workgroups come from: one image (descs == NULL:
-// workgroup x is tile x of `single`) or a batch (work[x] = (image, tile), image
-// -1 for none).  blockIdx.y selects the component of componentwise passes.
+// workgroup x is tile x of `single`, at st.level) or a batch (work[x] =
+// (image, tile, level, zero): an up pass item with zero set starts from v = 0
+// with kCoarseSweeps sweeps, the coarsest level of an image without an LDS
+// tail).  blockIdx.y selects the component of componentwise passes.
 struct MgGrid {
     const MgImage* descs;
-    const int2* work;
+    const int4* work;
     int nwork;
 };
 
@@ -257,6 +259,9 @@ int mg_pass_tiles(int op, const MgImage& m, int level);
 size_t mg_pass_lds(int op, const MgImage& m, int sweeps);
 // LDS bytes of the tail from level t of an image with level sides W[], H[].
 size_t mg_tail_lds(const int* W, const int* H, int t, int L);
+// Dynamic LDS bytes of a down / up pass with nu sweeps.
+size_t mg_lds_down(int nu);
+size_t mg_lds_up(int nu);
 
 // Enqueue one multigrid pass.  Fine-level passes (defect + restriction,
 // direction, update) are instantiated per N and need one N per launch (`N`);

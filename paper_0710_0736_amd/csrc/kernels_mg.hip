@@ -711,13 +711,17 @@ __device__ __forceinline__ void mg_update(const MgImage& d, int tile, const MgSt
         BODY;                                                                                \
     }                                                                                        \
     TPL __global__ __launch_bounds__(BOUND) void NAME##_b(const MgImage* __restrict__ descs, \
-                                                          const int2* __restrict__ work,     \
-                                                          int nwork, MgStep st) {            \
+                                                          const int4* __restrict__ work,     \
+                                                          int nwork, MgStep sb) {            \
         if ((int)blockIdx.x >= nwork) return;                                                \
-        const int2 wv = work[blockIdx.x];                                                    \
+        const int4 wv = work[blockIdx.x];                                                    \
         if (wv.x < 0) return;                                                                \
         const MgImage& d = descs[wv.x];                                                      \
         const int tile = wv.y;                                                               \
+        MgStep st = sb;                                                                      \
+        st.level = wv.z;                                                                     \
+        st.zero = wv.w;                                                                      \
+        if (wv.w) st.sweeps = kCoarseSweeps;                                                 \
         BODY;                                                                                \
     }
 
@@ -787,6 +791,9 @@ size_t mg_tail_lds(const int* W, const int* H, int t, int L) {
     for (int l = t; l < L; ++l) f += (size_t)W[l] * H[l] * 2;
     return f * sizeof(float);
 }
+
+size_t mg_lds_down(int nu) { return (size_t)2 * down_sx(nu) * down_sy(nu) * sizeof(float); }
+size_t mg_lds_up(int nu) { return (size_t)2 * up_sx(nu) * up_sy(nu) * sizeof(float); }
 
 size_t mg_pass_lds(int op, const MgImage& m, int sweeps) {
     switch (op) {

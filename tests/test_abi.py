@@ -95,7 +95,10 @@ def test_batch_validation_codes():
     assert _batch_code([a, base_problem(nu_post=2)])[0] == acseg.ERR_INVALID_ARG
     ck = base_problem(flags=acseg.FLAG_STORE_CHECKPOINTS)
     assert _batch_code([ck])[0] == acseg.ERR_INVALID_ARG
-    assert _batch_code([a, base_problem(levels=2)])[0] == acseg.ERR_UNSUPPORTED
+    # multigrid images batch with Gauss-Seidel ones; the subspace correction does not batch
+    assert _batch_code([a, base_problem(levels=2)])[0] == acseg.OK
+    assert _batch_code([base_problem(levels=2, flags=acseg.FLAG_SSC)])[0] == acseg.ERR_UNSUPPORTED
+    assert _batch_code([base_problem(levels=1, flags=acseg.FLAG_SSC)])[0] == acseg.OK
     assert _batch_code([a, base_problem(N=9)])[0] == acseg.ERR_UNSUPPORTED
 
 

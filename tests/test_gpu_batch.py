@@ -154,3 +154,71 @@ def test_batched_against_oracle_config5_sample():
             assert err <= GATE_U, (n, b, w.N, err)
             bad, total, raw = label_gate(ug, u_ref)
             assert bad <= 1e-3 * total, (n, b, bad, raw)
+
+
+MG_SPECS = [  # W, H, N, C, lambda, seed, levels: tails from level 1 and 2, and none (levels = 2)
+    (96, 80, 4, 3, 100.0, 1, 0), (37, 53, 3, 3, 50.0, 2, 0), (150, 64, 2, 1, 100.0, 3, 0),
+    (200, 120, 5, 3, 100.0, 5, 0), (70, 130, 6, 3, 100.0, 6, 0), (160, 140, 4, 3, 100.0, 7, 2),
+]
+
+
+def make_mg_batch(pixel: bool, steps: int, max_cycles: int, flags: int = 0):
+    problems, images, u0s = [], [], []
+    for (W, H, N, C, lam, seed, levels) in MG_SPECS:
+        base = synth.pixel_twin(synth.VORONOI1024) if pixel else synth.VORONOI1024
+        w = base.scaled(W, H, N=N, lam=lam)
+        img, u0, _ = w.make(seed)
+        if C == 1:
+            img = img.mean(axis=0, keepdims=True)
+        problems.append(acseg.Problem.from_workload(w, C=C, levels=levels, steps=steps, tol=1e-6,
+                                                    max_cycles=max_cycles, flags=flags))
+        images.append(cuda(img))
+        u0s.append(cuda(u0))
+    return problems, images, u0s
+
+
+@pytest.mark.parametrize("pixel,fixed,sor", [(True, False, False), (True, True, False), (False, False, False),
+                                             (True, False, True)])
+def test_batched_multigrid_equals_single(pixel, fixed, sor):
+    """Multigrid cycles over a batch (one launch per pass over the images that
+    have the pass's level: images with an LDS tail from level 1 or 2 and one
+    whose coarsest level is a global pass) give each image exactly its
+    one-image solve."""
+    steps = 3
+    flags = (acseg.FLAG_FIXED_CYCLES if fixed else 0) | (acseg.FLAG_SOR if sor else 0)
+    problems, images, u0s = make_mg_batch(pixel, steps, 6 if fixed else 200, flags)
+    singles = []
+    for p, im, u0 in zip(problems, images, u0s):
+        u, c, st, _ = acseg.solve(p, im, u0.clone())
+        singles.append((u, c, st))
+    us = [u0.clone() for u0 in u0s]
+    us, cs, sts = acseg.solve_batched(problems, images, us)
+    torch.cuda.synchronize()
+    for b, (u, c, st) in enumerate(singles):
+        assert torch.equal(us[b], u), b
+        assert torch.equal(cs[b], c), b
+        assert sts[b] == st, (b, sts[b], st)
+        if not fixed:
+            assert st["status"] == acseg.OK, (b, st)
+
+
+def test_batched_multigrid_step_against_oracle():
+    """One batched multigrid step of every image in pixel units against the
+    oracle's step (the per-step gates of the one-image tests)."""
+    from test_gpu_parity import GATE_U, host, label_gate
+    import oracle as orc
+    problems, images, u0s = make_mg_batch(True, 1, 200)
+    us, cs, sts = acseg.solve_batched(problems, images, [u.clone() for u in u0s])
+    torch.cuda.synchronize()
+    for b, (W, H, N, C, lam, seed, levels) in enumerate(MG_SPECS):
+        w = synth.pixel_twin(synth.VORONOI1024).scaled(W, H, N=N, lam=lam)
+        img = images[b].cpu().numpy().astype(np.float64)
+        P = orc.Params.from_workload(w, C=C, tol=1e-12, levels=0)
+        u_ref, c_ref, st_ref = orc.step(P, img, host(u0s[b]))
+        assert st_ref["converged"]
+        assert sts[b]["status"] == acseg.OK and sts[b]["final_residual"] <= 1e-6, (b, sts[b])
+        ug = host(us[b])
+        err = np.abs(ug - u_ref).max()
+        assert err <= GATE_U, (b, err)
+        bad, total, raw = label_gate(ug, u_ref)
+        assert bad <= 1e-3 * total, (b, bad, raw)
