@@ -111,8 +111,7 @@ def run_hetero(args):
     u0s = [torch.from_numpy(m[1]).to(dev) for m in made]
     us = [torch.empty_like(u) for u in u0s]
     nodes = sum(w.W * w.H for w in ws)
-    probs = [acseg.Problem.from_workload(w, C=3, levels=args.levels, max_cycles=args.max_cycles,
-                                         flags=acseg.FLAG_STREAM if args.stream else 0) for w in ws]
+    probs = [acseg.Problem.from_workload(w, C=3, levels=args.levels, max_cycles=args.max_cycles) for w in ws]
     cycles = 1
     for b in range(len(ws)):  # the slowest time step of any image fixes the schedule
         us[b].copy_(u0s[b])
@@ -120,7 +119,7 @@ def run_hetero(args):
         if st["status"] != acseg.OK:
             raise RuntimeError(f"calibration solve of image {b} did not converge: {st}")
         cycles = max(cycles, st["cycles_max"])
-    probs = [acseg.Problem(**{**p.__dict__, "max_cycles": cycles, "flags": acseg.FLAG_FIXED_CYCLES | p.flags})
+    probs = [acseg.Problem(**{**p.__dict__, "max_cycles": cycles, "flags": acseg.FLAG_FIXED_CYCLES})
              for p in probs]
 
     def one_by_one():
@@ -345,8 +344,6 @@ def main():
                          "which gives `value`)")
     ap.add_argument("--sor", action="store_true",
                     help="over-relaxed smoothing sweeps (ACSEG_FLAG_SOR)")
-    ap.add_argument("--stream", action="store_true",
-                    help="streamed cycles (ACSEG_FLAG_STREAM): one launch per cycle down lattice columns")
     ap.add_argument("--ssc", action="store_true",
                     help="coarse correction = the paper's subspace correction over all basis functions")
     ap.add_argument("--adjoint", action="store_true",
@@ -412,8 +409,7 @@ def main():
     us = [torch.empty_like(u0) for u0 in u0s]
     img, u0, u = imgs[0], u0s[0], us[0]
 
-    ssc_flag = ((acseg.FLAG_SSC if args.ssc else 0) | (acseg.FLAG_SOR if args.sor else 0)
-                | (acseg.FLAG_STREAM if args.stream else 0))
+    ssc_flag = (acseg.FLAG_SSC if args.ssc else 0) | (acseg.FLAG_SOR if args.sor else 0)
     # a workload's tolerance below 1e-6 is the FP64 oracle's; the FP32 solve stops at 1e-6,
     # above its rounding floor of about 1e-7
     gpu_tol = max(w.tol, 1e-6)

@@ -141,18 +141,6 @@ typedef int32_t acseg_status;
  * acseg_solve_batched (all problems of a batch share their flags).
  */
 #define ACSEG_FLAG_SOR 64u
-/*
- * Cycles of two Gauss-Seidel sweeps (levels == 1, nu_pre + nu_post == 2, no
- * ACSEG_FLAG_SOR) run as one launch that streams down columns of the lattice
- * (54 nodes wide, segments of 16 to 64 rows) instead of one over 64 x 16
- * tiles: the same sweeps, residual and colour means, with the recomputed halo
- * only at the sides of a column and the ends of a segment.  It needs many
- * columns and segments per launch to fill the GPU (batches, large images);
- * for one small image the tiles are faster.  Results agree with the tiled
- * launch to rounding (the colour-mean sums are added in another order).
- * Ignored where the cycle does not qualify.
- */
-#define ACSEG_FLAG_STREAM 128u
 
 /*
  * One segmentation problem.  Parameters follow eq. E and eq. alpha:

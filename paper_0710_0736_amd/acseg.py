@@ -33,7 +33,6 @@ FLAG_NO_HOST_WAIT = 8
 FLAG_SSC = 16
 FLAG_REUSE_TABLES = 32
 FLAG_SOR = 64
-FLAG_STREAM = 128
 
 
 class _Problem(ctypes.Structure):

@@ -96,7 +96,7 @@ acseg_status validate(const acseg_problem* p, bool need_steps) {
     if (L >= 2 && (p->nu_pre < 1 || p->nu_post < 1)) return ACSEG_ERR_UNSUPPORTED;
     if ((p->flags & ~(ACSEG_FLAG_STORE_CHECKPOINTS | ACSEG_FLAG_FIXED_CYCLES | ACSEG_FLAG_FIXED_C |
                       ACSEG_FLAG_NO_HOST_WAIT | ACSEG_FLAG_SSC | ACSEG_FLAG_REUSE_TABLES |
-                      ACSEG_FLAG_SOR | ACSEG_FLAG_STREAM)) != 0u)
+                      ACSEG_FLAG_SOR)) != 0u)
         return ACSEG_ERR_INVALID_ARG;
     return ACSEG_OK;
 }
@@ -158,25 +158,6 @@ struct Layout {
     int part_stride = 0;
 };
 
-// Segment rows of a streamed cycle for p, or 0 when its cycles are tiled:
-// streamed when asked for and the cycle is two Gauss-Seidel sweeps; the
-// segments are as tall as the lattice allows up to 64 rows (the halo rows at
-// the ends of a segment are recomputed) and tall enough that a 1024-row
-// lattice gives eight segments per column.
-int stream_rows_of(const acseg_problem* p) {
-    if ((p->flags & ACSEG_FLAG_STREAM) == 0u || (p->flags & ACSEG_FLAG_SOR) != 0u) return 0;
-    if (p->nu_pre + p->nu_post != 2) return 0;
-    const int L = p->levels == 0 ? auto_levels(p->W, p->H) : p->levels;
-    if (L != 1) return 0;
-    return p->H >= 512 ? 128 : (p->H >= 256 ? 64 : (p->H >= 64 ? 32 : 16));
-}
-
-// Work items of one cycle launch of p: streamed column segments or tiles.
-int cycle_items(const acseg_problem* p) {
-    const int S = stream_rows_of(p);
-    return S ? stream_items(p->W, p->H, S) : cycle_tiles(p->N, p->W, p->H);
-}
-
 int dir_blocks(int W, int H) {
     return std::min(((W + kDirTX - 1) / kDirTX) * ((H + kDirTY - 1) / kDirTY), kDirBlocks);
 }
@@ -192,7 +173,7 @@ Layout layout_of(const acseg_problem* p) {
     };
     L.ubuf = take(sizeof(float) * p->N * n);
     L.rhs = take(sizeof(float) * p->N * n);
-    L.part_stride = std::max(cycle_tiles(p->N, p->W, p->H), cycle_items(p));
+    L.part_stride = cycle_tiles(p->N, p->W, p->H);
     L.part_f = take(sizeof(float) * 2 * (size_t)L.part_stride);
     L.part_cm = take(sizeof(double) * 2 * (size_t)L.part_stride * cmeans_width(p->N, p->C));
     L.part_d = take(sizeof(double) * (size_t)kCmeansBlocks * kCmeansMaxM);
@@ -428,7 +409,6 @@ CycleArgs cycle_args_of(const acseg_problem* p, const Coefs& cf, const float* im
         a.omega = (float)std::min(1.95, 2.0 / (1.0 + std::sqrt(1.0 - q * q)));
     }
     cycle_tiling(p->N, p->W, p->H, &a);
-    if (const int S = stream_rows_of(p)) stream_tiling(p->W, p->H, S, &a);
     return a;
 }
 
@@ -703,7 +683,7 @@ BatchPlan plan_batch(int32_t B, const acseg_problem* ps) {
         // concatenated smoothing tiles of the group, dealt to the XCDs in contiguous bands
         std::vector<int2> tiles;
         for (int b : g.members)
-            for (int t = 0; t < cycle_items(&ps[b]); ++t) tiles.push_back(make_int2(b, t));
+            for (int t = 0; t < cycle_tiles(ps[b].N, ps[b].W, ps[b].H); ++t) tiles.push_back(make_int2(b, t));
         g.nwork = (int)((tiles.size() + kXcd - 1) / kXcd * kXcd);
         g.work0 = (int)bp.work.size();
         const int tpx = g.nwork / kXcd;

@@ -114,10 +114,6 @@ struct CycleArgs {
     int tiles_x, ntiles, tiles_per_xcd;
     int tiles_y, rows_per_xcd;  // tile rows; tile rows per XCD band (single-image launch order)
     float omega;                // over-relaxation of the smoothing sweeps (1: Gauss-Seidel; single image)
-    // streamed cycles (two sweeps and the residual in one launch down columns
-    // of the lattice): 0 = tiled kernel; else segment rows S, columns, segments
-    // per column, and items per XCD of a single-image launch (ntiles = items)
-    int stream, seg_rows, scols, ssegs, sitems_per_xcd;
 };
 
 // Per launch.
@@ -160,9 +156,6 @@ int cycle_launches(int sweeps);
 int cycle_tiles(int N, int W, int H);
 // Fill the lattice / tiling fields of a (W, H, tiles_x, ntiles, tiles_per_xcd).
 void cycle_tiling(int N, int W, int H, CycleArgs* a);
-// Work items of a streamed cycle with segments of S rows; switch a to it.
-int stream_items(int W, int H, int S);
-void stream_tiling(int W, int H, int S, CycleArgs* a);
 
 // `sweeps` red-black projected block Gauss-Seidel sweeps of the current time
 // step (launches of at most two).  The step's first launch builds the

@@ -624,12 +624,6 @@ __global__ __launch_bounds__(kCycT, cycle_min_waves(N)) void k_cycle_batch(const
     cycle_tile_any<N, C, K, FIRST, RESID, SOR>(descs[wv.x], st, wv.y);
 }
 
-}  // namespace acseg
-
-#include "stream_impl.hpp"
-
-namespace acseg {
-
 // ---------------------------------------------------------------------------
 // End of a time step, MD + 1 workgroups (MD = N C + N).  Workgroup q < MD
 // sums row q of the last cycle's colour-mean partials over the tiles (fixed
@@ -721,15 +715,10 @@ hipError_t run_cycle(const CycleArgs& a, const CycleStep& st, const CycleGrid& g
     return hipGetLastError();
 }
 
-// `sweeps` sweeps in launches of at most two.  A cycle of two sweeps of a
-// problem set to stream runs as one streamed launch.
+// `sweeps` sweeps in launches of at most two.
 template <int N, int C>
 hipError_t run_cycle_nc(int sweeps, const CycleArgs& a, CycleStep st, const CycleGrid& g, CycleRole role,
                         hipStream_t s) {
-    if (a.stream && sweeps == 2 && role.opens && role.closes) {
-        st.first = 1;
-        return role.step_first ? run_stream<N, C, true>(a, st, g, s) : run_stream<N, C, false>(a, st, g, s);
-    }
     const int nl = cycle_launches(sweeps);
     const int base = st.launch;
     hipError_t e = hipSuccess;

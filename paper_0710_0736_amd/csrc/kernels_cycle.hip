@@ -25,17 +25,6 @@ void cycle_tiling(int N, int W, int H, CycleArgs* a) {
     a->tiles_per_xcd = ((a->tiles_x + kStrip - 1) / kStrip) * kStrip * a->rows_per_xcd;
 }
 
-int stream_items(int W, int H, int S) { return ((W + kSOut - 1) / kSOut) * ((H + S - 1) / S); }
-
-void stream_tiling(int W, int H, int S, CycleArgs* a) {
-    a->stream = 1;
-    a->seg_rows = S;
-    a->scols = (W + kSOut - 1) / kSOut;
-    a->ssegs = (H + S - 1) / S;
-    a->ntiles = a->scols * a->ssegs;
-    a->sitems_per_xcd = (a->ntiles + kXcd - 1) / kXcd;
-}
-
 // Convergence test after `cycles` cycles of a step (one workgroup): the
 // largest per-tile residual of the last cycle against tol; marks the step done.
 __global__ __launch_bounds__(kBlock) void k_step_check(CycleArgs a, int slot_idx, int cycles) {
