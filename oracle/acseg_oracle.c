@@ -23,9 +23,9 @@
  *     the old time level.  Readings: the stiffness enters with a positive sign
  *     (it comes from eps |grad u|^2 / 2 in eq. E), and the time step multiplies
  *     the whole bracket of eq. alpha;
- *   - the Gibbs-simplex correction of Section "Gibbs Space Constraint
- *     Pseudocode" (zero the negative components, spread the removed amount
- *     equally over the others, repeat);
+ *   - the Gibbs-simplex constraint of Section "Gibbs Space Constraint
+ *     Pseudocode" as the exact Euclidean projection onto the simplex
+ *     (Michelot's finite algorithm, the procedure the section describes);
  *   - a lexicographic projected block Gauss-Seidel sweep over the nodal
  *     sub-problems (Section "Finite Element Notation") and a truncated
  *     multigrid correction with an exact line search (Section "Multigrid
@@ -163,46 +163,41 @@ static double stiff_offdiag(const grid_t *g, const double *v, int x, int y)
 /* ------------------------------------------------------------------------ */
 
 /*
- * Euclidean projection of y onto {x : sum_i x_i = 1, x_i >= 0}, following the
- * correction loop of Section "Gibbs Space Constraint Pseudocode":
- *   1. move y onto the hyperplane sum = 1 along 1_N (the operator T of eq.
- *      projection_operator_T applied to the update);
- *   2. if no component is negative, stop;
- *   3. set every negative component to zero and remove it from the free set;
- *      the sum has then grown by the removed amount, which is taken off the
- *      k remaining free components in equal parts;
- *   4. repeat from 2 with the free set only.
- * Each round removes at least one component, so there are at most N rounds.
- * Returns the number of rounds (>= 1).
+ * Euclidean projection of y onto the Gibbs simplex {x : sum_i x_i = 1,
+ * x_i >= 0}, the nodal constraint of Section "Gibbs Space Constraint
+ * Pseudocode", by Michelot's finite algorithm (C. Michelot, J. Optim. Theory
+ * Appl. 50, 1986).  With F the current free set, the projection onto the
+ * affine set {sum_{i in F} x_i = 1, x_i = 0 outside F} shifts every free
+ * component by the same theta = (sum_{i in F} y_i - 1) / |F|.  Components
+ * that come out negative leave F for good and the projection onto the
+ * smaller affine set is taken again from y; once none is negative, x is the
+ * projection onto the simplex.  F shrinks every round but never empties (its
+ * values sum to one), so there are at most N rounds.  Returns the number of
+ * rounds (>= 1).
  */
 int orc_project(int N, const double *y, double *x)
 {
-    unsigned char free_[ORC_MAX_N];
+    unsigned char in_f[ORC_MAX_N];
     if (N < 1 || N > ORC_MAX_N) return -1;
-    double s = 0.0;
-    for (int i = 0; i < N; ++i) s += y[i];
-    for (int i = 0; i < N; ++i) {
-        x[i] = y[i] + (1.0 - s) / N;
-        free_[i] = 1;
-    }
-    int rounds = 1;
+    for (int i = 0; i < N; ++i) in_f[i] = 1;
+    int size = N, rounds = 0;
     for (;;) {
-        double removed = 0.0;
-        int nneg = 0, nfree = 0;
-        for (int i = 0; i < N; ++i)
-            if (free_[i] && x[i] < 0.0) {
-                removed += -x[i];
-                x[i] = 0.0;
-                free_[i] = 0;
-                ++nneg;
-            }
-        if (nneg == 0) break;
-        for (int i = 0; i < N; ++i) nfree += free_[i];
-        for (int i = 0; i < N; ++i)
-            if (free_[i]) x[i] -= removed / nfree;
         ++rounds;
+        double s = 0.0;
+        for (int i = 0; i < N; ++i)
+            if (in_f[i]) s += y[i];
+        const double theta = (s - 1.0) / size;
+        int left = 0;
+        for (int i = 0; i < N; ++i) {
+            x[i] = in_f[i] ? y[i] - theta : 0.0;
+            if (in_f[i] && x[i] < 0.0) {
+                in_f[i] = 0;
+                ++left;
+            }
+        }
+        if (left == 0) return rounds;
+        size -= left;
     }
-    return rounds;
 }
 
 /* ------------------------------------------------------------------------ */
