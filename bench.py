@@ -78,6 +78,13 @@ def smoother_bytes_per_launch(N: int, C: int, n: int, lpc: int, cycles: int, fix
     return total * n / launches
 
 
+def sweep_bytes_per_launch(N: int, n: int, sweeps_per_cycle: int, lpc: int) -> float:
+    """Sweep-equivalent bytes of one k_cycle launch: 12N bytes per node and sweep
+    (read u and the right-hand side, write u, N float32 phases each) times the
+    sweeps the launch performs."""
+    return 12 * N * n * sweeps_per_cycle / lpc
+
+
 def copy_calibration(mib: int, reps: int):
     """A plain device copy of a known size: bytes for counter calibration, and
     the copy's own bandwidth (read + written bytes / time) as the attainable
@@ -175,6 +182,86 @@ def run_hetero(args):
     bad = [x for x in sts if x["status"] != acseg.OK]
     if bad:
         raise RuntimeError(f"batched schedule did not converge: {bad[0]}")
+    roof, groups = None, None
+    if not args.no_roofline:
+        lpc = launches_per_cycle(probs[0].levels, probs[0].nu_pre, probs[0].nu_post)
+        spc = probs[0].nu_pre + probs[0].nu_post
+        steps = ws[0].steps
+
+        def family_times(members):
+            acseg.timing_enable(True)
+            acseg.timing_read()
+            for b in members:
+                us[b].copy_(u0s[b])
+            acseg.solve_batched([probs[b] for b in members], [imgs[b] for b in members],
+                                [us[b] for b in members], want_stats=False, c_out=False)
+            torch.cuda.synchronize()
+            t = acseg.timing_read()
+            acseg.timing_enable(False)
+            return t
+
+        def smoother_rates(members, t):
+            launches, ms = t["smooth"]
+            sweep = sum(sweep_bytes_per_launch(ws[b].N, ws[b].W * ws[b].H, spc, lpc) for b in members)
+            comp = sum(smoother_bytes_per_launch(ws[b].N, 3, ws[b].W * ws[b].H, lpc, cycles, True)
+                       for b in members)
+            per_step = cycles * lpc * steps  # launches of one image's solve
+            total_s = ms / 1e3
+            return launches, total_s, sweep * per_step / total_s / 1e9, comp * per_step / total_s / 1e9
+
+        everyone = list(range(len(ws)))
+        t_all = family_times(everyone)
+        launches, total_s, sweep_gbs, comp_gbs = smoother_rates(everyone, t_all)
+        roof = {"bound": "hbm", "achieved": round(sweep_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(sweep_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_cycle_batch (one launch per (N, C) group and smoothing launch)",
+                "avg_launch_us": round(total_s / launches * 1e6, 2), "launches": launches,
+                "compulsory": {"achieved": round(comp_gbs, 1), "frac": round(comp_gbs / HBM_PEAK_GBS, 4)},
+                "per_family_ms": {k: round(v[1], 4) for k, v in t_all.items()},
+                "per_family_avg_launch_us": {k: round(v[1] / v[0] * 1e3, 2) for k, v in t_all.items()}}
+        # each (N, C) group alone: its launch time and rate show what a launch's
+        # tail costs when fewer tiles share it
+        groups = []
+        for N in sorted({w.N for w in ws}):
+            members = [b for b in everyone if ws[b].N == N]
+            t_g = family_times(members)
+            gl, gs, g_sweep, g_comp = smoother_rates(members, t_g)
+            tiles = sum(((ws[b].W + 63) // 64) * ((ws[b].H + (31 if N <= 3 else 15)) // (32 if N <= 3 else 16))
+                        for b in members)
+            groups.append({"N": N, "images": len(members), "nodes": sum(ws[b].W * ws[b].H for b in members),
+                           "tiles_per_launch": tiles, "tiles_per_cu": round(tiles / 256, 1),
+                           "avg_launch_us": round(gs / gl * 1e6, 2), "achieved": round(g_sweep, 1),
+                           "frac": round(g_sweep / HBM_PEAK_GBS, 4),
+                           "compulsory_frac": round(g_comp / HBM_PEAK_GBS, 4)})
+        # a launch merged over every group would move all bytes at the best group's
+        # rate at most: the time that would save bounds what merging can gain
+        best = max(g["achieved"] for g in groups)
+        merged_s = sweep_gbs * total_s / best
+        roof["merge_gain_bound_frac"] = round(1 - merged_s / total_s, 4)
+        log(f"[bench] hetero smoother: {sweep_gbs:.1f} GB/s sweep-equivalent over {launches} launches; "
+            f"groups: " + ", ".join(f"N={g['N']} {g['avg_launch_us']} us {g['achieved']} GB/s" for g in groups))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as orc
+        rng = np.random.default_rng(2024)
+        sample = sorted(rng.choice(len(ws), size=min(8, len(ws)), replace=False).tolist())
+        k = args.cpu_sample_steps or 2
+        tc = 0.0
+        for b in sample:
+            P = orc.Params.from_workload(ws[b], C=3, tol=ws[b].tol)
+            t0c = time.perf_counter()
+            orc.solve(P, k, made[b][0], made[b][1], keep_trajectory=False)
+            tc += time.perf_counter() - t0c
+        work_sample = sum(ws[b].W * ws[b].H * ws[b].N * k for b in sample)
+        work_all = sum(w.W * w.H * w.N * w.steps for w in ws)
+        t_all_cpu = tc * work_all / work_sample
+        cpu = {"value": round(len(ws) / t_all_cpu, 6), "unit": "images/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {k} of {ws[0].steps} time steps of 8 images drawn from the batch "
+                         f"(indices {sample}), FP64, single thread, {tc:.1f} s; extrapolated to the whole "
+                         f"batch by node-phase count (W H N x time steps)"}
+        log(f"[bench] oracle: {tc:.2f} s for {k} time steps of 8 sampled images")
+
     out = {"metric": "images/s, heterogeneous batch (batched vs one call per image)",
            "value": round(len(ws) / t_batch, 2), "unit": "images/s", "n_gpus": 1, "steps": k,
            "warmup": 1, "ms_per_step": round(t_batch * 1e3, 3), "higher_is_better": True,
@@ -184,8 +271,8 @@ def run_hetero(args):
            "graph": graph,
            "config": {"workload": f"hetero{len(ws)}", "images": len(ws), "nodes": nodes,
                       "N": sorted({w.N for w in ws}), "time_steps": ws[0].steps,
-                      "cycles_per_step": cycles, "sweeps_per_cycle": 2},
-           "roofline": None, "cpu_baseline": None}
+                      "cycles_per_step": cycles, "sweeps_per_cycle": 2, "levels": probs[0].levels},
+           "roofline": roof, "groups": groups, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 
@@ -246,9 +333,11 @@ def run_refined(args):
     acseg.timing_enable(False)
     launches, total_ms = tm["smooth"]
     avg_s = total_ms / launches / 1e3
-    bpl = smoother_bytes_per_launch(N, C, Wf * Hf, launches_per_cycle(prob.levels, prob.nu_pre, prob.nu_post),
-                                    cycles, True)
+    lpc = launches_per_cycle(prob.levels, prob.nu_pre, prob.nu_post)
+    bpl = smoother_bytes_per_launch(N, C, Wf * Hf, lpc, cycles, True)
     achieved = bpl / avg_s / 1e9
+    spl = sweep_bytes_per_launch(N, Wf * Hf, prob.nu_pre + prob.nu_post, lpc)
+    sweep_achieved = spl / avg_s / 1e9
     out = {"metric": "segmentations/s on a refined lattice (refine + solve + sample + labels)",
            "value": round(1.0 / t, 3), "unit": "segmentations/s", "n_gpus": 1, "steps": k,
            "warmup": args.warmup, "ms_per_step": round(t * 1e3, 3), "higher_is_better": True,
@@ -258,9 +347,11 @@ def run_refined(args):
                       "time_steps": steps, "levels": prob.levels,
                       "sweeps_per_cycle": prob.nu_pre + prob.nu_post, "cycles_per_step_max": cycles,
                       "cycles_total": st_run["cycles_total"], "final_residual": st_run["final_residual"]},
-           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_cycle",
-                        "bytes_per_launch": int(bpl), "avg_launch_us": round(avg_s * 1e6, 2),
+           "roofline": {"bound": "hbm", "achieved": round(sweep_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(sweep_achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_cycle",
+                        "bytes_per_launch": int(spl), "avg_launch_us": round(avg_s * 1e6, 2),
+                        "compulsory": {"bytes_per_launch": int(bpl), "achieved": round(achieved, 1),
+                                       "frac": round(achieved / HBM_PEAK_GBS, 4)},
                         "launches": launches,
                         "per_family_ms": {kk: round(v[1], 4) for kk, v in tm.items()}},
            "cpu_baseline": None}
@@ -307,6 +398,48 @@ def run_adjoint(args):
     u, ck = forward()
     _, _, _, _, bst = acseg.backward(p, I, ck, 2 * (u - y))
     _, _, fst, _ = acseg.solve(p, I, U0.clone())
+    gbar = 2 * (u - y)
+    roof = None
+    if not args.no_roofline:
+        acseg.timing_enable(True)
+        acseg.timing_read()
+        reps = 3
+        for _ in range(reps):
+            acseg.backward(p, I, ck, gbar, want_stats=False)
+        torch.cuda.synchronize()
+        tm = acseg.timing_read()
+        acseg.timing_enable(False)
+        launches, ms = tm["adj_sweep"]
+        n = w.W * w.H
+        # 12N bytes per node and sweep (read z and the loss gradient, write z);
+        # the launch also reads the free sets, 16N per node per launch compulsory
+        sweep_bytes = 12 * w.N * n * bst["cycles_total"] * reps
+        comp_bytes = 16 * w.N * n * launches
+        sec = ms / 1e3
+        roof = {"bound": "hbm", "achieved": round(sweep_bytes / sec / 1e9, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(sweep_bytes / sec / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_adj_sweep (two red-black sweeps of the adjoint solve per launch)",
+                "sweeps_per_backward": bst["cycles_total"], "launches_per_backward": launches // reps,
+                "avg_launch_us": round(ms / launches * 1e3, 2),
+                "compulsory": {"achieved": round(comp_bytes / sec / 1e9, 1),
+                               "frac": round(comp_bytes / sec / 1e9 / HBM_PEAK_GBS, 4)},
+                "per_family_ms": {kk: round(v[1] / reps, 4) for kk, v in tm.items()},
+                "per_family_launches": {kk: v[0] // reps for kk, v in tm.items()}}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as orc
+        P = orc.Params.from_workload(w, C=3, tol=w.tol)
+        t0c = time.perf_counter()
+        uT, traj, _, _ = orc.solve(P, w.steps, img_np, u0_np)
+        t1c = time.perf_counter()
+        orc.backward(P, w.steps, img_np, traj, 2 * (uT - y.cpu().numpy().astype(np.float64)))
+        t2c = time.perf_counter()
+        cpu = {"value": round((t2c - t0c) * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+               "sample": f"the whole workload: {w.steps} FP64 time steps forward ({(t1c - t0c):.1f} s, "
+                         f"levels={P.levels}, tol={P.tol}) and the adjoint through all of them "
+                         f"({(t2c - t1c):.1f} s), single thread",
+               "backward_ms": round((t2c - t1c) * 1e3, 1)}
+        log(f"[bench] oracle: forward {t1c - t0c:.2f} s, backward {t2c - t1c:.2f} s")
     out = {"metric": f"adjoint: forward+backward time per segmentation ({w.name}{'_sor' if args.sor else ''})",
            "value": round(t_fb * 1e3, 3), "unit": "ms", "n_gpus": 1, "steps": k, "warmup": 1,
            "ms_per_step": round(t_fb * 1e3, 3), "higher_is_better": False, "scaling": "weak",
@@ -318,7 +451,7 @@ def run_adjoint(args):
                       "forward_cycles_max": fst["cycles_max"], "forward_status": fst["status"],
                       "adjoint_sweeps_total": bst["cycles_total"], "adjoint_sweeps_max": bst["cycles_max"],
                       "status": bst["status"]},
-           "roofline": None, "cpu_baseline": None}
+           "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 
@@ -563,15 +696,24 @@ def main():
             w.N, C, n, launches_per_cycle(prob.levels, prob.nu_pre, prob.nu_post),
             cycles if fixed else st_run["cycles_total"] / w.steps, fixed)
         achieved = bytes_per_launch / avg_s / 1e9
+        lpc = launches_per_cycle(prob.levels, prob.nu_pre, prob.nu_post)
+        sweep_bytes = B * sweep_bytes_per_launch(w.N, n, prob.nu_pre + prob.nu_post, lpc)
+        sweep_achieved = sweep_bytes / avg_s / 1e9
         tkey = (w.name + ("_consistent_mass" if args.consistent_mass else "")
                 + ("_simplex_projection" if args.simplex_projection else ""), B, cycles, prob.levels,
                 prob.nu_pre + prob.nu_post)
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": (int(TRAFFIC[tkey]) if fixed and tkey in TRAFFIC else None),
+        # `achieved`/`frac`: the sweep-equivalent bytes (12N per node and sweep); the
+        # LDS temporal blocking keeps most of them out of HBM, so `compulsory` gives
+        # the bytes a launch cannot avoid (read u and I, write u) over the same time
+        roof = {"bound": "hbm", "achieved": round(sweep_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(sweep_achieved / HBM_PEAK_GBS, 4),
+                "traffic": (int(TRAFFIC[tkey]) if fixed and tkey in TRAFFIC else None),
                 "kernel": ("k_cycle_batch" if B > 1 else "k_cycle") +
                           " (time step: rhs + 2 red-black sweeps in LDS + residual + colour-mean partials)",
-                "images_per_launch": B,
-                "bytes_per_launch": int(bytes_per_launch), "avg_launch_us": round(avg_s * 1e6, 2),
+                "images_per_launch": B, "sweeps_per_launch": (prob.nu_pre + prob.nu_post) / lpc,
+                "bytes_per_launch": int(sweep_bytes), "avg_launch_us": round(avg_s * 1e6, 2),
+                "compulsory": {"bytes_per_launch": int(bytes_per_launch), "achieved": round(achieved, 1),
+                               "frac": round(achieved / HBM_PEAK_GBS, 4)},
                 "launches": launches,
                 "per_family_ms": {k: round(v[1] / reps, 4) for k, v in t.items()}}
         # the attainable streaming rate for the same bytes: a plain device copy that
@@ -589,10 +731,10 @@ def main():
         torch.cuda.synchronize()
         copy_gbs = 8 * ncp / (e0.elapsed_time(e1) / 20 * 1e-3) / 1e9
         del src_cp, dst_cp
-        roof["copy_same_bytes_GBs"] = round(copy_gbs, 1)
-        roof["frac_of_copy"] = round(achieved / copy_gbs, 4)
-        log(f"[bench] smoother {avg_s*1e6:.2f} us/launch -> {achieved:.1f} GB/s algorithmic "
-            f"(a device copy of the same bytes: {copy_gbs:.1f} GB/s)")
+        roof["compulsory"]["copy_same_bytes_GBs"] = round(copy_gbs, 1)
+        roof["compulsory"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
+        log(f"[bench] smoother {avg_s*1e6:.2f} us/launch -> {sweep_achieved:.1f} GB/s sweep-equivalent, "
+            f"{achieved:.1f} GB/s compulsory (a device copy of the compulsory bytes: {copy_gbs:.1f} GB/s)")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -423,15 +423,22 @@ acseg_status acseg_energy(acseg_ctx *ctx, const acseg_problem *p, const float *i
  * grad_c is float[N][C] = dL/dc_fixed; otherwise c_fixed is ignored.  Each step's
  * derivative holds the free sets {i : u^{n+1}_pi > 0} fixed (components at 0
  * count as active) and treats the kept mean of an empty phase as a constant.
- * The per-step linear solves are over-relaxed red-black sweeps, stopped when
- * the change dz of a sweep, with r the observed contraction per sweep (the
- * ratio of the last two changes, at least omega - 1, at most 0.999),
- * satisfies dz <= max(tol, 2e-7) max|z| (1 - r), so that the distance to the
- * solution, at most dz r / (1 - r), is below that relative tolerance; at most
- * max(4, 2 max_cycles) sweeps (stats count steps that hit the cap as not
- * converged, and the sweeps as cycles).  The sweeps are
- * enqueued in chunks of 4, 8, ... 64; between chunks the call waits for the
- * stream to read the convergence flag, so it returns with the work done.
+ * The per-step linear solves are over-relaxed red-black sweeps, two per
+ * launch, stopped after the first pair of sweeps that follows a sweep whose
+ * change dz, with r the observed contraction per sweep (the ratio of the last
+ * two changes, at least omega - 1, at most 0.999), satisfies
+ * dz <= max(tol, 2e-7) max|z| (1 - r), so that the distance to the solution,
+ * at most dz r / (1 - r), is below that relative tolerance, or
+ * dz <= 8 ulp(max|z|) (float32 rounding sets such changes); at most
+ * max(4, 2 max_cycles) sweeps, rounded up to even (stats count steps that hit
+ * the cap as not converged, and the sweeps as cycles).  The first call for a
+ * problem enqueues the sweeps in chunks of 4, 8, ... 64 and waits for the
+ * stream between chunks to read the convergence flag.  The context then
+ * remembers, per problem (all fields of p), the most sweeps a step took; a
+ * later call gives every step that many sweeps without waiting (launches
+ * after convergence do nothing), and runs again in chunks if a step did not
+ * converge within them.  Either way the call waits for the stream once at
+ * the end, so it returns with the work done.
  * Workspace from acseg_backward_workspace_size.
  */
 acseg_status acseg_backward_workspace_size(const acseg_problem *p, size_t *bytes);
@@ -447,7 +454,12 @@ acseg_status acseg_backward(acseg_ctx *ctx, const acseg_problem *p, const float 
  * events on the call's stream; acseg_timing_read waits for those events, adds
  * up the elapsed times per family into out[0..*count-1] (at most max entries)
  * and forgets them.  Families: "cmeans", "rhs", "smooth" (one smoothing
- * cycle, or one launch of it when a cycle needs several), "mg", "other".
+ * cycle, or one launch of it when a cycle needs several), the passes of the
+ * truncated multigrid correction ("mg_restrict": fine defect and first
+ * restriction, "mg_down", "mg_tail": the coarsest levels in one workgroup,
+ * "mg_up", "mg_dir": prolongated direction and line-search partials,
+ * "mg_update"), "ssc" (the subspace correction), "adj_sweep" (adjoint
+ * sweeps), "other".
  */
 typedef struct acseg_kernel_time {
     char name[16];

@@ -17,8 +17,17 @@
 using namespace acseg;
 
 namespace {
-enum Family { kFamCmeans = 0, kFamRhs, kFamSmooth, kFamMg, kFamOther, kFamCount };
-const char* const kFamName[kFamCount] = {"cmeans", "rhs", "smooth", "mg", "other"};
+// Timing families: the multigrid ones follow the order of MgPass.
+enum Family {
+    kFamCmeans = 0, kFamRhs, kFamSmooth,
+    kFamMgRestrict, kFamMgDown, kFamMgTail, kFamMgUp, kFamMgDir, kFamMgUpdate,
+    kFamSsc, kFamAdjSweep, kFamOther, kFamCount
+};
+const char* const kFamName[kFamCount] = {"cmeans", "rhs", "smooth", "mg_restrict", "mg_down",
+                                         "mg_tail", "mg_up", "mg_dir", "mg_update", "ssc",
+                                         "adj_sweep", "other"};
+static_assert(kFamMgUpdate - kFamMgRestrict == kMgUpdate - kMgDefectRestrict, "family order");
+int mg_family(int op) { return kFamMgRestrict + (op - kMgDefectRestrict); }
 struct TimedRec {
     int fam;
     hipEvent_t a, b;
@@ -46,6 +55,9 @@ struct acseg_ctx {
     // device address of this device's copy of the static scratch array
     // (acseg_solve_no_alloc), looked up once at creation with the device current
     void* scratch = nullptr;
+    // most adjoint sweeps any step of the last backward of a problem took, by
+    // problem (at most kAdjMemo entries, oldest dropped first)
+    std::vector<std::pair<acseg_problem, int>> adj_memo;
 };
 
 // Scratch of acseg_solve_no_alloc: a file-scope device array, one copy per
@@ -333,7 +345,7 @@ acseg_status enqueue_correction(acseg_ctx* ctx, const acseg_problem* p, const Mg
         st.sweeps = r.sweeps;
         st.zero = r.zero;
         const size_t lds = mg_pass_lds(r.op, d, r.sweeps);
-        ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_mg(r.op, p->N, p->N, d, single, st, lds, s); }));
+        ACSEG_TRY(timed(ctx, mg_family(r.op), s, [&] { return launch_mg(r.op, p->N, p->N, d, single, st, lds, s); }));
     }
     return ACSEG_OK;
 }
@@ -370,7 +382,7 @@ acseg_status enqueue_ssc(acseg_ctx* ctx, const acseg_problem* p, const MgPlan& m
         a.part = (l >= kSscChunkLevel && items <= part_cap) ? part : nullptr;
         for (int c = 0; c < 4; ++c) {
             a.colour = c;
-            ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_ssc(p->N, a, s); }));
+            ACSEG_TRY(timed(ctx, kFamSsc, s, [&] { return launch_ssc(p->N, a, s); }));
         }
     }
     return ACSEG_OK;
@@ -717,6 +729,8 @@ BatchPlan plan_batch(int32_t B, const acseg_problem* ps) {
 
 // ---- backward ---------------------------------------------------------------
 
+constexpr size_t kAdjMemo = 8;
+
 struct BackLayout {
     size_t ctl = 0, actl = 0, c64 = 0, tot = 0, part_cm = 0, part_adj = 0, part_f = 0, cbar = 0;
     size_t z = 0, z2 = 0, ub0 = 0, ub1 = 0, total = 0;
@@ -735,9 +749,10 @@ BackLayout back_layout_of(const acseg_problem* p) {
     L.actl = take(sizeof(AdjCtl));
     L.c64 = take(sizeof(double) * S * kNC);
     L.tot = take(sizeof(double) * S * kCmeansMaxM);
-    L.part_cm = take(sizeof(double) * (size_t)kCmeansBlocks * kCmeansMaxM);
-    L.part_adj = take(sizeof(double) * (size_t)kMgBlocks * (3 + kNC));
-    L.part_f = take(sizeof(float) * 6 * kMgBlocks);
+    L.part_cm = take(sizeof(double) * std::min<size_t>(S, kCmeansFields) * cmeans_blocks(p->W, p->H) *
+                     kCmeansMaxM);
+    L.part_adj = take(sizeof(double) * (size_t)kAdjAccBlocks * (3 + kNC));
+    L.part_f = take(sizeof(float) * 12 * kMgBlocks);
     L.cbar = take(sizeof(double) * kNC);
     L.z = take(sizeof(float) * p->N * n);
     L.z2 = take(sizeof(float) * p->N * n);
@@ -1133,7 +1148,7 @@ acseg_status acseg_solve_batched(acseg_ctx* ctx, int32_t B, const acseg_problem*
                 for (const MgLaunchRec& r : g.mgl) {
                     ms.sweeps = r.sweeps;
                     const MgGrid mgrid{dmg, dmgwork + r.work0, r.nwork};
-                    ACSEG_TRY(timed(ctx, kFamMg, s, [&] {
+                    ACSEG_TRY(timed(ctx, mg_family(r.op), s, [&] {
                         return launch_mg(r.op, g.N, g.N, none, mgrid, ms, r.lds, s);
                     }));
                 }
@@ -1204,26 +1219,11 @@ acseg_status acseg_backward(acseg_ctx* ctx, const acseg_problem* p, const float*
     hipStream_t s = (hipStream_t)stream;
     const int N = p->N, C = p->C, W = p->W, H = p->H;
     const int64_t n = (int64_t)W * H, nu = (int64_t)N * n;
+    const int K = adj_sweeps_per_launch();
     Ctl* ctl = at<Ctl>(ws, L.ctl);
     AdjCtl* actl = at<AdjCtl>(ws, L.actl);
     double* c64 = at<double>(ws, L.c64);
     double* tot = at<double>(ws, L.tot);
-    ACSEG_TRY(launch_ctl_init(ctl, 0, s));
-    ACSEG_TRY(launch_adj_init(actl, grad_params, s));
-    ACSEG_TRY(launch_fill(grad_image, (int64_t)C * n, 0.f, s));
-    if (fixed_c) {
-        ACSEG_TRY(launch_widen(c_fixed, c64, N * C, s));
-        if (grad_c) ACSEG_TRY(launch_fill(grad_c, (int64_t)N * C, 0.f, s));
-    }
-    // the means of every step, recomputed from the checkpoints
-    for (int st = 0; st < (fixed_c ? 0 : p->steps); ++st) {
-        const float* u = checkpoints + st * nu;
-        const Bufs bufs{{u, u, u}};
-        double* part = at<double>(ws, L.part_cm);
-        ACSEG_TRY(launch_cmeans(N, C, W, H, image, u, bufs, ctl, part, s));
-        ACSEG_TRY(launch_cmeans_finish(N, C, W, H, part, ctl, st > 0 ? c64 + (st - 1) * kNC : nullptr,
-                                       c64 + st * kNC, nullptr, tot + st * kCmeansMaxM, s));
-    }
     AdjArgs a{};
     a.ctl = ctl;
     a.actl = actl;
@@ -1255,48 +1255,112 @@ acseg_status acseg_backward(acseg_ctx* ctx, const acseg_problem* p, const float*
     a.W = W;
     a.H = H;
     a.nblocks = adj_sweep_blocks(W, H);
-    a.nblocks_acc = adj_accum_blocks(W, H);
-    a.max_sweeps = std::min(4000, std::max(4, 2 * p->max_cycles));
+    a.nblocks_acc = adj_accum_blocks(N, C, W, H);
+    a.max_sweeps = (std::min(4000, std::max(4, 2 * p->max_cycles)) + K - 1) / K * K;
     float* ubuf[2] = {at<float>(ws, L.ub0), at<float>(ws, L.ub1)};
-    const float* ub = grad_uT;
-    for (int st = p->steps - 1; st >= 0; --st) {
-        a.u0 = checkpoints + st * nu;
-        a.u1 = checkpoints + (st + 1) * nu;
-        a.ub = ub;
-        a.ub_out = ubuf[st & 1];
-        a.c64 = fixed_c ? c64 : c64 + st * kNC;
-        a.tot = tot + st * kCmeansMaxM;
-        a.cbar_out = grad_c ? (fixed_c ? grad_c : grad_c + (int64_t)st * N * C) : nullptr;
-        a.cbar_accumulate = fixed_c ? 1 : 0;
-        // sweeps in chunks of growing length; between chunks the host reads the
-        // convergence flag (one small copy and wait per chunk) instead of
-        // enqueueing the whole budget of mostly no-op launches
-        int sw = 0, chunk = 4;
-        while (sw < a.max_sweeps) {
-            const int end = std::min(a.max_sweeps, sw + chunk);
-            for (; sw < end; ++sw)
-                ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_adj(N, C, kAdjSweep, a, 0, sw, s); }));
-            if (sw >= a.max_sweeps) break;
-            // the next sweep's launch tests convergence first (and sweeps only if
-            // not converged); then the flag is read back
-            ACSEG_TRY(timed(ctx, kFamMg, s, [&] { return launch_adj(N, C, kAdjSweep, a, 0, sw, s); }));
-            ACSEG_TRY(hipMemcpyAsync(ctx->host_actl, actl, sizeof(AdjCtl), hipMemcpyDeviceToHost, s));
-            ACSEG_TRY(hipStreamSynchronize(s));
-            if (ctx->host_actl->done) break;
-            ++sw;
-            chunk = std::min(64, chunk * 2);
+
+    // The sweeps of a step stop at convergence; how many it takes is known on
+    // the device only.  With a remembered count for the same problem (the most
+    // sweeps any step of an earlier backward took), every step gets that
+    // budget and no host wait; a step that used its whole budget below the
+    // cap without converging makes the call run again with waits.  Without
+    // one, the sweeps go in chunks with a read of the convergence flag after
+    // each.
+    auto memo = std::find_if(ctx->adj_memo.begin(), ctx->adj_memo.end(), [&](const auto& e) {
+        return memcmp(&e.first, p, sizeof(*p)) == 0;
+    });
+    const int budget = memo == ctx->adj_memo.end() ? 0 : std::min(a.max_sweeps, (memo->second + K - 1) / K * K);
+
+    auto run = [&](int spec) -> acseg_status {
+        ACSEG_TRY(launch_ctl_init(ctl, 0, s));
+        ACSEG_TRY(launch_adj_init(actl, grad_params, s));
+        ACSEG_TRY(launch_fill(grad_image, (int64_t)C * n, 0.f, s));
+        if (fixed_c) {
+            ACSEG_TRY(launch_widen(c_fixed, c64, N * C, s));
+            if (grad_c) ACSEG_TRY(launch_fill(grad_c, (int64_t)N * C, 0.f, s));
+        } else {
+            // the means of every step, recomputed from the checkpoints
+            for (int f = 0; f < p->steps; f += kCmeansFields) {
+                const int cnt = std::min(kCmeansFields, p->steps - f);
+                ACSEG_TRY(timed(ctx, kFamCmeans, s, [&] {
+                    return launch_cmeans_fields(N, C, W, H, image, checkpoints, f, cnt, at<double>(ws, L.part_cm),
+                                                tot, c64, ctl, s);
+                }));
+            }
         }
-        ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjAccum, a, 0, 0, s); }));
-        ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjReduce, a, 0, 0, s); }));
-        if (!fixed_c)  // fixed means depend on neither u^n nor the image
-            ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjMeans, a, 0, 0, s); }));
-        ub = a.ub_out;
+        const float* ub = grad_uT;
+        a.cm_cbar = a.cm_c64 = a.cm_tot = nullptr;
+        for (int st = p->steps - 1; st >= 0; --st) {
+            a.u0 = checkpoints + st * nu;
+            a.u1 = checkpoints + (st + 1) * nu;
+            a.ub = ub;
+            a.ub_out = ubuf[st & 1];
+            a.c64 = fixed_c ? c64 : c64 + st * kNC;
+            a.tot = tot + st * kCmeansMaxM;
+            a.cbar_out = grad_c ? (fixed_c ? grad_c : grad_c + (int64_t)st * N * C) : nullptr;
+            a.cbar_accumulate = fixed_c ? 1 : 0;
+            int sw = 0;
+            if (spec > 0) {
+                for (; sw < spec; sw += K)
+                    ACSEG_TRY(timed(ctx, kFamAdjSweep, s, [&] { return launch_adj(N, C, kAdjSweep, a, 0, sw, s); }));
+            } else {
+                int chunk = 4;
+                while (true) {
+                    const int end = std::min(a.max_sweeps, sw + chunk);
+                    for (; sw < end; sw += K)
+                        ACSEG_TRY(timed(ctx, kFamAdjSweep, s,
+                                        [&] { return launch_adj(N, C, kAdjSweep, a, 0, sw, s); }));
+                    if (sw >= a.max_sweeps) break;
+                    ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjCheck, a, 0, sw, s); }));
+                    ACSEG_TRY(hipMemcpyAsync(ctx->host_actl, actl, sizeof(AdjCtl), hipMemcpyDeviceToHost, s));
+                    ACSEG_TRY(hipStreamSynchronize(s));
+                    if (ctx->host_actl->done) break;
+                    chunk = std::min(64, chunk * 2);
+                }
+            }
+            a.budget = sw;
+            ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjAccum, a, 0, 0, s); }));
+            ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjReduce, a, 0, 0, s); }));
+            ub = a.ub_out;
+            // this step's means share goes to the next step's launches (fixed
+            // means depend on neither u^n nor the image: no share)
+            if (!fixed_c) {
+                a.cm_cbar = a.cbar64;
+                a.cm_c64 = c64 + st * kNC;
+                a.cm_tot = tot + st * kCmeansMaxM;
+            }
+        }
+        if (a.cm_cbar) {
+            // the first step's share: grad_u0 and dL/dI
+            a.u0 = checkpoints;
+            a.ub = ub;
+            a.ub_out = grad_u0;
+            ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjFinal, a, 0, 0, s); }));
+        } else if (grad_u0) {
+            ACSEG_TRY(hipMemcpyAsync(grad_u0, ub, sizeof(float) * nu, hipMemcpyDeviceToDevice, s));
+        }
+        ACSEG_TRY(hipMemcpyAsync(ctx->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        ACSEG_TRY(hipMemcpyAsync(ctx->host_actl, actl, sizeof(AdjCtl), hipMemcpyDeviceToHost, s));
+        ACSEG_TRY(hipStreamSynchronize(s));
+        return ACSEG_OK;
+    };
+    acseg_status r = run(budget);
+    if (r != ACSEG_OK) return r;
+    const bool rerun = budget > 0 && ctx->host_actl->short_steps > 0;
+    if (rerun) {
+        r = run(0);
+        if (r != ACSEG_OK) return r;
     }
-    if (grad_u0) ACSEG_TRY(hipMemcpyAsync(grad_u0, ub, sizeof(float) * nu, hipMemcpyDeviceToDevice, s));
-    if (!stats) return ACSEG_OK;
-    ACSEG_TRY(hipMemcpyAsync(ctx->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    ACSEG_TRY(hipStreamSynchronize(s));
     const Ctl& c = *ctx->host_ctl;
+    if (memo != ctx->adj_memo.end()) {
+        // a count that sufficed decays by one launch per call, so one slow
+        // problem does not hold the budget up for good
+        memo->second = rerun ? c.cycles_max : std::max(c.cycles_max, memo->second - K);
+    } else {
+        if (ctx->adj_memo.size() >= kAdjMemo) ctx->adj_memo.erase(ctx->adj_memo.begin());
+        ctx->adj_memo.push_back({*p, c.cycles_max});
+    }
+    if (!stats) return ACSEG_OK;
     memset(stats, 0, sizeof(*stats));
     stats->steps_done = c.steps_done;
     stats->cycles_total = c.cycles_total;

@@ -189,10 +189,22 @@ __device__ __forceinline__ void project_simplex(float (&v)[N]) {
 // Wave / block reductions (wave64)
 // ---------------------------------------------------------------------------
 
+// Maximum over the 64 lanes of a wave (DPP moves as in wave_sum_last, lanes
+// a move does not reach keeping their own value), read back from lane 63:
+// every lane returns it.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_keep_f(float v) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
-    return v;
+    v = fmaxf(v, dpp_keep_f<0xB1, 0xF>(v));
+    v = fmaxf(v, dpp_keep_f<0x4E, 0xF>(v));
+    v = fmaxf(v, dpp_keep_f<0x124, 0xF>(v));
+    v = fmaxf(v, dpp_keep_f<0x128, 0xF>(v));
+    v = fmaxf(v, dpp_keep_f<0x142, 0xA>(v));
+    v = fmaxf(v, dpp_keep_f<0x143, 0xC>(v));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 // Sum over the 64 lanes of a wave in a fixed order (data-parallel-primitive
@@ -229,10 +241,27 @@ __device__ __forceinline__ float half_wave_sum_last(float v) {
     return v;
 }
 
+// Sum over the 64 lanes of a wave in the fixed order of wave_sum_last (each
+// DPP move on both 32-bit halves), read back from lane 63: every lane
+// returns the total.  All lanes of the wave must be active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_d(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+    v += dpp_d<0xB1, 0xF>(v);
+    v += dpp_d<0x4E, 0xF>(v);
+    v += dpp_d<0x124, 0xF>(v);
+    v += dpp_d<0x128, 0xF>(v);
+    v += dpp_d<0x142, 0xA>(v);
+    v += dpp_d<0x143, 0xC>(v);
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 // This thread's share (t, t + kBlock, ...) of a sum / max over n values, with

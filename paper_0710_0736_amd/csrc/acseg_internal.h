@@ -79,6 +79,16 @@ int cmeans_blocks(int W, int H);
 hipError_t launch_cmeans(int N, int C, int W, int H, const float* image, const float* u,
                          Bufs bufs, const Ctl* ctl, double* partials, hipStream_t s);
 
+// The colour means of fields[first .. first+count-1] (float[N][H][W] each,
+// count <= kCmeansFields) in
+// three launches: the sums of every field (partials: count x cmeans_blocks x
+// cmeans_width doubles), their totals into tot[field][kCmeansMaxM], then the
+// means into c64[field][kNC] in field order, an empty phase keeping the
+// previous field's mean (field 0: the mean image colour).
+hipError_t launch_cmeans_fields(int N, int C, int W, int H, const float* image, const float* fields,
+                                int first, int count, double* partials, double* tot, double* c64, Ctl* ctl,
+                                hipStream_t s);
+
 // One block: the reduced sums tot[cmeans_width] (may be NULL), c64 (float64
 // [N][C]) and c_out (float, may be NULL) from the partials; empty phases keep
 // c_prev64 (NULL: mean image colour).
@@ -93,6 +103,7 @@ hipError_t launch_cmeans_finish(int N, int C, int W, int H, const double* partia
 constexpr int kXcd = 8;  // XCDs of an MI355X: workgroup id mod 8 selects the XCD
 constexpr int kStrip = 8;  // tile columns per strip of a single-image cycle launch
 constexpr int kCmeansMaxM = 8 * 4 + 8 + 4 + 2;  // colour-mean sums per set, N <= 8, C <= 4
+constexpr int kCmeansFields = 64;                // most fields of one launch_cmeans_fields
 constexpr int kNC = 8 * 4;                       // stride of one set of means
 
 // Per image, constant over a solve.
@@ -304,13 +315,18 @@ hipError_t launch_mass_avg(int planes, int W, int H, const float* src, float* ds
 // ---- launchers (kernels_adjoint.hip): gradients through the time steps ------
 
 struct AdjCtl {
-    int done;     // the current adjoint solve converged
-    int sweeps;   // after this many sweeps
-    float omega;  // over-relaxation factor of the current solve, set at sweep kAdjOmegaSweep
-    int pad;
+    int done;         // the current adjoint solve converged
+    int sweeps;       // after this many sweeps
+    float omega;      // over-relaxation factor of the current solve, set at sweep kAdjOmegaSweep
+    int fin_done;     // the solve's outcome as the accumulation pass found it
+    int fin_sweeps;   // and its sweeps
+    int short_steps;  // steps whose enqueued sweeps, below the cap, did not converge
+    int pad[2];
 };
 
-enum AdjOp { kAdjSweep = 0, kAdjAccum, kAdjReduce, kAdjMeans };
+enum AdjOp { kAdjSweep = 0, kAdjCheck, kAdjAccum, kAdjReduce, kAdjFinal };
+
+constexpr int kAdjAccBlocks = 256;  // most workgroups (partial rows) of the accumulation pass
 
 // Step s backwards: u0 = u^s, u1 = u^{s+1}, ub = dL/du^{s+1}; out: ub_out =
 // dL/du^s; accumulated: Ibar, grads (lambda, eps, tau); cbar of the step.
@@ -331,7 +347,7 @@ struct AdjArgs {
     double* cbar64;       // [N][C]
     float* cbar_out;      // [N][C] or NULL
     int cbar_accumulate;  // add cbar to cbar_out (fixed means) instead of storing it
-    float* part_f;        // [3 (sweep mod 3)][2][kMgBlocks]: max |dz|, max |z| per workgroup
+    float* part_f;        // [6 (sweep mod 6)][2][kMgBlocks]: max |dz|, max |z| per workgroup
     double* part_d;       // [kMgBlocks][3 + N C]
     LevelCoef coef;       // finest level
     float diagA[4];       // stiffness diagonal per node class
@@ -339,10 +355,18 @@ struct AdjArgs {
     float omega;          // largest over-relaxation factor of the sweeps (from the coupling bound)
     double h2, eps, tau, lambda;
     int W, H, nblocks, nblocks_acc, max_sweeps;
+    int budget;  // sweeps enqueued for the current step (a multiple of the sweeps per launch)
+    // the colour means share of the step after this one, applied by this
+    // step's sweeps (to ub) and accumulation (to Ibar): its cbar [N][C], means
+    // and sums; cm_cbar NULL: none
+    const double* cm_cbar;
+    const double* cm_c64;
+    const double* cm_tot;
 };
 
 int adj_sweep_blocks(int W, int H);
-int adj_accum_blocks(int W, int H);
+int adj_accum_blocks(int N, int C, int W, int H);
+int adj_sweeps_per_launch();
 hipError_t launch_adj(int N, int C, int op, const AdjArgs& a, int colour, int sweep, hipStream_t s);
 hipError_t launch_adj_init(AdjCtl* ac, double* grads, hipStream_t s);
 

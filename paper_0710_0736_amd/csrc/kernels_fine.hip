@@ -34,19 +34,23 @@ struct CmeansArgs {
     const float* u;  // explicit field, or NULL: bufs.b[ctl->cur]
     Bufs bufs;
     const Ctl* ctl;
-    double* partials;  // [gridDim.x][cmeans_width(N, C)]
+    double* partials;  // [gridDim.y][gridDim.x][cmeans_width(N, C)]
     int W, H;
+    int64_t u_stride;  // floats from one explicit field to the next (grid row y: u + y u_stride)
 };
 
 template <int N, int C>
 __global__ __launch_bounds__(kBlock) void k_cmeans(CmeansArgs a) {
     constexpr int M = N * C + N + C + 2;  // S_ik, S_i, SI_k, Sw, non-finite count
     __shared__ double sh[kBlock / kWave][M];
-    const float* u = a.u ? a.u : a.bufs.b[__builtin_amdgcn_readfirstlane(a.ctl->cur)];
+    const float* u = a.u ? a.u + blockIdx.y * a.u_stride : a.bufs.b[__builtin_amdgcn_readfirstlane(a.ctl->cur)];
+    a.partials += (int64_t)blockIdx.y * gridDim.x * M;
     const int64_t n = (int64_t)a.W * a.H;
     double acc[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) acc[m] = 0.0;
+    // no stores in the loop: unrolled, the loads of several nodes issue together
+#pragma unroll 4
     for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * kBlock) {
         const int y = (int)(p / a.W), x = (int)(p - (int64_t)y * a.W);
@@ -111,6 +115,62 @@ __global__ __launch_bounds__(kBlock) void k_cmeans_finish(CmeansFinArgs a) {
         }
         a.ctl->empty_now = empty;
         if (tot[M - 1] > 0.0) a.ctl->nonfinite = 1;
+    }
+}
+
+// One workgroup per field of a k_cmeans launch over several fields: its
+// reduced sums into tot[y][kCmeansMaxM].
+template <int N, int C>
+__global__ __launch_bounds__(kBlock) void k_cmeans_tot(const double* partials, int nb, double* tot) {
+    constexpr int M = N * C + N + C + 2;
+    __shared__ double sh[kBlock / kWave][M];
+    __shared__ double t[M];
+    reduce_rows<M>(partials + (int64_t)blockIdx.x * nb * M, nb, t, sh);
+    if (threadIdx.x < M) tot[(int64_t)blockIdx.x * kCmeansMaxM + threadIdx.x] = t[threadIdx.x];
+}
+
+// One thread: the means of fields first..first+count-1 from their reduced
+// sums, in order, an empty phase keeping the previous field's mean (the first
+// field's previous means: c64 of field first - 1, or the mean image colour
+// when first is 0).
+// (The sums and means pass through LDS: the one thread that walks the
+// fields then waits on no memory.)  count <= kCmeansFields.
+template <int N, int C>
+__global__ __launch_bounds__(kBlock) void k_cmeans_chain(const double* tot, int first, int count, Ctl* ctl,
+                                                         double* c64) {
+    constexpr int M = N * C + N + C + 2;
+    __shared__ double ts[kCmeansFields][M];
+    __shared__ double cs[kCmeansFields + 1][N * C];
+    for (int q = threadIdx.x; q < count * M; q += kBlock) {
+        const int f = q / M, m = q - f * M;
+        ts[f][m] = tot[(int64_t)(first + f) * kCmeansMaxM + m];
+    }
+    if (first > 0 && threadIdx.x < N * C) cs[0][threadIdx.x] = c64[(int64_t)(first - 1) * kNC + threadIdx.x];
+    __syncthreads();
+    // thread i C + k follows c_ik through the fields (a phase's chain does
+    // not depend on the other phases)
+    if (threadIdx.x < N * C) {
+        const int i = threadIdx.x / C, k = threadIdx.x - i * C;
+        for (int f = 0; f < count; ++f) {
+            const double* t = ts[f];
+            const double area = t[N * C + N + C], S = t[N * C + i];
+            cs[f + 1][threadIdx.x] = S > 1e-12 * area
+                                         ? t[i * C + k] / S
+                                         : ((first + f) > 0 ? cs[f][threadIdx.x] : t[N * C + N + k] / area);
+        }
+    }
+    if (threadIdx.x == 0) {
+        const double* t = ts[count - 1];
+        int empty = 0, bad = 0;
+        for (int i = 0; i < N; ++i) empty |= t[N * C + i] > 1e-12 * t[N * C + N + C] ? 0 : 1;
+        for (int f = 0; f < count; ++f) bad |= ts[f][M - 1] > 0.0 ? 1 : 0;
+        ctl->empty_now = empty;
+        if (bad) ctl->nonfinite = 1;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < count * N * C; q += kBlock) {
+        const int f = q / (N * C), m = q - f * (N * C);
+        c64[(int64_t)(first + f) * kNC + m] = cs[f + 1][m];
     }
 }
 
@@ -331,8 +391,35 @@ struct CmeansRun {
 
 hipError_t launch_cmeans(int N, int C, int W, int H, const float* image, const float* u,
                          Bufs bufs, const Ctl* ctl, double* partials, hipStream_t s) {
-    const CmeansArgs a{image, u, bufs, ctl, partials, W, H};
+    const CmeansArgs a{image, u, bufs, ctl, partials, W, H, 0};
     return dispatch_nc<CmeansRun>(N, C, a, cmeans_blocks(W, H), s);
+}
+
+template <int N, int C>
+struct CmeansFieldsRun {
+    static hipError_t run(const CmeansArgs& a, int first, int count, double* tot, double* c64, Ctl* ctl,
+                          hipStream_t s) {
+        const int nb = cmeans_blocks(a.W, a.H);
+        hipLaunchKernelGGL((k_cmeans<N, C>), dim3(nb, count), dim3(kBlock), 0, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_cmeans_tot<N, C>), dim3(count), dim3(kBlock), 0, s, a.partials, nb,
+                           tot + (int64_t)first * kCmeansMaxM);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_cmeans_chain<N, C>), dim3(1), dim3(kBlock), 0, s, tot, first, count, ctl, c64);
+        return hipGetLastError();
+    }
+};
+
+hipError_t launch_cmeans_fields(int N, int C, int W, int H, const float* image, const float* fields,
+                                int first, int count, double* partials, double* tot, double* c64, Ctl* ctl,
+                                hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    if (count > kCmeansFields) return hipErrorInvalidValue;
+    const int64_t stride = (int64_t)N * W * H;
+    const CmeansArgs a{image, fields + first * stride, Bufs{}, ctl, partials, W, H, stride};
+    return dispatch_nc<CmeansFieldsRun>(N, C, a, first, count, tot, c64, ctl, s);
 }
 
 template <int N, int C>
