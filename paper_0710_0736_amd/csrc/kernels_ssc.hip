@@ -57,10 +57,44 @@ __device__ __forceinline__ float hat_at(int x, int y, int X, int Y, int sh, int 
     return t >= s ? 0.f : (float)(s - t) * inv_s;
 }
 
-__device__ __forceinline__ float wave_min_f(float v) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
+// Butterflies inside a row of 16 lanes by DPP moves: quad_perm [1,0,3,2] and
+// [2,3,0,1] (lane xor 1, xor 2), row_half_mirror (quads 0-1 and 2-3 swap) and
+// row_mirror (the row's halves swap).  Each step adds the partner's value, so
+// every lane of the row ends with the same sum (addition is commutative).
+template <int CTRL>
+__device__ __forceinline__ float dpp_row_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_row_d(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double row_sum(double v) {
+    v += dpp_row_d<0xB1>(v);
+    v += dpp_row_d<0x4E>(v);
+    v += dpp_row_d<0x141>(v);
+    v += dpp_row_d<0x140>(v);
     return v;
+}
+__device__ __forceinline__ float row_min(float v) {
+    v = fminf(v, dpp_row_f<0xB1>(v));
+    v = fminf(v, dpp_row_f<0x4E>(v));
+    v = fminf(v, dpp_row_f<0x141>(v));
+    v = fminf(v, dpp_row_f<0x140>(v));
+    return v;
+}
+// Minimum over the wave: the rows' minima, then the four rows read back (the
+// minimum does not depend on the order).
+__device__ __forceinline__ float wave_min_f(float v) {
+    v = row_min(v);
+    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return fminf(fminf(a, b), fminf(c, d));
 }
 
 // beta <- its projection onto {beta >= 0, sum beta = M} (M > 0): sort, then
@@ -316,22 +350,20 @@ __global__ __launch_bounds__(T) void k_ssc_apply(SscArgs a) {
     }
 }
 
-// Small supports: G lanes per function (G divides the wave), 256 / G functions
-// per workgroup, reduced by xor butterflies within the lane group (each lane
-// ends with the same sums: IEEE addition is commutative).  The loop over
-// functions is uniform across the workgroup so every lane takes part in the
-// shuffles; lanes past the last function only contribute zeros.
+// Small supports: G lanes per function (16: a DPP row, 64: the wave), 256 / G
+// functions per workgroup, reduced inside the lane group so that each lane
+// ends with the same sums.  The loop over functions is uniform across the
+// workgroup so every lane takes part in the moves; lanes past the last
+// function only contribute zeros.
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+    static_assert(G == 16 || G == 64, "a row or the wave");
+    return G == 16 ? row_sum(v) : wave_sum(v);
 }
 template <int G>
 __device__ __forceinline__ float group_min(float v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
-    return v;
+    static_assert(G == 16 || G == 64, "a row or the wave");
+    return G == 16 ? row_min(v) : wave_min_f(v);
 }
 
 template <int N, int G>
