@@ -20,13 +20,12 @@ namespace {
 // Timing families: the multigrid ones follow the order of MgPass.
 enum Family {
     kFamCmeans = 0, kFamRhs, kFamSmooth,
-    kFamMgRestrict, kFamMgDown, kFamMgTail, kFamMgUp, kFamMgDir, kFamMgUpdate,
+    kFamMgRestrict, kFamMgDown, kFamMgTail, kFamMgUp, kFamMgDir,
     kFamSsc, kFamAdjSweep, kFamOther, kFamCount
 };
 const char* const kFamName[kFamCount] = {"cmeans", "rhs", "smooth", "mg_restrict", "mg_down",
-                                         "mg_tail", "mg_up", "mg_dir", "mg_update", "ssc",
-                                         "adj_sweep", "other"};
-static_assert(kFamMgUpdate - kFamMgRestrict == kMgUpdate - kMgDefectRestrict, "family order");
+                                         "mg_tail", "mg_up", "mg_dir", "ssc", "adj_sweep", "other"};
+static_assert(kFamMgDir - kFamMgRestrict == kMgDir - kMgDefectRestrict, "family order");
 int mg_family(int op) { return kFamMgRestrict + (op - kMgDefectRestrict); }
 struct TimedRec {
     int fam;
@@ -307,7 +306,8 @@ MgImage mg_image_of(const acseg_problem* p, const MgPlan& m, const Layout& L, vo
 // The passes of one truncated multigrid correction, in order: (pass, level,
 // sweeps, zero).  Levels 1..tail-1 go down (sweeps from zero, restriction)
 // and up (prolongation, sweeps) in tiled passes, the LDS tail solves levels
-// tail..L-1; without a tail the coarsest level is an up pass from zero.
+// tail..L-1; without a tail the coarsest level is an up pass from zero.  The
+// direction pass closes it; the next smoothing launch applies the update.
 struct MgPassRec {
     int op, level, sweeps, zero;
 };
@@ -323,7 +323,6 @@ std::vector<MgPassRec> mg_passes(const MgPlan& m, int nu_pre, int nu_post) {
         v.push_back({kMgUp, m.L - 1, kCoarseSweeps, 1});
     for (int l = down_end - 1; l >= 1; --l) v.push_back({kMgUp, l, nu_post, 0});
     v.push_back({kMgDir, 0, 0, 0});
-    v.push_back({kMgUpdate, 0, 0, 0});
     return v;
 }
 
@@ -411,6 +410,11 @@ CycleArgs cycle_args_of(const acseg_problem* p, const Coefs& cf, const float* im
     a.rc = cf.rhs;
     a.tol = (float)p->tol;
     a.omega = 1.f;
+    if (plan_of(p).L >= 2 && (p->flags & ACSEG_FLAG_SSC) == 0u) {
+        a.mg_w = at<float>(ws, L.mg_gt);
+        a.mg_part = at<double>(ws, L.mg_part);
+        a.mg_parts = dir_blocks(p->W, p->H);
+    }
     if ((p->flags & ACSEG_FLAG_SOR) != 0u) {
         // Young's factor for the bound rho <= q = max over node classes of
         // kappa * (sum of edge weights = stiffness diagonal) of the block-Jacobi radius
@@ -483,7 +487,7 @@ acseg_status enqueue_step(acseg_ctx* ctx, const acseg_problem* p, const Coefs& c
                 : enqueue_correction(ctx, p, m, L, ws, bufs, st.slot, sc.fixed, k * sc.lpc + sc.lpre, s);
         if (v != ACSEG_OK) return v;
         st.launch = k * sc.lpc + sc.lpre;
-        const CycleRole post{false, false, true};
+        const CycleRole post{false, false, true, (p->flags & ACSEG_FLAG_SSC) == 0u};
         ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] { return launch_cycle(p->N, p->C, p->nu_post, a, st, single, post, s); }));
         return ACSEG_OK;
     };
@@ -614,8 +618,8 @@ struct BatchPlan {
 
 // The multigrid passes of a group: defect + restriction, down passes level by
 // level, LDS tails, up passes level by level (with the coarsest-level solve of
-// images without a tail), direction, update.  An image takes part in the
-// passes its hierarchy has.
+// images without a tail), direction (the post-smoothing launch applies the
+// update).  An image takes part in the passes its hierarchy has.
 void plan_group_mg(const acseg_problem* ps, BatchPlan& bp, BatchGroup& g) {
     const int nu_pre = ps[g.members[0]].nu_pre, nu_post = ps[g.members[0]].nu_post;
     auto add = [&](int op, int sweeps, size_t lds, const std::vector<int4>& items) {
@@ -667,10 +671,6 @@ void plan_group_mg(const acseg_problem* ps, BatchPlan& bp, BatchGroup& g) {
     for (int b : g.members)
         for (int k = 0; k < dir_blocks(ps[b].W, ps[b].H); ++k) it.push_back(make_int4(b, k, 0, 0));
     add(kMgDir, 0, 0, it);
-    it.clear();
-    for (int b : g.members)
-        for (int t = 0; t < tiles_of(ps[b].W, ps[b].H, kUpdTX, kUpdTY); ++t) it.push_back(make_int4(b, t, 0, 0));
-    add(kMgUpdate, 0, 0, it);
 }
 
 BatchPlan plan_batch(int32_t B, const acseg_problem* ps) {
@@ -1153,7 +1153,7 @@ acseg_status acseg_solve_batched(acseg_ctx* ctx, int32_t B, const acseg_problem*
                     }));
                 }
                 st.launch = k * sc.lpc + sc.lpre;
-                const CycleRole post{false, false, true};
+                const CycleRole post{false, false, true, true};  // applies the correction's update
                 ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] {
                     return launch_cycle(g.N, g.C, pg.nu_post, any, st, grid, post, s);
                 }));

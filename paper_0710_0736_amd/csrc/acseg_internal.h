@@ -125,6 +125,12 @@ struct CycleArgs {
     int tiles_x, ntiles, tiles_per_xcd;
     int tiles_y, rows_per_xcd;  // tile rows; tile rows per XCD band (single-image launch order)
     float omega;                // over-relaxation of the smoothing sweeps (1: Gauss-Seidel; single image)
+    // the truncated coarse correction's direction w and its line-search partials
+    // (pairs <g~, w>, <w, H w>), applied by the launch after it (CycleStep::mg_update);
+    // NULL without a truncated multigrid
+    const float* mg_w;
+    const double* mg_part;
+    int mg_parts;
 };
 
 // Per launch.
@@ -140,6 +146,7 @@ struct CycleStep {
     int c64_sel;    // the step's first launch writes the means of u^n to c64 set c64_sel
     int prev_sel;   // previous means (empty phases) in c64 set prev_sel, or -1
     int fixed_c;    // the means of every step are c64 set prev_sel (not recomputed)
+    int mg_update;  // stage u as max(u + alpha w, 0): the coarse correction's update (not in a step's first launch)
 };
 
 // What a run of smoothing launches is within its step and cycle.
@@ -147,6 +154,7 @@ struct CycleRole {
     bool step_first;  // the first launch opens the step: it builds the right-hand side
     bool opens;       // the first launch opens the cycle: convergence check
     bool closes;      // the last launch closes the cycle: residual and colour-mean partials
+    bool mg_update;   // the first launch applies the truncated coarse correction's update
 };
 
 // Where a launch's tiles come from: one image (descs == NULL) or a batch.
@@ -208,7 +216,6 @@ constexpr int kDnTX = 32, kDnTY = 16;   // down-leg of level l: level-(l+1) node
 constexpr int kUpTX = 64, kUpTY = 16;   // up-leg of level l: level-l nodes per workgroup
 constexpr int kDirTX = 64, kDirTY = 8;  // direction and line-search partials: fine nodes
 constexpr int kDirBlocks = 2048;        // most workgroups of one image's direction pass
-constexpr int kUpdTX = 64, kUpdTY = 8;  // update: fine nodes per workgroup
 
 // One coarse level l >= 1 of one image.  The level's correction problem is
 // H_l v = r (componentwise, H_l rediscretised at spacing 2^l h); v holds the
@@ -261,7 +268,7 @@ struct MgGrid {
     int nwork;
 };
 
-enum MgPass { kMgDefectRestrict = 0, kMgDown, kMgTail, kMgUp, kMgDir, kMgUpdate };
+enum MgPass { kMgDefectRestrict = 0, kMgDown, kMgTail, kMgUp, kMgDir };
 
 // Workgroups of pass `op` on level st.level of one image (single-image grid).
 int mg_pass_tiles(int op, const MgImage& m, int level);

@@ -315,6 +315,49 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
         lds_put<N>(lds, li, ust[q]);
     }
     __syncthreads();  // u and the sums staged
+    if constexpr (!FIRST) {
+        // after a truncated coarse correction: alpha = clamp(<g~,w>/<w,Hw>, 0, 1)
+        // from the direction pass's partials (every workgroup sums them in the
+        // same order), then u = max(u + alpha w, 0) on the staged field, node by
+        // node (few registers: the other launches keep their allocation)
+        if (st.mg_update) {
+            __shared__ double mgs[2 * (T / kWave)];
+            double ga = 0.0, qa = 0.0;
+            for (int k = threadIdx.x; k < a.mg_parts; k += T) {
+                ga += a.mg_part[2 * k];
+                qa += a.mg_part[2 * k + 1];
+            }
+            ga = wave_sum(ga);
+            qa = wave_sum(qa);
+            if (threadIdx.x % kWave == 0) {
+                mgs[2 * (threadIdx.x / kWave)] = ga;
+                mgs[2 * (threadIdx.x / kWave) + 1] = qa;
+            }
+            __syncthreads();
+            ga = qa = 0.0;
+            for (int w = 0; w < T / kWave; ++w) {
+                ga += mgs[2 * w];
+                qa += mgs[2 * w + 1];
+            }
+            const float alpha = (qa > 0.0 && ga > 0.0) ? (float)fmin(ga / qa, 1.0) : 0.f;
+            if (tile == 0 && threadIdx.x == 0) ctl->alpha = alpha;  // for inspection
+            for (int idx = threadIdx.x; idx < LX * LY; idx += T) {
+                const int ly = idx / LX, lx = idx - ly * LX;
+                const int gx = x0 + lx, gy = y0 + ly;
+                if (!(INT || (gx >= 0 && gx < W && gy >= 0 && gy < H))) continue;
+                const uint32_t g = (uint32_t)(gy * W + gx);
+                float wv[N], uv[N];
+#pragma unroll
+                for (int i = 0; i < N; ++i) wv[i] = gload(a.mg_w + i * P, g);
+                float* slot = lds + (ly * RW + (lx & 1) * HL + (lx >> 1)) * NPD;
+                lds_ld<N>(slot, uv);
+#pragma unroll
+                for (int i = 0; i < N; ++i) uv[i] = fmaxf(fmaf(alpha, wv[i], uv[i]), 0.f);
+                lds_st<N>(slot, uv);
+            }
+            __syncthreads();
+        }
+    }
     if (FIRST) {
         // colour means of u^n (identical in every workgroup): lane i < N of
         // the first wave finishes phase i
@@ -728,6 +771,7 @@ hipError_t run_cycle_nc(int sweeps, const CycleArgs& a, CycleStep st, const Cycl
         const bool first = role.step_first && k == 0;
         st.first = role.opens && k == 0;
         st.launch = base + k;
+        st.mg_update = (role.mg_update && k == 0) ? 1 : 0;
         if (kk == 2) {
             if (first)
                 e = last ? run_cycle<N, C, 2, true, true>(a, st, g, s) : run_cycle<N, C, 2, true, false>(a, st, g, s);

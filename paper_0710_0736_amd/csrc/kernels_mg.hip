@@ -546,14 +546,19 @@ __device__ __forceinline__ void mg_tail(const MgImage& d, const MgStep& st, int 
 // <g~, w>, <w, H w>: workgroup b of an image takes the kDirTX x kDirTY fine
 // tiles b, b + dir_blocks, ...; per tile w on the tile and a ring of one (for
 // H w) from u staged with that ring, g~ on the tile.  Each workgroup leaves
-// its two sums; the update pass reduces them.
+// its two sums; the smoothing launch after the correction reduces them to the
+// step length and applies the update as it stages u.
 // ---------------------------------------------------------------------------
 
 template <int N>
 __device__ __forceinline__ void mg_dir(const MgImage& d, int blk, const MgStep& st) {
     constexpr int SX = kDirTX + 2, SY = kDirTY + 2;
+    // the level-1 nodes the prolongation reads for the staged fine nodes
+    // (x0 - 1 .. x0 + kDirTX, and the right / lower neighbour of each)
+    constexpr int CX = kDirTX / 2 + 3, CY = kDirTY / 2 + 3;
     __shared__ float us[N][SY][SX];
     __shared__ float ws[N][SY][SX];
+    __shared__ float vcs[N][CY][CX];
     __shared__ double sh[kBlock / kWave];
     const int W = d.W, H = d.H;
     const MgLevel c = d.lv[1];
@@ -567,7 +572,9 @@ __device__ __forceinline__ void mg_dir(const MgImage& d, int blk, const MgStep& 
     for (int tile = blk; tile < ntiles; tile += d.dir_blocks) {
         const int x0 = (tile % tx) * kDirTX, y0 = (tile / tx) * kDirTY;
         const int sx0 = x0 - 1, sy0 = y0 - 1;
-        __syncthreads();  // the previous tile's reads of us / ws are done
+        const int cx0 = max(sx0, 0) >> 1, cy0 = max(sy0, 0) >> 1;
+        __syncthreads();  // the previous tile's reads of us / ws / vcs are done
+        stage_planes<N, CX, CY>(&vcs[0][0][0], c.v2, nc, cx0, cy0, c.W, c.H);
         stage_planes<N, SX, SY>(&us[0][0][0], u, n, sx0, sy0, W, H);
         __syncthreads();
 #pragma unroll
@@ -581,10 +588,16 @@ __device__ __forceinline__ void mg_dir(const MgImage& d, int blk, const MgStep& 
                 float uc[N], v[N];
                 int k = 0;
                 float s = 0.f;
+                // P v2_1 at (gx, gy) from the staged level-1 block (as prolong_at)
+                const int pa = min(gx, 2 * c.W - 2), pb = min(gy, 2 * c.H - 2);
+                const int cxl = (pa >> 1) - cx0, cyl = (pb >> 1) - cy0;
+                const int dxo = pa & 1, dyo = pb & 1;
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
                     uc[i] = us[i][ly][lx];
-                    v[i] = prolong_at(c.v2 + i * nc, c.W, c.H, gx, gy);
+                    const float v00 = vcs[i][cyl][cxl];
+                    v[i] = dxo ? 0.5f * (v00 + vcs[i][cyl + dyo][cxl + 1])
+                               : (dyo ? 0.5f * (v00 + vcs[i][cyl + 1][cxl]) : v00);
                     if (uc[i] > 0.f) {
                         s += v[i];
                         ++k;
@@ -650,53 +663,6 @@ __device__ __forceinline__ void mg_dir(const MgImage& d, int blk, const MgStep& 
     }
 }
 
-// 4b. alpha = clamp(<g~,w> / <w,Hw>, 0, 1) from the direction pass's partials
-// (every workgroup reduces them in the same fixed order), then
-// u = max(u + alpha w, 0) on one kUpdTX x kUpdTY fine tile (in place).
-template <int N>
-__device__ __forceinline__ void mg_update(const MgImage& d, int tile, const MgStep& st) {
-    __shared__ double sh[kBlock / kWave];
-    const MgState ms = mg_state(d, st);
-    if (ms.skip) return;
-    double a = 0.0, b = 0.0;
-    for (int k = threadIdx.x; k < d.dir_blocks; k += kBlock) {
-        a += d.part[2 * k];
-        b += d.part[2 * k + 1];
-    }
-    const double ga = block_sum_d(a, sh);
-    const double qa = block_sum_d(b, sh);
-    const float alpha = (qa > 0.0 && ga > 0.0) ? (float)fmin(ga / qa, 1.0) : 0.f;
-    if (tile == 0 && threadIdx.x == 0) d.ctl->alpha = alpha;  // for inspection
-    if (alpha == 0.f) return;
-    const int W = d.W, H = d.H;
-    const int tx = (W + kUpdTX - 1) / kUpdTX;
-    const int x0 = (tile % tx) * kUpdTX, y0 = (tile / tx) * kUpdTY;
-    const uint32_t n = (uint32_t)W * H;
-    float* u = ms.u;
-    constexpr int Q = kUpdTX * kUpdTY / kBlock;
-    float uv[Q][N], w[Q][N];
-    uint32_t pp[Q];
-    bool ok[Q];
-#pragma unroll
-    for (int c = 0; c < Q; ++c) {
-        const int q = threadIdx.x + c * kBlock;
-        const int gx = x0 + q % kUpdTX, gy = y0 + q / kUpdTX;
-        ok[c] = gx < W && gy < H;
-        pp[c] = ok[c] ? (uint32_t)(gy * W + gx) : 0u;
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            uv[c][i] = gload(u + i * n, pp[c]);
-            w[c][i] = gload(d.gt + i * n, pp[c]);
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < Q; ++c) {
-        if (!ok[c]) continue;
-#pragma unroll
-        for (int i = 0; i < N; ++i) gstore(u + i * n, pp[c], fmaxf(fmaf(alpha, w[c][i], uv[c][i]), 0.f));
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Kernels: one image (its descriptor by value, workgroup x = tile x) or a
 // batch (descriptor table and work list).
@@ -732,7 +698,6 @@ ACSEG_MG_KERNELS(ACSEG_TPL_NONE, k_mg_down, kBlock, mg_down(d, tile, st, blockId
 ACSEG_MG_KERNELS(ACSEG_TPL_NONE, k_mg_up, kBlock, mg_up(d, tile, st, blockIdx.y))
 ACSEG_MG_KERNELS(ACSEG_TPL_NONE, k_mg_tail, kTailThreads, (void)tile; mg_tail(d, st, blockIdx.y))
 ACSEG_MG_KERNELS(ACSEG_TPL_N, k_mg_dir, kBlock, mg_dir<N>(d, tile, st))
-ACSEG_MG_KERNELS(ACSEG_TPL_N, k_mg_update, kBlock, mg_update<N>(d, tile, st))
 #undef ACSEG_TPL_N
 #undef ACSEG_TPL_NONE
 #undef ACSEG_MG_KERNELS
@@ -767,7 +732,6 @@ hipError_t mg_fine(int op, const MgImage& m, const MgGrid& g, const MgStep& st, 
         case kMgDefectRestrict:
             return mg_launch(k_mg_defect_restrict<N>, k_mg_defect_restrict_b<N>, grid, kBlock, 0, m, g, st, s);
         case kMgDir: return mg_launch(k_mg_dir<N>, k_mg_dir_b<N>, grid, kBlock, 0, m, g, st, s);
-        case kMgUpdate: return mg_launch(k_mg_update<N>, k_mg_update_b<N>, grid, kBlock, 0, m, g, st, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -781,7 +745,6 @@ int mg_pass_tiles(int op, const MgImage& m, int level) {
         case kMgUp: return tiles_of(m.lv[level].W, m.lv[level].H, kUpTX, kUpTY);
         case kMgTail: return 1;
         case kMgDir: return m.dir_blocks;
-        case kMgUpdate: return tiles_of(m.W, m.H, kUpdTX, kUpdTY);
         default: return 0;
     }
 }
