@@ -358,6 +358,9 @@ __device__ __forceinline__ void mg_down(const MgImage& d, int tile, const MgStep
 
 __host__ __device__ inline int up_sx(int nu) { return kUpTX + 4 * nu; }
 __host__ __device__ inline int up_sy(int nu) { return kUpTY + 4 * nu; }
+// the coarser level's block that the prolongation reads for the staged nodes
+__host__ __device__ inline int up_cx(int nu) { return up_sx(nu) / 2 + 2; }
+__host__ __device__ inline int up_cy(int nu) { return up_sy(nu) / 2 + 2; }
 
 __device__ __forceinline__ void mg_up(const MgImage& d, int tile, const MgStep& st, int comp) {
     extern __shared__ __attribute__((aligned(16))) float lds[];
@@ -374,9 +377,22 @@ __device__ __forceinline__ void mg_up(const MgImage& d, int tile, const MgStep& 
     const uint32_t n = (uint32_t)W * H;
     float* rs = lds;
     float* vs = lds + SX * SY;
+    float* cs = lds + 2 * SX * SY;  // the coarser block, CX x CY
     const float* r = f.r + comp * n;
     const float* vd = f.v + comp * n;
     const float* vc = c.v2 + (size_t)comp * c.W * c.H;
+    const int CX = up_cx(nu), CY = up_cy(nu);
+    const int cx0 = max(sx0, 0) >> 1, cy0 = max(sy0, 0) >> 1;
+    if (!zero) {
+        for (int q = threadIdx.x; q < CX * CY; q += kBlock) {
+            const int qy = q / CX, qx = q - qy * CX;
+            const int X = cx0 + qx, Y = cy0 + qy;
+            const bool ok = X < c.W && Y < c.H;
+            const float t = gload(vc, ok ? (uint32_t)(Y * c.W + X) : 0u);
+            cs[q] = ok ? t : 0.f;
+        }
+        __syncthreads();
+    }
     const float inv = 1.0f / (float)SX;
     constexpr int CH = 4;  // staged nodes in flight per thread
     for (int base = 0; base < SX * SY; base += CH * kBlock) {
@@ -390,7 +406,15 @@ __device__ __forceinline__ void mg_up(const MgImage& d, int tile, const MgStep& 
             ok[k] = q < SX * SY && gx >= 0 && gx < W && gy >= 0 && gy < H;
             const uint32_t g = ok[k] ? (uint32_t)(gy * W + gx) : 0u;
             t[k] = gload(r, g);
-            v[k] = (ok[k] && !zero) ? gload(vd, g) + prolong_at(vc, c.W, c.H, gx, gy) : 0.f;
+            v[k] = (ok[k] && !zero) ? gload(vd, g) : 0.f;
+            if (ok[k] && !zero) {
+                // P v2 at (gx, gy) from the staged block (as prolong_at)
+                const int pa = min(gx, 2 * c.W - 2), pb = min(gy, 2 * c.H - 2);
+                const int o = ((pb >> 1) - cy0) * CX + ((pa >> 1) - cx0);
+                const int dxo = pa & 1, dyo = pb & 1;
+                const float c00 = cs[o];
+                v[k] += dxo ? 0.5f * (c00 + cs[o + dyo * CX + 1]) : (dyo ? 0.5f * (c00 + cs[o + CX]) : c00);
+            }
         }
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
@@ -756,12 +780,12 @@ size_t mg_tail_lds(const int* W, const int* H, int t, int L) {
 }
 
 size_t mg_lds_down(int nu) { return (size_t)2 * down_sx(nu) * down_sy(nu) * sizeof(float); }
-size_t mg_lds_up(int nu) { return (size_t)2 * up_sx(nu) * up_sy(nu) * sizeof(float); }
+size_t mg_lds_up(int nu) { return ((size_t)2 * up_sx(nu) * up_sy(nu) + (size_t)up_cx(nu) * up_cy(nu)) * sizeof(float); }
 
 size_t mg_pass_lds(int op, const MgImage& m, int sweeps) {
     switch (op) {
         case kMgDown: return (size_t)2 * down_sx(sweeps) * down_sy(sweeps) * sizeof(float);
-        case kMgUp: return (size_t)2 * up_sx(sweeps) * up_sy(sweeps) * sizeof(float);
+        case kMgUp: return mg_lds_up(sweeps);
         case kMgTail: {
             int W[kMaxLevels], H[kMaxLevels];
             for (int l = 1; l < m.L; ++l) {

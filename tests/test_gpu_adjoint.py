@@ -141,3 +141,29 @@ def test_differentiation_workload_at_full_size():
     g = gp.cpu().numpy()
     for k in range(3):
         assert abs(g[k] - grads[k]) <= 2e-3 * abs(grads[k]) + 1e-9, (k, g[k], grads[k])
+
+
+def test_remembered_sweep_budget_rerun_and_reuse():
+    """The context remembers the most adjoint sweeps a step of a problem took.
+    A zero loss gradient converges at once, so a first call leaves a budget of
+    two sweeps; a real gradient then needs more, runs again with host waits,
+    and a third call, on the budget it left, must give the same result bit
+    for bit (the sweeps after convergence do nothing)."""
+    w, p, img, u0, y = setup(False, 72, 56, 3, 3, 5, 50)
+    I = cuda(img)
+    u, _, st, ck = acseg.solve(p, I, cuda(u0), checkpoints=True)
+    assert st["status"] == acseg.OK, st
+    _, _, _, _, b0 = acseg.backward(p, I, ck, torch.zeros_like(u))
+    assert b0["status"] == acseg.OK and b0["cycles_max"] == 2, b0
+    gT = 2 * (u - cuda(y))
+    r1 = acseg.backward(p, I, ck, gT)
+    r2 = acseg.backward(p, I, ck, gT)
+    torch.cuda.synchronize()
+    assert r1[4]["cycles_max"] > 2, r1[4]  # the remembered budget was too small
+    assert r1[4] == r2[4], (r1[4], r2[4])
+    for a, b in zip(r1[:4], r2[:4]):
+        assert torch.equal(a, b)
+    P = orc.Params.from_workload(w, C=3, tol=1e-12, levels=1)
+    Ibar, grads, cbar, ubar0 = orc.backward(P, p.steps, img, host(ck), host(gT))
+    assert rel_err(host(r2[0]), Ibar) <= 2e-3
+    assert rel_err(host(r2[1]), ubar0) <= 2e-3
