@@ -470,8 +470,9 @@ def main():
                     help="fixed cycles per time step without a calibration solve (0: calibrate)")
     ap.add_argument("--nu", type=int, nargs=2, default=(1, 1), metavar=("PRE", "POST"),
                     help="smoothing sweeps before / after the coarse correction")
-    ap.add_argument("--vcycle-levels", type=int, default=8,
-                    help="also time the workload with this many multigrid levels, one image per call (0: skip)")
+    ap.add_argument("--vcycle-levels", type=int, default=-1,
+                    help="levels of the V-cycle solve timed beside a Gauss-Seidel bench line "
+                         "(-1: the workload's configured hierarchy; 0: none)")
     ap.add_argument("--no-graph", action="store_true",
                     help="time the batched segmentation eagerly only (default: also as a captured graph, "
                          "which gives `value`)")
@@ -642,8 +643,9 @@ def main():
     # the configuration's own hierarchy (config text: 8-level V-cycles), one image per
     # call, timed beside the headline: same converged steps, a coarse correction per cycle
     vcycle = None
-    if args.vcycle_levels and prob.levels == 1 and not args.pixel_units:
-        pv = acseg.Problem(**{**base.__dict__, "levels": args.vcycle_levels, "max_cycles": args.max_cycles})
+    vlevels = w.levels if args.vcycle_levels < 0 else args.vcycle_levels
+    if vlevels > 1 and prob.levels == 1 and not args.pixel_units:
+        pv = acseg.Problem(**{**base.__dict__, "levels": vlevels, "max_cycles": args.max_cycles})
         u.copy_(u0)
         _, _, stv, _ = acseg.solve(pv, prep(img), u)
         if stv["status"] != acseg.OK:
@@ -676,7 +678,7 @@ def main():
         _, _, stv3, _ = acseg.solve(pvd, prep(img), u)
         if stv3["status"] != acseg.OK:
             raise RuntimeError(f"V-cycle schedule with device exits did not converge: {stv3}")
-        vcycle = {"levels": args.vcycle_levels, "value": round(args.steps / tvd, 3), "unit": "segmentations/s",
+        vcycle = {"levels": vlevels, "value": round(args.steps / tvd, 3), "unit": "segmentations/s",
                   "ms_per_segmentation": round(tvd / args.steps * 1e3, 4), "batch": 1,
                   "schedule": "device exits (at most cycles_per_step_max cycles; the converged ones do nothing)",
                   "cycles_total": stv3["cycles_total"], "cycles_per_step_max": stv["cycles_max"],
@@ -684,7 +686,7 @@ def main():
                   "fixed_schedule": {"value": round(args.steps / tv, 3), "unit": "segmentations/s",
                                      "cycles_total": stv2["cycles_total"],
                                      "final_residual": stv2["final_residual"]}}
-        log(f"[bench] {args.vcycle_levels}-level V-cycles, one image per call: {args.steps} segmentations in "
+        log(f"[bench] {vlevels}-level V-cycles, one image per call: {args.steps} segmentations in "
             f"{tvd:.4f} s with device exits ({stv3['cycles_total']} cycles), {tv:.4f} s fixed")
 
     # the timed schedule converges: check it once with statistics
