@@ -43,13 +43,15 @@ HBM_PEAK_GBS = 8000.0
 # DRAM bytes per smoothing launch, (workload, images per launch) -> bytes:
 # rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
 # same counter reads for a 256 MiB device copy (FETCH x 2.000, WRITE x 1.000);
-# see profiles/k_cycle_voronoi1024_n4_batch8_traffic.md.  Measured on the
-# fixed one-cycle schedule of the default run (keyed by workload, batch,
-# cycles per step, levels, sweeps per cycle); must be re-measured whenever
-# the kernel changes (absent: null).
+# see profiles/k_cycle_voronoi1024_n4_batch8_traffic.md and
+# profiles/dram_per_kernel_hbm4096.md.  Measured on the fixed one-cycle
+# schedule's launches only (keyed by workload, batch, cycles per step, levels,
+# sweeps per cycle); must be re-measured whenever the kernel changes (absent:
+# null).
 TRAFFIC = {
     ("voronoi1024_n4", 8, 1, 1, 2): 374.67e6,
-    ("voronoi1024_n4", 1, 1, 1, 2): 64.24e6,
+    ("voronoi1024_n4", 1, 1, 1, 2): 48.96e6,
+    ("voronoi4096_n8", 1, 1, 1, 2): 1397.67e6,
 }
 
 
