@@ -1302,16 +1302,16 @@ acseg_status acseg_backward(acseg_ctx* ctx, const acseg_problem* p, const float*
             int sw = 0;
             if (spec > 0) {
                 for (; sw < spec; sw += K)
-                    ACSEG_TRY(timed(ctx, kFamAdjSweep, s, [&] { return launch_adj(N, C, kAdjSweep, a, 0, sw, s); }));
+                    ACSEG_TRY(timed(ctx, kFamAdjSweep, s, [&] { return launch_adj(N, C, kAdjSweep, a, sw, s); }));
             } else {
                 int chunk = 4;
                 while (true) {
                     const int end = std::min(a.max_sweeps, sw + chunk);
                     for (; sw < end; sw += K)
                         ACSEG_TRY(timed(ctx, kFamAdjSweep, s,
-                                        [&] { return launch_adj(N, C, kAdjSweep, a, 0, sw, s); }));
+                                        [&] { return launch_adj(N, C, kAdjSweep, a, sw, s); }));
                     if (sw >= a.max_sweeps) break;
-                    ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjCheck, a, 0, sw, s); }));
+                    ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjCheck, a, sw, s); }));
                     ACSEG_TRY(hipMemcpyAsync(ctx->host_actl, actl, sizeof(AdjCtl), hipMemcpyDeviceToHost, s));
                     ACSEG_TRY(hipStreamSynchronize(s));
                     if (ctx->host_actl->done) break;
@@ -1319,8 +1319,8 @@ acseg_status acseg_backward(acseg_ctx* ctx, const acseg_problem* p, const float*
                 }
             }
             a.budget = sw;
-            ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjAccum, a, 0, 0, s); }));
-            ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjReduce, a, 0, 0, s); }));
+            ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjAccum, a, 0, s); }));
+            ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjReduce, a, 0, s); }));
             ub = a.ub_out;
             // this step's means share goes to the next step's launches (fixed
             // means depend on neither u^n nor the image: no share)
@@ -1335,7 +1335,7 @@ acseg_status acseg_backward(acseg_ctx* ctx, const acseg_problem* p, const float*
             a.u0 = checkpoints;
             a.ub = ub;
             a.ub_out = grad_u0;
-            ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjFinal, a, 0, 0, s); }));
+            ACSEG_TRY(timed(ctx, kFamOther, s, [&] { return launch_adj(N, C, kAdjFinal, a, 0, s); }));
         } else if (grad_u0) {
             ACSEG_TRY(hipMemcpyAsync(grad_u0, ub, sizeof(float) * nu, hipMemcpyDeviceToDevice, s));
         }

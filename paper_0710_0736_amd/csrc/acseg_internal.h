@@ -374,7 +374,7 @@ struct AdjArgs {
 int adj_sweep_blocks(int W, int H);
 int adj_accum_blocks(int N, int C, int W, int H);
 int adj_sweeps_per_launch();
-hipError_t launch_adj(int N, int C, int op, const AdjArgs& a, int colour, int sweep, hipStream_t s);
+hipError_t launch_adj(int N, int C, int op, const AdjArgs& a, int sweep, hipStream_t s);
 hipError_t launch_adj_init(AdjCtl* ac, double* grads, hipStream_t s);
 
 // Initialise a control block (cur = initial buffer index).

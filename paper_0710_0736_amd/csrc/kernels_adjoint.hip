@@ -584,7 +584,7 @@ int adj_blocks(int64_t n, int threads, int cap) {
 }
 
 template <int N, int C>
-hipError_t adj_nc(int op, const AdjArgs& a, int colour, int sweep, hipStream_t s) {
+hipError_t adj_nc(int op, const AdjArgs& a, int sweep, hipStream_t s) {
     const int64_t n = (int64_t)a.W * a.H;
     switch (op) {
         case kAdjSweep:
@@ -604,12 +604,12 @@ hipError_t adj_nc(int op, const AdjArgs& a, int colour, int sweep, hipStream_t s
 }
 
 template <int N>
-hipError_t adj_n(int C, int op, const AdjArgs& a, int colour, int sweep, hipStream_t s) {
+hipError_t adj_n(int C, int op, const AdjArgs& a, int sweep, hipStream_t s) {
     switch (C) {
-        case 1: return adj_nc<N, 1>(op, a, colour, sweep, s);
-        case 2: return adj_nc<N, 2>(op, a, colour, sweep, s);
-        case 3: return adj_nc<N, 3>(op, a, colour, sweep, s);
-        case 4: return adj_nc<N, 4>(op, a, colour, sweep, s);
+        case 1: return adj_nc<N, 1>(op, a, sweep, s);
+        case 2: return adj_nc<N, 2>(op, a, sweep, s);
+        case 3: return adj_nc<N, 3>(op, a, sweep, s);
+        case 4: return adj_nc<N, 4>(op, a, sweep, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -622,15 +622,15 @@ int adj_accum_blocks(int N, int C, int W, int H) {
 }
 int adj_sweeps_per_launch() { return kAdjK; }
 
-hipError_t launch_adj(int N, int C, int op, const AdjArgs& a, int colour, int sweep, hipStream_t s) {
+hipError_t launch_adj(int N, int C, int op, const AdjArgs& a, int sweep, hipStream_t s) {
     switch (N) {
-        case 2: return adj_n<2>(C, op, a, colour, sweep, s);
-        case 3: return adj_n<3>(C, op, a, colour, sweep, s);
-        case 4: return adj_n<4>(C, op, a, colour, sweep, s);
-        case 5: return adj_n<5>(C, op, a, colour, sweep, s);
-        case 6: return adj_n<6>(C, op, a, colour, sweep, s);
-        case 7: return adj_n<7>(C, op, a, colour, sweep, s);
-        case 8: return adj_n<8>(C, op, a, colour, sweep, s);
+        case 2: return adj_n<2>(C, op, a, sweep, s);
+        case 3: return adj_n<3>(C, op, a, sweep, s);
+        case 4: return adj_n<4>(C, op, a, sweep, s);
+        case 5: return adj_n<5>(C, op, a, sweep, s);
+        case 6: return adj_n<6>(C, op, a, sweep, s);
+        case 7: return adj_n<7>(C, op, a, sweep, s);
+        case 8: return adj_n<8>(C, op, a, sweep, s);
         default: return hipErrorInvalidValue;
     }
 }
