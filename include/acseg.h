@@ -159,7 +159,9 @@ typedef int32_t acseg_status;
  *           (multigrid) -- with levels == 1, nu_pre + nu_post red-black
  *           sweeps form one cycle; each >= 0, sum >= 1.  With two or more
  *           levels both must be >= 1 (ACSEG_ERR_UNSUPPORTED otherwise); the
- *           coarse levels use the same counts and the coarsest level 8 sweeps
+ *           coarse levels use the same counts; the coarsest level runs as
+ *           many red-black sweeps from zero as its Jacobi contraction bound
+ *           needs for FP32 rounding, at most 8
  *   max_cycles  cycle budget per time step; >= 1
  *   tol     natural-residual tolerance (max norm, absolute); >= 0
  */

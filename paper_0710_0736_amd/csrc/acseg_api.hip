@@ -117,7 +117,7 @@ acseg_status validate(const acseg_problem* p, bool need_steps) {
 // kTailSide and whose tail fits in kTailLds bytes of LDS, and every coarser
 // one) run in the LDS tail kernel; tail == L when none does.
 struct MgPlan {
-    int L = 1, tail = 1;
+    int L = 1, tail = 1, coarse_sweeps = kCoarseSweeps;
     int W[kMaxLevels], H[kMaxLevels];
     LevelCoef coef[kMaxLevels];
 };
@@ -139,6 +139,23 @@ LevelCoef level_coef(const acseg_problem* p, int l) {
     return c;
 }
 
+// Red-black sweeps that solve the coarsest level to FP32 rounding, at most
+// kCoarseSweeps.  The level's matrix is strictly diagonally dominant, so one
+// Gauss-Seidel sweep shrinks the error's max norm at least by the Jacobi bound
+// rho = max_k kappa_k a_k (a_k: the sum of the neighbour weights of node class
+// k, equal to its stiffness diagonal); from v = 0, rho^s <= 2^-24 after s
+// sweeps.  With a large mass term (coarse spacing, short time step) rho is
+// tiny and one to three sweeps do.
+int coarse_sweeps_of(const LevelCoef& c) {
+    static const double a[4] = {4.0, 2.0, 1.0, 1.0};
+    double rho = 0.0;
+    for (int k = 0; k < 4; ++k) rho = std::max(rho, (double)c.kappa[k] * a[k]);
+    if (!(rho > 0.0)) return 1;
+    if (rho >= 1.0) return kCoarseSweeps;
+    const double s = ceil(24.0 * log(2.0) / -log(rho));
+    return (int)std::min<double>(std::max(s, 1.0), kCoarseSweeps);
+}
+
 MgPlan plan_of(const acseg_problem* p) {
     MgPlan m;
     m.L = std::min(p->levels == 0 ? auto_levels(p->W, p->H) : p->levels, kMaxLevels);
@@ -151,6 +168,7 @@ MgPlan plan_of(const acseg_problem* p) {
         }
         m.coef[l] = level_coef(p, l);
     }
+    m.coarse_sweeps = coarse_sweeps_of(m.coef[m.L - 1]);
     m.tail = m.L;
     for (int l = 1; l < m.L; ++l)
         if (m.W[l] <= kTailSide && m.H[l] <= kTailSide && mg_tail_lds(m.W, m.H, l, m.L) <= (size_t)kTailLds) {
@@ -290,6 +308,7 @@ MgImage mg_image_of(const acseg_problem* p, const MgPlan& m, const Layout& L, vo
     d.L = m.L;
     d.tail = m.tail;
     d.dir_blocks = dir_blocks(p->W, p->H);
+    d.coarse_sweeps = m.coarse_sweeps;
     d.fine = m.coef[0];
     for (int l = 1; l < m.L; ++l) {
         MgLevel& v = d.lv[l];
@@ -320,7 +339,7 @@ std::vector<MgPassRec> mg_passes(const MgPlan& m, int nu_pre, int nu_post) {
     if (m.tail < m.L)
         v.push_back({kMgTail, m.tail, 0, 0});
     else
-        v.push_back({kMgUp, m.L - 1, kCoarseSweeps, 1});
+        v.push_back({kMgUp, m.L - 1, m.coarse_sweeps, 1});
     for (int l = down_end - 1; l >= 1; --l) v.push_back({kMgUp, l, nu_post, 0});
     v.push_back({kMgDir, 0, 0, 0});
     return v;

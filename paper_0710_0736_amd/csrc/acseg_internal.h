@@ -207,7 +207,7 @@ hipError_t launch_means_from_tot(int N, int C, const double* tot, const double* 
 constexpr int kMgBlocks = 1024;    // most workgroups of a pass with per-workgroup partials
 constexpr int kTailSide = 64;      // levels with both sides <= this may run in the LDS tail
 constexpr int kTailLds = 64 * 1024;   // LDS bytes the tail may use
-constexpr int kCoarseSweeps = 8;   // red-black sweeps on the coarsest level
+constexpr int kCoarseSweeps = 8;   // most red-black sweeps on the coarsest level
 constexpr int kMaxLevels = 16;     // lattice levels of a hierarchy (sides up to 2^15)
 
 // Tiles of the multigrid passes.
@@ -244,6 +244,7 @@ struct MgImage {
     int N, W, H;        // finest level
     int L, tail;
     int dir_blocks;     // workgroups of the direction pass (partials to reduce)
+    int coarse_sweeps;  // red-black sweeps on the coarsest level
     LevelCoef fine;
     MgLevel lv[kMaxLevels];  // lv[1..L-1]
 };
@@ -260,8 +261,8 @@ struct MgStep {
 // Where a multigrid launch's workgroups come from: one image (descs == NULL:
 // workgroup x is tile x of `single`, at st.level) or a batch (work[x] =
 // (image, tile, level, zero): an up pass item with zero set starts from v = 0
-// with kCoarseSweeps sweeps, the coarsest level of an image without an LDS
-// tail).  blockIdx.y selects the component of componentwise passes.
+// with the image's coarse_sweeps sweeps, the coarsest level of an image
+// without an LDS tail).  blockIdx.y selects the component of componentwise passes.
 struct MgGrid {
     const MgImage* descs;
     const int4* work;

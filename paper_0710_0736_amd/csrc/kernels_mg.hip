@@ -17,9 +17,10 @@
 //      in one workgroup per component;
 //   4. direction w_p = Pi(u_p + T_I (P v_1)_p) - u_p (feasible, since the
 //      simplex is convex), and the exact line search on the step's quadratic
-//      along w: alpha = clamp(<g~, w> / <w, H w>, 0, 1), u += alpha w.  The
-//      direction pass also forms the two dot products (the last workgroup
-//      to finish reduces them to alpha), and the update is a pass of its own.
+//      along w: alpha = clamp(<g~, w> / <w, H w>, 0, 1), u += alpha w.  Each
+//      workgroup of the direction pass leaves its partial sums of the two
+//      dot products; the post-smoothing launch reduces them to alpha and
+//      applies the update as it stages u.
 //      w vanishes on the active components and sums to zero over the free
 //      ones at every node, so <g, w> = <g~, w>; the truncated form keeps the
 //      per-node multiplier of the sum constraint out of the dot product.
@@ -49,10 +50,9 @@ __device__ __forceinline__ float prolong_at(const float* __restrict__ vc, int Wc
     const int X = a >> 1, Y = b >> 1;
     const float* r0 = vc + (int64_t)Y * Wc + X;
     const int ao = a & 1, bo = b & 1;
-    if (!ao && !bo) return r0[0];
-    if (ao && !bo) return 0.5f * (r0[0] + r0[1]);
-    if (!ao && bo) return 0.5f * (r0[0] + r0[Wc]);
-    return 0.5f * (r0[0] + r0[Wc + 1]);
+    // the second coarse node: right, below, or along the diagonal (itself on a coarse node)
+    const float r1 = r0[ao * (bo ? Wc + 1 : 1) + (ao ? 0 : bo * Wc)];
+    return (ao | bo) ? 0.5f * (r0[0] + r1) : r0[0];
 }
 
 // Visit the fine nodes that prolong_at lets coarse node (X, Y) reach, with
@@ -445,7 +445,8 @@ __device__ __forceinline__ void mg_up(const MgImage& d, int tile, const MgStep& 
 // ---------------------------------------------------------------------------
 // 3b. LDS tail: the V-cycle over levels t = tail .. L-1 (sides <= kTailSide)
 // of one component in one workgroup of kTailThreads, v and r of every level
-// in LDS.  Residuals are restricted as they are computed.  The levels' sizes,
+// in LDS.  A restriction first writes the fine level's residual to an LDS
+// scratch, then every coarse node gathers from it.  The levels' sizes,
 // coefficients and LDS offsets are copied to LDS once, so the dozens of
 // steps that follow read them there instead of waiting on scalar loads of the
 // descriptor.  The result v_t goes to v2 of level t.
@@ -457,54 +458,103 @@ struct TailLevel {
     int pad;
 };
 
-__device__ __forceinline__ float lattice_nb(const float* __restrict__ v, int W, int H, int x, int y, int p) {
-    return edge_w_h(y, H) * ((x > 0 ? v[p - 1] : 0.f) + (x < W - 1 ? v[p + 1] : 0.f)) +
-           edge_w_v(x, W) * ((y > 0 ? v[p - W] : 0.f) + (y < H - 1 ? v[p + W] : 0.f));
+// A level's coefficients per node class, read once into wave-uniform registers.
+struct TailCoef {
+    float kappa[4], inv_d[4], d[4], e2;
+};
+
+__device__ __forceinline__ TailCoef tail_coef(const LevelCoef& c) {
+    TailCoef t;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        t.kappa[k] = uniform_f(c.kappa[k]);
+        t.inv_d[k] = uniform_f(c.inv_d[k]);
+        t.d[k] = uniform_f(c.d[k]);
+    }
+    t.e2 = uniform_f(c.e2);
+    return t;
 }
 
+__device__ __forceinline__ float pick4(const float (&a)[4], int k) {
+    return k == 0 ? a[0] : (k == 1 ? a[1] : (k == 2 ? a[2] : a[3]));
+}
+
+// sum_q c_pq v_q over the lattice neighbours of node (x, y) at p, without
+// branches: a missing neighbour's read takes the node itself (in bounds) and a
+// select drops it, so the waves that hold boundary nodes do not diverge.
+__device__ __forceinline__ float lattice_nb(const float* __restrict__ v, int W, int H, int x, int y, int p) {
+    const bool lf = x > 0, rt = x < W - 1, up = y > 0, dn = y < H - 1;
+    const float a = v[lf ? p - 1 : p], b = v[rt ? p + 1 : p];
+    const float c = v[up ? p - W : p], e = v[dn ? p + W : p];
+    return edge_w_h(y, H) * ((lf ? a : 0.f) + (rt ? b : 0.f)) + edge_w_v(x, W) * ((up ? c : 0.f) + (dn ? e : 0.f));
+}
+
+// The nodes of `colour` ((x + y) & 1) of a W x H level: v = r / D + kappa
+// sum_q c_pq v_q (zero: v is 0 beforehand, so v = r / D).  Lanes `lane`,
+// lane + T, ... of the T threads that take part.
+template <int T>
 __device__ __forceinline__ void tail_half(float* __restrict__ v, const float* __restrict__ r, int W, int H,
-                                          const LevelCoef c, int colour, bool zero) {
+                                          const TailCoef& c, int colour, bool zero, int lane) {
     const int hw = (W + 1) / 2;
     const float inv = 1.0f / (float)hw;
-    const float k0 = uniform_f(c.kappa[0]), i0 = uniform_f(c.inv_d[0]);
-    for (int q = threadIdx.x; q < hw * H; q += kTailThreads) {
+    for (int q = lane; q < hw * H; q += T) {
         const int y = fdiv(q, inv), j = q - y * hw;
         const int x = 2 * j + ((y + colour) & 1);
         if (x >= W) continue;
         const int p = y * W + x;
-        if (zero) {
-            v[p] = r[p] * sel4(c.inv_d, node_class(x, y, W, H));
-        } else if (y > 0 && y < H - 1 && x > 0 && x < W - 1) {
-            v[p] = fmaf(k0, (v[p - 1] + v[p + 1]) + (v[p - W] + v[p + W]), r[p] * i0);
-        } else {
-            const int cls = node_class(x, y, W, H);
-            v[p] = fmaf(sel4(c.kappa, cls), lattice_nb(v, W, H, x, y, p), r[p] * sel4(c.inv_d, cls));
+        const int cls = node_class(x, y, W, H);
+        const float rd = r[p] * pick4(c.inv_d, cls);
+        if (zero)
+            v[p] = rd;
+        else
+            v[p] = fmaf(pick4(c.kappa, cls), lattice_nb(v, W, H, x, y, p), rd);
+    }
+}
+
+__device__ __forceinline__ void tail_sweeps(float* v, const float* r, int W, int H, const TailCoef& c, int sweeps,
+                                            bool zero) {
+    for (int s = 0; s < sweeps; ++s) {
+        tail_half<kTailThreads>(v, r, W, H, c, 0, zero && s == 0, threadIdx.x);
+        __syncthreads();
+        tail_half<kTailThreads>(v, r, W, H, c, 1, false, threadIdx.x);
+        __syncthreads();
+    }
+}
+
+// The same sweeps on a small level by wavefront 0 alone.  The LDS accesses of
+// one wavefront take effect in the order it issues them, so its half-sweeps
+// need no workgroup barrier between them, only a fence that keeps the compiler
+// from moving LDS accesses across.
+constexpr int kTailWaveNodes = 256;
+
+__device__ __forceinline__ void tail_sweeps_wave(float* v, const float* r, int W, int H, const TailCoef& c,
+                                                 int sweeps, bool zero) {
+    if (threadIdx.x < kWave) {
+        for (int s = 0; s < sweeps; ++s) {
+            tail_half<kWave>(v, r, W, H, c, 0, zero && s == 0, threadIdx.x);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            tail_half<kWave>(v, r, W, H, c, 1, false, threadIdx.x);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         }
     }
     __syncthreads();
 }
 
-__device__ __forceinline__ void tail_sweeps(float* v, const float* r, int W, int H, const LevelCoef c, int sweeps,
-                                            bool zero) {
-    for (int s = 0; s < sweeps; ++s) {
-        tail_half(v, r, W, H, c, 0, zero && s == 0);
-        tail_half(v, r, W, H, c, 1, false);
-    }
-}
-
-// rc = P^T (r - H v) from level (W, H) to (Wc, Hc).
+// rc = P^T (r - H v) from level (W, H) to (Wc, Hc): the residual of every fine
+// node goes to s, then every coarse node sums its weighted fine nodes from s.
 __device__ __forceinline__ void tail_resid_restrict(const float* __restrict__ v, const float* __restrict__ r,
-                                                    int W, int H, const LevelCoef c, float* __restrict__ rc,
-                                                    int Wc, int Hc) {
-    const float inv = 1.0f / (float)Wc;
+                                                    int W, int H, const TailCoef& c, float* __restrict__ rc,
+                                                    int Wc, int Hc, float* __restrict__ s) {
+    const float inv = 1.0f / (float)W;
+    for (int q = threadIdx.x; q < W * H; q += kTailThreads) {
+        const int y = fdiv(q, inv), x = q - y * W;
+        s[q] = r[q] - (pick4(c.d, node_class(x, y, W, H)) * v[q] - c.e2 * lattice_nb(v, W, H, x, y, q));
+    }
+    __syncthreads();
+    const float invc = 1.0f / (float)Wc;
     for (int q = threadIdx.x; q < Wc * Hc; q += kTailThreads) {
-        const int Y = fdiv(q, inv), X = q - Y * Wc;
-        float sum = 0.f;
-        for_restrict(W, H, Wc, Hc, X, Y, [&](int x, int y, float wt) {
-            const int p = y * W + x;
-            sum += wt * (r[p] - (sel4(c.d, node_class(x, y, W, H)) * v[p] - c.e2 * lattice_nb(v, W, H, x, y, p)));
-        });
-        rc[q] = sum;
+        const int Y = fdiv(q, invc), X = q - Y * Wc;
+        rc[q] = restrict_at(s, W, H, Wc, Hc, X, Y);
     }
     __syncthreads();
 }
@@ -519,47 +569,71 @@ __device__ __forceinline__ void tail_prolong_add(float* __restrict__ v, int W, i
     __syncthreads();
 }
 
+// Level t's r is read into registers before anything else (the workgroup's
+// kTailPre loads per thread overlap the convergence check and the descriptor
+// copy); levels tail..L-1 then follow in LDS, then the residual scratch s.
+constexpr int kTailPre = (kTailSide * kTailSide + kTailThreads - 1) / kTailThreads;
+
 __device__ __forceinline__ void mg_tail(const MgImage& d, const MgStep& st, int comp) {
     extern __shared__ __attribute__((aligned(16))) float lds[];
     __shared__ TailLevel tl[kMaxLevels];
-    if (comp >= d.N || mg_skip(d, st)) return;
+    if (comp >= d.N) return;
     const int t = d.tail, L = d.L;
-    if (threadIdx.x == 0) {
-        int off = 0;
-        for (int l = t; l < L; ++l) {
+    const int Wt = d.lv[t].W, Ht = d.lv[t].H;
+    const uint32_t nt = (uint32_t)Wt * Ht;
+    float pre[kTailPre];
+    {
+        const float* rt = d.lv[t].r + comp * nt;
+#pragma unroll
+        for (int k = 0; k < kTailPre; ++k) {
+            const uint32_t q = threadIdx.x + k * kTailThreads;
+            pre[k] = q < nt ? gload(rt, q) : 0.f;
+        }
+    }
+    if (mg_skip(d, st)) return;
+    int off = 0;
+    for (int l = t; l < L; ++l) {
+        if (threadIdx.x == 0) {
             tl[l].coef = d.lv[l].coef;
             tl[l].W = d.lv[l].W;
             tl[l].H = d.lv[l].H;
             tl[l].off = off;
-            off += 2 * d.lv[l].W * d.lv[l].H;
         }
+        off += 2 * d.lv[l].W * d.lv[l].H;
     }
-    const int Wt = d.lv[t].W, Ht = d.lv[t].H;
-    const uint32_t nt = (uint32_t)Wt * Ht;
+    float* const s = lds + off;
     {
-        const float* rt = d.lv[t].r + comp * nt;
         float* r0 = lds + nt;  // level t's v starts at offset 0
-        for (int q = threadIdx.x; q < (int)nt; q += kTailThreads) r0[q] = gload(rt, (uint32_t)q);
+#pragma unroll
+        for (int k = 0; k < kTailPre; ++k) {
+            const uint32_t q = threadIdx.x + k * kTailThreads;
+            if (q < nt) r0[q] = pre[k];
+        }
         __syncthreads();
     }
     for (int l = t; l < L; ++l) {  // down
         const TailLevel& g = tl[l];
+        const TailCoef c = tail_coef(g.coef);
         float* v = lds + g.off;
         float* r = v + g.W * g.H;
         if (l == L - 1) {
-            tail_sweeps(v, r, g.W, g.H, g.coef, kCoarseSweeps, true);
+            if (g.W * g.H <= kTailWaveNodes)
+                tail_sweeps_wave(v, r, g.W, g.H, c, d.coarse_sweeps, true);
+            else
+                tail_sweeps(v, r, g.W, g.H, c, d.coarse_sweeps, true);
         } else {
-            tail_sweeps(v, r, g.W, g.H, g.coef, st.nu_pre, true);
-            const TailLevel& c = tl[l + 1];
-            tail_resid_restrict(v, r, g.W, g.H, g.coef, lds + c.off + c.W * c.H, c.W, c.H);
+            tail_sweeps(v, r, g.W, g.H, c, st.nu_pre, true);
+            const TailLevel& n = tl[l + 1];
+            tail_resid_restrict(v, r, g.W, g.H, c, lds + n.off + n.W * n.H, n.W, n.H, s);
         }
     }
     for (int l = L - 2; l >= t; --l) {  // up
         const TailLevel& g = tl[l];
-        const TailLevel& c = tl[l + 1];
+        const TailLevel& n = tl[l + 1];
+        const TailCoef c = tail_coef(g.coef);
         float* v = lds + g.off;
-        tail_prolong_add(v, g.W, g.H, lds + c.off, c.W, c.H);
-        tail_sweeps(v, v + g.W * g.H, g.W, g.H, g.coef, st.nu_post, false);
+        tail_prolong_add(v, g.W, g.H, lds + n.off, n.W, n.H);
+        tail_sweeps(v, v + g.W * g.H, g.W, g.H, c, st.nu_post, false);
     }
     float* out = d.lv[t].v2 + comp * nt;
     for (int q = threadIdx.x; q < (int)nt; q += kTailThreads) gstore(out, (uint32_t)q, lds[q]);
@@ -711,7 +785,7 @@ __device__ __forceinline__ void mg_dir(const MgImage& d, int blk, const MgStep& 
         MgStep st = sb;                                                                      \
         st.level = wv.z;                                                                     \
         st.zero = wv.w;                                                                      \
-        if (wv.w) st.sweeps = kCoarseSweeps;                                                 \
+        if (wv.w) st.sweeps = d.coarse_sweeps;                                               \
         BODY;                                                                                \
     }
 
@@ -774,7 +848,8 @@ int mg_pass_tiles(int op, const MgImage& m, int level) {
 }
 
 size_t mg_tail_lds(const int* W, const int* H, int t, int L) {
-    size_t f = 0;
+    if (t >= L) return 0;
+    size_t f = (size_t)W[t] * H[t];  // residual scratch
     for (int l = t; l < L; ++l) f += (size_t)W[l] * H[l] * 2;
     return f * sizeof(float);
 }
