@@ -29,6 +29,7 @@
 // D_p (y_p - u_p) with y_p the nodal map of the smoother.  The stored
 // right-hand side is shifted per node by a constant vector, which T_I removes.
 #include <algorithm>
+#include <atomic>
 
 #include "acseg_internal.h"
 
@@ -282,6 +283,7 @@ __host__ __device__ inline int down_halo(int nu) { return 2 * nu + 1; }
 __host__ __device__ inline int down_sx(int nu) { return 2 * kDnTX + 1 + 2 * down_halo(nu); }
 __host__ __device__ inline int down_sy(int nu) { return 2 * kDnTY + 1 + 2 * down_halo(nu); }
 
+template <int T>
 __device__ __forceinline__ void mg_down(const MgImage& d, int tile, const MgStep& st, int comp) {
     extern __shared__ __attribute__((aligned(16))) float lds[];
     const int l = st.level, nu = st.sweeps;
@@ -298,13 +300,13 @@ __device__ __forceinline__ void mg_down(const MgImage& d, int tile, const MgStep
     float* vs = lds + SX * SY;
     const float* r = f.r + comp * n;
     const float inv = 1.0f / (float)SX;
-    constexpr int CH = 8;  // loads in flight per thread
-    for (int base = 0; base < SX * SY; base += CH * kBlock) {
+    constexpr int CH = T >= 1024 ? 4 : 8;  // loads in flight per thread (one or two rounds for nu <= 2)
+    for (int base = 0; base < SX * SY; base += CH * T) {
         float t[CH];
         bool ok[CH];
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
-            const int q = base + k * kBlock + threadIdx.x;
+            const int q = base + k * T + threadIdx.x;
             const int ly = fdiv(q, inv), lx = q - ly * SX;
             const int gx = sx0 + lx, gy = sy0 + ly;
             ok[k] = q < SX * SY && gx >= 0 && gx < W && gy >= 0 && gy < H;
@@ -312,7 +314,7 @@ __device__ __forceinline__ void mg_down(const MgImage& d, int tile, const MgStep
         }
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
-            const int q = base + k * kBlock + threadIdx.x;
+            const int q = base + k * T + threadIdx.x;
             if (q < SX * SY) {
                 rs[q] = ok[k] ? t[k] : 0.f;
                 vs[q] = 0.f;
@@ -323,13 +325,13 @@ __device__ __forceinline__ void mg_down(const MgImage& d, int tile, const MgStep
     for (int h = 0; h < 2 * nu; ++h) {
         __syncthreads();
         if (in)
-            block_half<kBlock, true>(vs, rs, SX, SY, sx0, sy0, W, H, f.coef, h & 1);
+            block_half<T, true>(vs, rs, SX, SY, sx0, sy0, W, H, f.coef, h & 1);
         else
-            block_half<kBlock, false>(vs, rs, SX, SY, sx0, sy0, W, H, f.coef, h & 1);
+            block_half<T, false>(vs, rs, SX, SY, sx0, sy0, W, H, f.coef, h & 1);
     }
     __syncthreads();
     // r_{l+1} = P^T (r - H v) on this workgroup's level-(l+1) nodes
-    for (int q = threadIdx.x; q < kDnTX * kDnTY; q += kBlock) {
+    for (int q = threadIdx.x; q < kDnTX * kDnTY; q += T) {
         const int X = X0 + q % kDnTX, Y = Y0 + q / kDnTX;
         if (X >= Wc || Y >= Hc) continue;
         float sum = 0.f;
@@ -340,7 +342,7 @@ __device__ __forceinline__ void mg_down(const MgImage& d, int tile, const MgStep
     }
     // v of the owned level-l nodes
     float* v = f.v + comp * n;
-    for (int q = threadIdx.x; q < 4 * kDnTX * kDnTY; q += kBlock) {
+    for (int q = threadIdx.x; q < 4 * kDnTX * kDnTY; q += T) {
         const int ox = q % (2 * kDnTX), oy = q / (2 * kDnTX);
         const int gx = 2 * X0 + ox, gy = 2 * Y0 + oy;
         if (gx >= W || gy >= H) continue;
@@ -362,6 +364,7 @@ __host__ __device__ inline int up_sy(int nu) { return kUpTY + 4 * nu; }
 __host__ __device__ inline int up_cx(int nu) { return up_sx(nu) / 2 + 2; }
 __host__ __device__ inline int up_cy(int nu) { return up_sy(nu) / 2 + 2; }
 
+template <int T>
 __device__ __forceinline__ void mg_up(const MgImage& d, int tile, const MgStep& st, int comp) {
     extern __shared__ __attribute__((aligned(16))) float lds[];
     const int l = st.level, nu = st.sweeps;
@@ -384,7 +387,7 @@ __device__ __forceinline__ void mg_up(const MgImage& d, int tile, const MgStep& 
     const int CX = up_cx(nu), CY = up_cy(nu);
     const int cx0 = max(sx0, 0) >> 1, cy0 = max(sy0, 0) >> 1;
     if (!zero) {
-        for (int q = threadIdx.x; q < CX * CY; q += kBlock) {
+        for (int q = threadIdx.x; q < CX * CY; q += T) {
             const int qy = q / CX, qx = q - qy * CX;
             const int X = cx0 + qx, Y = cy0 + qy;
             const bool ok = X < c.W && Y < c.H;
@@ -394,13 +397,13 @@ __device__ __forceinline__ void mg_up(const MgImage& d, int tile, const MgStep& 
         __syncthreads();
     }
     const float inv = 1.0f / (float)SX;
-    constexpr int CH = 4;  // staged nodes in flight per thread
-    for (int base = 0; base < SX * SY; base += CH * kBlock) {
+    constexpr int CH = T >= 1024 ? 2 : 4;  // staged nodes in flight per thread (one or two rounds for nu <= 2)
+    for (int base = 0; base < SX * SY; base += CH * T) {
         float t[CH], v[CH];
         bool ok[CH];
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
-            const int q = base + k * kBlock + threadIdx.x;
+            const int q = base + k * T + threadIdx.x;
             const int ly = fdiv(q, inv), lx = q - ly * SX;
             const int gx = sx0 + lx, gy = sy0 + ly;
             ok[k] = q < SX * SY && gx >= 0 && gx < W && gy >= 0 && gy < H;
@@ -418,7 +421,7 @@ __device__ __forceinline__ void mg_up(const MgImage& d, int tile, const MgStep& 
         }
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
-            const int q = base + k * kBlock + threadIdx.x;
+            const int q = base + k * T + threadIdx.x;
             if (q < SX * SY) {
                 rs[q] = ok[k] ? t[k] : 0.f;
                 vs[q] = v[k];
@@ -429,13 +432,13 @@ __device__ __forceinline__ void mg_up(const MgImage& d, int tile, const MgStep& 
     for (int h = 0; h < 2 * nu; ++h) {
         __syncthreads();
         if (in)
-            block_half<kBlock, true>(vs, rs, SX, SY, sx0, sy0, W, H, f.coef, h & 1);
+            block_half<T, true>(vs, rs, SX, SY, sx0, sy0, W, H, f.coef, h & 1);
         else
-            block_half<kBlock, false>(vs, rs, SX, SY, sx0, sy0, W, H, f.coef, h & 1);
+            block_half<T, false>(vs, rs, SX, SY, sx0, sy0, W, H, f.coef, h & 1);
     }
     __syncthreads();
     float* v2 = f.v2 + comp * n;
-    for (int q = threadIdx.x; q < kUpTX * kUpTY; q += kBlock) {
+    for (int q = threadIdx.x; q < kUpTX * kUpTY; q += T) {
         const int gx = x0 + q % kUpTX, gy = y0 + q / kUpTX;
         if (gx >= W || gy >= H) continue;
         gstore(v2, (uint32_t)(gy * W + gx), vs[(gy - sy0) * SX + (gx - sx0)]);
@@ -791,13 +794,15 @@ __device__ __forceinline__ void mg_dir(const MgImage& d, int blk, const MgStep& 
 
 #define ACSEG_TPL_N template <int N>
 #define ACSEG_TPL_NONE
+#define ACSEG_TPL_T template <int T>
 ACSEG_MG_KERNELS(ACSEG_TPL_N, k_mg_defect_restrict, kBlock, mg_defect_restrict<N>(d, tile, st))
-ACSEG_MG_KERNELS(ACSEG_TPL_NONE, k_mg_down, kBlock, mg_down(d, tile, st, blockIdx.y))
-ACSEG_MG_KERNELS(ACSEG_TPL_NONE, k_mg_up, kBlock, mg_up(d, tile, st, blockIdx.y))
+ACSEG_MG_KERNELS(ACSEG_TPL_T, k_mg_down, T, mg_down<T>(d, tile, st, blockIdx.y))
+ACSEG_MG_KERNELS(ACSEG_TPL_T, k_mg_up, T, mg_up<T>(d, tile, st, blockIdx.y))
 ACSEG_MG_KERNELS(ACSEG_TPL_NONE, k_mg_tail, kTailThreads, (void)tile; mg_tail(d, st, blockIdx.y))
 ACSEG_MG_KERNELS(ACSEG_TPL_N, k_mg_dir, kBlock, mg_dir<N>(d, tile, st))
 #undef ACSEG_TPL_N
 #undef ACSEG_TPL_NONE
+#undef ACSEG_TPL_T
 #undef ACSEG_MG_KERNELS
 
 // ---------------------------------------------------------------------------
@@ -873,15 +878,39 @@ size_t mg_pass_lds(int op, const MgImage& m, int sweeps) {
     }
 }
 
+// Compute units of the current device, queried once per device.
+static int device_cus() {
+    static std::atomic<int> cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int n = cus[dev].load(std::memory_order_relaxed);
+    if (n <= 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cus[dev].store(n, std::memory_order_relaxed);
+    }
+    return n;
+}
+
 hipError_t launch_mg(int op, int N, int ncomp, const MgImage& single, const MgGrid& g, const MgStep& st,
                      size_t lds, hipStream_t s) {
     const int items = g.descs ? g.nwork : mg_pass_tiles(op, single, st.level);
     if (items <= 0) return hipSuccess;
+    // A down / up pass's tile stages 1.4-2.8k nodes; more threads take fewer of
+    // them at a time in every phase.  The most that lets all of the pass's
+    // workgroups fit on the device at once (2048 threads per CU) is taken.
+    const int64_t fit = 2048 * (int64_t)device_cus() / ((int64_t)items * ncomp);
+    const int T = fit >= 1024 ? 1024 : (fit >= 512 ? 512 : kBlock);
+    const dim3 cg(items, ncomp);  // componentwise passes
     switch (op) {
-        case kMgDown: return mg_launch(k_mg_down, k_mg_down_b, dim3(items, ncomp), kBlock, lds, single, g, st, s);
-        case kMgUp: return mg_launch(k_mg_up, k_mg_up_b, dim3(items, ncomp), kBlock, lds, single, g, st, s);
-        case kMgTail:
-            return mg_launch(k_mg_tail, k_mg_tail_b, dim3(items, ncomp), kTailThreads, lds, single, g, st, s);
+        case kMgDown:
+            if (T == 1024) return mg_launch(k_mg_down<1024>, k_mg_down_b<1024>, cg, T, lds, single, g, st, s);
+            if (T == 512) return mg_launch(k_mg_down<512>, k_mg_down_b<512>, cg, T, lds, single, g, st, s);
+            return mg_launch(k_mg_down<kBlock>, k_mg_down_b<kBlock>, cg, T, lds, single, g, st, s);
+        case kMgUp:
+            if (T == 1024) return mg_launch(k_mg_up<1024>, k_mg_up_b<1024>, cg, T, lds, single, g, st, s);
+            if (T == 512) return mg_launch(k_mg_up<512>, k_mg_up_b<512>, cg, T, lds, single, g, st, s);
+            return mg_launch(k_mg_up<kBlock>, k_mg_up_b<kBlock>, cg, T, lds, single, g, st, s);
+        case kMgTail: return mg_launch(k_mg_tail, k_mg_tail_b, cg, kTailThreads, lds, single, g, st, s);
         default: break;
     }
     const dim3 grid(items);
