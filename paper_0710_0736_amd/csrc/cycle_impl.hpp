@@ -314,18 +314,43 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
         const int li = ly * RW + (lx & 1) * HL + (lx >> 1);
         lds_put<N>(lds, li, ust[q]);
     }
-    __syncthreads();  // u and the sums staged
-    if constexpr (!FIRST) {
-        // after a truncated coarse correction: alpha = clamp(<g~,w>/<w,Hw>, 0, 1)
-        // from the direction pass's partials (every workgroup sums them in the
-        // same order), then u = max(u + alpha w, 0) on the staged field, node by
-        // node (few registers: the other launches keep their allocation)
+    // After a truncated coarse correction this launch applies
+    // u = max(u + alpha w, 0), alpha = clamp(<g~,w>/<w,Hw>, 0, 1) from the
+    // direction pass's partials (every workgroup sums them in the same order).
+    // In the one-sweep launches (the multigrid's post-smoothing) the partial
+    // sums and w at the thread's staged nodes are loaded here, into the
+    // registers u has left, so their latency overlaps the barrier; the
+    // two-sweep launches keep their register allocation and load them after it.
+    constexpr bool kEarly = K == 1;
+    [[maybe_unused]] float wst[kEarly ? NS : 1][N];
+    [[maybe_unused]] double ga = 0.0, qa = 0.0;
+    if constexpr (!FIRST && kEarly) {
         if (st.mg_update) {
-            __shared__ double mgs[2 * (T / kWave)];
-            double ga = 0.0, qa = 0.0;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const int idx = threadIdx.x + q * T;
+                const int ly = idx / LX, lx = idx - ly * LX;
+                const int gx = x0 + lx, gy = y0 + ly;
+                const bool in = idx < LX * LY && (INT || (gx >= 0 && gx < W && gy >= 0 && gy < H));
+                const uint32_t g = in ? (uint32_t)(gy * W + gx) : 0u;
+#pragma unroll
+                for (int i = 0; i < N; ++i) wst[q][i] = gload(a.mg_w + i * P, g);
+            }
             for (int k = threadIdx.x; k < a.mg_parts; k += T) {
                 ga += a.mg_part[2 * k];
                 qa += a.mg_part[2 * k + 1];
+            }
+        }
+    }
+    __syncthreads();  // u and the sums staged
+    if constexpr (!FIRST) {
+        if (st.mg_update) {
+            __shared__ double mgs[2 * (T / kWave)];
+            if constexpr (!kEarly) {
+                for (int k = threadIdx.x; k < a.mg_parts; k += T) {
+                    ga += a.mg_part[2 * k];
+                    qa += a.mg_part[2 * k + 1];
+                }
             }
             ga = wave_sum(ga);
             qa = wave_sum(qa);
@@ -341,19 +366,36 @@ __device__ __forceinline__ void cycle_tile(const CycleArgs& a, const CycleStep& 
             }
             const float alpha = (qa > 0.0 && ga > 0.0) ? (float)fmin(ga / qa, 1.0) : 0.f;
             if (tile == 0 && threadIdx.x == 0) ctl->alpha = alpha;  // for inspection
-            for (int idx = threadIdx.x; idx < LX * LY; idx += T) {
-                const int ly = idx / LX, lx = idx - ly * LX;
-                const int gx = x0 + lx, gy = y0 + ly;
-                if (!(INT || (gx >= 0 && gx < W && gy >= 0 && gy < H))) continue;
-                const uint32_t g = (uint32_t)(gy * W + gx);
-                float wv[N], uv[N];
+            if constexpr (kEarly) {
+                // each thread updates the nodes it staged
 #pragma unroll
-                for (int i = 0; i < N; ++i) wv[i] = gload(a.mg_w + i * P, g);
-                float* slot = lds + (ly * RW + (lx & 1) * HL + (lx >> 1)) * NPD;
-                lds_ld<N>(slot, uv);
+                for (int q = 0; q < NS; ++q) {
+                    const int idx = threadIdx.x + q * T;
+                    const int ly = idx / LX, lx = idx - ly * LX;
+                    const int gx = x0 + lx, gy = y0 + ly;
+                    if (!(idx < LX * LY && (INT || (gx >= 0 && gx < W && gy >= 0 && gy < H)))) continue;
+                    float* slot = lds + (ly * RW + (lx & 1) * HL + (lx >> 1)) * NPD;
+                    float uv[N];
+                    lds_ld<N>(slot, uv);
 #pragma unroll
-                for (int i = 0; i < N; ++i) uv[i] = fmaxf(fmaf(alpha, wv[i], uv[i]), 0.f);
-                lds_st<N>(slot, uv);
+                    for (int i = 0; i < N; ++i) uv[i] = fmaxf(fmaf(alpha, wst[q][i], uv[i]), 0.f);
+                    lds_st<N>(slot, uv);
+                }
+            } else {
+                for (int idx = threadIdx.x; idx < LX * LY; idx += T) {
+                    const int ly = idx / LX, lx = idx - ly * LX;
+                    const int gx = x0 + lx, gy = y0 + ly;
+                    if (!(INT || (gx >= 0 && gx < W && gy >= 0 && gy < H))) continue;
+                    const uint32_t g = (uint32_t)(gy * W + gx);
+                    float wv[N], uv[N];
+#pragma unroll
+                    for (int i = 0; i < N; ++i) wv[i] = gload(a.mg_w + i * P, g);
+                    float* slot = lds + (ly * RW + (lx & 1) * HL + (lx >> 1)) * NPD;
+                    lds_ld<N>(slot, uv);
+#pragma unroll
+                    for (int i = 0; i < N; ++i) uv[i] = fmaxf(fmaf(alpha, wv[i], uv[i]), 0.f);
+                    lds_st<N>(slot, uv);
+                }
             }
             __syncthreads();
         }
