@@ -222,3 +222,29 @@ def test_batched_multigrid_step_against_oracle():
         assert err <= GATE_U, (b, err)
         bad, total, raw = label_gate(ug, u_ref)
         assert bad <= 1e-3 * total, (b, bad, raw)
+
+
+def test_multigrid_passes_equal_across_workgroup_sizes():
+    """A down or up pass runs 1024, 512 or 256 threads per workgroup, the most
+    that let all of its workgroups be resident at once, so a batch and a single
+    image of the same size take different variants (on a 256-CU device: six
+    512^2 images put 1536 workgroups into the level-1 up pass and 768 into the
+    level-1 down pass, against 256 and 128 for one image).  Every node is
+    updated by the same arithmetic whichever thread takes it, so the batch
+    must give each image exactly its one-image solve."""
+    base = synth.pixel_twin(synth.VORONOI1024)
+    problems, images, u0s = [], [], []
+    for seed in range(6):
+        w = base.scaled(512, 512, N=4)
+        img, u0, _ = w.make(20 + seed)
+        problems.append(acseg.Problem.from_workload(w, levels=0, steps=2, max_cycles=3,
+                                                    flags=acseg.FLAG_FIXED_CYCLES))
+        images.append(cuda(img))
+        u0s.append(cuda(u0))
+    singles = [acseg.solve(p, im, u0.clone())[:3] for p, im, u0 in zip(problems, images, u0s)]
+    us, cs, sts = acseg.solve_batched(problems, images, [u0.clone() for u0 in u0s])
+    torch.cuda.synchronize()
+    for b, (u, c, st) in enumerate(singles):
+        assert torch.equal(us[b], u), b
+        assert torch.equal(cs[b], c), b
+        assert sts[b] == st, (b, sts[b], st)
