@@ -458,10 +458,11 @@ acseg_status acseg_backward(acseg_ctx *ctx, const acseg_problem *p, const float 
  * and forgets them.  Families: "cmeans", "rhs", "smooth" (one smoothing
  * cycle, or one launch of it when a cycle needs several), the passes of the
  * truncated multigrid correction ("mg_restrict": fine defect and first
- * restriction, "mg_down", "mg_tail": the coarsest levels in one workgroup,
- * "mg_up", "mg_dir": prolongated direction and line-search partials,
- * "mg_update"), "ssc" (the subspace correction), "adj_sweep" (adjoint
- * sweeps), "other".
+ * restriction, "mg_down", "mg_tail": the coarsest levels in one workgroup
+ * per component, "mg_up", "mg_dir": prolongated direction and line-search
+ * partials; the step length and update count with the post-smoothing under
+ * "smooth"), "ssc" (the subspace correction), "adj_sweep" (adjoint sweeps),
+ * "other".
  */
 typedef struct acseg_kernel_time {
     char name[16];
