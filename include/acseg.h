@@ -161,7 +161,11 @@ typedef int32_t acseg_status;
  *           levels both must be >= 1 (ACSEG_ERR_UNSUPPORTED otherwise); the
  *           coarse levels use the same counts; the coarsest level runs as
  *           many red-black sweeps from zero as its Jacobi contraction bound
- *           needs for FP32 rounding, at most 8
+ *           needs for FP32 rounding, at most 8.  With nu_pre = nu_post = 1 a
+ *           cycle ends with the next cycle's pre-smoothing sweep (one launch
+ *           of two sweeps), and the convergence test follows both: a step's
+ *           first cycle is pre-smoothing, correction, two sweeps, every later
+ *           one correction, two sweeps
  *   max_cycles  cycle budget per time step; >= 1
  *   tol     natural-residual tolerance (max norm, absolute); >= 0
  */

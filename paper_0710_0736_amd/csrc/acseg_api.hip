@@ -309,6 +309,12 @@ MgImage mg_image_of(const acseg_problem* p, const MgPlan& m, const Layout& L, vo
     d.tail = m.tail;
     d.dir_blocks = dir_blocks(p->W, p->H);
     d.coarse_sweeps = m.coarse_sweeps;
+    CycleArgs tiling{};
+    cycle_tiling(p->N, p->W, p->H, &tiling);
+    d.res_part = at<float>(ws, L.part_f);
+    d.part_stride = L.part_stride;
+    d.ntiles = tiling.ntiles;
+    d.tol = (float)p->tol;
     d.fine = m.coef[0];
     for (int l = 1; l < m.L; ++l) {
         MgLevel& v = d.lv[l];
@@ -349,13 +355,14 @@ std::vector<MgPassRec> mg_passes(const MgPlan& m, int nu_pre, int nu_post) {
 // smoothing launches of the current step (in place).
 acseg_status enqueue_correction(acseg_ctx* ctx, const acseg_problem* p, const MgPlan& m,
                                 const Layout& L, void* ws, Bufs bufs, int slot, bool fixed,
-                                int launch, hipStream_t s) {
+                                int launch, int check, hipStream_t s) {
     const MgImage d = mg_image_of(p, m, L, ws, bufs);
     const MgGrid single{nullptr, nullptr, 0};
     MgStep st{};
     st.slot = slot;
     st.fixed = fixed ? 1 : 0;
     st.launch = launch;
+    st.check = check;
     st.nu_pre = p->nu_pre;
     st.nu_post = p->nu_post;
     for (const MgPassRec& r : mg_passes(m, p->nu_pre, p->nu_post)) {
@@ -447,9 +454,16 @@ CycleArgs cycle_args_of(const acseg_problem* p, const Coefs& cf, const float* im
     return a;
 }
 
-// Launches per cycle and whether the first launch must store the rhs.
+// Launches per cycle and whether the first launch must store the rhs.  A
+// truncated V(1,1) cycle (merged) closes with one launch of two sweeps: its
+// post-smoothing sweep and the next cycle's pre-smoothing sweep, the residual
+// measured after both; the defect pass of the next cycle makes the
+// convergence test.  A step takes one launch per cycle plus its first
+// pre-smoothing, with a fixed cycle count or not, and its last cycle keeps
+// the pre-smoothing sweep of the cycle it does not run.
 struct Schedule {
     int lpc, lpre;
+    bool merged;
     bool fixed, store_rhs, mg;
 };
 
@@ -461,6 +475,7 @@ Schedule schedule_of(const acseg_problem* p) {
     sc.mg = m.L >= 2;
     sc.lpre = cycle_launches(p->nu_pre);
     sc.lpc = sc.mg ? sc.lpre + cycle_launches(p->nu_post) : cycle_launches(sweeps);
+    sc.merged = sc.mg && (p->flags & ACSEG_FLAG_SSC) == 0u && p->nu_pre == 1 && p->nu_post == 1;
     // a one-launch step keeps the rhs in registers; the defect reads it
     sc.store_rhs = sc.mg || !(sc.fixed && p->max_cycles == 1 && sc.lpc == 1);
     return sc;
@@ -498,12 +513,25 @@ acseg_status enqueue_step(acseg_ctx* ctx, const acseg_problem* p, const Coefs& c
             }));
             return ACSEG_OK;
         }
+        if (sc.merged) {
+            if (k == 0) {
+                const CycleRole pre{true, true, false};
+                st.launch = 0;
+                ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] { return launch_cycle(p->N, p->C, 1, a, st, single, pre, s); }));
+            }
+            const acseg_status v = enqueue_correction(ctx, p, m, L, ws, bufs, st.slot, sc.fixed, k + 1, k, s);
+            if (v != ACSEG_OK) return v;
+            st.launch = k + 1;
+            const CycleRole post{false, false, true, true};
+            ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] { return launch_cycle(p->N, p->C, 2, a, st, single, post, s); }));
+            return ACSEG_OK;
+        }
         const CycleRole pre{k == 0, true, false};
         ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] { return launch_cycle(p->N, p->C, p->nu_pre, a, st, single, pre, s); }));
         const acseg_status v =
             (p->flags & ACSEG_FLAG_SSC) != 0u
                 ? enqueue_ssc(ctx, p, m, L, ws, bufs, st.slot, sc.fixed, k * sc.lpc + sc.lpre, s)
-                : enqueue_correction(ctx, p, m, L, ws, bufs, st.slot, sc.fixed, k * sc.lpc + sc.lpre, s);
+                : enqueue_correction(ctx, p, m, L, ws, bufs, st.slot, sc.fixed, k * sc.lpc + sc.lpre, 0, s);
         if (v != ACSEG_OK) return v;
         st.launch = k * sc.lpc + sc.lpre;
         const CycleRole post{false, false, true, (p->flags & ACSEG_FLAG_SSC) == 0u};
@@ -537,7 +565,7 @@ acseg_status enqueue_step(acseg_ctx* ctx, const acseg_problem* p, const Coefs& c
         // the next step starts with as many cycles as this one needed
         ctx->cycle_hint = std::max(1, ctx->host_slot->done ? ctx->host_slot->cycles : k);
     }
-    const StepEndArgs e{p->max_cycles, sc.lpc};
+    const StepEndArgs e = sc.merged ? StepEndArgs{p->max_cycles, 1, 1} : StepEndArgs{p->max_cycles, sc.lpc, 0};
     ACSEG_TRY(timed(ctx, kFamOther, s, [&] {
         return launch_step_end(p->N, p->C, a, st, e, nullptr, nullptr, 0, s);
     }));
@@ -1154,14 +1182,17 @@ acseg_status acseg_solve_batched(acseg_ctx* ctx, int32_t B, const acseg_problem*
                     }));
                     continue;
                 }
-                const CycleRole pre{k == 0, true, false};
-                ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] {
-                    return launch_cycle(g.N, g.C, pg.nu_pre, any, st, grid, pre, s);
-                }));
+                if (!sc.merged || k == 0) {
+                    const CycleRole pre{k == 0, true, false};
+                    ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] {
+                        return launch_cycle(g.N, g.C, pg.nu_pre, any, st, grid, pre, s);
+                    }));
+                }
                 MgStep ms{};
                 ms.slot = a;
                 ms.fixed = st.fixed;
-                ms.launch = k * sc.lpc + sc.lpre;
+                ms.launch = sc.merged ? k + 1 : k * sc.lpc + sc.lpre;
+                ms.check = sc.merged ? k : 0;
                 ms.nu_pre = pg.nu_pre;
                 ms.nu_post = pg.nu_post;
                 for (const MgLaunchRec& r : g.mgl) {
@@ -1171,13 +1202,14 @@ acseg_status acseg_solve_batched(acseg_ctx* ctx, int32_t B, const acseg_problem*
                         return launch_mg(r.op, g.N, g.N, none, mgrid, ms, r.lds, s);
                     }));
                 }
-                st.launch = k * sc.lpc + sc.lpre;
+                st.launch = sc.merged ? k + 1 : k * sc.lpc + sc.lpre;
                 const CycleRole post{false, false, true, true};  // applies the correction's update
+                const int sweeps = sc.merged ? 2 : pg.nu_post;
                 ACSEG_TRY(timed(ctx, kFamSmooth, s, [&] {
-                    return launch_cycle(g.N, g.C, pg.nu_post, any, st, grid, post, s);
+                    return launch_cycle(g.N, g.C, sweeps, any, st, grid, post, s);
                 }));
             }
-            const StepEndArgs e{p0.max_cycles, sc.lpc};
+            const StepEndArgs e = sc.merged ? StepEndArgs{p0.max_cycles, 1, 1} : StepEndArgs{p0.max_cycles, sc.lpc, 0};
             ACSEG_TRY(timed(ctx, kFamOther, s, [&] {
                 return launch_step_end(g.N, g.C, any, st, e, ddesc, dimgs + g.img0, (int)g.members.size(), s);
             }));

@@ -165,8 +165,10 @@ struct CycleGrid {
     int sor;  // batched launch with over-relaxed sweeps (omega from each descriptor)
 };
 
+// The iterate after a step of `cycles` cycles is the one left by
+// cycles * launches_per_cycle + launch_offset smoothing launches.
 struct StepEndArgs {
-    int max_cycles, launches_per_cycle;
+    int max_cycles, launches_per_cycle, launch_offset;
 };
 
 // A cycle's tiles are 64 x cycle_tile_rows(N) nodes.
@@ -245,6 +247,11 @@ struct MgImage {
     int L, tail;
     int dir_blocks;     // workgroups of the direction pass (partials to reduce)
     int coarse_sweeps;  // red-black sweeps on the coarsest level
+    // the convergence test that opens a cycle (MgStep::check): the residual
+    // partials of the smoothing launches, one per tile, in two sets by cycle parity
+    const float* res_part;
+    int part_stride, ntiles;
+    float tol;
     LevelCoef fine;
     MgLevel lv[kMaxLevels];  // lv[1..L-1]
 };
@@ -256,6 +263,7 @@ struct MgStep {
     int sweeps;   // red-black sweeps of a coarse pass
     int zero;     // up-leg pass starts from v = 0 without a prolongation (coarsest global level)
     int nu_pre, nu_post;
+    int check;    // > 0: the defect pass first tests whether cycle check - 1 converged
 };
 
 // Where a multigrid launch's workgroups come from: one image (descs == NULL:

@@ -753,7 +753,7 @@ __device__ __forceinline__ void step_end(const CycleArgs& a, const CycleStep& st
         resid = block_max(strided_max4(last, a.ntiles), red);
     }
     if (threadIdx.x != 0) return;
-    ctl->cur = iterate_buf(ctl->cur, cycles * e.launches_per_cycle);
+    ctl->cur = iterate_buf(ctl->cur, cycles * e.launches_per_cycle + e.launch_offset);
     ctl->resid = resid;
     ctl->cycles_total += cycles;
     ctl->cycles_max = cycles > ctl->cycles_max ? cycles : ctl->cycles_max;

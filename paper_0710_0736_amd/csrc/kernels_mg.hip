@@ -217,6 +217,29 @@ __device__ __forceinline__ void mg_defect_restrict(const MgImage& d, int tile, c
     const int W = d.W, H = d.H, Wc = c.W, Hc = c.H;
     const MgState ms = mg_state(d, st);
     if (ms.skip) return;
+    if (st.check > 0 && !st.fixed) {
+        // The test that opens cycle st.check when one launch smooths both after
+        // the previous correction and before this one: the residual that launch
+        // left.  Every workgroup reduces the same partials, so all take the
+        // same decision; workgroup 0 records it.
+        __shared__ float red[kBlock / kWave];
+        __shared__ int stop;
+        const float* prev = d.res_part + ((st.check - 1) & 1) * d.part_stride;
+        float r = 0.f;
+        for (int b = threadIdx.x; b < d.ntiles; b += kBlock) r = fmaxf(r, prev[b]);
+        r = block_max(r, red);
+        if (threadIdx.x == 0) {
+            stop = !(r > d.tol);
+            if (stop && tile == 0) {
+                StepSlot* slot = &d.ctl->step[st.slot];
+                slot->done = 1;
+                slot->cycles = st.check;
+                slot->resid = r;
+            }
+        }
+        __syncthreads();
+        if (stop) return;
+    }
     const int tx = (Wc + kDrTX - 1) / kDrTX;
     const int X0 = (tile % tx) * kDrTX, Y0 = (tile / tx) * kDrTY;
     const int sx0 = 2 * X0 - 2, sy0 = 2 * Y0 - 2;
