@@ -125,3 +125,30 @@ def test_cycles_never_raise_the_step_objective(flags):
     slack = 1e-6 * abs(Js[0])
     assert all(Js[k + 1] <= Js[k] + slack for k in range(len(Js) - 1)), Js
     assert Js[-1] < Js[0]
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_stopped_step_equals_fixed_schedule_and_reports_its_residual(seed):
+    """With V(1,1) every cycle closes with one launch of two sweeps (its
+    post-smoothing and the next cycle's pre-smoothing), and the next cycle's
+    defect pass tests convergence.  A step that stops after c cycles has then
+    run exactly the launches of a fixed schedule of c cycles, so both return
+    the same iterate bit for bit, and the residual the step reports is that
+    iterate's natural residual (evaluated by the oracle in FP64)."""
+    w = synth.pixel_twin(synth.VORONOI1024).scaled(160, 120, N=4)
+    img, u0, _ = w.make(seed)
+    u0 = np.asarray(u0, np.float32)
+    p_ad = gpu_problem(w, levels=0, max_cycles=60)
+    u_a, _, st_a = acseg.step(p_ad, cuda(img), cuda(u0))
+    torch.cuda.synchronize()
+    assert st_a["status"] == acseg.OK and 1 <= st_a["cycles_max"] < 60, st_a
+    p_fx = gpu_problem(w, levels=0, max_cycles=st_a["cycles_max"], flags=acseg.FLAG_FIXED_CYCLES)
+    u_f, _, st_f = acseg.step(p_fx, cuda(img), cuda(u0))
+    torch.cuda.synchronize()
+    assert torch.equal(u_a, u_f)
+    assert st_f["final_residual"] == st_a["final_residual"], (st_a, st_f)
+    P = orc_params(w, levels=0)
+    c, _ = orc.colour_means(P, img, u0)
+    b = orc.rhs(P, img, u0, c)
+    r = orc.residual(P, b, host(u_a).astype(np.float64))
+    assert abs(r - st_a["final_residual"]) <= 2e-7 and r <= GPU_TOL + 2e-7, (r, st_a)
