@@ -152,3 +152,13 @@ def test_stopped_step_equals_fixed_schedule_and_reports_its_residual(seed):
     b = orc.rhs(P, img, u0, c)
     r = orc.residual(P, b, host(u_a).astype(np.float64))
     assert abs(r - st_a["final_residual"]) <= 2e-7 and r <= GPU_TOL + 2e-7, (r, st_a)
+
+
+@pytest.mark.parametrize("nu_pre,nu_post", [(2, 1), (1, 2)])
+def test_multigrid_step_parity_other_smoothing_counts(nu_pre, nu_post):
+    """Cycles other than V(1,1) keep a pre-smoothing and a post-smoothing launch
+    per cycle (the pre-smoothing launch makes the convergence test): the step
+    still reaches the oracle's step."""
+    w = synth.pixel_twin(synth.VORONOI1024).scaled(120, 96, N=4)
+    img, u0, _ = w.make(15)
+    check_step(w, img, u0, levels=0, max_cycles=400, nu_pre=nu_pre, nu_post=nu_post)
