@@ -695,6 +695,28 @@ def main():
                                      "final_residual": stv2["final_residual"]}}
         log(f"[bench] {vlevels}-level V-cycles, one image per call: {args.steps} segmentations in "
             f"{tvd:.4f} s with device exits ({stv3['cycles_total']} cycles), {tv:.4f} s fixed")
+        if B > 1:
+            # the same V-cycles over the headline's batch (eager, device exits)
+            probs_v = [pvd] * B
+
+            def segment_vb():
+                ims = [prep(x) for x in imgs]
+                for b in range(B):
+                    us[b].copy_(u0s[b])
+                _, cs, _ = acseg.solve_batched(probs_v, ims, us, want_stats=False)
+                return [acseg.labels(pvd, us[b], cs[b]) for b in range(B)]
+
+            tvb = timed(segment_vb, args.steps)
+            for b in range(B):
+                us[b].copy_(u0s[b])
+            _, _, stsb = acseg.solve_batched(probs_v, [prep(x) for x in imgs], us)
+            if any(x["status"] != acseg.OK for x in stsb):
+                raise RuntimeError(f"batched V-cycles did not converge: {stsb}")
+            vcycle["batched"] = {"value": round(args.steps * B / tvb, 3), "unit": "segmentations/s",
+                                 "batch": B, "graph": False,
+                                 "cycles_total": [x["cycles_total"] for x in stsb],
+                                 "final_residual_max": max(x["final_residual"] for x in stsb)}
+            log(f"[bench] {vlevels}-level V-cycles, batched: {args.steps} x {B} segmentations in {tvb:.4f} s")
 
     # the timed schedule converges: check it once with statistics
     u.copy_(u0)
